@@ -1,0 +1,112 @@
+"""CPU oracle for Brandes betweenness centrality -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the benchmark's
+``cpu_baseline`` leg may import this package.  The GPU library never loads it
+and shares no code with it.
+
+``bc_oracle.c`` is a plain single-threaded C implementation of the paper's
+sequential algorithm (Section "Background", Eq. 1-2 and the algorithm figure
+"Betweenness Centrality Algorithm").  This module compiles it with gcc and
+wraps it with ctypes.  ``brute.py`` holds definition-level checkers (path
+enumeration, walk counting) used to pin the oracle.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bc_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle_bc.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle (gcc -O2, no fast-math: evaluation order is kept)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall",
+                               "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    lib.oracle_bc.restype = ctypes.c_int
+    lib.oracle_bc.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.c_int64, P, P]
+    lib.oracle_source.restype = ctypes.c_int
+    lib.oracle_source.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_int32, P, P, P, P, P]
+    lib.oracle_sizeof_long_double.restype = ctypes.c_int
+    if lib.oracle_sizeof_long_double() != np.dtype(np.longdouble).itemsize:
+        raise RuntimeError("long double size mismatch between gcc and numpy")
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _rp(g):
+    rp = np.ascontiguousarray(g.row_ptr)
+    if rp.dtype == np.int64:
+        return None, rp
+    return np.ascontiguousarray(rp, dtype=np.int32), None
+
+
+def bc(g, sources=None):
+    """Raw ordered-pair BC sums over ``sources`` (None = all vertices).
+
+    Returns (bc float64[n], modes int32[len(sources)]) where mode 1 marks a
+    source whose path counts exceed uint64 and were evaluated in long double.
+    """
+    lib = _load()
+    rp32, rp64 = _rp(g)
+    col = np.ascontiguousarray(g.col_idx, dtype=np.int32)
+    out = np.zeros(g.n, dtype=np.float64)
+    if sources is None:
+        src = None
+        ns = g.n
+    else:
+        src = np.ascontiguousarray(sources, dtype=np.int32)
+        ns = src.size
+    modes = np.zeros(ns, dtype=np.int32)
+    rc = lib.oracle_bc(g.n, _ptr(rp32), _ptr(rp64), _ptr(col), _ptr(src), ns, _ptr(out), _ptr(modes))
+    if rc != 0:
+        raise ValueError(f"oracle_bc failed with code {rc}")
+    return out, modes
+
+
+class SourceDetail:
+    __slots__ = ("d", "sigma_u64", "sigma_ld", "delta", "mode", "n_levels")
+
+
+def source(g, s: int) -> SourceDetail:
+    """Distances, path counts and dependencies for one source."""
+    lib = _load()
+    rp32, rp64 = _rp(g)
+    col = np.ascontiguousarray(g.col_idx, dtype=np.int32)
+    n = g.n
+    r = SourceDetail()
+    r.d = np.empty(n, np.int32)
+    r.sigma_u64 = np.empty(n, np.uint64)
+    r.sigma_ld = np.empty(n, np.longdouble)
+    r.delta = np.empty(n, np.float64)
+    nl = np.zeros(1, np.int32)
+    mode = lib.oracle_source(n, _ptr(rp32), _ptr(rp64), _ptr(col), int(s), _ptr(r.d),
+                             _ptr(r.sigma_u64), _ptr(r.sigma_ld), _ptr(r.delta), _ptr(nl))
+    if mode < 0:
+        raise ValueError(f"oracle_source failed with code {mode}")
+    r.mode = int(mode)
+    r.n_levels = int(nl[0])
+    return r
