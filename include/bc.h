@@ -1,0 +1,233 @@
+/*
+ * bc.h -- C ABI of libbc, exact Brandes betweenness centrality on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (Mishra, Vadhiyar, Nasre, Pingali, "A Fine-Grained Hybrid
+ * CPU-GPU Algorithm for Betweenness Centrality Computations", Section
+ * "Background"):
+ *   Eq. 1   BC[v] = sum over s != v != t of sigma_st(v) / sigma_st,
+ *   Eq. 2   delta_s(v) = sum over successors u of v of
+ *                        sigma_sv / sigma_su * (1 + delta_s(u)),
+ *           BC[v] = sum over sources s != v of delta_s(v),
+ * evaluated with the level-synchronous forward phase (distances d and path
+ * counts sigma) and the level-by-level backward phase of the algorithm figure
+ * "Betweenness Centrality Algorithm".  Input graphs are undirected and
+ * unweighted (Section "Experiments and Results" converts every graph to an
+ * undirected one), stored as CSR (Section "Space Complexity").
+ *
+ * Conventions for every entry point:
+ *   - Every call returns a bc_status; no exception or abort crosses the ABI.
+ *     bc_last_error() returns a thread-local text for the last failure.
+ *   - Output buffers are left untouched on error.
+ *   - A handle is not re-entrant: calls on one handle must not overlap.
+ *     Separate handles are independent.  After BC_ERR_DEVICE the handle must
+ *     be destroyed; after argument errors it stays usable.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it and the call returns once that work is complete.
+ */
+#ifndef BC_H
+#define BC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum bc_status {
+    BC_OK = 0,
+    BC_ERR_INVALID_ARG = 1,    /* bad pointer, size, source id or option   */
+    BC_ERR_INVALID_GRAPH = 2,  /* CSR fails validation (see bc_graph_create) */
+    BC_ERR_OUT_OF_MEMORY = 3,  /* device allocation failed or over max_device_bytes */
+    BC_ERR_DEVICE = 4,         /* a HIP call failed; destroy the handle     */
+    BC_ERR_SIGMA_RANGE = 5,    /* scaled FP64 path counts left the double range */
+    BC_ERR_NOT_SUPPORTED = 6
+} bc_status;
+
+typedef struct bc_graph bc_graph;
+
+/* Name of a status code, and the thread-local text of the last failure. */
+const char *bc_status_string(bc_status s);
+const char *bc_last_error(void);
+
+/* ------------------------------------------------------------------ graph */
+
+/* bc_graph_create flags */
+#define BC_INPUT_DEVICE        0x1u  /* row_ptr / col_idx are device pointers   */
+#define BC_SKIP_SYMMETRY_CHECK 0x2u  /* caller guarantees symmetric arcs        */
+
+/*
+ * Build a graph handle from a CSR adjacency (Section "Space Complexity":
+ * offsets plus adjacency arrays).
+ *   n        number of vertices, 0 <= n < 2^31 - 1.
+ *   nnz      number of stored arcs; each undirected edge is stored twice.
+ *            nnz <= 2^31 - 1.
+ *   row_ptr  int32[n + 1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz.
+ *   col_idx  int32[nnz]; the neighbours of v are col_idx[row_ptr[v] ..
+ *            row_ptr[v+1]), strictly ascending (no duplicates), in [0, n),
+ *            never v itself (no self-loops), and symmetric: w is a neighbour
+ *            of v iff v is a neighbour of w.
+ *   flags    BC_INPUT_* bits above.
+ * Ownership: the arrays are copied into library-owned device memory; the
+ * caller may free them on return.  Validation runs on the device.
+ * Errors: BC_ERR_INVALID_ARG (NULL pointers, negative sizes),
+ * BC_ERR_INVALID_GRAPH (validation failure; bc_last_error names the rule),
+ * BC_ERR_OUT_OF_MEMORY, BC_ERR_DEVICE.  *out is set only on success.
+ */
+bc_status bc_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr,
+                          const int32_t *col_idx, uint32_t flags, bc_graph **out);
+
+/*
+ * Block-diagonal union of n_graphs independent graphs, one handle.  Graph g
+ * owns vertices [vtx_offsets[g], vtx_offsets[g+1]); vtx_offsets is host
+ * int32[n_graphs + 1] with vtx_offsets[0] = 0 and vtx_offsets[n_graphs] = n.
+ * No arc may cross a block boundary (BC_ERR_INVALID_GRAPH otherwise).  Since
+ * the components are independent, the BC of the union restricted to block g
+ * equals the BC of graph g; batches of sources never mix graphs.  Other
+ * arguments as in bc_graph_create.
+ */
+bc_status bc_graph_create_multi(int32_t n_graphs, const int32_t *vtx_offsets, int32_t n,
+                                int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                                uint32_t flags, bc_graph **out);
+
+/* NULL-safe.  Frees every device and host resource of the handle. */
+void bc_destroy(bc_graph *g);
+
+/* Basic facts: n, nnz, number of graphs, bytes of device memory held. */
+bc_status bc_graph_info(const bc_graph *g, int32_t *n, int64_t *nnz, int32_t *n_graphs,
+                        int64_t *device_bytes);
+
+/* -------------------------------------------------------------------- run */
+
+/* Direction / load-balancing variants of one forward level. */
+#define BC_VARIANT_PUSH_TPV 0  /* top-down, one thread per frontier vertex   */
+#define BC_VARIANT_PUSH_WPV 1  /* top-down, one 64-lane wavefront per vertex */
+#define BC_VARIANT_PULL     2  /* bottom-up over unvisited vertices          */
+
+/* Level policies (bc_run_options.policy). */
+#define BC_POLICY_AUTO       0 /* MLP when weights are loaded, else heuristic */
+#define BC_POLICY_HEURISTIC  1 /* direction-optimising alpha/beta rule        */
+#define BC_POLICY_MLP        2 /* learned switch; BC_ERR_INVALID_ARG if no weights */
+#define BC_POLICY_FORCE_PUSH_TPV 3
+#define BC_POLICY_FORCE_PUSH_WPV 4
+#define BC_POLICY_FORCE_PULL     5
+
+/* bc_run_options.flags */
+#define BC_RUN_ACCUMULATE  0x1u  /* add to the existing scores instead of resetting */
+#define BC_RUN_NO_GRAPHS   0x2u  /* launch level steps one by one, no hipGraph  */
+#define BC_RUN_FORCE_F64   0x4u  /* test hook: evaluate every source in FP64 mode */
+
+typedef struct bc_run_options {
+    uint32_t flags;
+    int32_t batch;        /* K: 0 = autotuned, 1 = plain per-source engine,
+                             8/16/32/64 = sources traversed together        */
+    int32_t policy;       /* BC_POLICY_*                                     */
+    float alpha;          /* top-down -> bottom-up when m_f > m_u / alpha (0 = 14) */
+    float beta;           /* bottom-up -> top-down when n_f < n / beta   (0 = 24) */
+    float wpv_degree;     /* push uses WPV when mean frontier degree > this (0 = 24) */
+    int32_t grid_blocks;  /* workgroups per step launch (0 = autotuned)      */
+    int32_t chunk_steps;  /* level steps per captured hipGraph (0 = default) */
+    int64_t sigma_limit;  /* test hook: treat path counts above this as overflow
+                             (0 = none, i.e. 2^64 - 1)                       */
+    int32_t reserved[8];
+} bc_run_options;
+
+/* Fill *opt with defaults (all zero fields, i.e. autotuned/automatic). */
+void bc_run_options_init(bc_run_options *opt);
+
+/*
+ * Brandes over a source list (Eq. 2 summed over s).
+ *   sources    host int32[n_sources]; NULL means every vertex 0 .. n-1 in order.
+ *              Ids outside [0, n) -> BC_ERR_INVALID_ARG.  A source listed
+ *              twice is counted twice.
+ *   opt        NULL = defaults.
+ * Scores are reset to zero first unless opt->flags has BC_RUN_ACCUMULATE.
+ * Distances and path counts are exact; a source whose path counts exceed
+ * 2^64 - 1 (or opt->sigma_limit) is evaluated again with FP64 path counts
+ * scaled by per-level powers of two.  Results do not depend on the policy,
+ * the variant chosen at any level, or graph capture.
+ */
+bc_status bc_run(bc_graph *g, const int32_t *sources, int64_t n_sources,
+                 const bc_run_options *opt, void *stream);
+
+/* bc_scores flags */
+#define BC_OUT_DEVICE 0x1u
+
+/*
+ * Copy the n FP64 scores (raw ordered-pair sums over the sources run so far,
+ * i.e. twice the unordered-pair betweenness for all-sources runs) to out
+ * (host, or device with BC_OUT_DEVICE).  len < n -> BC_ERR_INVALID_ARG.
+ */
+bc_status bc_scores(const bc_graph *g, double *out, int64_t len, uint32_t flags, void *stream);
+
+/*
+ * Per-source detail, extracted from a real run of the same kernels.
+ * Runs sources[0 .. n_sources) exactly like bc_run (scores included) and
+ * copies out the lane of sources[dump_index]: host arrays of length n, any
+ * may be NULL.
+ *   d          int32 distance, -1 = unreached.
+ *   sigma_u64  path counts (mode 0); zero in mode 1.
+ *   sigma_mant, sigma_exp   path count = sigma_mant * 2^sigma_exp (both modes).
+ *   delta      dependency delta_s(v); 0 for unreached vertices and for s.
+ *   *mode      0 = uint64 path counts, 1 = FP64 fallback.
+ */
+typedef struct bc_detail {
+    int32_t *d;
+    uint64_t *sigma_u64;
+    double *sigma_mant;
+    int32_t *sigma_exp;
+    double *delta;
+    int32_t mode;
+    int32_t n_levels;
+} bc_detail;
+
+bc_status bc_run_detail(bc_graph *g, const int32_t *sources, int64_t n_sources,
+                        const bc_run_options *opt, int64_t dump_index, bc_detail *out,
+                        void *stream);
+
+/* Statistics of the last bc_run on this handle. */
+typedef struct bc_stats {
+    int64_t n_sources;
+    int64_t n_batches;
+    int32_t batch;             /* K actually used                              */
+    int32_t policy;            /* policy actually used                         */
+    int32_t grid_blocks;
+    int32_t chunk_steps;
+    int64_t steps;             /* level steps executed (all phases)            */
+    int64_t launches;          /* step-kernel launches issued                  */
+    int64_t forward_levels;    /* forward levels over all batches              */
+    int64_t max_levels;
+    int64_t variant_levels[3]; /* forward levels run with each BC_VARIANT_*   */
+    int64_t f64_sources;       /* sources evaluated in FP64 mode              */
+    int64_t arcs_scanned;      /* adjacency entries read, all phases          */
+    int64_t lane_arcs;         /* (arc, source) pairs on shortest-path DAGs, both phases */
+    int64_t queue_entries;     /* level-queue entries written                  */
+    double algo_bytes;         /* algorithmic bytes (see design notes)        */
+    double ms;                 /* wall time of the run, host clock            */
+} bc_stats;
+
+bc_status bc_run_stats(const bc_graph *g, bc_stats *out);
+
+/* ---------------------------------------------------------- learned policy */
+
+/*
+ * Policy network: 5 features -> 32 -> 32 -> 3, ReLU hidden layers, FP32,
+ * predicting log2 of the time of each BC_VARIANT_*; the level takes the
+ * argmin.  Weights are packed row-major as W1[32][5], b1[32], W2[32][32],
+ * b2[32], W3[3][32], b3[3]: BC_MLP_PARAMS floats.
+ * Features of a level, in order: log2(1+n_f)/log2(1+n), log2(1+m_f)/log2(1+nnz),
+ * log2(1+n_u)/log2(1+n), log2(1+m_u)/log2(1+nnz), level/64, where n_f/m_f
+ * are the frontier's vertices/arcs and n_u/m_u the unvisited ones.
+ */
+#define BC_MLP_PARAMS (32 * 5 + 32 + 32 * 32 + 32 + 3 * 32 + 3)
+
+/* Load weights (host float[len], len == BC_MLP_PARAMS); weights == NULL
+ * unloads them.  A wrong length or non-finite weights -> BC_ERR_INVALID_ARG
+ * and the handle keeps its previous policy. */
+bc_status bc_load_policy(bc_graph *g, const float *weights, int64_t len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BC_H */

@@ -1,0 +1,933 @@
+// bc_api.hip -- the C ABI of libbc (include/bc.h): graph handles, device
+// validation, the host driver of the device-resident level state machine
+// (direct launches or captured hipGraph chunks), FP64 fallback, detail dumps,
+// statistics and the policy weights.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bc.h"
+#include "bc_common.h"
+
+namespace bcx {
+template <int MODE> __global__ void plain_step(PlainArgs a);
+template <int MODE> __global__ void batch_step(BatchArgs a);
+}  // namespace bcx
+
+using namespace bcx;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+static bc_status fail(bc_status st, const std::string &msg) {
+    g_last_error = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t _e = (expr);                                                               \
+        if (_e != hipSuccess) {                                                               \
+            return fail(_e == hipErrorOutOfMemory ? BC_ERR_OUT_OF_MEMORY : BC_ERR_DEVICE,     \
+                        std::string(#expr) + ": " + hipGetErrorString(_e));                   \
+        }                                                                                     \
+    } while (0)
+
+// ----------------------------------------------------------- small kernels
+namespace {
+
+__global__ void fill_i32(int32_t *p, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+enum : unsigned {
+    VAL_NONMONO = 1, VAL_RANGE = 2, VAL_SELF = 4, VAL_UNSORTED = 8, VAL_ASYM = 16, VAL_CROSS = 32
+};
+
+// Pass 1: row pointers are monotone and inside [0, nnz]; count non-isolated.
+__global__ void validate_rows(int32_t n, int64_t nnz, const int32_t *rp, unsigned *err,
+                              unsigned long long *nonisolated) {
+    unsigned long long cnt = 0;
+    unsigned e = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a = rp[v], b = rp[v + 1];
+        if (a > b || a < 0 || (int64_t)b > nnz) e |= VAL_NONMONO;
+        else if (b > a) ++cnt;
+    }
+    if (e) atomicOr(err, e);
+    cnt = wave_sum_u64(cnt);
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(nonisolated, cnt);
+}
+
+// Pass 2 (only after pass 1 is clean): one wavefront per vertex checks every
+// arc: range, self-loop, strict order, block membership, symmetry.
+__global__ void validate_arcs(int32_t n, const int32_t *rp, const int32_t *col, const int32_t *voff,
+                              int32_t n_graphs, int check_sym, unsigned *err) {
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    unsigned e = 0;
+    for (int64_t vv = gw; vv < n; vv += nw) {
+        const int32_t v = (int32_t)vv;
+        int glo = 0, ghi = n_graphs;  // block of v: voff[g] <= v < voff[g+1]
+        while (ghi - glo > 1) {
+            const int mid = (glo + ghi) >> 1;
+            if (voff[mid] <= v) glo = mid;
+            else ghi = mid;
+        }
+        const int32_t blo = voff[glo], bhi = voff[glo + 1];
+        const int32_t e0 = rp[v], e1 = rp[v + 1];
+        for (int32_t k = e0 + lane; k < e1; k += 64) {
+            const int32_t w = col[k];
+            if (w < 0 || w >= n) { e |= VAL_RANGE; continue; }
+            if (w == v) e |= VAL_SELF;
+            if (k > e0 && col[k - 1] >= w) e |= VAL_UNSORTED;
+            if (w < blo || w >= bhi) e |= VAL_CROSS;
+            if (check_sym) {
+                int32_t lo = rp[w], hi = rp[w + 1];
+                bool found = false;
+                while (lo < hi) {
+                    const int32_t mid = lo + ((hi - lo) >> 1);
+                    const int32_t x = col[mid];
+                    if (x == v) { found = true; break; }
+                    if (x < v) lo = mid + 1;
+                    else hi = mid;
+                }
+                if (!found) e |= VAL_ASYM;
+            }
+        }
+    }
+    if (e) atomicOr(err, e);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ handle
+template <typename T>
+static hipError_t dalloc(T **p, size_t count, size_t *acc) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    const size_t bytes = count * sizeof(T);
+    hipError_t e = hipMalloc((void **)p, bytes);
+    if (e == hipSuccess && acc) *acc += bytes;
+    return e;
+}
+
+struct CachedGraph {
+    std::vector<unsigned char> key;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+struct bc_graph {
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int32_t n_graphs = 1;
+    std::vector<int32_t> voff;     // host copy of vertex offsets
+    std::vector<int32_t> vgraph;   // not kept (large); block lookups use voff
+    int32_t *row_ptr = nullptr, *col = nullptr;
+    int64_t nonisolated = 0;
+    double *bc = nullptr;
+    size_t bytes = 0;
+    hipStream_t cap_stream = nullptr;
+    Ctl *ctl = nullptr;
+    Ctl *ctl_host = nullptr;       // pinned
+    int32_t *flag_host = nullptr;  // pinned: {phase, err} polled after chunks
+    // plain engine
+    bool plain_ready = false, plain_dirty = false;
+    int32_t *p_d = nullptr, *p_queue = nullptr, *p_level_off = nullptr, *p_shift = nullptr;
+    unsigned long long *p_sig = nullptr;
+    double *p_chat = nullptr;
+    // batched engine
+    bool batch_ready = false;
+    VisNext *b_vn = nullptr;
+    Tagged *b_fw0 = nullptr, *b_fw1 = nullptr;
+    int32_t *b_lq_vtx = nullptr;
+    unsigned long long *b_lq_mask = nullptr;
+    uint32_t b_lq_cap = 0;
+    int32_t *b_level_off = nullptr;
+    int32_t b_max_levels = 0;
+    unsigned long long *b_sig = nullptr;
+    double *b_chat = nullptr;
+    int32_t *b_shift = nullptr, *b_maxexp = nullptr, *b_lane_src = nullptr;
+    // per-run buffers (grown on demand)
+    int32_t *srcs = nullptr;
+    int64_t srcs_cap = 0;
+    int64_t *ovf = nullptr;
+    int64_t ovf_cap = 0;
+    int64_t *bstart = nullptr;
+    int32_t *blo = nullptr, *bhi = nullptr;
+    int64_t bcap = 0;
+    // policy
+    float *mlp = nullptr;
+    bool has_mlp = false;
+    // graph cache
+    std::vector<CachedGraph> graphs;
+    bc_stats stats{};
+};
+
+static void free_graphs(bc_graph *g) {
+    for (auto &cg : g->graphs) {
+        if (cg.exec) (void)hipGraphExecDestroy(cg.exec);
+        if (cg.graph) (void)hipGraphDestroy(cg.graph);
+    }
+    g->graphs.clear();
+}
+
+extern "C" void bc_destroy(bc_graph *g) {
+    if (!g) return;
+    (void)hipDeviceSynchronize();
+    free_graphs(g);
+    void *dev[] = {g->row_ptr, g->col, g->bc, g->ctl, g->p_d, g->p_queue, g->p_level_off, g->p_shift,
+                   g->p_sig, g->p_chat, g->b_vn, g->b_fw0, g->b_fw1, g->b_lq_vtx, g->b_lq_mask,
+                   g->b_level_off, g->b_sig, g->b_chat, g->b_shift, g->b_maxexp, g->b_lane_src,
+                   g->srcs, g->ovf, g->bstart, g->blo, g->bhi, g->mlp};
+    for (void *p : dev)
+        if (p) (void)hipFree(p);
+    if (g->ctl_host) (void)hipHostFree(g->ctl_host);
+    if (g->flag_host) (void)hipHostFree(g->flag_host);
+    if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+    delete g;
+}
+
+extern "C" const char *bc_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *bc_status_string(bc_status s) {
+    switch (s) {
+    case BC_OK: return "BC_OK";
+    case BC_ERR_INVALID_ARG: return "BC_ERR_INVALID_ARG";
+    case BC_ERR_INVALID_GRAPH: return "BC_ERR_INVALID_GRAPH";
+    case BC_ERR_OUT_OF_MEMORY: return "BC_ERR_OUT_OF_MEMORY";
+    case BC_ERR_DEVICE: return "BC_ERR_DEVICE";
+    case BC_ERR_SIGMA_RANGE: return "BC_ERR_SIGMA_RANGE";
+    case BC_ERR_NOT_SUPPORTED: return "BC_ERR_NOT_SUPPORTED";
+    }
+    return "BC_ERR_UNKNOWN";
+}
+
+static int grid_for(int64_t work, int per_block, int cap) {
+    int64_t b = (work + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n, int64_t nnz,
+                             const int32_t *row_ptr, const int32_t *col_idx, uint32_t flags, bc_graph **out) {
+    if (!out) return fail(BC_ERR_INVALID_ARG, "out is NULL");
+    if (n < 0 || n >= INT32_MAX - 2) return fail(BC_ERR_INVALID_ARG, "n out of range");
+    if (nnz < 0 || nnz > INT32_MAX) return fail(BC_ERR_INVALID_ARG, "nnz out of range (must be <= 2^31-1)");
+    if (!row_ptr || (nnz > 0 && !col_idx)) return fail(BC_ERR_INVALID_ARG, "NULL CSR array");
+    if (n_graphs < 1) return fail(BC_ERR_INVALID_ARG, "n_graphs < 1");
+    std::vector<int32_t> voff;
+    if (voff_in) {
+        voff.assign(voff_in, voff_in + n_graphs + 1);
+        if (voff[0] != 0 || voff[n_graphs] != n) return fail(BC_ERR_INVALID_ARG, "vtx_offsets must run from 0 to n");
+        for (int i = 0; i < n_graphs; ++i)
+            if (voff[i] > voff[i + 1]) return fail(BC_ERR_INVALID_ARG, "vtx_offsets not non-decreasing");
+    } else {
+        voff = {0, n};
+    }
+    const bool on_dev = flags & BC_INPUT_DEVICE;
+    bc_graph *g = new bc_graph();
+    g->n = n;
+    g->nnz = nnz;
+    g->n_graphs = n_graphs;
+    g->voff = voff;
+    auto bail = [&](bc_status st) {
+        bc_destroy(g);
+        return st;
+    };
+    hipError_t e;
+    unsigned *derr = nullptr;
+    unsigned long long *dcnt = nullptr;
+    int32_t *dvoff = nullptr;
+#define CR_TRY(expr)                                                                           \
+    do {                                                                                       \
+        e = (expr);                                                                            \
+        if (e != hipSuccess) {                                                                 \
+            if (derr) (void)hipFree(derr);                                                     \
+            if (dcnt) (void)hipFree(dcnt);                                                     \
+            if (dvoff) (void)hipFree(dvoff);                                                   \
+            fail(e == hipErrorOutOfMemory ? BC_ERR_OUT_OF_MEMORY : BC_ERR_DEVICE,              \
+                 std::string(#expr) + ": " + hipGetErrorString(e));                            \
+            return bail(e == hipErrorOutOfMemory ? BC_ERR_OUT_OF_MEMORY : BC_ERR_DEVICE);      \
+        }                                                                                      \
+    } while (0)
+    CR_TRY(dalloc(&g->row_ptr, (size_t)n + 1, &g->bytes));
+    CR_TRY(dalloc(&g->col, (size_t)nnz, &g->bytes));
+    const hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    CR_TRY(hipMemcpy(g->row_ptr, row_ptr, sizeof(int32_t) * ((size_t)n + 1), kind));
+    if (nnz) CR_TRY(hipMemcpy(g->col, col_idx, sizeof(int32_t) * (size_t)nnz, kind));
+    int32_t ends[2];
+    CR_TRY(hipMemcpy(&ends[0], g->row_ptr, sizeof(int32_t), hipMemcpyDeviceToHost));
+    CR_TRY(hipMemcpy(&ends[1], g->row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (ends[0] != 0 || (int64_t)ends[1] != nnz) {
+        fail(BC_ERR_INVALID_GRAPH, "row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
+        return bail(BC_ERR_INVALID_GRAPH);
+    }
+    CR_TRY(hipMalloc((void **)&derr, sizeof(unsigned)));
+    CR_TRY(hipMalloc((void **)&dcnt, sizeof(unsigned long long)));
+    CR_TRY(hipMalloc((void **)&dvoff, sizeof(int32_t) * voff.size()));
+    CR_TRY(hipMemcpy(dvoff, voff.data(), sizeof(int32_t) * voff.size(), hipMemcpyHostToDevice));
+    CR_TRY(hipMemset(derr, 0, sizeof(unsigned)));
+    CR_TRY(hipMemset(dcnt, 0, sizeof(unsigned long long)));
+    if (n > 0) {
+        validate_rows<<<grid_for(n, 256, 4096), 256>>>(n, nnz, g->row_ptr, derr, dcnt);
+        CR_TRY(hipGetLastError());
+    }
+    unsigned herr = 0;
+    unsigned long long hcnt = 0;
+    CR_TRY(hipMemcpy(&herr, derr, sizeof(unsigned), hipMemcpyDeviceToHost));
+    CR_TRY(hipMemcpy(&hcnt, dcnt, sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    if (!herr && n > 0 && nnz > 0) {
+        validate_arcs<<<grid_for((int64_t)n * 64, 256, 8192), 256>>>(
+            n, g->row_ptr, g->col, dvoff, n_graphs, (flags & BC_SKIP_SYMMETRY_CHECK) ? 0 : 1, derr);
+        CR_TRY(hipGetLastError());
+        CR_TRY(hipMemcpy(&herr, derr, sizeof(unsigned), hipMemcpyDeviceToHost));
+    }
+    (void)hipFree(derr);
+    (void)hipFree(dcnt);
+    (void)hipFree(dvoff);
+    derr = nullptr;
+    dcnt = nullptr;
+    dvoff = nullptr;
+    if (herr) {
+        std::string m = "invalid CSR:";
+        if (herr & VAL_NONMONO) m += " row_ptr not monotone / outside [0, nnz];";
+        if (herr & VAL_RANGE) m += " column index outside [0, n);";
+        if (herr & VAL_SELF) m += " self-loop;";
+        if (herr & VAL_UNSORTED) m += " row not strictly ascending (unsorted or duplicate arc);";
+        if (herr & VAL_ASYM) m += " arcs not symmetric;";
+        if (herr & VAL_CROSS) m += " arc crosses a graph boundary;";
+        fail(BC_ERR_INVALID_GRAPH, m);
+        return bail(BC_ERR_INVALID_GRAPH);
+    }
+    g->nonisolated = (int64_t)hcnt;
+    CR_TRY(dalloc(&g->bc, (size_t)n, &g->bytes));
+    CR_TRY(hipMemset(g->bc, 0, sizeof(double) * (size_t)(n > 0 ? n : 1)));
+    CR_TRY(dalloc(&g->ctl, 1, &g->bytes));
+    CR_TRY(hipHostMalloc((void **)&g->ctl_host, sizeof(Ctl), hipHostMallocDefault));
+    CR_TRY(hipHostMalloc((void **)&g->flag_host, 64 * sizeof(int32_t), hipHostMallocDefault));
+    CR_TRY(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+    CR_TRY(dalloc(&g->mlp, (size_t)kMlpParams, &g->bytes));
+#undef CR_TRY
+    *out = g;
+    return BC_OK;
+}
+
+extern "C" bc_status bc_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                                     uint32_t flags, bc_graph **out) {
+    return create_impl(1, nullptr, n, nnz, row_ptr, col_idx, flags, out);
+}
+
+extern "C" bc_status bc_graph_create_multi(int32_t n_graphs, const int32_t *vtx_offsets, int32_t n, int64_t nnz,
+                                           const int32_t *row_ptr, const int32_t *col_idx, uint32_t flags,
+                                           bc_graph **out) {
+    if (!vtx_offsets) return fail(BC_ERR_INVALID_ARG, "vtx_offsets is NULL");
+    return create_impl(n_graphs, vtx_offsets, n, nnz, row_ptr, col_idx, flags, out);
+}
+
+extern "C" bc_status bc_graph_info(const bc_graph *g, int32_t *n, int64_t *nnz, int32_t *n_graphs,
+                                   int64_t *device_bytes) {
+    if (!g) return fail(BC_ERR_INVALID_ARG, "NULL handle");
+    if (n) *n = g->n;
+    if (nnz) *nnz = g->nnz;
+    if (n_graphs) *n_graphs = g->n_graphs;
+    if (device_bytes) *device_bytes = (int64_t)g->bytes;
+    return BC_OK;
+}
+
+extern "C" void bc_run_options_init(bc_run_options *opt) {
+    if (opt) std::memset(opt, 0, sizeof(*opt));
+}
+
+// ------------------------------------------------------------ engine setup
+static bc_status ensure_plain(bc_graph *g, hipStream_t st) {
+    const int64_t n = g->n;
+    if (!g->plain_ready) {
+        HIP_TRY(dalloc(&g->p_d, (size_t)n, &g->bytes));
+        HIP_TRY(dalloc(&g->p_queue, (size_t)n, &g->bytes));
+        HIP_TRY(dalloc(&g->p_level_off, (size_t)n + 2, &g->bytes));
+        HIP_TRY(dalloc(&g->p_shift, (size_t)n + 2, &g->bytes));
+        HIP_TRY(dalloc(&g->p_sig, (size_t)n, &g->bytes));
+        HIP_TRY(dalloc(&g->p_chat, (size_t)n, &g->bytes));
+        g->plain_ready = true;
+        g->plain_dirty = true;
+    }
+    if (g->plain_dirty && n > 0) {
+        // invariant between sources: d = -1, sig = 0 everywhere
+        fill_i32<<<grid_for(n, 256, 4096), 256, 0, st>>>(g->p_d, n, -1);
+        fill_u64<<<grid_for(n, 256, 4096), 256, 0, st>>>(g->p_sig, n, 0ull);
+        HIP_TRY(hipGetLastError());
+        g->plain_dirty = false;
+    }
+    return BC_OK;
+}
+
+static bc_status ensure_batched(bc_graph *g) {
+    if (g->batch_ready) return BC_OK;
+    const int64_t n = g->n;
+    HIP_TRY(dalloc(&g->b_vn, (size_t)n, &g->bytes));
+    HIP_TRY(dalloc(&g->b_fw0, (size_t)n, &g->bytes));
+    HIP_TRY(dalloc(&g->b_fw1, (size_t)n, &g->bytes));
+    // every (vertex, lane) pair enters the level queues at most once
+    const int64_t cap = std::min<int64_t>((int64_t)kLanes * std::max<int64_t>(n, 1) + 64, (int64_t)INT32_MAX);
+    g->b_lq_cap = (uint32_t)cap;
+    HIP_TRY(dalloc(&g->b_lq_vtx, (size_t)cap, &g->bytes));
+    HIP_TRY(dalloc(&g->b_lq_mask, (size_t)cap, &g->bytes));
+    g->b_max_levels = (int32_t)std::min<int64_t>(n + 2, 65536);
+    if (g->b_max_levels < 4) g->b_max_levels = 4;
+    HIP_TRY(dalloc(&g->b_level_off, (size_t)g->b_max_levels + 2, &g->bytes));
+    HIP_TRY(dalloc(&g->b_sig, (size_t)n * kLanes, &g->bytes));
+    HIP_TRY(dalloc(&g->b_chat, (size_t)n * kLanes, &g->bytes));
+    HIP_TRY(dalloc(&g->b_shift, ((size_t)g->b_max_levels + 2) * kLanes, &g->bytes));
+    HIP_TRY(dalloc(&g->b_maxexp, (size_t)2 * kLanes, &g->bytes));
+    HIP_TRY(dalloc(&g->b_lane_src, (size_t)kLanes, &g->bytes));
+    g->batch_ready = true;
+    return BC_OK;
+}
+
+template <typename T>
+static bc_status grow(T **p, int64_t *cap, int64_t need, size_t *bytes) {
+    if (need <= *cap && *p) return BC_OK;
+    if (*p) {
+        HIP_TRY(hipFree(*p));
+        *bytes -= (size_t)(*cap) * sizeof(T);
+    }
+    int64_t c = std::max<int64_t>(need, 16);
+    HIP_TRY(dalloc(p, (size_t)c, bytes));
+    *cap = c;
+    return BC_OK;
+}
+
+// ------------------------------------------------------------------ driver
+struct RunCfg {
+    int engine;   // 1 = plain, 64 = batched
+    int lanes;    // batched: sources per batch (8 .. 64)
+    int mode;     // 0 / 1
+    int policy;   // POL_*
+    int grid;
+    int chunk;
+    bool use_graphs;
+};
+
+template <typename Args>
+static bc_status get_graph(bc_graph *g, const Args &args, void (*kern)(Args), const RunCfg &cfg,
+                           hipGraphExec_t *out) {
+    std::vector<unsigned char> key(sizeof(Args) + 3 * sizeof(int));
+    std::memcpy(key.data(), &args, sizeof(Args));
+    int extra[3] = {cfg.grid, cfg.chunk, cfg.engine * 2 + cfg.mode};
+    std::memcpy(key.data() + sizeof(Args), extra, sizeof(extra));
+    for (auto &cg : g->graphs)
+        if (cg.key == key) {
+            *out = cg.exec;
+            return BC_OK;
+        }
+    CachedGraph cg;
+    cg.key = key;
+    HIP_TRY(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
+    Args argcopy = args;
+    void *kargs[] = {(void *)&argcopy};
+    for (int i = 0; i < cfg.chunk; ++i)
+        (void)hipLaunchKernel((const void *)kern, dim3(cfg.grid), dim3(kBlock), kargs, 0, g->cap_stream);
+    // flag readback at the end of the chunk
+    (void)hipMemcpyAsync(g->flag_host, g->ctl, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, g->cap_stream);
+    hipError_t e = hipStreamEndCapture(g->cap_stream, &cg.graph);
+    if (e != hipSuccess) return fail(BC_ERR_DEVICE, std::string("graph capture failed: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&cg.exec, cg.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(cg.graph);
+        return fail(BC_ERR_DEVICE, std::string("graph instantiate failed: ") + hipGetErrorString(e));
+    }
+    if (g->graphs.size() >= 16) {
+        (void)hipGraphExecDestroy(g->graphs.front().exec);
+        (void)hipGraphDestroy(g->graphs.front().graph);
+        g->graphs.erase(g->graphs.begin());
+    }
+    g->graphs.push_back(cg);
+    *out = cg.exec;
+    return BC_OK;
+}
+
+// Launch chunks of step kernels until the device state machine reports done.
+template <typename Args>
+static bc_status drive(bc_graph *g, const Args &args, void (*kern)(Args), const RunCfg &cfg, hipStream_t st,
+                       int64_t max_steps, int64_t *launches) {
+    hipGraphExec_t exec = nullptr;
+    if (cfg.use_graphs) {
+        bc_status s = get_graph(g, args, kern, cfg, &exec);
+        if (s != BC_OK) return s;
+    }
+    const int kRing = 4;
+    hipEvent_t ev[kRing];
+    for (int i = 0; i < kRing; ++i) HIP_TRY(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+    int64_t issued = 0, chunks = 0;
+    bc_status result = BC_OK;
+    g->flag_host[0] = PH_IDLE;
+    g->flag_host[1] = 0;
+    const auto t0 = std::chrono::steady_clock::now();
+    double max_seconds = 900.0;
+    if (const char *s = std::getenv("BC_MAX_SECONDS")) max_seconds = std::atof(s);
+    for (;;) {
+        if (chunks >= kRing) {
+            hipError_t e = hipEventSynchronize(ev[chunks % kRing]);
+            if (e != hipSuccess) { result = fail(BC_ERR_DEVICE, std::string("step sync: ") + hipGetErrorString(e)); break; }
+            const int32_t ph = ((volatile int32_t *)g->flag_host)[0];
+            const int32_t er = ((volatile int32_t *)g->flag_host)[1];
+            if (er) break;  // reported by the caller from the control block
+            if (ph == PH_DONE) break;
+        }
+        if (issued >= max_steps) {
+            result = fail(BC_ERR_DEVICE, "level state machine did not finish within its step bound");
+            break;
+        }
+        if (std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > max_seconds) {
+            result = fail(BC_ERR_DEVICE, "run exceeded BC_MAX_SECONDS");
+            break;
+        }
+        if (exec) {
+            hipError_t e = hipGraphLaunch(exec, st);
+            if (e != hipSuccess) { result = fail(BC_ERR_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e)); break; }
+        } else {
+            Args argcopy = args;
+            void *kargs[] = {(void *)&argcopy};
+            for (int i = 0; i < cfg.chunk; ++i)
+                (void)hipLaunchKernel((const void *)kern, dim3(cfg.grid), dim3(kBlock), kargs, 0, st);
+            hipError_t e = hipMemcpyAsync(g->flag_host, g->ctl, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+            if (e != hipSuccess) { result = fail(BC_ERR_DEVICE, std::string("flag copy: ") + hipGetErrorString(e)); break; }
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) { result = fail(BC_ERR_DEVICE, std::string("step launch: ") + hipGetErrorString(e)); break; }
+        e = hipEventRecord(ev[chunks % kRing], st);
+        if (e != hipSuccess) { result = fail(BC_ERR_DEVICE, std::string("event record: ") + hipGetErrorString(e)); break; }
+        issued += cfg.chunk;
+        ++chunks;
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    for (int i = 0; i < kRing; ++i) (void)hipEventDestroy(ev[i]);
+    if (e != hipSuccess && result == BC_OK) result = fail(BC_ERR_DEVICE, std::string("stream sync: ") + hipGetErrorString(e));
+    *launches += issued;
+    return result;
+}
+
+static void init_ctl(Ctl *c) {
+    std::memset(c, 0, sizeof(*c));
+    c->dump_pos = -1;
+    c->dump_lane = -1;
+    c->maxexp = INT_MIN;
+    c->minexp = INT_MAX;
+}
+
+static PolicyArgs policy_args(const bc_graph *g, const bc_run_options &o) {
+    PolicyArgs p;
+    p.alpha = o.alpha > 0 ? o.alpha : 14.0f;
+    p.beta = o.beta > 0 ? o.beta : 24.0f;
+    p.wpv_degree = o.wpv_degree > 0 ? o.wpv_degree : 24.0f;
+    p.has_mlp = g->has_mlp ? 1 : 0;
+    p.mlp = g->mlp;
+    return p;
+}
+
+struct DumpBufs {
+    int32_t *d = nullptr;
+    unsigned long long *sig = nullptr;
+    double *delta = nullptr;
+    int32_t *shift = nullptr;
+};
+
+static void accumulate_stats(bc_stats *s, const Ctl &c) {
+    s->steps += (int64_t)c.st_steps;
+    s->forward_levels += (int64_t)c.st_fwd_levels;
+    for (int i = 0; i < 3; ++i) s->variant_levels[i] += (int64_t)c.st_var[i];
+    s->arcs_scanned += (int64_t)c.st_arcs;
+    s->lane_arcs += (int64_t)c.st_lane_arcs;
+    s->queue_entries += (int64_t)c.st_qentries;
+    s->max_levels = std::max<int64_t>(s->max_levels, (int64_t)c.st_max_levels);
+    s->n_batches += (int64_t)c.st_batches;
+}
+
+static bc_status ctl_error(const Ctl &c) {
+    if (c.err & ERR_SIGMA_RANGE)
+        return fail(BC_ERR_SIGMA_RANGE, "scaled FP64 path counts left the double range");
+    if (c.err & ERR_LEVEL_CAP) return fail(BC_ERR_NOT_SUPPORTED, "more BFS levels than the batched engine holds (65534)");
+    if (c.err) return fail(BC_ERR_DEVICE, "device capacity error (queue / overflow list)");
+    return BC_OK;
+}
+
+// One pass of one engine over a device source list.  Overflowed source
+// positions (mode 0) are returned in *ovf_positions.
+static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &o, const int32_t *h_srcs,
+                          int64_t ns, int64_t dump_pos, DumpBufs *dump, hipStream_t st,
+                          std::vector<int64_t> *ovf_positions, int *dump_done, Ctl *ctl_out) {
+    bc_status s;
+    s = grow(&g->srcs, &g->srcs_cap, ns, &g->bytes);
+    if (s != BC_OK) return s;
+    s = grow(&g->ovf, &g->ovf_cap, ns, &g->bytes);
+    if (s != BC_OK) return s;
+    if (ns) HIP_TRY(hipMemcpyAsync(g->srcs, h_srcs, sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
+    Ctl *hc = g->ctl_host;
+    init_ctl(hc);
+    hc->policy = cfg.policy;
+    hc->mode = cfg.mode;
+    hc->dump_pos = dump_pos;
+    const unsigned long long limit = o.sigma_limit > 0 ? (unsigned long long)o.sigma_limit : ~0ull;
+    GraphArgs ga;
+    ga.n = g->n;
+    ga.nnz_lo = (int32_t)g->nnz;
+    ga.row_ptr = g->row_ptr;
+    ga.col = g->col;
+    ga.nonisolated = g->nonisolated;
+    int64_t launches = 0;
+    if (cfg.engine == 1) {
+        s = ensure_plain(g, st);
+        if (s != BC_OK) return s;
+        hc->phase = PH_FIN;
+        hc->pos = -1;
+        hc->n_items = ns;
+        hc->total_queued = 0;
+        HIP_TRY(hipMemcpyAsync(g->ctl, hc, sizeof(Ctl), hipMemcpyHostToDevice, st));
+        PlainArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.g = ga;
+        a.p = policy_args(g, o);
+        a.ctl = g->ctl;
+        a.d = g->p_d;
+        a.sig = g->p_sig;
+        a.chat = g->p_chat;
+        a.bc = g->bc;
+        a.queue = g->p_queue;
+        a.level_off = g->p_level_off;
+        a.shift = g->p_shift;
+        a.srcs = g->srcs;
+        a.ovf_list = g->ovf;
+        a.ovf_cap = (uint32_t)std::min<int64_t>(g->ovf_cap, UINT32_MAX);
+        a.sigma_limit = limit;
+        if (dump) {
+            a.dump_d = dump->d;
+            a.dump_sig = dump->sig;
+            a.dump_delta = dump->delta;
+            a.dump_shift = dump->shift;
+        }
+        const double bound = (double)ns * (2.0 * (double)g->n + 6.0) + 64.0;
+        const int64_t max_steps = bound > 4e18 ? (int64_t)4e18 : (int64_t)bound;
+        s = drive(g, a, cfg.mode ? plain_step<1> : plain_step<0>, cfg, st, max_steps, &launches);
+        if (s != BC_OK) g->plain_dirty = true;
+    } else {
+        s = ensure_batched(g);
+        if (s != BC_OK) return s;
+        // batches of up to 64 sources that never cross a graph boundary
+        std::vector<int64_t> bs;
+        std::vector<int32_t> lo, hi;
+        int64_t i = 0;
+        while (i < ns) {
+            const int32_t v = h_srcs[i];
+            const int gi = (int)(std::upper_bound(g->voff.begin(), g->voff.end(), v) - g->voff.begin()) - 1;
+            const int32_t glo = g->voff[gi], ghi = g->voff[gi + 1];
+            int64_t j = i + 1;
+            while (j < ns && j - i < cfg.lanes && h_srcs[j] >= glo && h_srcs[j] < ghi) ++j;
+            bs.push_back(i);
+            lo.push_back(glo);
+            hi.push_back(ghi);
+            i = j;
+        }
+        bs.push_back(ns);
+        const int64_t nb = (int64_t)lo.size();
+        int64_t cap64 = g->bcap;
+        s = grow(&g->bstart, &cap64, nb + 1, &g->bytes);
+        if (s != BC_OK) return s;
+        int64_t c1 = g->bcap, c2 = g->bcap;
+        s = grow(&g->blo, &c1, nb + 1, &g->bytes);
+        if (s != BC_OK) return s;
+        s = grow(&g->bhi, &c2, nb + 1, &g->bytes);
+        if (s != BC_OK) return s;
+        g->bcap = std::min(cap64, std::min(c1, c2));
+        HIP_TRY(hipMemcpyAsync(g->bstart, bs.data(), sizeof(int64_t) * bs.size(), hipMemcpyHostToDevice, st));
+        if (nb) {
+            HIP_TRY(hipMemcpyAsync(g->blo, lo.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(g->bhi, hi.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
+        }
+        // fresh tags and visited words for this run
+        const int64_t n = g->n;
+        if (n > 0) {
+            fill_u64<<<grid_for(2 * n, 256, 4096), 256, 0, st>>>((unsigned long long *)g->b_vn, 2 * n, 0ull);
+            fill_u64<<<grid_for(2 * n, 256, 4096), 256, 0, st>>>((unsigned long long *)g->b_fw0, 2 * n, 0ull);
+            fill_u64<<<grid_for(2 * n, 256, 4096), 256, 0, st>>>((unsigned long long *)g->b_fw1, 2 * n, 0ull);
+        }
+        fill_i32<<<1, 128, 0, st>>>(g->b_maxexp, kLanes, INT_MIN);
+        fill_i32<<<1, 128, 0, st>>>(g->b_maxexp + kLanes, kLanes, INT_MAX);
+        HIP_TRY(hipGetLastError());
+        hc->phase = PH_BC;
+        hc->pos = -1;
+        hc->n_items = nb;
+        hc->range_lo = 0;
+        hc->range_hi = 0;
+        hc->epoch_b = 0;
+        hc->n_levels = 0;
+        HIP_TRY(hipMemcpyAsync(g->ctl, hc, sizeof(Ctl), hipMemcpyHostToDevice, st));
+        BatchArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.g = ga;
+        a.p = policy_args(g, o);
+        a.ctl = g->ctl;
+        a.vn = g->b_vn;
+        a.fw0 = g->b_fw0;
+        a.fw1 = g->b_fw1;
+        a.lq_vtx = g->b_lq_vtx;
+        a.lq_mask = g->b_lq_mask;
+        a.lq_cap = g->b_lq_cap;
+        a.level_off = g->b_level_off;
+        a.max_levels = g->b_max_levels;
+        a.sig = g->b_sig;
+        a.chat = g->b_chat;
+        a.shift = g->b_shift;
+        a.maxexp = g->b_maxexp;
+        a.bc = g->bc;
+        a.srcs = g->srcs;
+        a.batch_start = g->bstart;
+        a.batch_lo = g->blo;
+        a.batch_hi = g->bhi;
+        a.lane_src = g->b_lane_src;
+        a.ovf_list = g->ovf;
+        a.ovf_cap = (uint32_t)std::min<int64_t>(g->ovf_cap, UINT32_MAX);
+        a.sigma_limit = limit;
+        if (dump) {
+            a.dump_d = dump->d;
+            a.dump_sig = dump->sig;
+            a.dump_delta = dump->delta;
+            a.dump_shift = dump->shift;
+        }
+        const int64_t maxl = std::min<int64_t>(g->n, g->b_max_levels) + 2;
+        const int64_t max_steps = (nb + 1) * (3 * maxl + 8) + 64;
+        s = drive(g, a, cfg.mode ? batch_step<1> : batch_step<0>, cfg, st, max_steps, &launches);
+    }
+    g->stats.launches += launches;
+    if (s != BC_OK) return s;
+    HIP_TRY(hipMemcpyAsync(hc, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *ctl_out = *hc;
+    accumulate_stats(&g->stats, *hc);
+    if (hc->err) {
+        g->plain_dirty = true;
+        return ctl_error(*hc);
+    }
+    if (hc->phase != PH_DONE) return fail(BC_ERR_DEVICE, "run ended before the state machine finished");
+    if (dump_done) *dump_done = hc->dump_state == 2;
+    if (ovf_positions && hc->n_ovf) {
+        std::vector<int64_t> tmp(hc->n_ovf);
+        HIP_TRY(hipMemcpy(tmp.data(), g->ovf, sizeof(int64_t) * hc->n_ovf, hipMemcpyDeviceToHost));
+        std::sort(tmp.begin(), tmp.end());
+        *ovf_positions = tmp;
+    }
+    return BC_OK;
+}
+
+static bc_status resolve_cfg(const bc_graph *g, const bc_run_options &o, int64_t ns, RunCfg *cfg) {
+    if (o.batch != 0 && o.batch != 1 && o.batch != 8 && o.batch != 16 && o.batch != 32 && o.batch != 64)
+        return fail(BC_ERR_INVALID_ARG, "batch must be 0, 1, 8, 16, 32 or 64");
+    cfg->engine = o.batch == 1 ? 1 : 64;
+    if (o.batch == 0) cfg->engine = ns >= 2 ? 64 : 1;
+    cfg->lanes = (o.batch >= 8) ? o.batch : 64;
+    switch (o.policy) {
+    case BC_POLICY_AUTO: cfg->policy = g->has_mlp ? POL_MLP : POL_HEUR; break;
+    case BC_POLICY_HEURISTIC: cfg->policy = POL_HEUR; break;
+    case BC_POLICY_MLP:
+        if (!g->has_mlp) return fail(BC_ERR_INVALID_ARG, "BC_POLICY_MLP without loaded weights");
+        cfg->policy = POL_MLP;
+        break;
+    case BC_POLICY_FORCE_PUSH_TPV: cfg->policy = POL_FORCE_TPV; break;
+    case BC_POLICY_FORCE_PUSH_WPV: cfg->policy = POL_FORCE_WPV; break;
+    case BC_POLICY_FORCE_PULL: cfg->policy = POL_FORCE_PULL; break;
+    default: return fail(BC_ERR_INVALID_ARG, "unknown policy");
+    }
+    if (o.grid_blocks < 0 || o.grid_blocks > 65536) return fail(BC_ERR_INVALID_ARG, "grid_blocks out of range");
+    if (o.chunk_steps < 0 || o.chunk_steps > 4096) return fail(BC_ERR_INVALID_ARG, "chunk_steps out of range");
+    cfg->grid = o.grid_blocks ? o.grid_blocks : 1024;
+    cfg->chunk = o.chunk_steps ? o.chunk_steps : 16;
+    cfg->use_graphs = !(o.flags & BC_RUN_NO_GRAPHS);
+    cfg->mode = 0;
+    return BC_OK;
+}
+
+static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources, const bc_run_options *opt,
+                          void *stream, int64_t dump_index, bc_detail *detail) {
+    if (!g) return fail(BC_ERR_INVALID_ARG, "NULL handle");
+    bc_run_options o;
+    bc_run_options_init(&o);
+    if (opt) o = *opt;
+    std::vector<int32_t> all;
+    const int32_t *src = sources;
+    int64_t ns = n_sources;
+    if (!sources) {
+        all.resize(g->n);
+        for (int32_t i = 0; i < g->n; ++i) all[i] = i;
+        src = all.data();
+        ns = g->n;
+    } else if (n_sources < 0) {
+        return fail(BC_ERR_INVALID_ARG, "n_sources < 0");
+    }
+    for (int64_t i = 0; i < ns; ++i)
+        if (src[i] < 0 || src[i] >= g->n) return fail(BC_ERR_INVALID_ARG, "source id outside [0, n)");
+    if (detail && (dump_index < 0 || dump_index >= ns)) return fail(BC_ERR_INVALID_ARG, "dump_index out of range");
+    RunCfg cfg;
+    bc_status s = resolve_cfg(g, o, ns, &cfg);
+    if (s != BC_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    std::memset(&g->stats, 0, sizeof(g->stats));
+    g->stats.n_sources = ns;
+    g->stats.batch = cfg.engine;
+    g->stats.policy = cfg.policy;
+    g->stats.grid_blocks = cfg.grid;
+    g->stats.chunk_steps = cfg.use_graphs ? cfg.chunk : 0;
+    if (!(o.flags & BC_RUN_ACCUMULATE) && g->n > 0) {
+        fill_u64<<<grid_for(g->n, 256, 4096), 256, 0, st>>>((unsigned long long *)g->bc, g->n, 0ull);
+        HIP_TRY(hipGetLastError());
+    }
+    DumpBufs db;
+    if (detail) {
+        const size_t n = (size_t)std::max<int32_t>(g->n, 1);
+        HIP_TRY(hipMalloc((void **)&db.d, n * sizeof(int32_t)));
+        HIP_TRY(hipMalloc((void **)&db.sig, n * sizeof(unsigned long long)));
+        HIP_TRY(hipMalloc((void **)&db.delta, n * sizeof(double)));
+        HIP_TRY(hipMalloc((void **)&db.shift, ((size_t)g->n + 2) * sizeof(int32_t)));
+        fill_i32<<<grid_for(n, 256, 4096), 256, 0, st>>>(db.d, n, -1);
+        fill_u64<<<grid_for(n, 256, 4096), 256, 0, st>>>(db.sig, n, 0ull);
+        fill_u64<<<grid_for(n, 256, 4096), 256, 0, st>>>((unsigned long long *)db.delta, n, 0ull);
+        fill_i32<<<grid_for(n + 2, 256, 4096), 256, 0, st>>>(db.shift, n + 2, 0);
+        HIP_TRY(hipGetLastError());
+    }
+    auto free_dump = [&]() {
+        if (db.d) (void)hipFree(db.d);
+        if (db.sig) (void)hipFree(db.sig);
+        if (db.delta) (void)hipFree(db.delta);
+        if (db.shift) (void)hipFree(db.shift);
+    };
+    std::vector<int64_t> ovf;
+    int dump_done = 0;
+    int dump_mode = 0;
+    Ctl last{};
+    const bool force_f64 = (o.flags & BC_RUN_FORCE_F64) != 0;
+    RunCfg c0 = cfg;
+    c0.mode = force_f64 ? 1 : 0;
+    s = run_pass(g, c0, o, src, ns, detail ? dump_index : -1, detail ? &db : nullptr, st, &ovf, &dump_done, &last);
+    if (s != BC_OK) { free_dump(); return s; }
+    if (force_f64) {
+        g->stats.f64_sources = ns;
+        dump_mode = 1;
+    }
+    if (!ovf.empty()) {
+        // second pass: the overflowed sources, in list order, with FP64 path counts
+        std::vector<int32_t> redo(ovf.size());
+        int64_t redo_dump = -1;
+        for (size_t i = 0; i < ovf.size(); ++i) {
+            redo[i] = src[ovf[i]];
+            if (detail && ovf[i] == dump_index) redo_dump = (int64_t)i;
+        }
+        RunCfg c1 = cfg;
+        c1.mode = 1;
+        int dd = 0;
+        s = run_pass(g, c1, o, redo.data(), (int64_t)redo.size(), redo_dump, detail ? &db : nullptr, st, nullptr,
+                     &dd, &last);
+        if (s != BC_OK) { free_dump(); return s; }
+        g->stats.f64_sources = (int64_t)redo.size();
+        if (redo_dump >= 0) {
+            dump_done = dd;
+            dump_mode = 1;
+        }
+    }
+    if (detail) {
+        if (!dump_done) { free_dump(); return fail(BC_ERR_DEVICE, "detail dump did not complete"); }
+        const size_t n = (size_t)g->n;
+        std::vector<int32_t> hd(n), hsh(n + 2);
+        std::vector<unsigned long long> hs(n);
+        std::vector<double> hdel(n);
+        HIP_TRY(hipMemcpy(hd.data(), db.d, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(hs.data(), db.sig, n * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(hdel.data(), db.delta, n * sizeof(double), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(hsh.data(), db.shift, (n + 2) * sizeof(int32_t), hipMemcpyDeviceToHost));
+        free_dump();
+        // sigma(v) = raw * 2^(shift_0 + ... + shift_{d-1}) in mode 1
+        std::vector<int64_t> E(n + 2, 0);
+        int32_t L = 0;
+        for (size_t v = 0; v < n; ++v) L = std::max(L, hd[v] + 1);
+        for (int32_t l = 1; l <= L && l < (int32_t)(n + 2); ++l) E[l] = E[l - 1] + hsh[l - 1];
+        for (size_t v = 0; v < n; ++v) {
+            if (detail->d) detail->d[v] = hd[v];
+            const bool reached = hd[v] >= 0;
+            if (dump_mode == 0) {
+                if (detail->sigma_u64) detail->sigma_u64[v] = hs[v];
+                if (detail->sigma_mant) detail->sigma_mant[v] = (double)hs[v];
+                if (detail->sigma_exp) detail->sigma_exp[v] = 0;
+            } else {
+                double raw;
+                std::memcpy(&raw, &hs[v], sizeof(raw));
+                if (detail->sigma_u64) detail->sigma_u64[v] = 0;
+                if (detail->sigma_mant) detail->sigma_mant[v] = reached ? raw : 0.0;
+                if (detail->sigma_exp) detail->sigma_exp[v] = reached ? (int32_t)E[hd[v]] : 0;
+            }
+            if (detail->delta) detail->delta[v] = hdel[v];
+        }
+        detail->mode = dump_mode;
+        detail->n_levels = L;
+    }
+    g->stats.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    // algorithmic bytes: every scanned arc reads its column index and a 4-8
+    // byte word of the neighbour (8 B + 8 B), every DAG (arc, source) pair
+    // moves one 8-byte path count or c value, every level-queue entry costs
+    // its row offsets, queue slots and per-vertex words (32 B).
+    g->stats.algo_bytes = 16.0 * g->stats.arcs_scanned + 8.0 * g->stats.lane_arcs + 32.0 * g->stats.queue_entries;
+    return BC_OK;
+}
+
+extern "C" bc_status bc_run(bc_graph *g, const int32_t *sources, int64_t n_sources, const bc_run_options *opt,
+                            void *stream) {
+    return run_impl(g, sources, n_sources, opt, stream, -1, nullptr);
+}
+
+extern "C" bc_status bc_run_detail(bc_graph *g, const int32_t *sources, int64_t n_sources,
+                                   const bc_run_options *opt, int64_t dump_index, bc_detail *out, void *stream) {
+    if (!out) return fail(BC_ERR_INVALID_ARG, "out is NULL");
+    return run_impl(g, sources, n_sources, opt, stream, dump_index, out);
+}
+
+extern "C" bc_status bc_scores(const bc_graph *g, double *out, int64_t len, uint32_t flags, void *stream) {
+    if (!g || !out) return fail(BC_ERR_INVALID_ARG, "NULL argument");
+    if (len < g->n) return fail(BC_ERR_INVALID_ARG, "len < n");
+    if (g->n == 0) return BC_OK;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(out, g->bc, sizeof(double) * g->n,
+                           (flags & BC_OUT_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return BC_OK;
+}
+
+extern "C" bc_status bc_run_stats(const bc_graph *g, bc_stats *out) {
+    if (!g || !out) return fail(BC_ERR_INVALID_ARG, "NULL argument");
+    *out = g->stats;
+    return BC_OK;
+}
+
+extern "C" bc_status bc_load_policy(bc_graph *g, const float *weights, int64_t len) {
+    if (!g) return fail(BC_ERR_INVALID_ARG, "NULL handle");
+    if (!weights) {
+        g->has_mlp = false;  // unload
+        return BC_OK;
+    }
+    if (len != kMlpParams) return fail(BC_ERR_INVALID_ARG, "weights length must be BC_MLP_PARAMS");
+    for (int64_t i = 0; i < len; ++i)
+        if (!std::isfinite(weights[i])) return fail(BC_ERR_INVALID_ARG, "non-finite policy weight");
+    HIP_TRY(hipMemcpy(g->mlp, weights, sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
+    g->has_mlp = true;
+    free_graphs(g);  // captured args carry has_mlp
+    return BC_OK;
+}

@@ -1,0 +1,166 @@
+// bc_dev.h -- device-side structures shared by the libbc kernels and the host
+// driver.  Internal to libbc (not part of the public C ABI in include/bc.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bcx {
+
+constexpr int kBlock = 256;  // threads per workgroup of every step kernel
+constexpr int kWave = 64;    // CDNA wavefront width
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kLanes = 64;   // sources per batch = wavefront lanes
+constexpr int kLightDeg = 64;  // per-vertex reductions: thread (<=) vs wavefront (>)
+
+// Phases of the device-resident state machine.  One launch of a step kernel
+// performs the work of the current phase; the last workgroup to finish moves
+// the machine to the next phase.
+enum : int32_t {
+    PH_IDLE = 0,
+    PH_FWD = 1,      // discover level l+1 from the frontier at level l
+    PH_SIG = 2,      // path counts of level l+1 (pull, fixed summation order)
+    PH_BWD = 3,      // dependencies of level l (pull from level l+1)
+    PH_FIN = 4,      // plain: reset the visited set, start the next source
+    PH_BC = 5,       // batched: add dependencies to BC in source order, reset
+    PH_DUMP_FWD = 6, // copy one source's d / sigma out (detail runs only)
+    PH_DUMP_BWD = 7, // copy one source's delta out (detail runs only)
+    PH_DONE = 8,
+};
+
+enum : int32_t { V_PUSH_TPV = 0, V_PUSH_WPV = 1, V_PULL = 2 };
+enum : int32_t { POL_HEUR = 1, POL_MLP = 2, POL_FORCE_TPV = 3, POL_FORCE_WPV = 4, POL_FORCE_PULL = 5 };
+
+constexpr int kMlpIn = 5, kMlpH = 32, kMlpOut = 3;
+constexpr int kMlpParams = kMlpH * kMlpIn + kMlpH + kMlpH * kMlpH + kMlpH + kMlpOut * kMlpH + kMlpOut;
+
+// Control block in device memory.  Written by the host before a run, then
+// only by the last workgroup of each step launch.
+struct Ctl {
+    // --- polled by the host after every chunk of launches (keep first)
+    int32_t phase;
+    int32_t err;          // sticky device error bits (capacity, range)
+    // --- progress
+    int64_t pos;          // plain: index of the current source; batched: current batch
+    int64_t n_items;      // plain: number of sources; batched: number of batches
+    int32_t level;        // current level l
+    int32_t n_levels;     // levels of the finished forward (L)
+    int32_t variant;      // discover variant of the current level
+    int32_t prev_variant;
+    int32_t policy;
+    int32_t mode;         // 0 = uint64 path counts, 1 = scaled FP64
+    int32_t lanes;        // batched: sources in the current batch
+    uint32_t epoch;       // batched: tag base of the current forward
+    uint32_t epoch_b;     // batched: tag base of the current backward
+    int32_t range_lo;     // batched: vertex range of the current batch's graph
+    int32_t range_hi;
+    unsigned long long lane_mask;   // valid lanes of the batch
+    unsigned long long active;      // lanes with a non-empty frontier at level l
+    unsigned long long dead;        // lanes that overflowed in uint64 mode
+    // --- level under construction (atomics)
+    uint32_t blocks_done;
+    uint32_t next_count;
+    unsigned long long next_edges;
+    unsigned long long next_active;
+    unsigned long long ovf_lanes;
+    int32_t overflow;     // plain: the current source overflowed
+    int32_t maxexp;       // plain FP64: max binary exponent of the level built
+    int32_t minexp;
+    uint32_t total_queued;
+    uint32_t n_ovf;       // overflowed sources recorded
+    // --- features of the frontier at level l
+    unsigned long long f_nf, f_mf, visited_n, visited_m, full_n, full_m;
+    unsigned long long range_nodeg, range_arcs;  // non-isolated vertices / arcs of the range
+    // --- detail dump
+    int64_t dump_pos;     // source position to dump (-1 = none)
+    int32_t dump_lane;    // batched: lane of the dumped source in its batch
+    int32_t dump_state;   // 0 = pending, 1 = forward dumped, 2 = done
+    // --- statistics
+    unsigned long long st_steps, st_fwd_levels, st_var[3], st_arcs, st_lane_arcs, st_qentries,
+        st_max_levels, st_batches;
+};
+
+enum : int32_t { ERR_QUEUE_CAP = 1, ERR_SIGMA_RANGE = 2, ERR_LEVEL_CAP = 4, ERR_OVF_CAP = 8 };
+
+// Read-only graph description passed to every kernel.
+struct GraphArgs {
+    int32_t n;
+    int32_t nnz_lo;         // nnz fits int32 by construction
+    const int32_t *row_ptr; // int32[n+1]
+    const int32_t *col;     // int32[nnz]
+    int64_t nonisolated;    // vertices with degree >= 1
+};
+
+struct PolicyArgs {
+    float alpha, beta, wpv_degree;
+    int32_t has_mlp;
+    const float *mlp;       // kMlpParams floats (device), or nullptr
+};
+
+// Plain engine (one source at a time, whole GPU per level).
+struct PlainArgs {
+    GraphArgs g;
+    PolicyArgs p;
+    Ctl *ctl;
+    int32_t *d;              // int32[n], -1 = unvisited (kept -1 between sources)
+    unsigned long long *sig; // uint64[n] or FP64 bits (mode 1); kept 0 between sources
+    double *chat;            // FP64[n] scaled (1 + delta) / sigma
+    double *bc;              // FP64[n]
+    int32_t *queue;          // int32[n]: all levels of the current source
+    int32_t *level_off;      // int32[n + 2]
+    int32_t *shift;          // int32[n + 2]: per-level exponent shift (mode 1)
+    const int32_t *srcs;     // sources of this run
+    int64_t *ovf_list;       // positions of sources that overflowed uint64
+    uint32_t ovf_cap;
+    unsigned long long sigma_limit;
+    // detail dump (host-pinned or device buffers of length n)
+    int32_t *dump_d;
+    unsigned long long *dump_sig;
+    double *dump_delta;
+    int32_t *dump_shift;     // per-level shifts of the dumped source
+};
+
+// Tagged frontier word: lanes of vertex v that sit on level (tag - epoch).
+struct __attribute__((aligned(16))) Tagged {
+    unsigned long long mask;
+    uint32_t tag;
+    uint32_t pad;
+};
+// Visited / next lane words of a vertex, one 16-byte load.
+struct __attribute__((aligned(16))) VisNext {
+    unsigned long long vis;
+    unsigned long long nxt;
+};
+
+// Batched engine (64 sources per traversal, one wavefront lane per source).
+struct BatchArgs {
+    GraphArgs g;
+    PolicyArgs p;
+    Ctl *ctl;
+    VisNext *vn;                 // [n]
+    Tagged *fw0, *fw1;           // [n] each; level parity selects the buffer
+    int32_t *lq_vtx;             // level queues: vertex
+    unsigned long long *lq_mask; // level queues: lane mask
+    uint32_t lq_cap;
+    int32_t *level_off;          // [max_levels + 2]
+    int32_t max_levels;
+    unsigned long long *sig;     // [n][64] uint64 / FP64 bits; delta after the backward
+    double *chat;                // [n][64]
+    int32_t *shift;              // [max_levels + 2][64] (mode 1)
+    int32_t *maxexp;             // [64] (mode 1)
+    double *bc;                  // [n]
+    const int32_t *srcs;         // source list of this run
+    const int64_t *batch_start;  // [n_batches + 1] positions into srcs
+    const int32_t *batch_lo;     // [n_batches] vertex range of each batch's graph
+    const int32_t *batch_hi;
+    int32_t *lane_src;           // [64] sources of the current batch
+    int64_t *ovf_list;
+    uint32_t ovf_cap;
+    unsigned long long sigma_limit;
+    int32_t *dump_d;
+    unsigned long long *dump_sig;
+    double *dump_delta;
+    int32_t *dump_shift;         // [max_levels + 2]
+};
+
+}  // namespace bcx

@@ -1,0 +1,262 @@
+"""GPU parity: libbc (through its C ABI) against the CPU oracle.
+
+d and uint64 sigma must match bit for bit; BC, delta and FP64 sigma within
+1e-10 relative per vertex (exact zeros must stay zero).  Both engines (plain
+K=1 and batched K<=64), every level variant, graph capture on/off and several
+batch widths must give bitwise-identical BC within one engine.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_bc_close, check_detail, run_bc, say
+from paper_2008_05718_amd import binding as b
+from paper_2008_05718_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+ENGINES = [1, 64]
+
+
+def _g(n, edges):
+    e = np.array(edges, dtype=np.int64).reshape(-1, 2)
+    return W.csr_from_edges(n, e[:, 0], e[:, 1])
+
+
+CLOSED = {
+    "path50": (_g(50, [(i, i + 1) for i in range(49)]), lambda n: np.array([i * (n - 1 - i) for i in range(n)], float)),
+    "star40": (_g(40, [(0, i) for i in range(1, 40)]), lambda n: np.array([(n - 1) * (n - 2) / 2] + [0] * (n - 1), float)),
+    "cycle21": (_g(21, [(i, (i + 1) % 21) for i in range(21)]), lambda n: np.full(n, (n - 1) * (n - 3) / 8)),
+    "cycle30": (_g(30, [(i, (i + 1) % 30) for i in range(30)]), lambda n: np.full(n, (n - 2) ** 2 / 8)),
+    "complete17": (_g(17, list(itertools.combinations(range(17), 2))), lambda n: np.zeros(n)),
+    "hypercube6": (_g(64, [(v, v ^ (1 << i)) for v in range(64) for i in range(6) if v < v ^ (1 << i)]),
+                   lambda n: np.full(n, (6 * 2 ** 5 - 2 ** 6 + 1) / 2)),
+    "k35": (_g(8, [(i, 3 + j) for i in range(3) for j in range(5)]),
+            lambda n: np.array([math.comb(5, 2) / 3] * 3 + [math.comb(3, 2) / 5] * 5)),
+}
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("name", sorted(CLOSED))
+def test_closed_forms(name, engine):
+    g, f = CLOSED[name]
+    say(f"[closed] {name} engine={engine}")
+    bc, st = run_bc(g, None, batch=engine)
+    want = f(g.n)
+    assert_bc_close(bc / 2.0, want, 1e-12)
+    ref, _ = oracle.bc(g)
+    assert_bc_close(bc, ref)
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_er2000_all_sources(engine):
+    g, srcs = W.workload("er2000")
+    say(f"[er2000] engine={engine}")
+    ref, modes = oracle.bc(g, srcs)
+    bc, st = run_bc(g, srcs, batch=engine)
+    say("  stats", st)
+    assert_bc_close(bc, ref)
+    with b.Graph(g) as G:
+        for idx in (0, 77, 1999):
+            det = G.detail(srcs, dump_index=idx, batch=engine)
+            check_detail(g, det, srcs[idx])
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_policies_and_capture_bit_identical(engine):
+    g = W.rmat(12, 16, seed=21)
+    srcs = W.choose_sources(g, 200, seed=5)
+    say(f"[policies] rmat12 engine={engine}")
+    ref, _ = oracle.bc(g, srcs)
+    outs = {}
+    with b.Graph(g) as G:
+        for pol in (b.BC_POLICY_HEURISTIC, b.BC_POLICY_FORCE_PUSH_TPV, b.BC_POLICY_FORCE_PUSH_WPV,
+                    b.BC_POLICY_FORCE_PULL):
+            for flags in (0, b.BC_RUN_NO_GRAPHS):
+                G.run(srcs, batch=engine, policy=pol, flags=flags)
+                outs[(pol, flags)] = G.scores().copy()
+                st = G.stats()
+                if pol == b.BC_POLICY_FORCE_PULL:
+                    assert st["variant_levels"][0] == st["variant_levels"][1] == 0
+    base = outs[(b.BC_POLICY_HEURISTIC, 0)]
+    assert_bc_close(base, ref)
+    for k, v in outs.items():
+        assert np.array_equal(v.view(np.uint64), base.view(np.uint64)), f"bits differ for {k}"
+
+
+def test_batch_widths_bit_identical():
+    g = W.rmat(12, 16, seed=22)
+    srcs = W.choose_sources(g, 150, seed=6)
+    say("[widths] rmat12")
+    outs = []
+    with b.Graph(g) as G:
+        for K in (8, 16, 32, 64):
+            G.run(srcs, batch=K)
+            outs.append(G.scores().copy())
+            assert G.stats()["n_batches"] == -(-150 // K)
+    for o in outs[1:]:
+        assert np.array_equal(o.view(np.uint64), outs[0].view(np.uint64))
+    ref, _ = oracle.bc(g, srcs)
+    assert_bc_close(outs[0], ref)
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_rmat_details(engine):
+    g = W.rmat(13, 16, seed=23)
+    srcs = W.choose_sources(g, 130, seed=7)
+    say(f"[rmat13 detail] engine={engine}")
+    with b.Graph(g) as G:
+        for idx in (0, 63, 64, 129):
+            det = G.detail(srcs, dump_index=idx, batch=engine)
+            check_detail(g, det, srcs[idx])
+        ref, _ = oracle.bc(g, srcs)
+        assert_bc_close(G.scores(), ref)
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_grid_uint64_overflow_fallback(engine):
+    L = 40
+    g = W.grid(L)
+    # corner sources overflow uint64 (C(78, 39) > 2^64); central ones do not
+    srcs = np.array([0, L - 1, L * L - 1, 20 * L + 20, 5 * L + 7, 0], dtype=np.int32)
+    say(f"[grid40 overflow] engine={engine}")
+    ref, modes = oracle.bc(g, srcs)
+    assert modes.tolist() == [1, 1, 1, 0, 0, 1]
+    with b.Graph(g) as G:
+        G.run(srcs, batch=engine)
+        assert G.stats()["f64_sources"] == 4
+        assert_bc_close(G.scores(), ref)
+        for idx in range(len(srcs)):
+            det = G.detail(srcs, dump_index=idx, batch=engine)
+            check_detail(g, det, srcs[idx])
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_sigma_limit_and_forced_f64(engine):
+    g, _ = W.workload("er2000")
+    srcs = np.arange(0, 2000, 13, dtype=np.int32)
+    ref, _ = oracle.bc(g, srcs)
+    say(f"[sigma limit / force f64] engine={engine}")
+    with b.Graph(g) as G:
+        G.run(srcs, batch=engine, sigma_limit=3)
+        st = G.stats()
+        assert 0 < st["f64_sources"] <= len(srcs)
+        assert_bc_close(G.scores(), ref)
+        G.run(srcs, batch=engine, flags=b.BC_RUN_FORCE_F64)
+        assert G.stats()["f64_sources"] == len(srcs)
+        assert_bc_close(G.scores(), ref)
+        det = G.detail(srcs, dump_index=5, batch=engine, flags=b.BC_RUN_FORCE_F64)
+        assert det["mode"] == 1
+        o = oracle.source(g, int(srcs[5]))
+        np.testing.assert_array_equal(det["d"], o.d)
+        r = o.d >= 0
+        got = np.ldexp(det["sigma_mant"][r], det["sigma_exp"][r])
+        np.testing.assert_array_equal(got, o.sigma_u64[r].astype(np.float64))
+
+
+def test_multi_graph_union_equals_per_graph():
+    gs = [W.barabasi_albert(n, 4, seed=30 + i) for i, n in enumerate([60, 300, 150, 1000, 90])]
+    gs.append(W.grid(12, 0.1, 0.0, seed=1))
+    u = W.union(gs)
+    say("[multi] union of", [x.n for x in gs])
+    with b.Graph(u) as G:
+        for K in (16, 64):
+            G.run(None, batch=K)
+            got = G.scores()
+            for i, gg in enumerate(gs):
+                lo, hi = u.vtx_offsets[i], u.vtx_offsets[i + 1]
+                ref, _ = oracle.bc(gg)
+                assert_bc_close(got[lo:hi], ref)
+        G.run(None, batch=1)
+        ref_u, _ = oracle.bc(u)
+        assert_bc_close(G.scores(), ref_u)
+
+
+def test_invalid_inputs_and_handle_survives():
+    good = W.grid(4)
+    bad_cases = {
+        "self_loop": W.CSR(np.array([0, 2, 3], np.int32), np.array([0, 1, 0], np.int32)),
+        "asym": W.CSR(np.array([0, 1, 1], np.int32), np.array([1], np.int32)),
+        "unsorted": W.CSR(np.array([0, 2, 3, 4], np.int32), np.array([2, 1, 0, 0], np.int32)),
+        "dup": W.CSR(np.array([0, 2, 4], np.int32), np.array([1, 1, 0, 0], np.int32)),
+        "range": W.CSR(np.array([0, 1, 2], np.int32), np.array([1, 5], np.int32)),
+        "nonmono": W.CSR(np.array([0, 2, 1, 2], np.int32), np.array([1, 0], np.int32)),
+    }
+    for name, g in bad_cases.items():
+        say(f"[invalid] {name}")
+        with pytest.raises(b.BCError) as ei:
+            b.Graph(g)
+        assert ei.value.status == 2, name
+    with pytest.raises(b.BCError) as ei:
+        b.Graph(W.union([W.grid(3), W.grid(3)]), vtx_offsets=[0, 4, 18])
+    assert ei.value.status == 2
+    with b.Graph(good) as G:
+        for bad in ([-1], [16], [3, 99]):
+            with pytest.raises(b.BCError) as ei:
+                G.run(bad)
+            assert ei.value.status == 1
+        with pytest.raises(b.BCError):
+            G.run([0], batch=3)
+        with pytest.raises(b.BCError):
+            G.run([0], policy=b.BC_POLICY_MLP)  # no weights loaded
+        G.run(None)
+        ref, _ = oracle.bc(good)
+        assert_bc_close(G.scores(), ref)
+
+
+def test_degenerate_inputs():
+    say("[degenerate]")
+    one = W.CSR(np.array([0, 0], np.int32), np.zeros(0, np.int32))
+    with b.Graph(one) as G:
+        for K in (1, 64):
+            G.run([0, 0], batch=K)
+            assert G.scores().tolist() == [0.0]
+    iso = _g(7, [(0, 1), (1, 2), (4, 5)])  # 3 and 6 isolated
+    ref, _ = oracle.bc(iso)
+    for K in (1, 8, 64):
+        bc, _ = run_bc(iso, None, batch=K)
+        assert_bc_close(bc, ref)
+    with b.Graph(iso) as G:
+        G.run([], batch=64)
+        assert (G.scores() == 0).all()
+        G.run([3, 3, 6], batch=64)
+        assert (G.scores() == 0).all()
+
+
+def test_accumulate_and_duplicates():
+    g = W.rmat(11, 8, seed=24)
+    s1 = W.choose_sources(g, 70, seed=1)
+    s2 = W.choose_sources(g, 40, seed=2)
+    say("[accumulate]")
+    with b.Graph(g) as G:
+        for K in (1, 64):
+            G.run(s1, batch=K)
+            G.run(s2, batch=K, flags=b.BC_RUN_ACCUMULATE)
+            ref, _ = oracle.bc(g, np.concatenate([s1, s2]))
+            assert_bc_close(G.scores(), ref)
+            dup = np.concatenate([s1[:5], s1[:5]])
+            G.run(dup, batch=K)
+            r1, _ = oracle.bc(g, s1[:5])
+            assert_bc_close(G.scores(), 2 * r1)
+
+
+def test_torch_device_interop():
+    import torch
+    g = W.rmat(11, 8, seed=25)
+    srcs = W.choose_sources(g, 100, seed=3)
+    say("[torch interop]")
+    stream = torch.cuda.Stream()
+    rp = torch.from_numpy(g.row_ptr.astype(np.int32)).cuda()
+    ci = torch.from_numpy(g.col_idx.astype(np.int32)).cuda()
+    ref, _ = oracle.bc(g, srcs)
+    with torch.cuda.stream(stream):
+        with b.Graph(row_ptr=rp, col_idx=ci) as G:
+            G.run(srcs, stream=stream, batch=64)
+            out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+            G.scores(out, stream=stream)
+    stream.synchronize()
+    assert_bc_close(out.cpu().numpy(), ref)
