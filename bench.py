@@ -43,7 +43,21 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2008_05718_amd", "policy_weights.npy"))
+    ap.add_argument("--sources", type=int, default=0, help="use only the first N sources (profiling runs)")
+    ap.add_argument("--no-graphs", action="store_true", help="launch level steps one by one")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB mebibytes 3 times (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        bb = torch.empty_like(a)
+        for _ in range(3):
+            bb.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 4, "copies": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part "
                                    "of this build (sources would shard across GPUs with one BC reduction)"}))
@@ -61,6 +75,8 @@ def main():
 
     t0 = time.time()
     g, srcs = W.workload(args.workload)
+    if args.sources > 0:
+        srcs = srcs[:args.sources]
     log(f"[bench] generated {args.workload}: n={g.n} m={g.m} sources={len(srcs)} in {time.time() - t0:.1f}s")
 
     pol = {"auto": b.BC_POLICY_AUTO, "heuristic": b.BC_POLICY_HEURISTIC, "mlp": b.BC_POLICY_MLP,
@@ -91,7 +107,8 @@ def main():
         return wall, gpu_ms, stats
 
     # ---- batched (headline)
-    wall, gpu_ms, stats = timed(srcs, args.steps, args.warmup, batch=64, policy=pol)
+    gflags = b.BC_RUN_NO_GRAPHS if args.no_graphs else 0
+    wall, gpu_ms, stats = timed(srcs, args.steps, args.warmup, batch=64, policy=pol, flags=gflags)
     st = stats[-1]
     ms_step = wall * 1e3 / args.steps
     gteps = g.m * len(srcs) * args.steps / wall / 1e9
@@ -104,15 +121,18 @@ def main():
     log(f"[bench] batched: {ms_step:.1f} ms/step, {gteps:.2f} GTEPS, launches/step={launches // args.steps}, "
         f"avg launch {avg_launch_us:.2f} us, algo {achieved_gbs:.1f} GB/s, policy={st['policy']} "
         f"variants={st['variant_levels']} f64={st['f64_sources']}")
+    log("[bench] batched phase ms (fwd, sig, bwd, fin, bc):",
+        [round(x, 1) for x in st["phase_ms"][1:6]], "variant ms:", [round(x, 1) for x in st["variant_ms"]])
 
     # ---- plain per-source engine on the same workload
     plain = None
     if not args.no_plain:
         ps = srcs if args.plain_sources <= 0 else srcs[:args.plain_sources]
-        pw, pg, pst = timed(ps, 1, 1, batch=1, policy=pol)
+        pw, pg, pst = timed(ps, 1, 1, batch=1, policy=pol, flags=gflags)
         plain = {"value": round(g.m * len(ps) / pw / 1e9, 4), "unit": "GTEPS", "ms_per_step": round(pw * 1e3, 2),
                  "sources": int(len(ps)), "variants": pst[-1]["variant_levels"]}
-        log(f"[bench] plain: {pw * 1e3:.1f} ms for {len(ps)} sources, {plain['value']} GTEPS")
+        log(f"[bench] plain: {pw * 1e3:.1f} ms for {len(ps)} sources, {plain['value']} GTEPS; phase ms",
+            [round(x, 1) for x in pst[-1]["phase_ms"][1:6]], "variant ms", [round(x, 1) for x in pst[-1]["variant_ms"]])
 
     # ---- oracle on the host, bounded sample of the same workload
     cpu = None

@@ -202,8 +202,13 @@ typedef struct bc_stats {
     int64_t arcs_scanned;      /* adjacency entries read, all phases          */
     int64_t lane_arcs;         /* (arc, source) pairs on shortest-path DAGs, both phases */
     int64_t queue_entries;     /* level-queue entries written                  */
-    double algo_bytes;         /* algorithmic bytes (see design notes)        */
+    double algo_bytes;         /* algorithmic bytes: 16 per scanned arc, 8 per DAG
+                                  (arc, source) pair, 32 per level-queue entry  */
     double ms;                 /* wall time of the run, host clock            */
+    double phase_ms[9];        /* device time per phase (index = internal phase id:
+                                  1 discover, 2 path counts, 3 backward,
+                                  4 reset, 5 BC accumulate, 6-7 detail dumps)   */
+    double variant_ms[3];      /* discover time per BC_VARIANT_*              */
 } bc_stats;
 
 bc_status bc_run_stats(const bc_graph *g, bc_stats *out);

@@ -74,7 +74,8 @@ class Stats(ctypes.Structure):
                 ("steps", ctypes.c_int64), ("launches", ctypes.c_int64), ("forward_levels", ctypes.c_int64),
                 ("max_levels", ctypes.c_int64), ("variant_levels", ctypes.c_int64 * 3),
                 ("f64_sources", ctypes.c_int64), ("arcs_scanned", ctypes.c_int64), ("lane_arcs", ctypes.c_int64),
-                ("queue_entries", ctypes.c_int64), ("algo_bytes", ctypes.c_double), ("ms", ctypes.c_double)]
+                ("queue_entries", ctypes.c_int64), ("algo_bytes", ctypes.c_double), ("ms", ctypes.c_double),
+                ("phase_ms", ctypes.c_double * 9), ("variant_ms", ctypes.c_double * 3)]
 
 
 _lib = None
@@ -253,7 +254,7 @@ def bc_run_stats(h) -> dict:
     out = {}
     for name, _ in Stats._fields_:
         v = getattr(s, name)
-        out[name] = list(v) if name == "variant_levels" else v
+        out[name] = list(v) if name in ("variant_levels", "phase_ms", "variant_ms") else v
     return out
 
 

@@ -136,6 +136,12 @@ struct bc_graph {
     std::vector<int32_t> vgraph;   // not kept (large); block lookups use voff
     int32_t *row_ptr = nullptr, *col = nullptr;
     int64_t nonisolated = 0;
+    // vertices of degree > kSeg (ascending) and their segment prefix sums
+    int32_t *hv_vtx = nullptr, *hv_seg = nullptr;
+    int32_t n_heavy = 0;
+    int64_t heavy_segs = 0;
+    double clock_khz = 100000.0;
+    int grid_plain = 1024, grid_batch = 1024;  // resident workgroups of the step kernels
     double *bc = nullptr;
     size_t bytes = 0;
     hipStream_t cap_stream = nullptr;
@@ -147,6 +153,7 @@ struct bc_graph {
     int32_t *p_d = nullptr, *p_queue = nullptr, *p_level_off = nullptr, *p_shift = nullptr;
     unsigned long long *p_sig = nullptr;
     double *p_chat = nullptr;
+    HeavyQ p_hq{};
     // batched engine
     bool batch_ready = false;
     VisNext *b_vn = nullptr;
@@ -159,6 +166,7 @@ struct bc_graph {
     unsigned long long *b_sig = nullptr;
     double *b_chat = nullptr;
     int32_t *b_shift = nullptr, *b_maxexp = nullptr, *b_lane_src = nullptr;
+    HeavyQ b_hq{};
     // per-run buffers (grown on demand)
     int32_t *srcs = nullptr;
     int64_t srcs_cap = 0;
@@ -190,7 +198,10 @@ extern "C" void bc_destroy(bc_graph *g) {
     void *dev[] = {g->row_ptr, g->col, g->bc, g->ctl, g->p_d, g->p_queue, g->p_level_off, g->p_shift,
                    g->p_sig, g->p_chat, g->b_vn, g->b_fw0, g->b_fw1, g->b_lq_vtx, g->b_lq_mask,
                    g->b_level_off, g->b_sig, g->b_chat, g->b_shift, g->b_maxexp, g->b_lane_src,
-                   g->srcs, g->ovf, g->bstart, g->blo, g->bhi, g->mlp};
+                   g->srcs, g->ovf, g->bstart, g->blo, g->bhi, g->mlp, g->hv_vtx, g->hv_seg,
+                   g->p_hq.pos, g->p_hq.seg, g->p_hq.cnt, g->p_hq.off, g->p_hq.nseg, g->p_hq.part_lo,
+                   g->p_hq.part_hi, g->b_hq.pos, g->b_hq.seg, g->b_hq.cnt, g->b_hq.off, g->b_hq.nseg,
+                   g->b_hq.part_lo, g->b_hq.part_hi};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (g->ctl_host) (void)hipHostFree(g->ctl_host);
@@ -313,6 +324,43 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
         return bail(BC_ERR_INVALID_GRAPH);
     }
     g->nonisolated = (int64_t)hcnt;
+    {
+        // vertices heavier than one segment, for the split load balancing
+        std::vector<int32_t> rp((size_t)n + 1);
+        CR_TRY(hipMemcpy(rp.data(), g->row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost));
+        std::vector<int32_t> hv, hs(1, 0);
+        int64_t segs = 0;
+        for (int32_t v = 0; v < n; ++v) {
+            const int32_t deg = rp[v + 1] - rp[v];
+            if (deg > kSeg) {
+                hv.push_back(v);
+                segs += (deg + kSeg - 1) / kSeg;
+                hs.push_back((int32_t)segs);
+            }
+        }
+        g->n_heavy = (int32_t)hv.size();
+        g->heavy_segs = segs;
+        CR_TRY(dalloc(&g->hv_vtx, hv.size(), &g->bytes));
+        CR_TRY(dalloc(&g->hv_seg, hs.size(), &g->bytes));
+        if (!hv.empty()) CR_TRY(hipMemcpy(g->hv_vtx, hv.data(), sizeof(int32_t) * hv.size(), hipMemcpyHostToDevice));
+        CR_TRY(hipMemcpy(g->hv_seg, hs.data(), sizeof(int32_t) * hs.size(), hipMemcpyHostToDevice));
+        int dev = 0, khz = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+            g->clock_khz = khz;
+        // one full wave of workgroups: every CU holds as many as occupancy allows
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
+            int bp = 0, bb = 0;
+            // the plain engine's levels are small: half a wave of workgroups
+            // keeps the per-step arrival count (and idle launches) down
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bp, (const void *)plain_step<0>, kBlock, 0) == hipSuccess &&
+                bp > 0)
+                g->grid_plain = std::max(cus, cus * bp / 2);
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bb, (const void *)batch_step<0>, kBlock, 0) == hipSuccess &&
+                bb > 0)
+                g->grid_batch = cus * bb;
+        }
+    }
     CR_TRY(dalloc(&g->bc, (size_t)n, &g->bytes));
     CR_TRY(hipMemset(g->bc, 0, sizeof(double) * (size_t)(n > 0 ? n : 1)));
     CR_TRY(dalloc(&g->ctl, 1, &g->bytes));
@@ -352,9 +400,26 @@ extern "C" void bc_run_options_init(bc_run_options *opt) {
 }
 
 // ------------------------------------------------------------ engine setup
+static bc_status alloc_hq(bc_graph *g, HeavyQ *q, int64_t entries, int64_t levels, int lanes) {
+    HIP_TRY(dalloc(&q->pos, (size_t)entries, &g->bytes));
+    HIP_TRY(dalloc(&q->seg, (size_t)entries, &g->bytes));
+    HIP_TRY(dalloc(&q->cnt, (size_t)entries, &g->bytes));
+    HIP_TRY(dalloc(&q->off, (size_t)levels, &g->bytes));
+    HIP_TRY(dalloc(&q->nseg, (size_t)levels, &g->bytes));
+    const int64_t segs = g->heavy_segs + 1;
+    HIP_TRY(dalloc(&q->part_lo, (size_t)segs * lanes, &g->bytes));
+    HIP_TRY(dalloc(&q->part_hi, (size_t)segs * lanes, &g->bytes));
+    q->cap = (uint32_t)std::min<int64_t>(entries, UINT32_MAX);
+    q->part_cap = (uint32_t)std::min<int64_t>(segs, UINT32_MAX);
+    return BC_OK;
+}
+
 static bc_status ensure_plain(bc_graph *g, hipStream_t st) {
     const int64_t n = g->n;
     if (!g->plain_ready) {
+        // each heavy vertex enters a source's level queues once
+        bc_status s = alloc_hq(g, &g->p_hq, (int64_t)g->n_heavy + 1, n + 3, 1);
+        if (s != BC_OK) return s;
         HIP_TRY(dalloc(&g->p_d, (size_t)n, &g->bytes));
         HIP_TRY(dalloc(&g->p_queue, (size_t)n, &g->bytes));
         HIP_TRY(dalloc(&g->p_level_off, (size_t)n + 2, &g->bytes));
@@ -393,6 +458,9 @@ static bc_status ensure_batched(bc_graph *g) {
     HIP_TRY(dalloc(&g->b_shift, ((size_t)g->b_max_levels + 2) * kLanes, &g->bytes));
     HIP_TRY(dalloc(&g->b_maxexp, (size_t)2 * kLanes, &g->bytes));
     HIP_TRY(dalloc(&g->b_lane_src, (size_t)kLanes, &g->bytes));
+    // a heavy vertex sits on at most 64 distinct levels of a batch (one per lane)
+    bc_status s = alloc_hq(g, &g->b_hq, (int64_t)g->n_heavy * kLanes + kLanes, (int64_t)g->b_max_levels + 3, kLanes);
+    if (s != BC_OK) return s;
     g->batch_ready = true;
     return BC_OK;
 }
@@ -545,7 +613,9 @@ struct DumpBufs {
     int32_t *shift = nullptr;
 };
 
-static void accumulate_stats(bc_stats *s, const Ctl &c) {
+static void accumulate_stats(bc_stats *s, const Ctl &c, double clock_khz) {
+    for (int i = 0; i < kPhases && i < 9; ++i) s->phase_ms[i] += (double)c.st_ticks[i] / clock_khz;
+    for (int i = 0; i < 3; ++i) s->variant_ms[i] += (double)c.st_vticks[i] / clock_khz;
     s->steps += (int64_t)c.st_steps;
     s->forward_levels += (int64_t)c.st_fwd_levels;
     for (int i = 0; i < 3; ++i) s->variant_levels[i] += (int64_t)c.st_var[i];
@@ -587,6 +657,9 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
     ga.row_ptr = g->row_ptr;
     ga.col = g->col;
     ga.nonisolated = g->nonisolated;
+    ga.hv_vtx = g->hv_vtx;
+    ga.hv_seg = g->hv_seg;
+    ga.n_heavy = g->n_heavy;
     int64_t launches = 0;
     if (cfg.engine == 1) {
         s = ensure_plain(g, st);
@@ -612,6 +685,7 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
         a.ovf_list = g->ovf;
         a.ovf_cap = (uint32_t)std::min<int64_t>(g->ovf_cap, UINT32_MAX);
         a.sigma_limit = limit;
+        a.hq = g->p_hq;
         if (dump) {
             a.dump_d = dump->d;
             a.dump_sig = dump->sig;
@@ -697,6 +771,7 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
         a.batch_lo = g->blo;
         a.batch_hi = g->bhi;
         a.lane_src = g->b_lane_src;
+        a.hq = g->b_hq;
         a.ovf_list = g->ovf;
         a.ovf_cap = (uint32_t)std::min<int64_t>(g->ovf_cap, UINT32_MAX);
         a.sigma_limit = limit;
@@ -715,7 +790,7 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
     HIP_TRY(hipMemcpyAsync(hc, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     *ctl_out = *hc;
-    accumulate_stats(&g->stats, *hc);
+    accumulate_stats(&g->stats, *hc, g->clock_khz);
     if (hc->err) {
         g->plain_dirty = true;
         return ctl_error(*hc);
@@ -751,7 +826,7 @@ static bc_status resolve_cfg(const bc_graph *g, const bc_run_options &o, int64_t
     }
     if (o.grid_blocks < 0 || o.grid_blocks > 65536) return fail(BC_ERR_INVALID_ARG, "grid_blocks out of range");
     if (o.chunk_steps < 0 || o.chunk_steps > 4096) return fail(BC_ERR_INVALID_ARG, "chunk_steps out of range");
-    cfg->grid = o.grid_blocks ? o.grid_blocks : 1024;
+    cfg->grid = o.grid_blocks ? o.grid_blocks : (cfg->engine == 1 ? g->grid_plain : g->grid_batch);
     cfg->chunk = o.chunk_steps ? o.chunk_steps : 16;
     cfg->use_graphs = !(o.flags & BC_RUN_NO_GRAPHS);
     cfg->mode = 0;

@@ -23,17 +23,452 @@
 //   PH_BC   BC[v] += delta_k(v) for k = 0 .. 63 in order (source-list
 //           order), then the visited words are cleared.
 // Frontier words carry a level tag so stale entries never need clearing.
+//
+// Load balance: a vertex of degree <= kLightDeg is handled by one thread
+// (thread-per-vertex variants), one of degree <= kSeg by one wavefront, and a
+// heavier one is split into kSeg-arc segments, one wavefront each.  Segment
+// partial sums are combined in segment order by the last segment to finish,
+// so every sum has an order fixed by the vertex and the results are bitwise
+// reproducible.
 #include "bc_common.h"
 
 namespace bcx {
 
-__device__ __forceinline__ unsigned long long shfl_u64(unsigned long long x, int src) {
-    const unsigned lo = __shfl((unsigned)x, src), hi = __shfl((unsigned)(x >> 32), src);
+// ------------------------------------------------------------------ pieces
+
+// Push from frontier vertex u (lane mask f) over arcs [a0, a1), one arc per
+// lane per chunk.  Appends newly reached vertices to the next level.
+__device__ __forceinline__ void push_arcs_wave(const BatchArgs &a, unsigned long long f, int a0, int a1,
+                                               const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                               uint32_t qe, uint32_t hq_base, unsigned long long &my_edges,
+                                               Stage &st, int &sn) {
+    Ctl *c = a.ctl;
+    for (int eb = a0; eb < a1; eb += kWave) {
+        const int e = eb + lane_id();
+        bool newly = false;
+        int w = 0, dw = 0;
+        if (e < a1) {
+            w = col[e];
+            const VisNext x = a.vn[w];
+            const unsigned long long add = f & ~x.vis & ~x.nxt;
+            if (add) newly = atomicOr(&a.vn[w].nxt, add) == 0ull;
+            if (newly) {
+                dw = rp[w + 1] - rp[w];
+                my_edges += (unsigned)dw;
+            }
+        }
+        stage_push(newly, w, dw, st, sn, c, a.lq_vtx, qe, a.lq_cap, a.hq, hq_base, &c->err);
+    }
+}
+
+constexpr int kUnroll = 8;  // matched neighbours whose rows are loaded together
+
+// Pop up to kUnroll matched neighbours (ascending lane order) from bal:
+// their vertex ids and lane masks, broadcast to the wavefront.
+__device__ __forceinline__ void pop_matches(unsigned long long &bal, int uj, unsigned long long xj, int *u,
+                                            unsigned long long *xm) {
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+        if (bal) {
+            // j is wavefront-uniform: readlane keeps u and xm in scalar registers
+            const int j = __ffsll(bal) - 1;
+            bal &= bal - 1;
+            u[q] = __builtin_amdgcn_readlane(uj, j);
+            const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)xj, j);
+            const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(xj >> 32), j);
+            xm[q] = ((unsigned long long)hi << 32) | lo;
+        } else {
+            u[q] = 0;
+            xm[q] = 0ull;
+        }
+    }
+}
+
+// Path counts: sum over arcs [a0, a1) of w's neighbours u on level l (tag T)
+// of sigma_k(u) for the lanes k of m; lane k accumulates its own source, in
+// CSR order.  Row loads of up to kUnroll neighbours are issued together.
+template <int MODE>
+__device__ __forceinline__ void sig_arcs(const BatchArgs &a, const Tagged *__restrict__ fw_cur, uint32_t T,
+                                         unsigned long long m, int a0, int a1, int sh,
+                                         const int32_t *__restrict__ col, unsigned long long &lo,
+                                         unsigned long long &hi, double &accd, unsigned long long &my_larcs) {
+    const int lane = lane_id();
+    for (int eb = a0; eb < a1; eb += kWave) {
+        const int e = eb + lane;
+        int uj = 0;
+        unsigned long long xj = 0;
+        if (e < a1) {
+            uj = col[e];
+            const Tagged F = fw_cur[uj];
+            if (F.tag == T) xj = F.mask & m;
+        }
+        unsigned long long bal = __ballot(xj != 0ull);
+        while (bal) {
+            int u[kUnroll];
+            unsigned long long xm[kUnroll], val[kUnroll];
+            pop_matches(bal, uj, xj, u, xm);
+#pragma unroll
+            for (int q = 0; q < kUnroll; ++q)
+                val[q] = ((xm[q] >> lane) & 1ull) ? a.sig[(size_t)u[q] * kLanes + lane] : 0ull;
+#pragma unroll
+            for (int q = 0; q < kUnroll; ++q) {
+                if ((xm[q] >> lane) & 1ull) {
+                    if (MODE == 0) {
+                        lo += val[q];
+                        hi += (lo < val[q]) ? 1ull : 0ull;
+                    } else {
+                        accd += ldexp(as_f64(val[q]), -sh);
+                    }
+                }
+                if (lane == 0) my_larcs += (unsigned)__popcll(xm[q]);
+            }
+        }
+    }
+}
+
+// Dependencies: sum over arcs [a0, a1) of v's neighbours w on level l+1 (tag
+// TB1) of c_k(w) for the lanes k of M, in CSR order.
+__device__ __forceinline__ double bwd_arcs(const BatchArgs &a, const Tagged *__restrict__ fb_nxt, uint32_t TB1,
+                                           unsigned long long M, int a0, int a1, const int32_t *__restrict__ col,
+                                           unsigned long long &my_larcs) {
+    const int lane = lane_id();
+    double acc = 0.0;
+    for (int eb = a0; eb < a1; eb += kWave) {
+        const int e = eb + lane;
+        int wj = 0;
+        unsigned long long xj = 0;
+        if (e < a1) {
+            wj = col[e];
+            const Tagged F = fb_nxt[wj];
+            if (F.tag == TB1) xj = F.mask & M;
+        }
+        unsigned long long bal = __ballot(xj != 0ull);
+        while (bal) {
+            int w[kUnroll];
+            unsigned long long xm[kUnroll];
+            double val[kUnroll];
+            pop_matches(bal, wj, xj, w, xm);
+#pragma unroll
+            for (int q = 0; q < kUnroll; ++q)
+                val[q] = ((xm[q] >> lane) & 1ull) ? a.chat[(size_t)w[q] * kLanes + lane] : 0.0;
+#pragma unroll
+            for (int q = 0; q < kUnroll; ++q) {
+                if ((xm[q] >> lane) & 1ull) acc += val[q];
+                if (lane == 0) my_larcs += (unsigned)__popcll(xm[q]);
+            }
+        }
+    }
+    return acc;
+}
+
+// Segment-partial protocol: every wavefront of a heavy entry stores its
+// partial, then counts itself in; the last one returns true and may read all
+// partials.
+__device__ __forceinline__ bool seg_arrive(int32_t *cnt, int nseg) {
+    __threadfence();
+    int old = 0;
+    if (lane_id() == 0) old = atomicAdd(cnt, 1);
+    old = __shfl(old, 0);
+    const bool last = (old == nseg - 1);
+    if (last) __threadfence();
+    return last;
+}
+
+// Per-lane counters the path-count finalisation feeds.
+struct SigCounters {
+    unsigned long long edges = 0, act = 0, ovf = 0, full_n = 0, full_m = 0, larcs = 0, arcs = 0;
+    int maxe = INT_MIN, mine = INT_MAX;
+};
+
+// Store the path counts of new vertex w (queue position p, visited/next words
+// x, degree deg) and publish it as part of the level-(l+1) frontier.
+template <int MODE>
+__device__ __forceinline__ void sig_finalize(const BatchArgs &a, Tagged *fw_nxt, uint32_t T1, int p, int w,
+                                             unsigned long long vis, unsigned long long m, int deg,
+                                             unsigned long long lo, unsigned long long hi, double accd,
+                                             unsigned long long lmask, SigCounters &sc) {
+    const int lane = lane_id();
+    if ((m >> lane) & 1ull) {
+        if (MODE == 0) {
+            a.sig[(size_t)w * kLanes + lane] = lo;
+            if (hi != 0 || lo > a.sigma_limit) sc.ovf |= 1ull << lane;
+        } else {
+            a.sig[(size_t)w * kLanes + lane] = as_u64(accd);
+            if (accd > 0.0) {
+                int ex;
+                frexp(accd, &ex);
+                sc.maxe = max(sc.maxe, ex);
+                sc.mine = min(sc.mine, ex);
+            }
+        }
+    }
+    if (lane == 0) {
+        VisNext y;
+        y.vis = vis | m;
+        y.nxt = 0ull;
+        a.vn[w] = y;
+        Tagged tg;
+        tg.mask = m;
+        tg.tag = T1;
+        tg.pad = 0;
+        fw_nxt[w] = tg;
+        a.lq_mask[p] = m;
+        sc.edges += (unsigned)deg;
+        sc.act |= m;
+        if ((y.vis & lmask) == lmask) {
+            sc.full_n += 1;
+            sc.full_m += (unsigned)deg;
+        }
+    }
+}
+
+// Dependencies of vertex v (queue position p, live lanes M) from the sum acc.
+template <int MODE>
+__device__ __forceinline__ void bwd_finalize(const BatchArgs &a, Tagged *fb_cur, uint32_t TB, int v,
+                                             unsigned long long M, double acc, int sh, int shn) {
+    const int lane = lane_id();
+    if ((M >> lane) & 1ull) {
+        const size_t at = (size_t)v * kLanes + lane;
+        const unsigned long long raw = a.sig[at];
+        const double sv = MODE ? ldexp(as_f64(raw), -sh) : (double)raw;
+        double delta = sv * acc;
+        if (MODE) delta = ldexp(delta, -shn);
+        a.chat[at] = (1.0 + delta) / sv;
+        a.sig[at] = as_u64(delta);
+    }
+    if (lane == 0) {
+        Tagged tg;
+        tg.mask = M;
+        tg.tag = TB;
+        tg.pad = 0;
+        fb_cur[v] = tg;
+    }
+}
+
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long x, int j) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, j);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), j);
     return ((unsigned long long)hi << 32) | lo;
 }
 
+// Owner of packed arc index ai: the number of entries whose inclusive arc
+// prefix is <= ai (all lanes take part; incl[63] > ai is required).
+__device__ __forceinline__ int packed_owner(int incl, int ai) {
+    int o = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int v = __shfl(incl, o + step - 1);
+        if (v <= ai) o += step;
+    }
+    return o;
+}
+
+constexpr int kPack = 64;   // entries of degree <= kPack share 64-arc scan chunks
+constexpr int kGroup = 16;  // queue entries per packed work item
+
+// Path counts for the kGroup queue entries [g0, g0 + kGroup) of level l+1: entries of
+// degree <= kPack have their adjacencies packed into dense 64-arc chunks;
+// entries of degree <= kSeg follow one at a time; heavier ones run as
+// segments elsewhere.  Every entry's sum keeps CSR order.
 template <int MODE>
-__device__ void batch_begin(BatchArgs &a, Ctl *c, int64_t b, float *lds, LevelFeatures *sf, int *s_lsrc,
+__device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__restrict__ fw_cur, Tagged *fw_nxt, uint32_t T,
+                          int qs, int g0, int cnt, int sh, unsigned long long lmask, SigCounters &sc) {
+    const int32_t *__restrict__ rp = a.g.row_ptr;
+    const int32_t *__restrict__ col = a.g.col;
+    const int lane = lane_id();
+    const int i = g0 + lane;
+    const bool valid = lane < kGroup && i < cnt;
+    const int p = qs + i;
+    const int w = valid ? a.lq_vtx[p] : 0;
+    const int e0 = valid ? rp[w] : 0;
+    const int deg = valid ? rp[w + 1] - e0 : 0;
+    const bool light = valid && deg <= kPack;
+    const bool medium = valid && deg > kPack && deg <= kSeg;
+    unsigned long long vis = 0, nxt = 0;
+    if (light || medium) {
+        const VisNext x = a.vn[w];
+        vis = x.vis;
+        nxt = x.nxt;
+    }
+    const int dl = light ? deg : 0;
+    const int incl = wave_incl_scan(dl);
+    const int off = incl - dl;
+    const int total = __shfl(incl, 63);
+    unsigned long long lo = 0, hi = 0;
+    double accd = 0.0;
+    int cur = 0;  // entries below cur are finalised; cur is being summed
+    auto finalize_upto = [&](int upto) {  // finalise cur (with the sum) .. upto-1 (empty sums)
+        for (int e = cur; e < upto; ++e) {
+            if (__builtin_amdgcn_readlane((int)light, e)) {
+                sig_finalize<MODE>(a, fw_nxt, T + 1u, __builtin_amdgcn_readlane(p, e),
+                                   __builtin_amdgcn_readlane(w, e), readlane_u64(vis, e), readlane_u64(nxt, e),
+                                   __builtin_amdgcn_readlane(deg, e), lo, hi, accd, lmask, sc);
+            }
+            lo = hi = 0;
+            accd = 0.0;
+        }
+        cur = upto;
+    };
+    for (int base = 0; base < total; base += kWave) {
+        const int ai = base + lane;
+        const int o = packed_owner(incl, min(ai, total - 1));
+        const int e0o = __shfl(e0, o), offo = __shfl(off, o);
+        const unsigned long long mo = shfl_u64(nxt, o);
+        int uj = 0;
+        unsigned long long xj = 0;
+        if (ai < total) {
+            uj = col[e0o + (ai - offo)];
+            const Tagged F = fw_cur[uj];
+            if (F.tag == T) xj = F.mask & mo;
+        }
+        if (lane == 0) sc.arcs += (unsigned)min(kWave, total - base);
+        unsigned long long bal = __ballot(xj != 0ull);
+        while (bal) {
+            int u[kUnroll], own[kUnroll];
+            unsigned long long xm[kUnroll], val[kUnroll];
+#pragma unroll
+            for (int q = 0; q < kUnroll; ++q) {
+                if (bal) {
+                    const int j = __ffsll(bal) - 1;
+                    bal &= bal - 1;
+                    u[q] = __builtin_amdgcn_readlane(uj, j);
+                    own[q] = __builtin_amdgcn_readlane(o, j);
+                    xm[q] = readlane_u64(xj, j);
+                } else {
+                    u[q] = 0;
+                    own[q] = -1;
+                    xm[q] = 0ull;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kUnroll; ++q)
+                val[q] = ((xm[q] >> lane) & 1ull) ? a.sig[(size_t)u[q] * kLanes + lane] : 0ull;
+#pragma unroll
+            for (int q = 0; q < kUnroll; ++q) {
+                if (own[q] < 0) continue;
+                if (own[q] != cur) finalize_upto(own[q]);
+                if ((xm[q] >> lane) & 1ull) {
+                    if (MODE == 0) {
+                        lo += val[q];
+                        hi += (lo < val[q]) ? 1ull : 0ull;
+                    } else {
+                        accd += ldexp(as_f64(val[q]), -sh);
+                    }
+                }
+                if (lane == 0) sc.larcs += (unsigned)__popcll(xm[q]);
+            }
+        }
+    }
+    finalize_upto(kGroup);
+    // medium-degree entries: one wavefront-wide scan each
+    unsigned long long mm = __ballot(medium);
+    while (mm) {
+        const int j = __ffsll(mm) - 1;
+        mm &= mm - 1;
+        const int wj = __builtin_amdgcn_readlane(w, j);
+        const int a0 = __builtin_amdgcn_readlane(e0, j), dj = __builtin_amdgcn_readlane(deg, j);
+        const unsigned long long mj = readlane_u64(nxt, j);
+        lo = hi = 0;
+        accd = 0.0;
+        sig_arcs<MODE>(a, fw_cur, T, mj, a0, a0 + dj, sh, col, lo, hi, accd, sc.larcs);
+        if (lane == 0) sc.arcs += (unsigned)dj;
+        sig_finalize<MODE>(a, fw_nxt, T + 1u, __builtin_amdgcn_readlane(p, j), wj, readlane_u64(vis, j), mj, dj,
+                           lo, hi, accd, lmask, sc);
+    }
+}
+
+// Dependencies for the kGroup queue entries [g0, g0 + kGroup) of level l, packed
+// like sig_group.
+template <int MODE>
+__device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__restrict__ fb_nxt, Tagged *fb_cur, uint32_t TB,
+                          int qb, int g0, int cnt, unsigned long long dead, int sh, int shn,
+                          unsigned long long &my_larcs, unsigned long long &my_arcs) {
+    const int32_t *__restrict__ rp = a.g.row_ptr;
+    const int32_t *__restrict__ col = a.g.col;
+    const int lane = lane_id();
+    const int i = g0 + lane;
+    const bool valid = lane < kGroup && i < cnt;
+    const int p = qb + i;
+    const int v = valid ? a.lq_vtx[p] : 0;
+    const int e0 = valid ? rp[v] : 0;
+    const int deg = valid ? rp[v + 1] - e0 : 0;
+    const bool light = valid && deg <= kPack;
+    const bool medium = valid && deg > kPack && deg <= kSeg;
+    const unsigned long long M = (light || medium) ? (a.lq_mask[p] & ~dead) : 0ull;
+    const int dl = (light && M) ? deg : 0;
+    const int incl = wave_incl_scan(dl);
+    const int off = incl - dl;
+    const int total = __shfl(incl, 63);
+    double acc = 0.0;
+    int cur = 0;
+    auto finalize_upto = [&](int upto) {
+        for (int e = cur; e < upto; ++e) {
+            if (__builtin_amdgcn_readlane((int)light, e))
+                bwd_finalize<MODE>(a, fb_cur, TB, __builtin_amdgcn_readlane(v, e), readlane_u64(M, e), acc, sh, shn);
+            acc = 0.0;
+        }
+        cur = upto;
+    };
+    for (int base = 0; base < total; base += kWave) {
+        const int ai = base + lane;
+        const int o = packed_owner(incl, min(ai, total - 1));
+        const int e0o = __shfl(e0, o), offo = __shfl(off, o);
+        const unsigned long long mo = shfl_u64(M, o);
+        int wj = 0;
+        unsigned long long xj = 0;
+        if (ai < total) {
+            wj = col[e0o + (ai - offo)];
+            const Tagged F = fb_nxt[wj];
+            if (F.tag == TB + 1u) xj = F.mask & mo;
+        }
+        if (lane == 0) my_arcs += (unsigned)min(kWave, total - base);
+        unsigned long long bal = __ballot(xj != 0ull);
+        while (bal) {
+            int ww[kUnroll], own[kUnroll];
+            unsigned long long xm[kUnroll];
+            double val[kUnroll];
+#pragma unroll
+            for (int q = 0; q < kUnroll; ++q) {
+                if (bal) {
+                    const int j = __ffsll(bal) - 1;
+                    bal &= bal - 1;
+                    ww[q] = __builtin_amdgcn_readlane(wj, j);
+                    own[q] = __builtin_amdgcn_readlane(o, j);
+                    xm[q] = readlane_u64(xj, j);
+                } else {
+                    ww[q] = 0;
+                    own[q] = -1;
+                    xm[q] = 0ull;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kUnroll; ++q)
+                val[q] = ((xm[q] >> lane) & 1ull) ? a.chat[(size_t)ww[q] * kLanes + lane] : 0.0;
+#pragma unroll
+            for (int q = 0; q < kUnroll; ++q) {
+                if (own[q] < 0) continue;
+                if (own[q] != cur) finalize_upto(own[q]);
+                if ((xm[q] >> lane) & 1ull) acc += val[q];
+                if (lane == 0) my_larcs += (unsigned)__popcll(xm[q]);
+            }
+        }
+    }
+    finalize_upto(kGroup);
+    unsigned long long mm = __ballot(medium);
+    while (mm) {
+        const int j = __ffsll(mm) - 1;
+        mm &= mm - 1;
+        const int vj = __builtin_amdgcn_readlane(v, j);
+        const int a0 = __builtin_amdgcn_readlane(e0, j), dj = __builtin_amdgcn_readlane(deg, j);
+        const unsigned long long Mj = readlane_u64(M, j);
+        const double s = Mj ? bwd_arcs(a, fb_nxt, TB + 1u, Mj, a0, a0 + dj, col, my_larcs) : 0.0;
+        if (lane == 0) my_arcs += (unsigned)dj;
+        bwd_finalize<MODE>(a, fb_cur, TB, vj, Mj, s, sh, shn);
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void batch_begin(const BatchArgs &a, Ctl *c, int64_t b, float *lds, LevelFeatures *sf, int *s_lsrc,
                             int *s_cnt, unsigned long long *s_tmp) {
     const int t = threadIdx.x;
     const int64_t start = a.batch_start[b], end = a.batch_start[b + 1];
@@ -59,7 +494,6 @@ __device__ void batch_begin(BatchArgs &a, Ctl *c, int64_t b, float *lds, LevelFe
             }
         }
         a.sig[(size_t)s * kLanes + t] = MODE ? as_u64(1.0) : 1ull;
-        if (MODE) a.shift[t] = 0;
         if (leader) {
             const int j = atomicAdd(s_cnt, 1);
             a.lq_vtx[j] = s;
@@ -72,14 +506,28 @@ __device__ void batch_begin(BatchArgs &a, Ctl *c, int64_t b, float *lds, LevelFe
             a.fw0[s] = tg;
             s_tmp[j] = (unsigned long long)(a.g.row_ptr[s + 1] - a.g.row_ptr[s]);
         }
-    } else if (MODE && t < kLanes) {
-        a.shift[t] = 0;
     }
+    if (MODE && t < kLanes) a.shift[t] = 0;
     __syncthreads();
     if (t == 0) {
         const int cnt = *s_cnt;
         unsigned long long mf = 0;
-        for (int j = 0; j < cnt; ++j) mf += s_tmp[j];
+        int nh = 0, segs = 0;
+        for (int j = 0; j < cnt; ++j) {
+            const int deg = (int)s_tmp[j];
+            mf += (unsigned long long)deg;
+            if (deg > kSeg) {  // heavy source: level-0 segments for the push
+                a.hq.pos[nh] = j;
+                a.hq.seg[nh] = segs;
+                a.hq.cnt[nh] = 0;
+                segs += n_segments(deg);
+                ++nh;
+            }
+        }
+        a.hq.off[0] = 0;
+        a.hq.off[1] = nh;
+        a.hq.nseg[0] = segs;
+        c->next_hq = 0;
         c->epoch = epoch;
         c->pos = b;
         c->lanes = lanes;
@@ -120,11 +568,15 @@ __device__ void batch_begin(BatchArgs &a, Ctl *c, int64_t b, float *lds, LevelFe
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
     __shared__ int s_phase, s_level, s_variant, s_last, s_qb, s_qe, s_qn, s_L, s_lo, s_hi, s_dlane, s_cnt;
+    __shared__ int s_h0, s_h1, s_hseg, s_hqb;
+    __shared__ unsigned s_nblk;
     __shared__ uint32_t s_epoch, s_epoch_b;
     __shared__ unsigned long long s_active, s_dead, s_lmask;
-    __shared__ unsigned long long s_red[kWavesPerBlock];
+    __shared__ unsigned long long s_red[kSlots * kNCnt];
+    __shared__ unsigned long long s_tot[kNCnt];
     __shared__ unsigned long long s_tmp[kLanes];
     __shared__ int s_lsrc[kLanes];
+    __shared__ Stage s_stage[kWavesPerBlock];
     __shared__ float s_lds[2 * kMlpH + 4];
     __shared__ LevelFeatures s_feat;
     Ctl *c = a.ctl;
@@ -142,198 +594,286 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
         s_lo = c->range_lo;
         s_hi = c->range_hi;
         s_dlane = c->dump_lane;
+        s_qb = s_qe = s_qn = 0;
+        s_h0 = s_h1 = s_hseg = s_hqb = 0;
         const int l = s_level;
         if (s_phase == PH_FWD || s_phase == PH_SIG || s_phase == PH_BWD) {
             s_qb = a.level_off[l];
             s_qe = a.level_off[l + 1];
-            s_qn = (s_phase == PH_SIG) ? a.level_off[l + 2] : 0;
+            if (s_phase == PH_SIG) s_qn = a.level_off[l + 2];
         } else if (s_phase == PH_DUMP_FWD || s_phase == PH_DUMP_BWD) {
-            s_qb = 0;
             s_qe = a.level_off[s_L];
-            s_qn = 0;
-        } else {
-            s_qb = s_qe = s_qn = 0;
         }
+        if (s_phase == PH_FWD) {
+            if (s_variant == V_PULL) {  // static heavy vertices of the batch's range
+                const int i0 = lower_bound_i32(a.g.hv_vtx, a.g.n_heavy, s_lo);
+                const int i1 = lower_bound_i32(a.g.hv_vtx, a.g.n_heavy, s_hi);
+                s_h0 = i0;
+                s_h1 = i1;
+                s_hseg = a.g.hv_seg[i1] - a.g.hv_seg[i0];
+            } else {                    // heavy frontier entries of level l
+                s_h0 = a.hq.off[l];
+                s_h1 = a.hq.off[l + 1];
+                s_hseg = a.hq.nseg[l];
+            }
+            s_hqb = a.hq.off[l + 1];    // heavy entries of level l+1 start here
+        } else if (s_phase == PH_SIG) {
+            s_h0 = a.hq.off[l + 1];
+            s_h1 = a.hq.off[l + 2];
+            s_hseg = a.hq.nseg[l + 1];
+        } else if (s_phase == PH_BWD) {
+            s_h0 = a.hq.off[l];
+            s_h1 = a.hq.off[l + 1];
+            s_hseg = a.hq.nseg[l];
+        }
+        // wavefront work items of this step -> workgroups taking part
+        long long items = 1;
+        const int cnt = s_qe - s_qb;
+        if (s_phase == PH_FWD) {
+            if (s_variant == V_PUSH_TPV) items = (cnt + kWave - 1) / kWave + s_hseg;
+            else if (s_variant == V_PUSH_WPV) items = cnt + s_hseg;
+            else items = (s_hi - s_lo + kWave - 1) / kWave + s_hseg;
+        } else if (s_phase == PH_SIG) {
+            items = (s_qn - s_qe + kGroup - 1) / kGroup + s_hseg;
+        } else if (s_phase == PH_BWD) {
+            items = (cnt + kGroup - 1) / kGroup + s_hseg;
+        } else if (s_phase == PH_BC) {
+            items = (s_hi - s_lo + kWave - 1) / kWave;
+        } else if (s_phase == PH_DUMP_FWD || s_phase == PH_DUMP_BWD) {
+            items = (s_qe + kWave - 1) / kWave;
+        }
+        s_nblk = active_blocks(items);
     }
     if (tid < kLanes) s_lsrc[tid] = a.lane_src[tid];
     __syncthreads();
     const int phase = s_phase;
     if (phase == PH_DONE || phase == PH_IDLE) return;
+    const unsigned nblk = s_nblk;
+    const bool active = blockIdx.x < nblk;  // workgroups beyond nblk only count in
 
     const int gw = blockIdx.x * kWavesPerBlock + wid;
-    const int nw = gridDim.x * kWavesPerBlock;
+    const int nw = (int)nblk * kWavesPerBlock;
     const int l = s_level;
     const int32_t *__restrict__ rp = a.g.row_ptr;
     const int32_t *__restrict__ col = a.g.col;
     Tagged *fw_cur = (l & 1) ? a.fw1 : a.fw0;
     Tagged *fw_nxt = (l & 1) ? a.fw0 : a.fw1;
+    const int h0 = s_h0, h1 = s_h1, hseg = s_hseg;
 
     unsigned long long my_edges = 0, my_arcs = 0, my_larcs = 0, my_act = 0, my_ovf = 0;
     unsigned long long my_full_n = 0, my_full_m = 0;
     int my_maxe = INT_MIN, my_mine = INT_MAX;
 
-    if (phase == PH_FWD) {
+    if (!active) {
+    } else if (phase == PH_FWD) {
         const int qb = s_qb, qe = s_qe, cnt = qe - qb;
         const uint32_t T = s_epoch + (uint32_t)l;
         const unsigned long long act = s_active;
-        const uint32_t cap = a.lq_cap - (uint32_t)qe;
-        int32_t *nq = a.lq_vtx + qe;
+        const uint32_t hqb = (uint32_t)s_hqb;
         const int variant = s_variant;
-        if (variant == V_PUSH_TPV) {
-            for (int base = gw * kWave; base < cnt; base += nw * kWave) {
-                const int i = base + lane;
-                const bool valid = i < cnt;
-                const int u = valid ? a.lq_vtx[qb + i] : 0;
-                const unsigned long long f = valid ? (a.lq_mask[qb + i] & act) : 0ull;
-                const int e0 = f ? rp[u] : 0;
-                const int len = f ? rp[u + 1] - e0 : 0;
-                my_arcs += (unsigned)len;
-                const int maxlen = wave_max_i(len);
-                for (int t = 0; t < maxlen; ++t) {
-                    bool newly = false;
-                    int w = 0;
-                    if (t < len) {
-                        w = col[e0 + t];
-                        const VisNext x = a.vn[w];
-                        const unsigned long long add = f & ~x.vis & ~x.nxt;
-                        if (add) {
-                            const unsigned long long old = atomicOr(&a.vn[w].nxt, add);
-                            newly = (old == 0ull);
+        Stage &st = s_stage[wid];
+        int sn = 0;
+        if (variant == V_PUSH_TPV || variant == V_PUSH_WPV) {
+            const int n_light = variant == V_PUSH_TPV ? (cnt + kWave - 1) / kWave : cnt;
+            const int total = n_light + hseg;
+            for (int it = gw; it < total; it += nw) {
+                if (it >= n_light) {  // one segment of a heavy frontier vertex
+                    const int t = it - n_light;
+                    const int h = seg_owner(a.hq.seg, h0, h1, t);
+                    const int s = t - a.hq.seg[h];
+                    const int p = a.hq.pos[h];
+                    const int u = a.lq_vtx[p];
+                    const unsigned long long f = a.lq_mask[p] & act;
+                    const int a0 = rp[u] + s * kSeg;
+                    const int a1 = min(rp[u + 1], a0 + kSeg);
+                    if (lane == 0) my_arcs += (unsigned)(a1 - a0);
+                    if (f) push_arcs_wave(a, f, a0, a1, rp, col, (uint32_t)qe, hqb, my_edges, st, sn);
+                } else if (variant == V_PUSH_WPV) {
+                    const int u = a.lq_vtx[qb + it];
+                    const unsigned long long f = a.lq_mask[qb + it] & act;
+                    const int e0 = rp[u], e1 = rp[u + 1];
+                    if (!f || e1 - e0 > kSeg) continue;  // heavy ones run as segments
+                    if (lane == 0) my_arcs += (unsigned)(e1 - e0);
+                    push_arcs_wave(a, f, e0, e1, rp, col, (uint32_t)qe, hqb, my_edges, st, sn);
+                } else {  // TPV: 64 frontier vertices per wavefront
+                    const int i = it * kWave + lane;
+                    const bool valid = i < cnt;
+                    const int u = valid ? a.lq_vtx[qb + i] : 0;
+                    const unsigned long long f = valid ? (a.lq_mask[qb + i] & act) : 0ull;
+                    const int e0 = f ? rp[u] : 0;
+                    const int deg = f ? rp[u + 1] - e0 : 0;
+                    const int len = deg <= kLightDeg ? deg : 0;
+                    my_arcs += (unsigned)(deg <= kSeg ? deg : 0);
+                    const int maxlen = wave_max_i(len);
+                    for (int t = 0; t < maxlen; ++t) {
+                        bool newly = false;
+                        int w = 0, dw = 0;
+                        if (t < len) {
+                            w = col[e0 + t];
+                            const VisNext x = a.vn[w];
+                            const unsigned long long add = f & ~x.vis & ~x.nxt;
+                            if (add) newly = atomicOr(&a.vn[w].nxt, add) == 0ull;
+                            if (newly) {
+                                dw = rp[w + 1] - rp[w];
+                                my_edges += (unsigned)dw;
+                            }
                         }
-                        if (newly) my_edges += (unsigned)(rp[w + 1] - rp[w]);
+                        stage_push(newly, w, dw, st, sn, c, a.lq_vtx, (uint32_t)qe, a.lq_cap, a.hq, hqb, &c->err);
                     }
-                    wave_append(newly, w, &c->next_count, nq, cap, &c->err);
-                }
-            }
-        } else if (variant == V_PUSH_WPV) {
-            for (int i = gw; i < cnt; i += nw) {
-                const int u = a.lq_vtx[qb + i];
-                const unsigned long long f = a.lq_mask[qb + i] & act;
-                if (!f) continue;
-                const int e0 = rp[u], e1 = rp[u + 1];
-                if (lane == 0) my_arcs += (unsigned)(e1 - e0);
-                for (int eb = e0; eb < e1; eb += kWave) {
-                    const int e = eb + lane;
-                    bool newly = false;
-                    int w = 0;
-                    if (e < e1) {
-                        w = col[e];
-                        const VisNext x = a.vn[w];
-                        const unsigned long long add = f & ~x.vis & ~x.nxt;
-                        if (add) {
-                            const unsigned long long old = atomicOr(&a.vn[w].nxt, add);
-                            newly = (old == 0ull);
-                        }
-                        if (newly) my_edges += (unsigned)(rp[w + 1] - rp[w]);
+                    // medium-degree vertices: the whole wavefront, one at a time
+                    unsigned long long mm = __ballot(deg > kLightDeg && deg <= kSeg);
+                    while (mm) {
+                        const int j = __ffsll(mm) - 1;
+                        mm &= mm - 1;
+                        const int m0 = __shfl(e0, j), m1 = m0 + __shfl(deg, j);
+                        push_arcs_wave(a, shfl_u64(f, j), m0, m1, rp, col, (uint32_t)qe, hqb, my_edges, st, sn);
                     }
-                    wave_append(newly, w, &c->next_count, nq, cap, &c->err);
                 }
             }
         } else {  // V_PULL over the batch's vertex range
             const int lo = s_lo, span = s_hi - s_lo;
-            for (int base = gw * kWave; base < span; base += nw * kWave) {
-                const int w = lo + base + lane;
-                const bool valid = base + lane < span;
+            const int n_light = (span + kWave - 1) / kWave;
+            const int total = n_light + hseg;
+            const int hs0 = a.g.hv_seg[h0];
+            for (int it = gw; it < total; it += nw) {
+                if (it >= n_light) {  // one segment of a heavy unvisited vertex
+                    const int t = hs0 + (it - n_light);
+                    const int h = seg_owner(a.g.hv_seg, h0, h1, t);
+                    const int s = t - a.g.hv_seg[h];
+                    const int w = a.g.hv_vtx[h];
+                    const unsigned long long need = act & ~a.vn[w].vis;
+                    unsigned long long got = 0;
+                    const int a0 = rp[w] + s * kSeg, a1 = min(rp[w + 1], a0 + kSeg);
+                    int scanned = 0;
+                    if (need) {
+                        for (int eb = a0; eb < a1; eb += kWave) {
+                            const int e = eb + lane;
+                            if (e < a1) {
+                                const Tagged F = fw_cur[col[e]];
+                                if (F.tag == T) got |= F.mask & need;
+                            }
+                            scanned += kWave;
+                            got = wave_or_u64(got);
+                            if (got == need) break;
+                        }
+                    }
+                    if (lane == 0) my_arcs += (unsigned)min(scanned, a1 - a0);
+                    bool newly = false;
+                    if (lane == 0 && got) newly = atomicOr(&a.vn[w].nxt, got) == 0ull;
+                    const int deg = rp[w + 1] - rp[w];
+                    if (newly) my_edges += (unsigned)deg;
+                    stage_push(newly, w, deg, st, sn, c, a.lq_vtx, (uint32_t)qe, a.lq_cap, a.hq, hqb, &c->err);
+                    continue;
+                }
+                const int w = lo + it * kWave + lane;
+                const bool valid = it * kWave + lane < span;
                 const unsigned long long vis = valid ? a.vn[w].vis : ~0ull;
                 const unsigned long long need = act & ~vis;
                 const int e0 = need ? rp[w] : 0;
-                const int len = need ? rp[w + 1] - e0 : 0;
+                const int deg = need ? rp[w + 1] - e0 : 0;
+                const int len = deg <= kLightDeg ? deg : 0;
                 const int maxlen = wave_max_i(len);
                 unsigned long long got = 0;
                 int scanned = 0;
                 for (int t = 0; t < maxlen; ++t) {
                     if (t < len && got != need) {
                         ++scanned;
-                        const int u = col[e0 + t];
-                        const Tagged F = fw_cur[u];
+                        const Tagged F = fw_cur[col[e0 + t]];
                         if (F.tag == T) got |= F.mask & need;
                     }
                     if (!__any(t + 1 < len && got != need)) break;
                 }
-                my_arcs += (unsigned)scanned;
-                if (got) {
-                    a.vn[w].nxt = got;
-                    my_edges += (unsigned)len;
+                // medium-degree vertices: the whole wavefront, one at a time
+                unsigned long long mm = __ballot(deg > kLightDeg && deg <= kSeg);
+                while (mm) {
+                    const int j = __ffsll(mm) - 1;
+                    mm &= mm - 1;
+                    const int m0 = __shfl(e0, j), m1 = m0 + __shfl(deg, j);
+                    const unsigned long long nj = shfl_u64(need, j);
+                    unsigned long long gj = 0;
+                    for (int eb = m0; eb < m1; eb += kWave) {
+                        const int e = eb + lane;
+                        if (e < m1) {
+                            const Tagged F = fw_cur[col[e]];
+                            if (F.tag == T) gj |= F.mask & nj;
+                        }
+                        if (lane == 0) scanned += min(kWave, m1 - eb);
+                        gj = wave_or_u64(gj);
+                        if (gj == nj) break;
+                    }
+                    if (lane == j) got = gj;
                 }
-                wave_append(got != 0ull, w, &c->next_count, nq, cap, &c->err);
+                my_arcs += (unsigned)scanned;
+                const bool found = got != 0ull && deg <= kSeg;
+                if (found) {
+                    a.vn[w].nxt = got;
+                    my_edges += (unsigned)deg;
+                }
+                stage_push(found, w, deg, st, sn, c, a.lq_vtx, (uint32_t)qe, a.lq_cap, a.hq, hqb, &c->err);
             }
         }
+        stage_flush(st, sn, c, a.lq_vtx, (uint32_t)qe, a.lq_cap, a.hq, hqb, &c->err);
     } else if (phase == PH_SIG) {
-        // path counts of the new level, one wavefront per vertex, lane = source
+        // path counts of the new level; lane = source
         const int qs = s_qe, cnt = s_qn - s_qe;
         const uint32_t T = s_epoch + (uint32_t)l;
         const int sh = MODE ? a.shift[(size_t)l * kLanes + lane] : 0;
         const unsigned long long lmask = s_lmask;
-        for (int i = gw; i < cnt; i += nw) {
-            const int w = a.lq_vtx[qs + i];
-            const VisNext x = a.vn[w];
-            const unsigned long long m = x.nxt;
+        const int n_groups = (cnt + kGroup - 1) / kGroup;
+        const int total = n_groups + hseg;
+        SigCounters sc;
+        for (int it = gw; it < total; it += nw) {
+            if (it < n_groups) {
+                sig_group<MODE>(a, fw_cur, fw_nxt, T, qs, it * kGroup, cnt, sh, lmask, sc);
+                continue;
+            }
+            // a segment of a heavy new vertex
+            const int t = it - n_groups;
+            const int h = seg_owner(a.hq.seg, h0, h1, t);
+            const int s = t - a.hq.seg[h];
+            const int p = a.hq.pos[h];
+            const int w = a.lq_vtx[p];
             const int e0 = rp[w], e1 = rp[w + 1];
+            const unsigned long long m = a.vn[w].nxt;
+            const int a0 = e0 + s * kSeg, a1 = min(e1, a0 + kSeg);
             unsigned long long lo = 0, hi = 0;
             double accd = 0.0;
-            for (int eb = e0; eb < e1; eb += kWave) {
-                const int e = eb + lane;
-                int uj = 0;
-                unsigned long long xj = 0;
-                if (e < e1) {
-                    uj = col[e];
-                    const Tagged F = fw_cur[uj];
-                    if (F.tag == T) xj = F.mask & m;
-                }
-                unsigned long long bal = __ballot(xj != 0ull);
-                while (bal) {
-                    const int j = __ffsll(bal) - 1;
-                    bal &= bal - 1;
-                    const int u = __shfl(uj, j);
-                    const unsigned long long xm = shfl_u64(xj, j);
-                    if ((xm >> lane) & 1ull) {
-                        const unsigned long long val = a.sig[(size_t)u * kLanes + lane];
-                        if (MODE == 0) {
-                            lo += val;
-                            hi += (lo < val) ? 1ull : 0ull;
-                        } else {
-                            accd += ldexp(as_f64(val), -sh);
-                        }
-                    }
-                    if (lane == 0) my_larcs += (unsigned)__popcll(xm);
-                }
+            sig_arcs<MODE>(a, fw_cur, T, m, a0, a1, sh, col, lo, hi, accd, sc.larcs);
+            if (lane == 0) sc.arcs += (unsigned)(a1 - a0);
+            const size_t slot = (size_t)(a.hq.seg[h] + s) * kLanes + lane;
+            if (MODE == 0) {
+                a.hq.part_lo[slot] = lo;
+                a.hq.part_hi[slot] = hi;
+            } else {
+                a.hq.part_lo[slot] = as_u64(accd);
             }
-            if (lane == 0) my_arcs += (unsigned)(e1 - e0);
-            const bool mine = (m >> lane) & 1ull;
-            if (mine) {
+            const int ns = n_segments(e1 - e0);
+            if (!seg_arrive(&a.hq.cnt[h], ns)) continue;
+            lo = hi = 0;
+            accd = 0.0;
+            for (int k = 0; k < ns; ++k) {  // combine in segment order
+                const size_t sl = (size_t)(a.hq.seg[h] + k) * kLanes + lane;
                 if (MODE == 0) {
-                    a.sig[(size_t)w * kLanes + lane] = lo;
-                    if (hi != 0 || lo > a.sigma_limit) my_ovf |= 1ull << lane;
+                    const unsigned long long x = a.hq.part_lo[sl];
+                    lo += x;
+                    hi += a.hq.part_hi[sl] + ((lo < x) ? 1ull : 0ull);
                 } else {
-                    a.sig[(size_t)w * kLanes + lane] = as_u64(accd);
-                    if (accd > 0.0) {
-                        int ex;
-                        frexp(accd, &ex);
-                        my_maxe = max(my_maxe, ex);
-                        my_mine = min(my_mine, ex);
-                    }
+                    accd += as_f64(a.hq.part_lo[sl]);
                 }
             }
-            if (lane == 0) {
-                VisNext y;
-                y.vis = x.vis | m;
-                y.nxt = 0ull;
-                a.vn[w] = y;
-                Tagged tg;
-                tg.mask = m;
-                tg.tag = T + 1u;
-                tg.pad = 0;
-                fw_nxt[w] = tg;
-                a.lq_mask[qs + i] = m;
-                const unsigned deg = (unsigned)(e1 - e0);
-                my_edges += deg;
-                my_act |= m;
-                if ((y.vis & lmask) == lmask) {
-                    my_full_n += 1;
-                    my_full_m += deg;
-                }
-            }
+            if (lane == 0) a.hq.cnt[h] = 0;
+            const VisNext x = a.vn[w];
+            sig_finalize<MODE>(a, fw_nxt, T + 1u, p, w, x.vis, x.nxt, e1 - e0, lo, hi, accd, lmask, sc);
         }
+        my_edges += sc.edges;
+        my_act |= sc.act;
+        my_ovf |= sc.ovf;
+        my_full_n += sc.full_n;
+        my_full_m += sc.full_m;
+        my_larcs += sc.larcs;
+        my_arcs += sc.arcs;
+        my_maxe = max(my_maxe, sc.maxe);
+        my_mine = min(my_mine, sc.mine);
     } else if (phase == PH_BWD) {
         const int qb = s_qb, cnt = s_qe - s_qb;
         const uint32_t TB = s_epoch_b + (uint32_t)l;
@@ -342,55 +882,36 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
         const unsigned long long dead = s_dead;
         const int sh = MODE ? a.shift[(size_t)l * kLanes + lane] : 0;
         const int shn = (MODE && l + 1 < s_L) ? a.shift[(size_t)(l + 1) * kLanes + lane] : 0;
-        for (int i = gw; i < cnt; i += nw) {
-            const int v = a.lq_vtx[qb + i];
-            const unsigned long long M = a.lq_mask[qb + i] & ~dead;
+        const int n_groups = (cnt + kGroup - 1) / kGroup;
+        const int total = n_groups + hseg;
+        for (int it = gw; it < total; it += nw) {
+            if (it < n_groups) {
+                bwd_group<MODE>(a, fb_nxt, fb_cur, TB, qb, it * kGroup, cnt, dead, sh, shn, my_larcs, my_arcs);
+                continue;
+            }
+            const int t = it - n_groups;
+            const int h = seg_owner(a.hq.seg, h0, h1, t);
+            const int s = t - a.hq.seg[h];
+            const int p = a.hq.pos[h];
+            const int v = a.lq_vtx[p];
+            const unsigned long long M = a.lq_mask[p] & ~dead;
             const int e0 = rp[v], e1 = rp[v + 1];
-            double acc = 0.0;
-            if (M) {
-                for (int eb = e0; eb < e1; eb += kWave) {
-                    const int e = eb + lane;
-                    int wj = 0;
-                    unsigned long long xj = 0;
-                    if (e < e1) {
-                        wj = col[e];
-                        const Tagged F = fb_nxt[wj];
-                        if (F.tag == TB + 1u) xj = F.mask & M;
-                    }
-                    unsigned long long bal = __ballot(xj != 0ull);
-                    while (bal) {
-                        const int j = __ffsll(bal) - 1;
-                        bal &= bal - 1;
-                        const int w = __shfl(wj, j);
-                        const unsigned long long xm = shfl_u64(xj, j);
-                        if ((xm >> lane) & 1ull) acc += a.chat[(size_t)w * kLanes + lane];
-                        if (lane == 0) my_larcs += (unsigned)__popcll(xm);
-                    }
-                }
-                if (lane == 0) my_arcs += (unsigned)(e1 - e0);
-                if ((M >> lane) & 1ull) {
-                    const size_t at = (size_t)v * kLanes + lane;
-                    const unsigned long long raw = a.sig[at];
-                    const double sv = MODE ? ldexp(as_f64(raw), -sh) : (double)raw;
-                    double delta = sv * acc;
-                    if (MODE) delta = ldexp(delta, -shn);
-                    a.chat[at] = (1.0 + delta) / sv;
-                    a.sig[at] = as_u64(delta);
-                }
-            }
-            if (lane == 0) {
-                Tagged tg;
-                tg.mask = M;
-                tg.tag = TB;
-                tg.pad = 0;
-                fb_cur[v] = tg;
-            }
+            const int a0 = e0 + s * kSeg, a1 = min(e1, a0 + kSeg);
+            double acc = M ? bwd_arcs(a, fb_nxt, TB + 1u, M, a0, a1, col, my_larcs) : 0.0;
+            if (lane == 0) my_arcs += (unsigned)(a1 - a0);
+            a.hq.part_lo[(size_t)(a.hq.seg[h] + s) * kLanes + lane] = as_u64(acc);
+            const int ns = n_segments(e1 - e0);
+            if (!seg_arrive(&a.hq.cnt[h], ns)) continue;
+            acc = 0.0;
+            for (int k = 0; k < ns; ++k) acc += as_f64(a.hq.part_lo[(size_t)(a.hq.seg[h] + k) * kLanes + lane]);
+            if (lane == 0) a.hq.cnt[h] = 0;
+            bwd_finalize<MODE>(a, fb_cur, TB, v, M, acc, sh, shn);
         }
     } else if (phase == PH_BC) {
         // dependencies -> BC in source-list order, then clear the visited words
         const int lo = s_lo, span = s_hi - s_lo;
         const unsigned long long keep = s_lmask & ~s_dead;
-        for (int i = blockIdx.x * kBlock + tid; i < span; i += gridDim.x * kBlock) {
+        for (int i = blockIdx.x * kBlock + tid; i < span; i += (int)nblk * kBlock) {
             const int w = lo + i;
             const VisNext x = a.vn[w];
             unsigned long long vis = x.vis & keep;
@@ -414,7 +935,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
         const int k = s_dlane;
         const int L = s_L;
         const int total = s_qe;
-        for (int j = blockIdx.x * kBlock + tid; j < total; j += gridDim.x * kBlock) {
+        for (int j = blockIdx.x * kBlock + tid; j < total; j += (int)nblk * kBlock) {
             if (!((a.lq_mask[j] >> k) & 1ull)) continue;
             int lo = 0, hi = L;  // level of entry j: level_off[lvl] <= j < level_off[lvl+1]
             while (hi - lo > 1) {
@@ -435,44 +956,45 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             for (int i = tid; i < L; i += kBlock) a.dump_shift[i] = MODE ? a.shift[(size_t)i * kLanes + k] : 0;
     }
 
-    // ---- per-launch statistics and level counters
-    {
-        const unsigned long long e = block_sum_u64(my_edges, s_red);
-        if (tid == 0 && e) atomicAdd(&c->next_edges, e);
-        const unsigned long long ar = block_sum_u64(my_arcs, s_red);
-        if (tid == 0 && ar) atomicAdd(&c->st_arcs, ar);
-        const unsigned long long la = block_sum_u64(my_larcs, s_red);
-        if (tid == 0 && la) atomicAdd(&c->st_lane_arcs, la);
-        if (phase == PH_SIG) {
-            const unsigned long long fn = block_sum_u64(my_full_n, s_red);
-            if (tid == 0 && fn) atomicAdd(&c->full_n, fn);
-            const unsigned long long fm = block_sum_u64(my_full_m, s_red);
-            if (tid == 0 && fm) atomicAdd(&c->full_m, fm);
-            const unsigned long long ac = wave_or_u64(my_act);
-            if (lane == 0 && ac) atomicOr(&c->next_active, ac);
-            if (MODE == 0) {
-                const unsigned long long ov = wave_or_u64(my_ovf);
-                if (lane == 0 && ov) atomicOr(&c->ovf_lanes, ov);
-            } else {
-                if (my_maxe != INT_MIN) atomicMax(&a.maxexp[lane], my_maxe);
-                if (my_mine != INT_MAX) atomicMin(&a.maxexp[kLanes + lane], my_mine);
-            }
-        }
+    // ---- per-launch counters into the slots; the last workgroup continues
+    Counters cn;
+    cn.v[SC_EDGES] = my_edges;
+    cn.v[SC_ARCS] = my_arcs;
+    cn.v[SC_LARCS] = my_larcs;
+    cn.v[SC_FULLN] = my_full_n;
+    cn.v[SC_FULLM] = my_full_m;
+    cn.v[SC_ACT] = my_act;
+    cn.v[SC_OVF] = my_ovf;
+    if (MODE == 1 && phase == PH_SIG) {  // per-lane exponent range of the new level
+        if (my_maxe != INT_MIN) atomicMax(&a.maxexp[lane], my_maxe);
+        if (my_mine != INT_MAX) atomicMin(&a.maxexp[kLanes + lane], my_mine);
     }
-
-    if (!last_block_arrive(&c->blocks_done, &s_last)) return;
+    if (!step_epilogue(c, cn, s_red, &s_last, active)) return;
+    collect_slots(c, s_tot, s_red);
 
     // ---- the last workgroup advances the state machine
     int action = 0;  // 1 = begin batch, 2 = advance level
     if (tid == 0) {
-        c->blocks_done = 0;
         c->st_steps += 1;
+        c->st_arcs += s_tot[SC_ARCS];
+        c->st_lane_arcs += s_tot[SC_LARCS];
+        const unsigned long long now = wall_clock64();
+        if (c->last_tick) {
+            const unsigned long long dt = now - c->last_tick;
+            c->st_ticks[phase] += dt;
+            if (phase == PH_FWD) c->st_vticks[s_variant] += dt;
+        }
+        c->last_tick = now;
         if (phase == PH_FWD) {
             const uint32_t cnt = ld_agent(&c->next_count);
+            const unsigned long long nh = ld_agent(&c->next_hq);
             const int qe = a.level_off[l + 1];
             c->st_fwd_levels += 1;
             c->st_var[s_variant] += 1;
             c->st_qentries += cnt;
+            a.hq.off[l + 2] = a.hq.off[l + 1] + (int)(uint32_t)nh;
+            a.hq.nseg[l + 1] = (int)(nh >> 32);
+            c->next_hq = 0;
             if (cnt == 0) {
                 const int L = l + 1;
                 c->n_levels = L;
@@ -522,7 +1044,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
     } else if (action == 2) {
         // finish level l+1: lane deaths, FP64 shifts, features, policy
         if (tid == 0) {
-            const unsigned long long ovf = ld_agent(&c->ovf_lanes) & ~c->dead;
+            const unsigned long long ovf = s_tot[SC_OVF] & ~c->dead;
             if (ovf) {
                 unsigned long long o = ovf;
                 const int64_t start = a.batch_start[c->pos];
@@ -535,13 +1057,11 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
                     c->n_ovf = q + 1;
                 }
                 c->dead |= ovf;
-                c->ovf_lanes = 0;
             }
-            c->active = ld_agent(&c->next_active) & ~c->dead;
-            c->next_active = 0;
+            c->active = s_tot[SC_ACT] & ~c->dead;
         }
         if (MODE && tid < kLanes) {
-            const int mx = a.maxexp[tid], mn = a.maxexp[kLanes + tid];
+            const int mx = ld_agent(&a.maxexp[tid]), mn = ld_agent(&a.maxexp[kLanes + tid]);
             int sh = 0;
             if (mx != INT_MIN && mx > 960) sh = mx - 900;
             if (mn != INT_MAX && mn - sh < -1000) atomicOr(&c->err, ERR_SIGMA_RANGE);
@@ -551,18 +1071,19 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
         }
         if (tid == 0) {
             const uint32_t cnt = ld_agent(&c->next_count);
-            const unsigned long long edges = ld_agent(&c->next_edges);
+            const unsigned long long edges = s_tot[SC_EDGES];
             c->level = l + 1;
             c->visited_n += cnt;
             c->visited_m += edges;
-            const unsigned long long fn = ld_agent(&c->full_n), fm = ld_agent(&c->full_m);
+            c->full_n += s_tot[SC_FULLN];
+            c->full_m += s_tot[SC_FULLM];
+            const unsigned long long fn = c->full_n, fm = c->full_m;
             s_feat.nf = (float)cnt;
             s_feat.mf = (float)edges;
             s_feat.nu = (float)((long long)c->range_nodeg - (long long)fn);
             s_feat.mu = (float)((long long)c->range_arcs - (long long)fm);
             s_feat.level = l + 1;
             c->next_count = 0;
-            c->next_edges = 0;
             c->prev_variant = c->variant;
             c->phase = PH_FWD;
         }

@@ -64,6 +64,268 @@ __device__ __forceinline__ void wave_append(bool pred, int32_t w, uint32_t *coun
     }
 }
 
+// ---------------------------------------------------------------- counters
+struct Counters {
+    unsigned long long v[kNCnt];
+    __device__ Counters() {
+#pragma unroll
+        for (int k = 0; k < kNCnt; ++k) v[k] = 0ull;
+    }
+    __device__ void exponent(int e) {
+        v[SC_MAXE] = max(v[SC_MAXE], (unsigned long long)(e + 4096));
+        v[SC_MINE] = max(v[SC_MINE], (unsigned long long)(4096 - e));
+    }
+};
+
+__device__ __forceinline__ int cnt_op(int k) { return k >= SC_MAXE ? 2 : (k >= SC_ACT ? 1 : 0); }  // 0 sum, 1 or, 2 max
+
+__device__ __forceinline__ unsigned long long cnt_combine(int k, unsigned long long a, unsigned long long b) {
+    const int op = cnt_op(k);
+    return op == 0 ? a + b : (op == 1 ? (a | b) : (a > b ? a : b));
+}
+
+// Workgroups a step needs for `items` wavefront work items (at least one, at
+// most the launched grid).  Workgroups beyond it leave at once.
+__device__ __forceinline__ unsigned active_blocks(long long items) {
+    long long b = (items + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (b < 1) b = 1;
+    if (b > (long long)gridDim.x) b = gridDim.x;
+    return (unsigned)b;
+}
+
+// End of a step for one workgroup: reduce the counters over the workgroup,
+// add them into the workgroup's slot, count the workgroup in (two-level
+// arrival so no single address takes one atomic per workgroup).  Returns
+// true in exactly one workgroup -- the last -- once every workgroup of the
+// launch has arrived.  Workgroups without work (active == false) only count
+// themselves in, so the last one cannot move the state machine on while a
+// late workgroup still has to read it.
+//
+// No fences: within a launch, workgroups exchange only device-scope atomics
+// here (slot counters, arrival counts, queue counters); plain stores are
+// consumed by later launches, which kernel boundaries order.  s_red needs
+// kWavesPerBlock * kNCnt entries.
+__device__ __forceinline__ bool step_epilogue(Ctl *c, Counters &cn, unsigned long long *s_red, int *s_last,
+                                              bool active) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int slot = blockIdx.x % kSlots;
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < kNCnt; ++k) {
+            unsigned long long x = cn.v[k];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) x = cnt_combine(k, x, __shfl_xor(x, o));
+            if (lane == 0) s_red[wid * kNCnt + k] = x;
+        }
+        __syncthreads();
+        if (threadIdx.x < kNCnt) {
+            const int k = threadIdx.x;
+            unsigned long long t = s_red[k];
+            for (int w = 1; w < kWavesPerBlock; ++w) t = cnt_combine(k, t, s_red[w * kNCnt + k]);
+            if (t) {
+                const int op = cnt_op(k);
+                if (op == 0) atomicAdd(&c->slot[slot][k], t);
+                else if (op == 1) atomicOr(&c->slot[slot][k], t);
+                else atomicMax(&c->slot[slot][k], t);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        int last = 0;
+        const unsigned in_slot = (gridDim.x - slot + kSlots - 1) / kSlots;
+        const unsigned t = atomicAdd(&c->arrive[slot], 1u);
+        if (t == in_slot - 1) {
+            const unsigned nslots = gridDim.x < (unsigned)kSlots ? gridDim.x : (unsigned)kSlots;
+            const unsigned t2 = atomicAdd(&c->blocks_done, 1u);
+            last = (t2 == nslots - 1) ? 1 : 0;
+        }
+        *s_last = last;
+    }
+    __syncthreads();
+    return *s_last != 0;
+}
+
+// In the last workgroup: totals of all slots into s_tot[kNCnt] (valid after
+// the call in every thread); slots and arrival counters are reset.
+__device__ __forceinline__ void collect_slots(Ctl *c, unsigned long long *s_tot, unsigned long long *s_tmp /*kSlots*kNCnt*/) {
+    const int t = threadIdx.x;
+    if (t < kSlots) {
+#pragma unroll
+        for (int k = 0; k < kNCnt; ++k) {
+            s_tmp[t * kNCnt + k] = __hip_atomic_load(&c->slot[t][k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            c->slot[t][k] = 0ull;
+        }
+        c->arrive[t] = 0u;
+    }
+    __syncthreads();
+    if (t < kNCnt) {
+        unsigned long long x = s_tmp[t];
+        for (int sl = 1; sl < kSlots; ++sl) x = cnt_combine(t, x, s_tmp[sl * kNCnt + t]);
+        s_tot[t] = x;
+    }
+    if (t == 0) c->blocks_done = 0u;
+    __syncthreads();
+}
+
+// ----------------------------------------------------------- staged appends
+// New level-queue entries are first gathered per wavefront in LDS and
+// written in runs, one position atomic per run instead of per append.
+constexpr int kStage = 128;
+struct Stage {
+    int32_t w[kStage];
+    int32_t deg[kStage];
+};
+
+// Wavefront-inclusive prefix sum of an int.
+__device__ __forceinline__ int wave_incl_scan(int x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ unsigned long long shfl_u64(unsigned long long x, int src) {
+    const unsigned lo = __shfl((unsigned)x, src), hi = __shfl((unsigned)(x >> 32), src);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int n_segments(int deg) { return (deg + kSeg - 1) / kSeg; }
+
+// Append w, for every lane with pred, to the level queue q at absolute
+// positions qbase + i (i from the level counter c->next_count), and the heavy
+// ones (deg > kSeg) to the heavy list of that level starting at hq_base.  The
+// wavefront must be converged.
+__device__ __forceinline__ void wave_append_level(bool pred, int32_t w, int32_t deg, Ctl *c, int32_t *q,
+                                                  uint32_t qbase, uint32_t qcap, const HeavyQ &hq,
+                                                  uint32_t hq_base, int32_t *err) {
+    const unsigned long long m = __ballot(pred);
+    if (m == 0) return;
+    const int lane = lane_id();
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(&c->next_count, (unsigned)__popcll(m));
+    base = __shfl(base, leader);
+    uint32_t p = 0;
+    if (pred) {
+        p = qbase + base + lanes_below(m);
+        if (p < qcap) q[p] = w;
+        else atomicOr(err, ERR_QUEUE_CAP);
+    }
+    const bool heavy = pred && deg > kSeg;
+    const unsigned long long hm = __ballot(heavy);
+    if (hm == 0) return;
+    const int ns = heavy ? n_segments(deg) : 0;
+    const int incl = wave_incl_scan(ns);
+    const int total = __shfl(incl, 63);
+    const int hl = __ffsll((unsigned long long)hm) - 1;
+    unsigned long long old = 0;
+    if (lane == hl)
+        old = atomicAdd(&c->next_hq, (unsigned long long)__popcll(hm) | ((unsigned long long)(unsigned)total << 32));
+    old = shfl_u64(old, hl);
+    if (heavy) {
+        const uint32_t idx = hq_base + (uint32_t)old + lanes_below(hm);
+        if (idx < hq.cap) {
+            hq.pos[idx] = (int32_t)p;
+            hq.seg[idx] = (int32_t)(old >> 32) + (incl - ns);
+            hq.cnt[idx] = 0;
+        } else {
+            atomicOr(err, ERR_QUEUE_CAP);
+        }
+    }
+}
+
+// Write the n staged entries of this wavefront to the level queue (absolute
+// positions qbase + counter), heavy ones also to the level's heavy list.
+__device__ __forceinline__ void stage_flush(Stage &st, int &n, Ctl *c, int32_t *q, uint32_t qbase, uint32_t qcap,
+                                            const HeavyQ &hq, uint32_t hq_base, int32_t *err) {
+    if (n == 0) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int lane = lane_id();
+    unsigned base = 0;
+    if (lane == 0) base = atomicAdd(&c->next_count, (unsigned)n);
+    base = __shfl(base, 0);
+    for (int i0 = 0; i0 < n; i0 += kWave) {
+        const int i = i0 + lane;
+        const bool on = i < n;
+        const int w = on ? st.w[i] : 0;
+        const int deg = on ? st.deg[i] : 0;
+        const uint32_t p = qbase + base + (uint32_t)i;
+        if (on) {
+            if (p < qcap) q[p] = w;
+            else atomicOr(err, ERR_QUEUE_CAP);
+        }
+        const bool heavy = on && deg > kSeg;
+        const unsigned long long hm = __ballot(heavy);
+        if (hm) {
+            const int ns = heavy ? n_segments(deg) : 0;
+            const int incl = wave_incl_scan(ns);
+            const int total = __shfl(incl, 63);
+            const int hl = __ffsll((unsigned long long)hm) - 1;
+            unsigned long long old = 0;
+            if (lane == hl)
+                old = atomicAdd(&c->next_hq,
+                                (unsigned long long)__popcll(hm) | ((unsigned long long)(unsigned)total << 32));
+            old = shfl_u64(old, hl);
+            if (heavy) {
+                const uint32_t idx = hq_base + (uint32_t)old + lanes_below(hm);
+                if (idx < hq.cap) {
+                    hq.pos[idx] = (int32_t)p;
+                    hq.seg[idx] = (int32_t)(old >> 32) + (incl - ns);
+                    hq.cnt[idx] = 0;
+                } else {
+                    atomicOr(err, ERR_QUEUE_CAP);
+                }
+            }
+        }
+    }
+    n = 0;
+}
+
+// Stage w (degree deg) for every lane with pred; flushes once 64 or more are
+// waiting.  n is the wavefront-uniform fill count.  The wavefront must be
+// converged.
+__device__ __forceinline__ void stage_push(bool pred, int32_t w, int32_t deg, Stage &st, int &n, Ctl *c, int32_t *q,
+                                           uint32_t qbase, uint32_t qcap, const HeavyQ &hq, uint32_t hq_base,
+                                           int32_t *err) {
+    const unsigned long long m = __ballot(pred);
+    if (m == 0) return;
+    if (pred) {
+        const int pos = n + (int)lanes_below(m);
+        st.w[pos] = w;
+        st.deg[pos] = deg;
+    }
+    n += __popcll(m);
+    if (n >= kWave) stage_flush(st, n, c, q, qbase, qcap, hq, hq_base, err);
+}
+
+// Largest h in [h0, h1) with seg[h] <= t (seg ascending, seg[h0] = 0 <= t).
+__device__ __forceinline__ int seg_owner(const int32_t *seg, int h0, int h1, int t) {
+    int lo = h0, hi = h1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (seg[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// First index i in [0, n) with a[i] >= x (a ascending).
+__device__ __forceinline__ int lower_bound_i32(const int32_t *a, int n, int x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // Block-wide sum of one unsigned 64-bit value per thread; result valid in
 // thread 0.  Uses the caller's shared scratch of kWavesPerBlock entries.
 __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long x, unsigned long long *sh) {
@@ -109,7 +371,7 @@ __device__ __forceinline__ int heuristic_variant(const PolicyArgs &p, int prev, 
 // Choose the variant of the next level.  Called by every thread of one
 // workgroup (the MLP spreads its hidden units over threads); the result is
 // returned to every thread.  lds needs 2 * kMlpH + 4 floats.
-__device__ int choose_variant(const PolicyArgs &p, int policy, int prev, const LevelFeatures &f, float n,
+__device__ __forceinline__ int choose_variant(const PolicyArgs &p, int policy, int prev, const LevelFeatures &f, float n,
                               float nnz, float *lds) {
     if (policy == POL_FORCE_TPV) return V_PUSH_TPV;
     if (policy == POL_FORCE_WPV) return V_PUSH_WPV;

@@ -11,7 +11,24 @@ constexpr int kBlock = 256;  // threads per workgroup of every step kernel
 constexpr int kWave = 64;    // CDNA wavefront width
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kLanes = 64;   // sources per batch = wavefront lanes
-constexpr int kLightDeg = 64;  // per-vertex reductions: thread (<=) vs wavefront (>)
+constexpr int kLightDeg = 32;  // thread-per-vertex loops handle up to this many arcs
+constexpr int kSeg = 1024;     // heavy vertices (degree > kSeg) are split into kSeg-arc segments
+constexpr int kPhases = 9;
+constexpr int kSlots = 32;     // per-step counters and arrivals are spread over this many slots
+
+// Counters every step kernel accumulates per workgroup into its slot.
+enum : int {
+    SC_EDGES = 0,  // arcs of newly appended vertices (sum)
+    SC_ARCS,       // adjacency entries scanned (sum)
+    SC_LARCS,      // (arc, source) pairs on shortest-path DAGs (sum)
+    SC_FULLN,      // vertices newly visited in every lane (sum)
+    SC_FULLM,      // their arcs (sum)
+    SC_ACT,        // lanes present in the new level (or)
+    SC_OVF,        // lanes / sources whose path counts overflowed (or)
+    SC_MAXE,       // max binary exponent + 4096 (max)
+    SC_MINE,       // 4096 - min binary exponent (max)
+    kNCnt
+};
 
 // Phases of the device-resident state machine.  One launch of a step kernel
 // performs the work of the current phase; the last workgroup to finish moves
@@ -75,9 +92,17 @@ struct Ctl {
     int64_t dump_pos;     // source position to dump (-1 = none)
     int32_t dump_lane;    // batched: lane of the dumped source in its batch
     int32_t dump_state;   // 0 = pending, 1 = forward dumped, 2 = done
+    // --- heavy entries of the level under construction: count | segments << 32
+    unsigned long long next_hq;
+    // --- per-slot counters and workgroup arrivals of the running step
+    unsigned long long slot[kSlots][kNCnt];
+    uint32_t arrive[kSlots];
     // --- statistics
     unsigned long long st_steps, st_fwd_levels, st_var[3], st_arcs, st_lane_arcs, st_qentries,
         st_max_levels, st_batches;
+    unsigned long long last_tick;            // wall clock at the end of the previous step
+    unsigned long long st_ticks[kPhases];    // wall-clock ticks spent per phase
+    unsigned long long st_vticks[3];         // forward (discover) ticks per variant
 };
 
 enum : int32_t { ERR_QUEUE_CAP = 1, ERR_SIGMA_RANGE = 2, ERR_LEVEL_CAP = 4, ERR_OVF_CAP = 8 };
@@ -89,6 +114,26 @@ struct GraphArgs {
     const int32_t *row_ptr; // int32[n+1]
     const int32_t *col;     // int32[nnz]
     int64_t nonisolated;    // vertices with degree >= 1
+    // vertices of degree > kSeg in ascending order, and the exclusive prefix
+    // sum of their segment counts (hv_seg[n_heavy] = all segments)
+    const int32_t *hv_vtx;
+    const int32_t *hv_seg;
+    int32_t n_heavy;
+};
+
+// Heavy entries of the level queues (vertices of degree > kSeg), per level:
+// entries hq_off[l] .. hq_off[l+1]; hq_seg holds each entry's first segment
+// relative to its level, hq_nseg[l] the level's segment count.
+struct HeavyQ {
+    int32_t *pos;            // queue position of the entry
+    int32_t *seg;            // first segment (relative to the level)
+    int32_t *cnt;            // arrival counter of the entry's segments
+    int32_t *off;            // [max_levels + 2]
+    int32_t *nseg;           // [max_levels + 2]
+    uint32_t cap;
+    unsigned long long *part_lo;  // [segments][lanes] partial sums
+    unsigned long long *part_hi;
+    uint32_t part_cap;       // segments the partial buffers hold
 };
 
 struct PolicyArgs {
@@ -118,6 +163,7 @@ struct PlainArgs {
     unsigned long long *dump_sig;
     double *dump_delta;
     int32_t *dump_shift;     // per-level shifts of the dumped source
+    HeavyQ hq;
 };
 
 // Tagged frontier word: lanes of vertex v that sit on level (tag - epoch).
@@ -147,7 +193,7 @@ struct BatchArgs {
     unsigned long long *sig;     // [n][64] uint64 / FP64 bits; delta after the backward
     double *chat;                // [n][64]
     int32_t *shift;              // [max_levels + 2][64] (mode 1)
-    int32_t *maxexp;             // [64] (mode 1)
+    int32_t *maxexp;             // [128]: per-lane max (0..63) and min (64..127) exponents (mode 1)
     double *bc;                  // [n]
     const int32_t *srcs;         // source list of this run
     const int64_t *batch_start;  // [n_batches + 1] positions into srcs
@@ -161,6 +207,7 @@ struct BatchArgs {
     unsigned long long *dump_sig;
     double *dump_delta;
     int32_t *dump_shift;         // [max_levels + 2]
+    HeavyQ hq;
 };
 
 }  // namespace bcx

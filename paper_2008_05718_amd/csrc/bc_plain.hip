@@ -19,8 +19,10 @@
 //
 // Backward (both modes): delta(v) = sigma(v) * sum over successors w of
 // c(w), c(w) = (1 + delta(w)) / sigma(w) -- Eq. 2 with sigma(v) factored
-// out.  Each vertex is written by one thread (or one wavefront for degree >
-// kLightDeg); no floating-point atomics, so results are bitwise reproducible.
+// out.  Each vertex's sum is formed by one thread (degree <= kLightDeg), one
+// wavefront (<= kSeg) or kSeg-arc segments combined in segment order by the
+// last segment to finish; no floating-point atomics, so results are bitwise
+// reproducible.
 #include "bc_common.h"
 
 namespace bcx {
@@ -31,9 +33,84 @@ __device__ __forceinline__ double norm_sigma(const PlainArgs &a, int v, int sh) 
     return ldexp(as_f64(a.sig[v]), -sh);
 }
 
+// Top-down over arcs [a0, a1) of frontier vertex v (path count sv): claim
+// unvisited neighbours, add sv to the neighbours on level l+1 (MODE 0).
+template <int MODE>
+__device__ __forceinline__ void plain_push_arcs(const PlainArgs &a, int l, unsigned long long sv, int a0, int a1,
+                                                uint32_t qe, uint32_t hqb, unsigned long long &my_edges,
+                                                unsigned long long &my_larcs, int &my_ovf, Stage &st, int &sn) {
+    const int32_t *__restrict__ rp = a.g.row_ptr;
+    const int32_t *__restrict__ col = a.g.col;
+    Ctl *c = a.ctl;
+    for (int eb = a0; eb < a1; eb += kWave) {
+        const int e = eb + lane_id();
+        bool newly = false;
+        int w = 0, dw = 0;
+        if (e < a1) {
+            w = col[e];
+            int dv = a.d[w];
+            if (dv == -1) {
+                const int old = atomicCAS(&a.d[w], -1, l + 1);
+                newly = (old == -1);
+                dv = newly ? l + 1 : old;
+            }
+            if (MODE == 0 && dv == l + 1) {
+                const unsigned long long old = atomicAdd(&a.sig[w], sv);
+                const unsigned long long nv = old + sv;
+                if (nv < old || nv > a.sigma_limit) my_ovf = 1;
+                ++my_larcs;
+            }
+            if (newly) {
+                dw = rp[w + 1] - rp[w];
+                my_edges += (unsigned)dw;
+            }
+        }
+        stage_push(newly, w, dw, st, sn, c, a.queue, qe, (uint32_t)a.g.n, a.hq, hqb, &c->err);
+    }
+}
+
+// Sum over arcs [a0, a1) of the values of neighbours u with d[u] == want:
+// sigma (normalised by 2^-sh, MODE 1) or c.  Lane-strided, then a fixed
+// butterfly: every lane returns the same bits.
+__device__ __forceinline__ double plain_wave_sum(const PlainArgs &a, int a0, int a1, int want, bool use_chat, int sh,
+                                                 unsigned long long &my_larcs) {
+    const int32_t *__restrict__ col = a.g.col;
+    double p = 0.0;
+    for (int e = a0 + lane_id(); e < a1; e += kWave) {
+        const int u = col[e];
+        if (a.d[u] == want) {
+            p += use_chat ? a.chat[u] : ldexp(as_f64(a.sig[u]), -sh);
+            ++my_larcs;
+        }
+    }
+    return wave_sum_f64(p);
+}
+
+__device__ __forceinline__ bool plain_seg_arrive(int32_t *cnt, int nseg) {
+    __threadfence();
+    int old = 0;
+    if (lane_id() == 0) old = atomicAdd(cnt, 1);
+    old = __shfl(old, 0);
+    const bool last = (old == nseg - 1);
+    if (last) __threadfence();
+    return last;
+}
+
+// Exact 128-bit wavefront sum of (lo, hi) pairs; every lane gets the total.
+__device__ __forceinline__ void wave_sum_u128(unsigned long long &lo, unsigned long long &hi) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long ol = shfl_u64(lo, lane ^ o), oh = shfl_u64(hi, lane ^ o);
+        const unsigned long long nl = lo + ol;
+        hi = hi + oh + ((nl < lo) ? 1ull : 0ull);
+        lo = nl;
+    }
+}
+
 // Transition helpers run by the last workgroup (all threads present).
 template <int MODE>
-__device__ void plain_begin_source(PlainArgs &a, Ctl *c, int64_t pos, float *lds, LevelFeatures *sf) {
+__device__ __forceinline__ void plain_begin_source(const PlainArgs &a, Ctl *c, int64_t pos, float *lds, LevelFeatures *sf) {
     if (threadIdx.x == 0) {
         const int s = a.srcs[pos];
         a.d[s] = 0;
@@ -43,6 +120,18 @@ __device__ void plain_begin_source(PlainArgs &a, Ctl *c, int64_t pos, float *lds
         a.level_off[1] = 1;
         a.shift[0] = 0;
         const int deg = a.g.row_ptr[s + 1] - a.g.row_ptr[s];
+        a.hq.off[0] = 0;
+        if (deg > kSeg) {  // heavy source: its level-0 push runs as segments
+            a.hq.pos[0] = 0;
+            a.hq.seg[0] = 0;
+            a.hq.cnt[0] = 0;
+            a.hq.off[1] = 1;
+            a.hq.nseg[0] = n_segments(deg);
+        } else {
+            a.hq.off[1] = 0;
+            a.hq.nseg[0] = 0;
+        }
+        c->next_hq = 0;
         c->pos = pos;
         c->level = 0;
         c->overflow = 0;
@@ -64,7 +153,7 @@ __device__ void plain_begin_source(PlainArgs &a, Ctl *c, int64_t pos, float *lds
 }
 
 template <int MODE>
-__device__ void plain_advance_level(PlainArgs &a, Ctl *c, int l, uint32_t cnt, unsigned long long edges,
+__device__ __forceinline__ void plain_advance_level(const PlainArgs &a, Ctl *c, int l, uint32_t cnt, unsigned long long edges,
                                     float *lds, LevelFeatures *sf) {
     if (threadIdx.x == 0) {
         c->level = l + 1;
@@ -86,7 +175,7 @@ __device__ void plain_advance_level(PlainArgs &a, Ctl *c, int l, uint32_t cnt, u
 }
 
 // After the forward of the current source ended with L levels.
-__device__ __forceinline__ void plain_after_forward(PlainArgs &a, Ctl *c, int L) {
+__device__ __forceinline__ void plain_after_forward(const PlainArgs &a, Ctl *c, int L) {
     c->n_levels = L;
     if ((unsigned long long)L > c->st_max_levels) c->st_max_levels = L;
     if (c->dump_pos == c->pos && c->dump_state == 0) {
@@ -102,7 +191,11 @@ __device__ __forceinline__ void plain_after_forward(PlainArgs &a, Ctl *c, int L)
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
     __shared__ int s_phase, s_level, s_variant, s_last, s_qb, s_qe, s_qn, s_sh0, s_sh1, s_dump;
-    __shared__ unsigned long long s_red[kWavesPerBlock];
+    __shared__ int s_h0, s_h1, s_hseg, s_hqb;
+    __shared__ unsigned s_nblk;
+    __shared__ unsigned long long s_red[kSlots * kNCnt];
+    __shared__ unsigned long long s_tot[kNCnt];
+    __shared__ Stage s_stage[kWavesPerBlock];
     __shared__ float s_lds[2 * kMlpH + 4];
     __shared__ LevelFeatures s_feat;
     Ctl *c = a.ctl;
@@ -113,6 +206,8 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
         s_variant = c->variant;
         s_dump = (c->dump_pos == c->pos && c->dump_state == 1) ? 1 : 0;
         const int l = s_level;
+        s_qb = s_qe = s_qn = s_sh0 = s_sh1 = 0;
+        s_h0 = s_h1 = s_hseg = s_hqb = 0;
         if (s_phase == PH_FWD || s_phase == PH_SIG || s_phase == PH_BWD) {
             s_qb = a.level_off[l];
             s_qe = a.level_off[l + 1];
@@ -120,102 +215,195 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
             s_sh0 = MODE ? a.shift[l] : 0;
             s_sh1 = (MODE && s_phase == PH_BWD && l + 1 < c->n_levels) ? a.shift[l + 1] : 0;
         } else if (s_phase == PH_FIN) {
-            s_qb = 0;
             s_qe = (int)c->total_queued;
-            s_qn = 0;
-            s_sh0 = s_sh1 = 0;
-        } else {
-            s_qb = s_qe = s_qn = s_sh0 = s_sh1 = 0;
         }
+        if (s_phase == PH_FWD) {
+            if (s_variant == V_PULL) {  // static heavy vertices
+                s_h0 = 0;
+                s_h1 = a.g.n_heavy;
+                s_hseg = a.g.hv_seg[a.g.n_heavy];
+            } else {                    // heavy frontier vertices of level l
+                s_h0 = a.hq.off[l];
+                s_h1 = a.hq.off[l + 1];
+                s_hseg = a.hq.nseg[l];
+            }
+            s_hqb = a.hq.off[l + 1];
+        } else if (s_phase == PH_SIG) {
+            s_h0 = a.hq.off[l + 1];
+            s_h1 = a.hq.off[l + 2];
+            s_hseg = a.hq.nseg[l + 1];
+        } else if (s_phase == PH_BWD) {
+            s_h0 = a.hq.off[l];
+            s_h1 = a.hq.off[l + 1];
+            s_hseg = a.hq.nseg[l];
+        }
+        // wavefront work items of this step -> workgroups taking part
+        long long items = 1;
+        const int cnt = s_qe - s_qb;
+        if (s_phase == PH_FWD) {
+            if (s_variant == V_PUSH_TPV) items = (cnt + kWave - 1) / kWave + s_hseg;
+            else if (s_variant == V_PUSH_WPV) items = cnt + s_hseg;
+            else items = (a.g.n + kWave - 1) / kWave + s_hseg;
+        } else if (s_phase == PH_SIG) {
+            items = (s_qn - s_qe + kWave - 1) / kWave + s_hseg;
+        } else if (s_phase == PH_BWD) {
+            items = (cnt + kWave - 1) / kWave + s_hseg;
+        } else if (s_phase == PH_FIN) {
+            items = (s_qe + kWave - 1) / kWave;
+        } else if (s_phase == PH_DUMP_FWD) {
+            items = (a.g.n + kWave - 1) / kWave;
+        }
+        s_nblk = active_blocks(items);
     }
     __syncthreads();
     const int phase = s_phase;
     if (phase == PH_DONE || phase == PH_IDLE) return;
+    const unsigned nblk = s_nblk;
+    const bool active = blockIdx.x < nblk;  // workgroups beyond nblk only count in
 
     const int gw = blockIdx.x * kWavesPerBlock + wid;
-    const int nw = gridDim.x * kWavesPerBlock;
+    const int nw = (int)nblk * kWavesPerBlock;
     const int l = s_level;
     const int n = a.g.n;
     const int32_t *__restrict__ rp = a.g.row_ptr;
     const int32_t *__restrict__ col = a.g.col;
     int32_t *d = a.d;
     unsigned long long *sig = a.sig;
+    const int h0 = s_h0, h1 = s_h1, hseg = s_hseg;
 
     unsigned long long my_edges = 0, my_arcs = 0, my_larcs = 0;
     int my_ovf = 0, my_maxe = INT_MIN, my_mine = INT_MAX;
 
-    if (phase == PH_FWD) {
+    if (!active) {
+    } else if (phase == PH_FWD) {
         const int qb = s_qb, qe = s_qe, cnt = qe - qb;
         const int variant = s_variant;
-        const uint32_t cap = (uint32_t)(n - qe);
-        int32_t *nq = a.queue + qe;
-        if (variant == V_PUSH_TPV) {
-            for (int base = gw * kWave; base < cnt; base += nw * kWave) {
-                const int i = base + lane;
-                const bool valid = i < cnt;
-                const int v = valid ? a.queue[qb + i] : 0;
-                const int e0 = valid ? rp[v] : 0;
-                const int len = valid ? rp[v + 1] - e0 : 0;
-                const unsigned long long sv = (MODE == 0 && valid) ? sig[v] : 0ull;
-                my_arcs += (unsigned)len;
-                const int maxlen = wave_max_i(len);
-                for (int t = 0; t < maxlen; ++t) {
-                    bool newly = false;
-                    int w = 0;
-                    if (t < len) {
-                        w = col[e0 + t];
-                        int dw = d[w];
-                        if (dw == -1) {
-                            const int old = atomicCAS(&d[w], -1, l + 1);
-                            newly = (old == -1);
-                            dw = newly ? l + 1 : old;
+        const uint32_t hqb = (uint32_t)s_hqb;
+        Stage &st = s_stage[wid];
+        int sn = 0;
+        if (variant == V_PUSH_TPV || variant == V_PUSH_WPV) {
+            const int n_light = variant == V_PUSH_TPV ? (cnt + kWave - 1) / kWave : cnt;
+            const int total = n_light + hseg;
+            for (int it = gw; it < total; it += nw) {
+                if (it >= n_light) {  // a segment of a heavy frontier vertex
+                    const int t = it - n_light;
+                    const int h = seg_owner(a.hq.seg, h0, h1, t);
+                    const int s = t - a.hq.seg[h];
+                    const int v = a.queue[a.hq.pos[h]];
+                    const int a0 = rp[v] + s * kSeg, a1 = min(rp[v + 1], a0 + kSeg);
+                    if (lane == 0) my_arcs += (unsigned)(a1 - a0);
+                    const unsigned long long sv = MODE == 0 ? sig[v] : 0ull;
+                    plain_push_arcs<MODE>(a, l, sv, a0, a1, (uint32_t)qe, hqb, my_edges, my_larcs, my_ovf, st, sn);
+                } else if (variant == V_PUSH_WPV) {
+                    const int v = a.queue[qb + it];
+                    const int e0 = rp[v], e1 = rp[v + 1];
+                    if (e1 - e0 > kSeg) continue;  // runs as segments
+                    if (lane == 0) my_arcs += (unsigned)(e1 - e0);
+                    const unsigned long long sv = MODE == 0 ? sig[v] : 0ull;
+                    plain_push_arcs<MODE>(a, l, sv, e0, e1, (uint32_t)qe, hqb, my_edges, my_larcs, my_ovf, st, sn);
+                } else {  // TPV: 64 frontier vertices per wavefront
+                    const int i = it * kWave + lane;
+                    const bool valid = i < cnt;
+                    const int v = valid ? a.queue[qb + i] : 0;
+                    const int e0 = valid ? rp[v] : 0;
+                    const int deg = valid ? rp[v + 1] - e0 : 0;
+                    const int len = deg <= kLightDeg ? deg : 0;
+                    const unsigned long long sv = (MODE == 0 && valid) ? sig[v] : 0ull;
+                    my_arcs += (unsigned)(deg <= kSeg ? deg : 0);
+                    const int maxlen = wave_max_i(len);
+                    for (int t = 0; t < maxlen; ++t) {
+                        bool newly = false;
+                        int w = 0, dw = 0;
+                        if (t < len) {
+                            w = col[e0 + t];
+                            int dv = d[w];
+                            if (dv == -1) {
+                                const int old = atomicCAS(&d[w], -1, l + 1);
+                                newly = (old == -1);
+                                dv = newly ? l + 1 : old;
+                            }
+                            if (MODE == 0 && dv == l + 1) {
+                                const unsigned long long old = atomicAdd(&sig[w], sv);
+                                const unsigned long long nv = old + sv;
+                                if (nv < old || nv > a.sigma_limit) my_ovf = 1;
+                                ++my_larcs;
+                            }
+                            if (newly) {
+                                dw = rp[w + 1] - rp[w];
+                                my_edges += (unsigned)dw;
+                            }
                         }
-                        if (MODE == 0 && dw == l + 1) {
-                            const unsigned long long old = atomicAdd(&sig[w], sv);
-                            const unsigned long long nv = old + sv;
-                            if (nv < old || nv > a.sigma_limit) my_ovf = 1;
-                            ++my_larcs;
-                        }
-                        if (newly) my_edges += (unsigned)(rp[w + 1] - rp[w]);
+                        stage_push(newly, w, dw, st, sn, c, a.queue, (uint32_t)qe, (uint32_t)n, a.hq, hqb, &c->err);
                     }
-                    wave_append(newly, w, &c->next_count, nq, cap, &c->err);
-                }
-            }
-        } else if (variant == V_PUSH_WPV) {
-            for (int i = gw; i < cnt; i += nw) {
-                const int v = a.queue[qb + i];
-                const int e0 = rp[v], e1 = rp[v + 1];
-                const unsigned long long sv = MODE == 0 ? sig[v] : 0ull;
-                if (lane == 0) my_arcs += (unsigned)(e1 - e0);
-                for (int eb = e0; eb < e1; eb += kWave) {
-                    const int e = eb + lane;
-                    bool newly = false;
-                    int w = 0;
-                    if (e < e1) {
-                        w = col[e];
-                        int dw = d[w];
-                        if (dw == -1) {
-                            const int old = atomicCAS(&d[w], -1, l + 1);
-                            newly = (old == -1);
-                            dw = newly ? l + 1 : old;
-                        }
-                        if (MODE == 0 && dw == l + 1) {
-                            const unsigned long long old = atomicAdd(&sig[w], sv);
-                            const unsigned long long nv = old + sv;
-                            if (nv < old || nv > a.sigma_limit) my_ovf = 1;
-                            ++my_larcs;
-                        }
-                        if (newly) my_edges += (unsigned)(rp[w + 1] - rp[w]);
+                    // medium-degree vertices: the whole wavefront, one at a time
+                    unsigned long long mm = __ballot(deg > kLightDeg && deg <= kSeg);
+                    while (mm) {
+                        const int j = __ffsll(mm) - 1;
+                        mm &= mm - 1;
+                        const int m0 = __shfl(e0, j), m1 = m0 + __shfl(deg, j);
+                        plain_push_arcs<MODE>(a, l, shfl_u64(sv, j), m0, m1, (uint32_t)qe, hqb, my_edges, my_larcs,
+                                              my_ovf, st, sn);
                     }
-                    wave_append(newly, w, &c->next_count, nq, cap, &c->err);
                 }
             }
         } else {  // V_PULL: every unvisited vertex looks for neighbours on level l
-            for (int base = gw * kWave; base < n; base += nw * kWave) {
-                const int w = base + lane;
+            const int n_light = (n + kWave - 1) / kWave;
+            const int total = n_light + hseg;
+            for (int it = gw; it < total; it += nw) {
+                if (it >= n_light) {  // a segment of a heavy vertex
+                    const int t = it - n_light;
+                    const int h = seg_owner(a.g.hv_seg, h0, h1, t);
+                    const int s = t - a.g.hv_seg[h];
+                    const int w = a.g.hv_vtx[h];
+                    const int dw0 = d[w];
+                    // unvisited before this level (another segment may have
+                    // claimed it during this step)
+                    if (dw0 != -1 && dw0 != l + 1) continue;
+                    const int a0 = rp[w] + s * kSeg, a1 = min(rp[w + 1], a0 + kSeg);
+                    unsigned long long lo = 0, hi = 0;
+                    bool found = false;
+                    int scanned = 0;
+                    for (int eb = a0; eb < a1; eb += kWave) {
+                        const int e = eb + lane;
+                        if (e < a1) {
+                            const int u = col[e];
+                            if (d[u] == l) {
+                                found = true;
+                                if (MODE == 0) {
+                                    const unsigned long long x = sig[u];
+                                    lo += x;
+                                    hi += (lo < x) ? 1ull : 0ull;
+                                    ++my_larcs;
+                                }
+                            }
+                        }
+                        scanned += min(kWave, a1 - eb);
+                        if (MODE == 1 && __any(found)) break;
+                    }
+                    if (lane == 0) my_arcs += (unsigned)scanned;
+                    const bool any = __any(found);
+                    bool newly = false;
+                    if (any) {
+                        if (MODE == 0) {  // exact 128-bit sum of the segment, one atomic
+                            wave_sum_u128(lo, hi);
+                            if (lane == 0) {
+                                const unsigned long long old = atomicAdd(&sig[w], lo);
+                                const unsigned long long nv = old + lo;
+                                if (hi != 0 || nv < old || nv > a.sigma_limit) my_ovf = 1;
+                            }
+                        }
+                        if (lane == 0) newly = atomicCAS(&d[w], -1, l + 1) == -1;
+                    }
+                    const int deg = rp[w + 1] - rp[w];
+                    if (newly) my_edges += (unsigned)deg;
+                    stage_push(newly, w, deg, st, sn, c, a.queue, (uint32_t)qe, (uint32_t)n, a.hq, hqb, &c->err);
+                    continue;
+                }
+                const int w = it * kWave + lane;
                 const bool cand = (w < n) && d[w] == -1;
                 const int e0 = cand ? rp[w] : 0;
-                const int len = cand ? rp[w + 1] - e0 : 0;
+                const int deg = cand ? rp[w + 1] - e0 : 0;
+                const int len = deg <= kLightDeg ? deg : 0;
                 const int maxlen = wave_max_i(len);
                 unsigned long long lo = 0, hi = 0;
                 bool found = false;
@@ -227,9 +415,9 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
                         const int u = col[e0 + t];
                         if (d[u] == l) {
                             if (MODE == 0) {
-                                const unsigned long long s = sig[u];
-                                lo += s;
-                                hi += (lo < s) ? 1ull : 0ull;
+                                const unsigned long long x = sig[u];
+                                lo += x;
+                                hi += (lo < x) ? 1ull : 0ull;
                                 ++my_larcs;
                             }
                             found = true;
@@ -237,53 +425,112 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
                     }
                     if (MODE == 1 && !__any(t + 1 < len && !found)) break;
                 }
+                // medium-degree candidates: the whole wavefront, one at a time
+                unsigned long long mm = __ballot(deg > kLightDeg && deg <= kSeg);
+                while (mm) {
+                    const int j = __ffsll(mm) - 1;
+                    mm &= mm - 1;
+                    const int m0 = __shfl(e0, j), m1 = m0 + __shfl(deg, j);
+                    unsigned long long ml = 0, mh = 0;
+                    bool mf = false;
+                    for (int eb = m0; eb < m1; eb += kWave) {
+                        const int e = eb + lane;
+                        if (e < m1) {
+                            const int u = col[e];
+                            if (d[u] == l) {
+                                mf = true;
+                                if (MODE == 0) {
+                                    const unsigned long long x = sig[u];
+                                    ml += x;
+                                    mh += (ml < x) ? 1ull : 0ull;
+                                    ++my_larcs;
+                                }
+                            }
+                        }
+                        if (lane == 0) scanned += min(kWave, m1 - eb);
+                        if (MODE == 1 && __any(mf)) break;
+                    }
+                    const bool fj = __any(mf);
+                    if (MODE == 0) wave_sum_u128(ml, mh);
+                    if (lane == j) {
+                        found = fj;
+                        lo = ml;
+                        hi = mh;
+                    }
+                }
                 my_arcs += (unsigned)scanned;
-                if (found) {
+                const bool ok = found && deg <= kSeg;
+                if (ok) {
                     d[w] = l + 1;
                     if (MODE == 0) {
                         sig[w] = lo;
                         if (hi != 0 || lo > a.sigma_limit) my_ovf = 1;
                     }
-                    my_edges += (unsigned)len;
+                    my_edges += (unsigned)deg;
                 }
-                wave_append(found, w, &c->next_count, nq, cap, &c->err);
+                stage_push(ok, w, deg, st, sn, c, a.queue, (uint32_t)qe, (uint32_t)n, a.hq, hqb, &c->err);
             }
         }
+        stage_flush(st, sn, c, a.queue, (uint32_t)qe, (uint32_t)n, a.hq, hqb, &c->err);
     } else if (MODE == 1 && phase == PH_SIG) {
-        // FP64 path counts of level l+1, pulled in CSR order.
+        // FP64 path counts of level l+1, pulled in CSR order
         const int qs = s_qe, cnt = s_qn - s_qe;
         const int sh = s_sh0;
-        for (int base = gw * kWave; base < cnt; base += nw * kWave) {
-            const int i = base + lane;
+        const int n_light = (cnt + kWave - 1) / kWave;
+        const int total = n_light + hseg;
+        for (int it = gw; it < total; it += nw) {
+            if (it >= n_light) {  // a segment of a heavy new vertex
+                const int t = it - n_light;
+                const int h = seg_owner(a.hq.seg, h0, h1, t);
+                const int s = t - a.hq.seg[h];
+                const int w = a.queue[a.hq.pos[h]];
+                const int e0 = rp[w], e1 = rp[w + 1];
+                const int a0 = e0 + s * kSeg, a1 = min(e1, a0 + kSeg);
+                const double p = plain_wave_sum(a, a0, a1, l, false, sh, my_larcs);
+                if (lane == 0) {
+                    my_arcs += (unsigned)(a1 - a0);
+                    a.hq.part_lo[a.hq.seg[h] + s] = as_u64(p);
+                }
+                const int ns = n_segments(e1 - e0);
+                if (!plain_seg_arrive(&a.hq.cnt[h], ns)) continue;
+                if (lane == 0) {
+                    double acc = 0.0;
+                    for (int k = 0; k < ns; ++k) acc += as_f64(a.hq.part_lo[a.hq.seg[h] + k]);
+                    sig[w] = as_u64(acc);
+                    if (acc > 0.0) {
+                        int ex;
+                        frexp(acc, &ex);
+                        my_maxe = max(my_maxe, ex);
+                        my_mine = min(my_mine, ex);
+                    }
+                    a.hq.cnt[h] = 0;
+                }
+                continue;
+            }
+            const int i = it * kWave + lane;
             const bool valid = i < cnt;
             const int w = valid ? a.queue[qs + i] : 0;
             const int e0 = valid ? rp[w] : 0;
-            const int len = valid ? rp[w + 1] - e0 : 0;
-            const bool heavy = len > kLightDeg;
-            const int llen = heavy ? 0 : len;
-            const int maxlen = wave_max_i(llen);
+            const int deg = valid ? rp[w + 1] - e0 : 0;
+            const int len = deg <= kLightDeg ? deg : 0;
+            const int maxlen = wave_max_i(len);
             double acc = 0.0;
             for (int t = 0; t < maxlen; ++t) {
-                if (t < llen) {
+                if (t < len) {
                     const int u = col[e0 + t];
                     if (d[u] == l) { acc += ldexp(as_f64(sig[u]), -sh); ++my_larcs; }
                 }
             }
-            my_arcs += (unsigned)len;
-            unsigned long long hm = __ballot(heavy);
-            while (hm) {
-                const int j = __ffsll(hm) - 1;
-                hm &= hm - 1;
-                const int h0 = __shfl(e0, j), h1 = h0 + __shfl(len, j);
-                double p = 0.0;
-                for (int e = h0 + lane; e < h1; e += kWave) {
-                    const int u = col[e];
-                    if (d[u] == l) { p += ldexp(as_f64(sig[u]), -sh); ++my_larcs; }
-                }
-                p = wave_sum_f64(p);
+            my_arcs += (unsigned)(deg <= kSeg ? deg : 0);
+            unsigned long long mm = __ballot(deg > kLightDeg && deg <= kSeg);
+            while (mm) {
+                const int j = __ffsll(mm) - 1;
+                mm &= mm - 1;
+                const int m0 = __shfl(e0, j), m1 = m0 + __shfl(deg, j);
+                const double p = plain_wave_sum(a, m0, m1, l, false, sh, my_larcs);
                 if (lane == j) acc = p;
             }
-            if (valid) {
+            if (valid && deg <= kSeg) {
                 sig[w] = as_u64(acc);
                 if (acc > 0.0) {
                     int ex;
@@ -297,37 +544,60 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
         const int qb = s_qb, cnt = s_qe - s_qb;
         const int sh = s_sh0, shn = s_sh1;
         const bool dump = s_dump != 0;
-        for (int base = gw * kWave; base < cnt; base += nw * kWave) {
-            const int i = base + lane;
+        const int n_light = (cnt + kWave - 1) / kWave;
+        const int total = n_light + hseg;
+        for (int it = gw; it < total; it += nw) {
+            if (it >= n_light) {  // a segment of a heavy vertex of level l
+                const int t = it - n_light;
+                const int h = seg_owner(a.hq.seg, h0, h1, t);
+                const int s = t - a.hq.seg[h];
+                const int v = a.queue[a.hq.pos[h]];
+                const int e0 = rp[v], e1 = rp[v + 1];
+                const int a0 = e0 + s * kSeg, a1 = min(e1, a0 + kSeg);
+                const double p = plain_wave_sum(a, a0, a1, l + 1, true, 0, my_larcs);
+                if (lane == 0) {
+                    my_arcs += (unsigned)(a1 - a0);
+                    a.hq.part_lo[a.hq.seg[h] + s] = as_u64(p);
+                }
+                const int ns = n_segments(e1 - e0);
+                if (!plain_seg_arrive(&a.hq.cnt[h], ns)) continue;
+                if (lane == 0) {
+                    double acc = 0.0;
+                    for (int k = 0; k < ns; ++k) acc += as_f64(a.hq.part_lo[a.hq.seg[h] + k]);
+                    const double sv = norm_sigma<MODE>(a, v, sh);
+                    double delta = sv * acc;
+                    if (MODE == 1) delta = ldexp(delta, -shn);
+                    a.chat[v] = (1.0 + delta) / sv;
+                    a.bc[v] += delta;
+                    if (dump) a.dump_delta[v] = delta;
+                    a.hq.cnt[h] = 0;
+                }
+                continue;
+            }
+            const int i = it * kWave + lane;
             const bool valid = i < cnt;
             const int v = valid ? a.queue[qb + i] : 0;
             const int e0 = valid ? rp[v] : 0;
-            const int len = valid ? rp[v + 1] - e0 : 0;
-            const bool heavy = len > kLightDeg;
-            const int llen = heavy ? 0 : len;
-            const int maxlen = wave_max_i(llen);
+            const int deg = valid ? rp[v + 1] - e0 : 0;
+            const int len = deg <= kLightDeg ? deg : 0;
+            const int maxlen = wave_max_i(len);
             double acc = 0.0;
             for (int t = 0; t < maxlen; ++t) {
-                if (t < llen) {
+                if (t < len) {
                     const int w = col[e0 + t];
                     if (d[w] == l + 1) { acc += a.chat[w]; ++my_larcs; }
                 }
             }
-            my_arcs += (unsigned)len;
-            unsigned long long hm = __ballot(heavy);
-            while (hm) {
-                const int j = __ffsll(hm) - 1;
-                hm &= hm - 1;
-                const int h0 = __shfl(e0, j), h1 = h0 + __shfl(len, j);
-                double p = 0.0;
-                for (int e = h0 + lane; e < h1; e += kWave) {
-                    const int w = col[e];
-                    if (d[w] == l + 1) { p += a.chat[w]; ++my_larcs; }
-                }
-                p = wave_sum_f64(p);
+            my_arcs += (unsigned)(deg <= kSeg ? deg : 0);
+            unsigned long long mm = __ballot(deg > kLightDeg && deg <= kSeg);
+            while (mm) {
+                const int j = __ffsll(mm) - 1;
+                mm &= mm - 1;
+                const int m0 = __shfl(e0, j), m1 = m0 + __shfl(deg, j);
+                const double p = plain_wave_sum(a, m0, m1, l + 1, true, 0, my_larcs);
                 if (lane == j) acc = p;
             }
-            if (valid) {
+            if (valid && deg <= kSeg) {
                 const double sv = norm_sigma<MODE>(a, v, sh);
                 double delta = sv * acc;
                 if (MODE == 1) delta = ldexp(delta, -shn);
@@ -338,13 +608,13 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
         }
     } else if (phase == PH_FIN) {
         const int total = s_qe;
-        for (int i = blockIdx.x * kBlock + tid; i < total; i += gridDim.x * kBlock) {
+        for (int i = blockIdx.x * kBlock + tid; i < total; i += (int)nblk * kBlock) {
             const int v = a.queue[i];
             d[v] = -1;
             sig[v] = 0ull;
         }
     } else if (phase == PH_DUMP_FWD) {
-        for (int v = blockIdx.x * kBlock + tid; v < n; v += gridDim.x * kBlock) {
+        for (int v = blockIdx.x * kBlock + tid; v < n; v += (int)nblk * kBlock) {
             a.dump_d[v] = d[v];
             a.dump_sig[v] = sig[v];
         }
@@ -352,27 +622,16 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
             for (int i = tid; i < c->n_levels; i += kBlock) a.dump_shift[i] = MODE ? a.shift[i] : 0;
     }
 
-    // ---- per-launch statistics and level counters
-    {
-        const unsigned long long e = block_sum_u64(my_edges, s_red);
-        if (tid == 0 && e) atomicAdd(&c->next_edges, e);
-        const unsigned long long ar = block_sum_u64(my_arcs, s_red);
-        if (tid == 0 && ar) atomicAdd(&c->st_arcs, ar);
-        const unsigned long long la = block_sum_u64(my_larcs, s_red);
-        if (tid == 0 && la) atomicAdd(&c->st_lane_arcs, la);
-        if (MODE == 0 && phase == PH_FWD) {
-            if (__any(my_ovf) && lane == 0) atomicOr(&c->overflow, 1);
-        }
-        if (MODE == 1 && phase == PH_SIG) {
-            const int mx = wave_max_i(my_maxe), mn = wave_min_i(my_mine);
-            if (lane == 0) {
-                if (mx != INT_MIN) atomicMax(&c->maxexp, mx);
-                if (mn != INT_MAX) atomicMin(&c->minexp, mn);
-            }
-        }
-    }
-
-    if (!last_block_arrive(&c->blocks_done, &s_last)) return;
+    // ---- per-launch counters into the slots; the last workgroup continues
+    Counters cn;
+    cn.v[SC_EDGES] = my_edges;
+    cn.v[SC_ARCS] = my_arcs;
+    cn.v[SC_LARCS] = my_larcs;
+    cn.v[SC_OVF] = my_ovf ? 1ull : 0ull;
+    if (my_maxe != INT_MIN) cn.exponent(my_maxe);
+    if (my_mine != INT_MAX) cn.exponent(my_mine);
+    if (!step_epilogue(c, cn, s_red, &s_last, active)) return;
+    collect_slots(c, s_tot, s_red);
 
     // ---- the last workgroup advances the state machine
     int begin_pos = 0;
@@ -380,16 +639,28 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
     uint32_t cnt_next = 0;
     unsigned long long edges_next = 0;
     if (tid == 0) {
-        c->blocks_done = 0;
         c->st_steps += 1;
+        c->st_arcs += s_tot[SC_ARCS];
+        c->st_lane_arcs += s_tot[SC_LARCS];
+        const unsigned long long now = wall_clock64();
+        if (c->last_tick) {
+            const unsigned long long dt = now - c->last_tick;
+            c->st_ticks[phase] += dt;
+            if (phase == PH_FWD) c->st_vticks[s_variant] += dt;
+        }
+        c->last_tick = now;
         if (phase == PH_FWD) {
             const uint32_t cnt = ld_agent(&c->next_count);
+            const unsigned long long nh = ld_agent(&c->next_hq);
             const int qe = a.level_off[l + 1];
             a.level_off[l + 2] = qe + (int)cnt;
+            a.hq.off[l + 2] = a.hq.off[l + 1] + (int)(uint32_t)nh;
+            a.hq.nseg[l + 1] = (int)(nh >> 32);
+            c->next_hq = 0;
             c->st_fwd_levels += 1;
             c->st_var[s_variant] += 1;
             c->st_qentries += cnt;
-            if (MODE == 0 && ld_agent(&c->overflow)) {
+            if (MODE == 0 && s_tot[SC_OVF]) {
                 const uint32_t k = c->n_ovf;
                 if (k < a.ovf_cap) a.ovf_list[k] = c->pos;
                 else c->err |= ERR_OVF_CAP;
@@ -401,22 +672,22 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
                 plain_after_forward(a, c, l + 1);
             } else if (MODE == 1) {
                 c->phase = PH_SIG;
-                c->maxexp = INT_MIN;
-                c->minexp = INT_MAX;
+                c->next_edges = s_tot[SC_EDGES];  // kept for the level advance after the path counts
             } else {
                 advance = 1;
                 cnt_next = cnt;
-                edges_next = ld_agent(&c->next_edges);
+                edges_next = s_tot[SC_EDGES];
             }
         } else if (phase == PH_SIG) {
-            const int mx = ld_agent(&c->maxexp), mn = ld_agent(&c->minexp);
+            const bool any = s_tot[SC_MAXE] != 0;
+            const int mx = (int)s_tot[SC_MAXE] - 4096, mn = 4096 - (int)s_tot[SC_MINE];
             int sh = 0;
-            if (mx != INT_MIN && mx > 960) sh = mx - 900;
-            if (mn != INT_MAX && mn - sh < -1000) c->err |= ERR_SIGMA_RANGE;
+            if (any && mx > 960) sh = mx - 900;
+            if (any && mn - sh < -1000) c->err |= ERR_SIGMA_RANGE;
             a.shift[l + 1] = sh;
             advance = 1;
             cnt_next = ld_agent(&c->next_count);
-            edges_next = ld_agent(&c->next_edges);
+            edges_next = c->next_edges;
         } else if (phase == PH_BWD) {
             if (l - 1 >= 1) {
                 c->level = l - 1;

@@ -158,9 +158,38 @@ def test_sigma_limit_and_forced_f64(engine):
         np.testing.assert_array_equal(got, o.sigma_u64[r].astype(np.float64))
 
 
+@pytest.mark.parametrize("engine", ENGINES)
+def test_heavy_vertices_segments(engine):
+    # RMAT scale 14: 15 vertices above one 1024-arc segment (max degree 3665);
+    # every policy must split them the same way and give identical bits
+    g = W.rmat(14, 16, seed=1)
+    deg = g.degrees()
+    hubs = np.argsort(-deg)[:3].astype(np.int32)
+    srcs = np.concatenate([hubs, W.choose_sources(g, 90, seed=8)]).astype(np.int32)
+    say(f"[heavy] rmat14 max degree {deg.max()} engine={engine}")
+    ref, _ = oracle.bc(g, srcs)
+    outs = []
+    with b.Graph(g) as G:
+        for pol in (b.BC_POLICY_HEURISTIC, b.BC_POLICY_FORCE_PUSH_TPV, b.BC_POLICY_FORCE_PUSH_WPV,
+                    b.BC_POLICY_FORCE_PULL):
+            G.run(srcs, batch=engine, policy=pol)
+            outs.append(G.scores().copy())
+        assert_bc_close(outs[0], ref)
+        for o in outs[1:]:
+            assert np.array_equal(o.view(np.uint64), outs[0].view(np.uint64))
+        for idx in (0, 1, 50):
+            det = G.detail(srcs, dump_index=idx, batch=engine, policy=b.BC_POLICY_FORCE_PULL)
+            check_detail(g, det, srcs[idx])
+        G.run(srcs[:20], batch=engine, flags=b.BC_RUN_FORCE_F64)
+        r20, _ = oracle.bc(g, srcs[:20])
+        assert_bc_close(G.scores(), r20)
+
+
 def test_multi_graph_union_equals_per_graph():
     gs = [W.barabasi_albert(n, 4, seed=30 + i) for i, n in enumerate([60, 300, 150, 1000, 90])]
     gs.append(W.grid(12, 0.1, 0.0, seed=1))
+    star = _g(2500, [(0, i) for i in range(1, 2500)] + [(i, i + 1) for i in range(1, 2499, 2)])
+    gs.insert(2, star)  # a heavy vertex (degree 2499) inside the union
     u = W.union(gs)
     say("[multi] union of", [x.n for x in gs])
     with b.Graph(u) as G:
