@@ -45,6 +45,7 @@ def main():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2008_05718_amd", "policy_weights.npy"))
     ap.add_argument("--sources", type=int, default=0, help="use only the first N sources (profiling runs)")
     ap.add_argument("--no-graphs", action="store_true", help="launch level steps one by one")
+    ap.add_argument("--grid", type=int, default=0, help="workgroups per step launch (0 = library default)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes 3 times (counter calibration)")
     args = ap.parse_args()
@@ -108,7 +109,8 @@ def main():
 
     # ---- batched (headline)
     gflags = b.BC_RUN_NO_GRAPHS if args.no_graphs else 0
-    wall, gpu_ms, stats = timed(srcs, args.steps, args.warmup, batch=64, policy=pol, flags=gflags)
+    wall, gpu_ms, stats = timed(srcs, args.steps, args.warmup, batch=64, policy=pol, flags=gflags,
+                                grid_blocks=args.grid)
     st = stats[-1]
     ms_step = wall * 1e3 / args.steps
     gteps = g.m * len(srcs) * args.steps / wall / 1e9
@@ -123,6 +125,8 @@ def main():
         f"variants={st['variant_levels']} f64={st['f64_sources']}")
     log("[bench] batched phase ms (fwd, sig, bwd, fin, bc):",
         [round(x, 1) for x in st["phase_ms"][1:6]], "variant ms:", [round(x, 1) for x in st["variant_ms"]])
+    log("[bench] batched per phase: arcs", st["phase_arcs"][1:4], "lane arcs", st["phase_lane_arcs"][1:4],
+        "pairs", st["phase_pairs"][1:4], "queue entries", st["queue_entries"], "batches", st["n_batches"])
 
     # ---- plain per-source engine on the same workload
     plain = None

@@ -205,10 +205,14 @@ typedef struct bc_stats {
     double algo_bytes;         /* algorithmic bytes: 16 per scanned arc, 8 per DAG
                                   (arc, source) pair, 32 per level-queue entry  */
     double ms;                 /* wall time of the run, host clock            */
-    double phase_ms[9];        /* device time per phase (index = internal phase id:
+    double phase_ms[10];       /* device time per phase (index = internal phase id:
                                   1 discover, 2 path counts, 3 backward,
-                                  4 reset, 5 BC accumulate, 6-7 detail dumps)   */
+                                  4 reset, 5 BC accumulate, 6-7 detail dumps,
+                                  9 undo while collecting timings)              */
     double variant_ms[3];      /* discover time per BC_VARIANT_*              */
+    int64_t phase_arcs[10];    /* arcs scanned per phase                      */
+    int64_t phase_lane_arcs[10];/* DAG (arc, source) pairs per phase          */
+    int64_t phase_pairs[10];   /* matched neighbours whose per-source values were read */
 } bc_stats;
 
 bc_status bc_run_stats(const bc_graph *g, bc_stats *out);
@@ -230,6 +234,37 @@ bc_status bc_run_stats(const bc_graph *g, bc_stats *out);
  * unloads them.  A wrong length or non-finite weights -> BC_ERR_INVALID_ARG
  * and the handle keeps its previous policy. */
 bc_status bc_load_policy(bc_graph *g, const float *weights, int64_t len);
+
+/*
+ * Training support for the policy network (no graph handle needed).
+ * Samples: X float[n][5] (normalised features as above), Y float[n][3]
+ * (log2 of the measured time of each variant, microseconds), mask uint8[n][3]
+ * (1 = Y entry measured).  Loss L = sum mask * (f(x) - y)^2 / (2 * sum mask).
+ * All pointers are host memory; weights are BC_MLP_PARAMS floats.
+ *   bc_mlp_loss_grad  L and dL/dweights (float[BC_MLP_PARAMS]) at weights.
+ *   bc_mlp_train      `steps` full-batch Adam steps (beta1 0.9, beta2 0.999,
+ *                     eps 1e-8) from *weights, updated in place; final loss.
+ *   bc_mlp_predict    f(X) into Y float[n][3].
+ * Errors: BC_ERR_INVALID_ARG for NULL pointers, n < 1, an all-zero mask or
+ * non-finite inputs; weights are left unchanged on any error.
+ */
+bc_status bc_mlp_loss_grad(const float *weights, const float *X, const float *Y, const uint8_t *mask,
+                           int64_t n, float *loss, float *grad, void *stream);
+bc_status bc_mlp_train(float *weights, const float *X, const float *Y, const uint8_t *mask, int64_t n,
+                       int32_t steps, float lr, float *final_loss, void *stream);
+bc_status bc_mlp_predict(const float *weights, const float *X, int64_t n, float *Y, void *stream);
+
+/*
+ * Training data from real runs: runs the batched engine over the sources
+ * like bc_run (scores included) but executes every forward level with each
+ * of the three variants in turn from the same state (undoing the first two),
+ * timing each one on the device clock.  One sample per forward level:
+ * X float[cap][5] features, Y float[cap][3] log2 microseconds.  *count gets
+ * the number of samples written (at most cap).
+ */
+bc_status bc_collect_level_times(bc_graph *g, const int32_t *sources, int64_t n_sources,
+                                 const bc_run_options *opt, float *X, float *Y, int64_t cap,
+                                 int64_t *count, void *stream);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbc.so")
+# BC_LIBRARY may point at another build of libbc.so (tuning experiments).
+LIB_PATH = os.environ.get("BC_LIBRARY") or os.path.join(_HERE, "libbc.so")
 
 BC_OK = 0
 STATUS = {0: "BC_OK", 1: "BC_ERR_INVALID_ARG", 2: "BC_ERR_INVALID_GRAPH", 3: "BC_ERR_OUT_OF_MEMORY",
@@ -41,7 +42,7 @@ BC_MLP_PARAMS = 32 * 5 + 32 + 32 * 32 + 32 + 3 * 32 + 3
 
 EXPORTS = ["bc_status_string", "bc_last_error", "bc_graph_create", "bc_graph_create_multi", "bc_destroy",
            "bc_graph_info", "bc_run_options_init", "bc_run", "bc_scores", "bc_run_detail", "bc_run_stats",
-           "bc_load_policy"]
+           "bc_load_policy", "bc_mlp_loss_grad", "bc_mlp_train", "bc_mlp_predict", "bc_collect_level_times"]
 
 
 class LibraryMissing(RuntimeError):
@@ -75,7 +76,9 @@ class Stats(ctypes.Structure):
                 ("max_levels", ctypes.c_int64), ("variant_levels", ctypes.c_int64 * 3),
                 ("f64_sources", ctypes.c_int64), ("arcs_scanned", ctypes.c_int64), ("lane_arcs", ctypes.c_int64),
                 ("queue_entries", ctypes.c_int64), ("algo_bytes", ctypes.c_double), ("ms", ctypes.c_double),
-                ("phase_ms", ctypes.c_double * 9), ("variant_ms", ctypes.c_double * 3)]
+                ("phase_ms", ctypes.c_double * 10), ("variant_ms", ctypes.c_double * 3),
+                ("phase_arcs", ctypes.c_int64 * 10), ("phase_lane_arcs", ctypes.c_int64 * 10),
+                ("phase_pairs", ctypes.c_int64 * 10)]
 
 
 _lib = None
@@ -121,6 +124,14 @@ def lib():
     L.bc_run_stats.argtypes = [P, ctypes.POINTER(Stats)]
     L.bc_load_policy.restype = ctypes.c_int
     L.bc_load_policy.argtypes = [P, P, I64]
+    L.bc_mlp_loss_grad.restype = ctypes.c_int
+    L.bc_mlp_loss_grad.argtypes = [P, P, P, P, I64, P, P, P]
+    L.bc_mlp_train.restype = ctypes.c_int
+    L.bc_mlp_train.argtypes = [P, P, P, P, I64, I32, ctypes.c_float, P, P]
+    L.bc_mlp_predict.restype = ctypes.c_int
+    L.bc_mlp_predict.argtypes = [P, P, I64, P, P]
+    L.bc_collect_level_times.restype = ctypes.c_int
+    L.bc_collect_level_times.argtypes = [P, P, I64, ctypes.POINTER(RunOptions), P, P, I64, P, P]
     _lib = L
     return L
 
@@ -254,7 +265,7 @@ def bc_run_stats(h) -> dict:
     out = {}
     for name, _ in Stats._fields_:
         v = getattr(s, name)
-        out[name] = list(v) if name in ("variant_levels", "phase_ms", "variant_ms") else v
+        out[name] = list(v) if hasattr(v, "__len__") else v
     return out
 
 
@@ -264,6 +275,63 @@ def bc_load_policy(h, weights):
         return
     w = np.ascontiguousarray(weights, dtype=np.float32)
     _check(lib().bc_load_policy(h, w.ctypes.data_as(ctypes.c_void_p), w.size))
+
+
+def _f32(a, shape):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def bc_mlp_loss_grad(weights, X, Y, mask):
+    """(loss, grad float32[BC_MLP_PARAMS]) of the policy-network loss."""
+    n = int(np.asarray(X).shape[0])
+    w = _f32(weights, (BC_MLP_PARAMS,))
+    x = _f32(X, (n, 5))
+    y = _f32(Y, (n, 3))
+    m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(n, 3)
+    loss = ctypes.c_float()
+    grad = np.zeros(BC_MLP_PARAMS, np.float32)
+    _check(lib().bc_mlp_loss_grad(_p(w), _p(x), _p(y), _p(m), n, ctypes.byref(loss), _p(grad), None))
+    return float(loss.value), grad
+
+
+def bc_mlp_train(weights, X, Y, mask, steps: int, lr: float):
+    """Adam training; returns (new weights, final loss)."""
+    n = int(np.asarray(X).shape[0])
+    w = _f32(weights, (BC_MLP_PARAMS,)).copy()
+    x = _f32(X, (n, 5))
+    y = _f32(Y, (n, 3))
+    m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(n, 3)
+    loss = ctypes.c_float()
+    _check(lib().bc_mlp_train(_p(w), _p(x), _p(y), _p(m), n, int(steps), float(lr), ctypes.byref(loss), None))
+    return w, float(loss.value)
+
+
+def bc_mlp_predict(weights, X):
+    n = int(np.asarray(X).shape[0])
+    w = _f32(weights, (BC_MLP_PARAMS,))
+    x = _f32(X, (n, 5))
+    y = np.zeros((n, 3), np.float32)
+    _check(lib().bc_mlp_predict(_p(w), _p(x), n, _p(y), None))
+    return y
+
+
+def bc_collect_level_times(h, sources, cap: int = 100000, options: RunOptions | None = None, stream=None):
+    """Per-level (features, log2 microseconds of each variant) from a real run."""
+    s = np.ascontiguousarray(sources, dtype=np.int32)
+    X = np.zeros((cap, 5), np.float32)
+    Y = np.zeros((cap, 3), np.float32)
+    cnt = ctypes.c_int64()
+    _check(lib().bc_collect_level_times(h, _p(s), s.size, ctypes.byref(options) if options is not None else None,
+                                        _p(X), _p(Y), cap, ctypes.byref(cnt), _stream(stream)))
+    k = cnt.value
+    return X[:k].copy(), Y[:k].copy()
 
 
 class Graph:
@@ -295,6 +363,9 @@ class Graph:
 
     def load_policy(self, weights):
         bc_load_policy(self.h, weights)
+
+    def collect_level_times(self, sources, cap=100000, stream=None, **opts):
+        return bc_collect_level_times(self.h, sources, cap, make_options(**opts), stream)
 
     def info(self):
         return bc_graph_info(self.h)

@@ -17,16 +17,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbc.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["bc_api.hip", "bc_plain.hip", "bc_batched.hip"]
+SOURCES = ["bc_api.hip", "bc_plain.hip", "bc_batched.hip", "bc_mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(HERE, "..", "include")]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, build_dir: str, extra: list) -> str:
+    obj = os.path.join(build_dir, src.replace(".hip", ".o"))
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
@@ -38,17 +38,21 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build() -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(out: str = OUT, defines: dict | None = None) -> str:
+    """Compile and link libbc.so (out); defines override tuning constants
+    (e.g. {"BC_GROUP": 8}) for experiments."""
+    extra = [f"-D{k}={v}" for k, v in (defines or {}).items()]
+    build_dir = BUILD if not defines else os.path.join(BUILD, "_".join(f"{k}{v}" for k, v in defines.items()))
+    os.makedirs(build_dir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = OUT + f".tmp{os.getpid()}"
+        objs = list(ex.map(lambda f: _compile(f, build_dir, extra), SOURCES))
+    tmp = out + f".tmp{os.getpid()}"
     r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp],
                        capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

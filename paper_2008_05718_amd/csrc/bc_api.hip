@@ -28,6 +28,8 @@ static bc_status fail(bc_status st, const std::string &msg) {
     return st;
 }
 
+bc_status bc_set_error(bc_status s, const char *msg) { return fail(s, msg ? msg : ""); }
+
 #define HIP_TRY(expr)                                                                         \
     do {                                                                                      \
         hipError_t _e = (expr);                                                               \
@@ -163,8 +165,10 @@ struct bc_graph {
     uint32_t b_lq_cap = 0;
     int32_t *b_level_off = nullptr;
     int32_t b_max_levels = 0;
-    unsigned long long *b_sig = nullptr;
+    unsigned long long *b_sig = nullptr, *b_pk_sig = nullptr;
     double *b_chat = nullptr;
+    uint32_t *b_lq_off = nullptr;
+    uint32_t b_pk_cap = 0;
     int32_t *b_shift = nullptr, *b_maxexp = nullptr, *b_lane_src = nullptr;
     HeavyQ b_hq{};
     // per-run buffers (grown on demand)
@@ -198,6 +202,7 @@ extern "C" void bc_destroy(bc_graph *g) {
     void *dev[] = {g->row_ptr, g->col, g->bc, g->ctl, g->p_d, g->p_queue, g->p_level_off, g->p_shift,
                    g->p_sig, g->p_chat, g->b_vn, g->b_fw0, g->b_fw1, g->b_lq_vtx, g->b_lq_mask,
                    g->b_level_off, g->b_sig, g->b_chat, g->b_shift, g->b_maxexp, g->b_lane_src,
+                   g->b_pk_sig, g->b_lq_off,
                    g->srcs, g->ovf, g->bstart, g->blo, g->bhi, g->mlp, g->hv_vtx, g->hv_seg,
                    g->p_hq.pos, g->p_hq.seg, g->p_hq.cnt, g->p_hq.off, g->p_hq.nseg, g->p_hq.part_lo,
                    g->p_hq.part_hi, g->b_hq.pos, g->b_hq.seg, g->b_hq.cnt, g->b_hq.off, g->b_hq.nseg,
@@ -454,7 +459,12 @@ static bc_status ensure_batched(bc_graph *g) {
     if (g->b_max_levels < 4) g->b_max_levels = 4;
     HIP_TRY(dalloc(&g->b_level_off, (size_t)g->b_max_levels + 2, &g->bytes));
     HIP_TRY(dalloc(&g->b_sig, (size_t)n * kLanes, &g->bytes));
-    HIP_TRY(dalloc(&g->b_chat, (size_t)n * kLanes, &g->bytes));
+    // packed per-entry values: every (vertex, lane) pair at most once per batch
+    const int64_t pk = std::min<int64_t>((int64_t)n * kLanes + kLanes, (int64_t)UINT32_MAX);
+    g->b_pk_cap = (uint32_t)pk;
+    HIP_TRY(dalloc(&g->b_pk_sig, (size_t)pk, &g->bytes));
+    HIP_TRY(dalloc(&g->b_chat, (size_t)pk, &g->bytes));
+    HIP_TRY(dalloc(&g->b_lq_off, (size_t)cap, &g->bytes));
     HIP_TRY(dalloc(&g->b_shift, ((size_t)g->b_max_levels + 2) * kLanes, &g->bytes));
     HIP_TRY(dalloc(&g->b_maxexp, (size_t)2 * kLanes, &g->bytes));
     HIP_TRY(dalloc(&g->b_lane_src, (size_t)kLanes, &g->bytes));
@@ -614,8 +624,13 @@ struct DumpBufs {
 };
 
 static void accumulate_stats(bc_stats *s, const Ctl &c, double clock_khz) {
-    for (int i = 0; i < kPhases && i < 9; ++i) s->phase_ms[i] += (double)c.st_ticks[i] / clock_khz;
+    for (int i = 0; i < kPhases; ++i) s->phase_ms[i] += (double)c.st_ticks[i] / clock_khz;
     for (int i = 0; i < 3; ++i) s->variant_ms[i] += (double)c.st_vticks[i] / clock_khz;
+    for (int i = 0; i < kPhases; ++i) {
+        s->phase_arcs[i] += (int64_t)c.st_parcs[i];
+        s->phase_lane_arcs[i] += (int64_t)c.st_plarcs[i];
+        s->phase_pairs[i] += (int64_t)c.st_ppairs[i];
+    }
     s->steps += (int64_t)c.st_steps;
     s->forward_levels += (int64_t)c.st_fwd_levels;
     for (int i = 0; i < 3; ++i) s->variant_levels[i] += (int64_t)c.st_var[i];
@@ -636,9 +651,15 @@ static bc_status ctl_error(const Ctl &c) {
 
 // One pass of one engine over a device source list.  Overflowed source
 // positions (mode 0) are returned in *ovf_positions.
+struct CollectBufs {
+    float *X = nullptr, *Y = nullptr;  // device
+    uint32_t cap = 0;
+};
+
 static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &o, const int32_t *h_srcs,
                           int64_t ns, int64_t dump_pos, DumpBufs *dump, hipStream_t st,
-                          std::vector<int64_t> *ovf_positions, int *dump_done, Ctl *ctl_out) {
+                          std::vector<int64_t> *ovf_positions, int *dump_done, Ctl *ctl_out,
+                          const CollectBufs *col = nullptr) {
     bc_status s;
     s = grow(&g->srcs, &g->srcs_cap, ns, &g->bytes);
     if (s != BC_OK) return s;
@@ -743,6 +764,7 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
         hc->phase = PH_BC;
         hc->pos = -1;
         hc->n_items = nb;
+        hc->collect = col ? 1 : 0;
         hc->range_lo = 0;
         hc->range_hi = 0;
         hc->epoch_b = 0;
@@ -762,7 +784,10 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
         a.level_off = g->b_level_off;
         a.max_levels = g->b_max_levels;
         a.sig = g->b_sig;
-        a.chat = g->b_chat;
+        a.pk_sig = g->b_pk_sig;
+        a.pk_chat = g->b_chat;
+        a.lq_off = g->b_lq_off;
+        a.pk_cap = g->b_pk_cap;
         a.shift = g->b_shift;
         a.maxexp = g->b_maxexp;
         a.bc = g->bc;
@@ -772,6 +797,11 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
         a.batch_hi = g->bhi;
         a.lane_src = g->b_lane_src;
         a.hq = g->b_hq;
+        if (col) {
+            a.col_X = col->X;
+            a.col_Y = col->Y;
+            a.col_cap = col->cap;
+        }
         a.ovf_list = g->ovf;
         a.ovf_cap = (uint32_t)std::min<int64_t>(g->ovf_cap, UINT32_MAX);
         a.sigma_limit = limit;
@@ -782,7 +812,7 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
             a.dump_shift = dump->shift;
         }
         const int64_t maxl = std::min<int64_t>(g->n, g->b_max_levels) + 2;
-        const int64_t max_steps = (nb + 1) * (3 * maxl + 8) + 64;
+        const int64_t max_steps = (nb + 1) * ((col ? 7 : 3) * maxl + 8) + 64;
         s = drive(g, a, cfg.mode ? batch_step<1> : batch_step<0>, cfg, st, max_steps, &launches);
     }
     g->stats.launches += launches;
@@ -973,6 +1003,78 @@ extern "C" bc_status bc_run_detail(bc_graph *g, const int32_t *sources, int64_t 
                                    const bc_run_options *opt, int64_t dump_index, bc_detail *out, void *stream) {
     if (!out) return fail(BC_ERR_INVALID_ARG, "out is NULL");
     return run_impl(g, sources, n_sources, opt, stream, dump_index, out);
+}
+
+extern "C" bc_status bc_collect_level_times(bc_graph *g, const int32_t *sources, int64_t n_sources,
+                                            const bc_run_options *opt, float *X, float *Y, int64_t cap,
+                                            int64_t *count, void *stream) {
+    if (!g || !X || !Y || !count || cap < 1 || !sources || n_sources < 1)
+        return fail(BC_ERR_INVALID_ARG, "NULL argument, empty source list or cap < 1");
+    for (int64_t i = 0; i < n_sources; ++i)
+        if (sources[i] < 0 || sources[i] >= g->n) return fail(BC_ERR_INVALID_ARG, "source id outside [0, n)");
+    bc_run_options o;
+    bc_run_options_init(&o);
+    if (opt) o = *opt;
+    o.batch = 64;
+    RunCfg cfg;
+    bc_status s = resolve_cfg(g, o, n_sources, &cfg);
+    if (s != BC_OK) return s;
+    cfg.mode = (o.flags & BC_RUN_FORCE_F64) ? 1 : 0;
+    hipStream_t st = (hipStream_t)stream;
+    CollectBufs cb;
+    cb.cap = (uint32_t)std::min<int64_t>(cap, UINT32_MAX);
+    HIP_TRY(hipMalloc((void **)&cb.X, (size_t)cb.cap * kMlpIn * sizeof(float)));
+    hipError_t e = hipMalloc((void **)&cb.Y, (size_t)cb.cap * 3 * sizeof(float));
+    if (e != hipSuccess) {
+        (void)hipFree(cb.X);
+        return fail(BC_ERR_OUT_OF_MEMORY, "collection buffers");
+    }
+    std::memset(&g->stats, 0, sizeof(g->stats));
+    if (!(o.flags & BC_RUN_ACCUMULATE) && g->n > 0) {
+        fill_u64<<<grid_for(g->n, 256, 4096), 256, 0, st>>>((unsigned long long *)g->bc, g->n, 0ull);
+    }
+    Ctl last{};
+    std::vector<int64_t> ovf;
+    RunCfg c0 = cfg;
+    c0.use_graphs = false;  // the machine inserts undo steps; keep launches simple
+    s = run_pass(g, c0, o, sources, n_sources, -1, nullptr, st, &ovf, nullptr, &last, &cb);
+    int64_t n_samples = std::min<int64_t>((int64_t)last.n_samples, (int64_t)cb.cap);
+    if (s == BC_OK && !ovf.empty()) {
+        // sources whose path counts overflowed 64 bits run again with FP64
+        // path counts, so that the scores stay complete; their levels are
+        // timed too (deep levels are only ever reached this way)
+        std::vector<int32_t> redo(ovf.size());
+        for (size_t i = 0; i < ovf.size(); ++i) redo[i] = sources[ovf[i]];
+        RunCfg c1 = c0;
+        c1.mode = 1;
+        CollectBufs cb1;
+        cb1.X = cb.X + (size_t)n_samples * kMlpIn;
+        cb1.Y = cb.Y + (size_t)n_samples * 3;
+        cb1.cap = cb.cap - (uint32_t)n_samples;
+        s = run_pass(g, c1, o, redo.data(), (int64_t)redo.size(), -1, nullptr, st, nullptr, nullptr, &last,
+                     cb1.cap ? &cb1 : nullptr);
+        if (cb1.cap) n_samples += std::min<int64_t>((int64_t)last.n_samples, (int64_t)cb1.cap);
+        g->stats.f64_sources = (int64_t)redo.size();
+    }
+    if (s == BC_OK) {
+        const int64_t k = n_samples;
+        std::vector<float> hy((size_t)k * 3);
+        hipError_t e1 = hipMemcpy(X, cb.X, (size_t)k * kMlpIn * sizeof(float), hipMemcpyDeviceToHost);
+        hipError_t e2 = hipMemcpy(hy.data(), cb.Y, (size_t)k * 3 * sizeof(float), hipMemcpyDeviceToHost);
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+            s = fail(BC_ERR_DEVICE, "copying collected samples");
+        } else {
+            // device ticks -> log2 microseconds
+            for (size_t i = 0; i < hy.size(); ++i) {
+                const double us = (double)hy[i] / g->clock_khz * 1000.0;
+                Y[i] = (float)std::log2(std::max(us, 0.01));
+            }
+            *count = k;
+        }
+    }
+    (void)hipFree(cb.X);
+    (void)hipFree(cb.Y);
+    return s;
 }
 
 extern "C" bc_status bc_scores(const bc_graph *g, double *out, int64_t len, uint32_t flags, void *stream) {

@@ -61,58 +61,83 @@ __device__ __forceinline__ void push_arcs_wave(const BatchArgs &a, unsigned long
     }
 }
 
-constexpr int kUnroll = 8;  // matched neighbours whose rows are loaded together
+#ifndef BC_UNROLL
+#define BC_UNROLL 8
+#endif
+constexpr int kUnroll = BC_UNROLL;  // matched neighbours whose values are loaded together
 
-// Pop up to kUnroll matched neighbours (ascending lane order) from bal:
-// their vertex ids and lane masks, broadcast to the wavefront.
-__device__ __forceinline__ void pop_matches(unsigned long long &bal, int uj, unsigned long long xj, int *u,
-                                            unsigned long long *xm) {
+// Per-source values (path counts, c) are stored packed per level-queue entry:
+// the entry of vertex v on level l with lane mask M owns popc(M) consecutive
+// slots from its offset, lane k at off + popc(M & lanes-below-k).  The
+// frontier tag of v carries (M, level tag, off), so reading a neighbour's
+// values for a subset x of M touches one short contiguous run.
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long x, int j) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, j);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), j);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Up to kUnroll matches, popped in ascending lane order: lanes x, the
+// neighbour entry's full mask mu and packed offset off (all wavefront-uniform).
+struct Matches {
+    unsigned long long x[kUnroll], mu[kUnroll];
+    uint32_t off[kUnroll];
+    int own[kUnroll];
+};
+
+__device__ __forceinline__ void pop_matches(unsigned long long &bal, unsigned long long xj, unsigned long long mj,
+                                            uint32_t oj, int ownj, Matches &mt) {
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q) {
         if (bal) {
-            // j is wavefront-uniform: readlane keeps u and xm in scalar registers
             const int j = __ffsll(bal) - 1;
             bal &= bal - 1;
-            u[q] = __builtin_amdgcn_readlane(uj, j);
-            const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)xj, j);
-            const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(xj >> 32), j);
-            xm[q] = ((unsigned long long)hi << 32) | lo;
+            mt.x[q] = readlane_u64(xj, j);
+            mt.mu[q] = readlane_u64(mj, j);
+            mt.off[q] = (uint32_t)__builtin_amdgcn_readlane((int)oj, j);
+            mt.own[q] = __builtin_amdgcn_readlane(ownj, j);
         } else {
-            u[q] = 0;
-            xm[q] = 0ull;
+            mt.x[q] = 0ull;
+            mt.mu[q] = 0ull;
+            mt.off[q] = 0u;
+            mt.own[q] = -1;
         }
     }
 }
 
 // Path counts: sum over arcs [a0, a1) of w's neighbours u on level l (tag T)
 // of sigma_k(u) for the lanes k of m; lane k accumulates its own source, in
-// CSR order.  Row loads of up to kUnroll neighbours are issued together.
+// CSR order.  Loads of up to kUnroll neighbours are issued together.
 template <int MODE>
 __device__ __forceinline__ void sig_arcs(const BatchArgs &a, const Tagged *__restrict__ fw_cur, uint32_t T,
                                          unsigned long long m, int a0, int a1, int sh,
                                          const int32_t *__restrict__ col, unsigned long long &lo,
-                                         unsigned long long &hi, double &accd, unsigned long long &my_larcs) {
+                                         unsigned long long &hi, double &accd, unsigned long long &my_larcs,
+                                         unsigned long long &my_pairs) {
     const int lane = lane_id();
     for (int eb = a0; eb < a1; eb += kWave) {
         const int e = eb + lane;
-        int uj = 0;
-        unsigned long long xj = 0;
+        unsigned long long xj = 0, mj = 0;
+        uint32_t oj = 0;
         if (e < a1) {
-            uj = col[e];
-            const Tagged F = fw_cur[uj];
-            if (F.tag == T) xj = F.mask & m;
+            const Tagged F = fw_cur[col[e]];
+            if (F.tag == T) {
+                xj = F.mask & m;
+                mj = F.mask;
+                oj = F.off;
+            }
         }
         unsigned long long bal = __ballot(xj != 0ull);
         while (bal) {
-            int u[kUnroll];
-            unsigned long long xm[kUnroll], val[kUnroll];
-            pop_matches(bal, uj, xj, u, xm);
+            Matches mt;
+            pop_matches(bal, xj, mj, oj, 0, mt);
+            unsigned long long val[kUnroll];
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q)
-                val[q] = ((xm[q] >> lane) & 1ull) ? a.sig[(size_t)u[q] * kLanes + lane] : 0ull;
+                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.pk_sig[mt.off[q] + lanes_below(mt.mu[q])] : 0ull;
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q) {
-                if ((xm[q] >> lane) & 1ull) {
+                if ((mt.x[q] >> lane) & 1ull) {
                     if (MODE == 0) {
                         lo += val[q];
                         hi += (lo < val[q]) ? 1ull : 0ull;
@@ -120,7 +145,10 @@ __device__ __forceinline__ void sig_arcs(const BatchArgs &a, const Tagged *__res
                         accd += ldexp(as_f64(val[q]), -sh);
                     }
                 }
-                if (lane == 0) my_larcs += (unsigned)__popcll(xm[q]);
+                if (lane == 0) {
+                    my_larcs += (unsigned)__popcll(mt.x[q]);
+                    my_pairs += mt.x[q] ? 1u : 0u;
+                }
             }
         }
     }
@@ -130,31 +158,36 @@ __device__ __forceinline__ void sig_arcs(const BatchArgs &a, const Tagged *__res
 // TB1) of c_k(w) for the lanes k of M, in CSR order.
 __device__ __forceinline__ double bwd_arcs(const BatchArgs &a, const Tagged *__restrict__ fb_nxt, uint32_t TB1,
                                            unsigned long long M, int a0, int a1, const int32_t *__restrict__ col,
-                                           unsigned long long &my_larcs) {
+                                           unsigned long long &my_larcs, unsigned long long &my_pairs) {
     const int lane = lane_id();
     double acc = 0.0;
     for (int eb = a0; eb < a1; eb += kWave) {
         const int e = eb + lane;
-        int wj = 0;
-        unsigned long long xj = 0;
+        unsigned long long xj = 0, mj = 0;
+        uint32_t oj = 0;
         if (e < a1) {
-            wj = col[e];
-            const Tagged F = fb_nxt[wj];
-            if (F.tag == TB1) xj = F.mask & M;
+            const Tagged F = fb_nxt[col[e]];
+            if (F.tag == TB1) {
+                xj = F.mask & M;
+                mj = F.mask;
+                oj = F.off;
+            }
         }
         unsigned long long bal = __ballot(xj != 0ull);
         while (bal) {
-            int w[kUnroll];
-            unsigned long long xm[kUnroll];
+            Matches mt;
+            pop_matches(bal, xj, mj, oj, 0, mt);
             double val[kUnroll];
-            pop_matches(bal, wj, xj, w, xm);
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q)
-                val[q] = ((xm[q] >> lane) & 1ull) ? a.chat[(size_t)w[q] * kLanes + lane] : 0.0;
+                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.pk_chat[mt.off[q] + lanes_below(mt.mu[q])] : 0.0;
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q) {
-                if ((xm[q] >> lane) & 1ull) acc += val[q];
-                if (lane == 0) my_larcs += (unsigned)__popcll(xm[q]);
+                if ((mt.x[q] >> lane) & 1ull) acc += val[q];
+                if (lane == 0) {
+                    my_larcs += (unsigned)__popcll(mt.x[q]);
+                    my_pairs += mt.x[q] ? 1u : 0u;
+                }
             }
         }
     }
@@ -174,32 +207,47 @@ __device__ __forceinline__ bool seg_arrive(int32_t *cnt, int nseg) {
     return last;
 }
 
+// Packed slots for new entries: exactly popc(mask) per entry, taken from the
+// batch's counter by one atomic per group of entries.  Every (vertex, lane)
+// pair gets slots once per batch, so K * n slots always suffice.
+__device__ __forceinline__ uint32_t alloc_packed(const BatchArgs &a, unsigned count) {
+    uint32_t base = 0;
+    if (lane_id() == 0 && count) {
+        base = atomicAdd(&a.ctl->pk_next, count);
+        if ((unsigned long long)base + count > a.pk_cap) {  // cannot happen: K * n bound
+            atomicOr(&a.ctl->err, ERR_QUEUE_CAP);
+            base = 0;  // keep every later access in bounds; the run reports the error
+        }
+    }
+    return (uint32_t)__shfl((int)base, 0);
+}
+
 // Per-lane counters the path-count finalisation feeds.
 struct SigCounters {
-    unsigned long long edges = 0, act = 0, ovf = 0, full_n = 0, full_m = 0, larcs = 0, arcs = 0;
+    unsigned long long edges = 0, act = 0, ovf = 0, full_n = 0, full_m = 0, larcs = 0, arcs = 0, pairs = 0;
     int maxe = INT_MIN, mine = INT_MAX;
 };
 
 // Store the path counts of new vertex w (queue position p, visited/next words
-// x, degree deg) and publish it as part of the level-(l+1) frontier.
+// vis/m, degree deg, packed offset off) and publish it as part of the
+// level-(l+1) frontier.
 template <int MODE>
 __device__ __forceinline__ void sig_finalize(const BatchArgs &a, Tagged *fw_nxt, uint32_t T1, int p, int w,
-                                             unsigned long long vis, unsigned long long m, int deg,
+                                             unsigned long long vis, unsigned long long m, int deg, uint32_t off,
                                              unsigned long long lo, unsigned long long hi, double accd,
                                              unsigned long long lmask, SigCounters &sc) {
     const int lane = lane_id();
     if ((m >> lane) & 1ull) {
+        const uint32_t at = off + lanes_below(m);
+        if (MODE == 0) a.pk_sig[at] = lo;
+        else a.pk_sig[at] = as_u64(accd);
         if (MODE == 0) {
-            a.sig[(size_t)w * kLanes + lane] = lo;
             if (hi != 0 || lo > a.sigma_limit) sc.ovf |= 1ull << lane;
-        } else {
-            a.sig[(size_t)w * kLanes + lane] = as_u64(accd);
-            if (accd > 0.0) {
-                int ex;
-                frexp(accd, &ex);
-                sc.maxe = max(sc.maxe, ex);
-                sc.mine = min(sc.mine, ex);
-            }
+        } else if (accd > 0.0) {
+            int ex;
+            frexp(accd, &ex);
+            sc.maxe = max(sc.maxe, ex);
+            sc.mine = min(sc.mine, ex);
         }
     }
     if (lane == 0) {
@@ -210,9 +258,10 @@ __device__ __forceinline__ void sig_finalize(const BatchArgs &a, Tagged *fw_nxt,
         Tagged tg;
         tg.mask = m;
         tg.tag = T1;
-        tg.pad = 0;
+        tg.off = off;
         fw_nxt[w] = tg;
         a.lq_mask[p] = m;
+        a.lq_off[p] = off;
         sc.edges += (unsigned)deg;
         sc.act |= m;
         if ((y.vis & lmask) == lmask) {
@@ -222,33 +271,29 @@ __device__ __forceinline__ void sig_finalize(const BatchArgs &a, Tagged *fw_nxt,
     }
 }
 
-// Dependencies of vertex v (queue position p, live lanes M) from the sum acc.
+// Dependencies of vertex v (entry mask Mf, live lanes M, packed offset off)
+// from the sum acc; delta also goes to the dense [n][64] slab for PH_BC.
 template <int MODE>
 __device__ __forceinline__ void bwd_finalize(const BatchArgs &a, Tagged *fb_cur, uint32_t TB, int v,
-                                             unsigned long long M, double acc, int sh, int shn) {
+                                             unsigned long long Mf, unsigned long long M, uint32_t off, double acc,
+                                             int sh, int shn) {
     const int lane = lane_id();
     if ((M >> lane) & 1ull) {
-        const size_t at = (size_t)v * kLanes + lane;
-        const unsigned long long raw = a.sig[at];
+        const uint32_t at = off + lanes_below(Mf);
+        const unsigned long long raw = a.pk_sig[at];
         const double sv = MODE ? ldexp(as_f64(raw), -sh) : (double)raw;
         double delta = sv * acc;
         if (MODE) delta = ldexp(delta, -shn);
-        a.chat[at] = (1.0 + delta) / sv;
-        a.sig[at] = as_u64(delta);
+        a.pk_chat[at] = (1.0 + delta) / sv;
+        a.sig[(size_t)v * kLanes + lane] = as_u64(delta);
     }
     if (lane == 0) {
         Tagged tg;
-        tg.mask = M;
+        tg.mask = Mf;
         tg.tag = TB;
-        tg.pad = 0;
+        tg.off = off;
         fb_cur[v] = tg;
     }
-}
-
-__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long x, int j) {
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, j);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), j);
-    return ((unsigned long long)hi << 32) | lo;
 }
 
 // Owner of packed arc index ai: the number of entries whose inclusive arc
@@ -263,16 +308,23 @@ __device__ __forceinline__ int packed_owner(int incl, int ai) {
     return o;
 }
 
-constexpr int kPack = 64;   // entries of degree <= kPack share 64-arc scan chunks
-constexpr int kGroup = 16;  // queue entries per packed work item
+#ifndef BC_PACK
+#define BC_PACK 64
+#endif
+#ifndef BC_GROUP
+#define BC_GROUP 8
+#endif
+constexpr int kPack = BC_PACK;    // entries of degree <= kPack share 64-arc scan chunks
+constexpr int kGroup = BC_GROUP;  // queue entries per packed work item
 
-// Path counts for the kGroup queue entries [g0, g0 + kGroup) of level l+1: entries of
-// degree <= kPack have their adjacencies packed into dense 64-arc chunks;
-// entries of degree <= kSeg follow one at a time; heavier ones run as
+// Path counts for the kGroup queue entries [g0, g0 + kGroup) of level l+1:
+// entries of degree <= kPack have their adjacencies packed into dense 64-arc
+// chunks; entries of degree <= kSeg follow one at a time; heavier ones run as
 // segments elsewhere.  Every entry's sum keeps CSR order.
 template <int MODE>
-__device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__restrict__ fw_cur, Tagged *fw_nxt, uint32_t T,
-                          int qs, int g0, int cnt, int sh, unsigned long long lmask, SigCounters &sc) {
+__device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__restrict__ fw_cur, Tagged *fw_nxt,
+                                          uint32_t T, int qs, int g0, int cnt, int sh, unsigned long long lmask,
+                                          SigCounters &sc) {
     const int32_t *__restrict__ rp = a.g.row_ptr;
     const int32_t *__restrict__ col = a.g.col;
     const int lane = lane_id();
@@ -290,6 +342,11 @@ __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__re
         vis = x.vis;
         nxt = x.nxt;
     }
+    // packed slots of every light or medium entry of the group, one atomic
+    const int need = (light || medium) ? __popcll(nxt) : 0;
+    const int pincl = wave_incl_scan(need);
+    const uint32_t pbase = alloc_packed(a, (unsigned)__shfl(pincl, 63));
+    const uint32_t poff = pbase + (uint32_t)(pincl - need);
     const int dl = light ? deg : 0;
     const int incl = wave_incl_scan(dl);
     const int off = incl - dl;
@@ -302,7 +359,8 @@ __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__re
             if (__builtin_amdgcn_readlane((int)light, e)) {
                 sig_finalize<MODE>(a, fw_nxt, T + 1u, __builtin_amdgcn_readlane(p, e),
                                    __builtin_amdgcn_readlane(w, e), readlane_u64(vis, e), readlane_u64(nxt, e),
-                                   __builtin_amdgcn_readlane(deg, e), lo, hi, accd, lmask, sc);
+                                   __builtin_amdgcn_readlane(deg, e),
+                                   (uint32_t)__builtin_amdgcn_readlane((int)poff, e), lo, hi, accd, lmask, sc);
             }
             lo = hi = 0;
             accd = 0.0;
@@ -314,40 +372,30 @@ __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__re
         const int o = packed_owner(incl, min(ai, total - 1));
         const int e0o = __shfl(e0, o), offo = __shfl(off, o);
         const unsigned long long mo = shfl_u64(nxt, o);
-        int uj = 0;
-        unsigned long long xj = 0;
+        unsigned long long xj = 0, mj = 0;
+        uint32_t oj = 0;
         if (ai < total) {
-            uj = col[e0o + (ai - offo)];
-            const Tagged F = fw_cur[uj];
-            if (F.tag == T) xj = F.mask & mo;
+            const Tagged F = fw_cur[col[e0o + (ai - offo)]];
+            if (F.tag == T) {
+                xj = F.mask & mo;
+                mj = F.mask;
+                oj = F.off;
+            }
         }
         if (lane == 0) sc.arcs += (unsigned)min(kWave, total - base);
         unsigned long long bal = __ballot(xj != 0ull);
         while (bal) {
-            int u[kUnroll], own[kUnroll];
-            unsigned long long xm[kUnroll], val[kUnroll];
-#pragma unroll
-            for (int q = 0; q < kUnroll; ++q) {
-                if (bal) {
-                    const int j = __ffsll(bal) - 1;
-                    bal &= bal - 1;
-                    u[q] = __builtin_amdgcn_readlane(uj, j);
-                    own[q] = __builtin_amdgcn_readlane(o, j);
-                    xm[q] = readlane_u64(xj, j);
-                } else {
-                    u[q] = 0;
-                    own[q] = -1;
-                    xm[q] = 0ull;
-                }
-            }
+            Matches mt;
+            pop_matches(bal, xj, mj, oj, o, mt);
+            unsigned long long val[kUnroll];
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q)
-                val[q] = ((xm[q] >> lane) & 1ull) ? a.sig[(size_t)u[q] * kLanes + lane] : 0ull;
+                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.pk_sig[mt.off[q] + lanes_below(mt.mu[q])] : 0ull;
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q) {
-                if (own[q] < 0) continue;
-                if (own[q] != cur) finalize_upto(own[q]);
-                if ((xm[q] >> lane) & 1ull) {
+                if (mt.own[q] < 0) continue;
+                if (mt.own[q] != cur) finalize_upto(mt.own[q]);
+                if ((mt.x[q] >> lane) & 1ull) {
                     if (MODE == 0) {
                         lo += val[q];
                         hi += (lo < val[q]) ? 1ull : 0ull;
@@ -355,7 +403,10 @@ __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__re
                         accd += ldexp(as_f64(val[q]), -sh);
                     }
                 }
-                if (lane == 0) sc.larcs += (unsigned)__popcll(xm[q]);
+                if (lane == 0) {
+                    sc.larcs += (unsigned)__popcll(mt.x[q]);
+                    sc.pairs += mt.x[q] ? 1u : 0u;
+                }
             }
         }
     }
@@ -370,19 +421,20 @@ __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__re
         const unsigned long long mj = readlane_u64(nxt, j);
         lo = hi = 0;
         accd = 0.0;
-        sig_arcs<MODE>(a, fw_cur, T, mj, a0, a0 + dj, sh, col, lo, hi, accd, sc.larcs);
+        sig_arcs<MODE>(a, fw_cur, T, mj, a0, a0 + dj, sh, col, lo, hi, accd, sc.larcs, sc.pairs);
         if (lane == 0) sc.arcs += (unsigned)dj;
         sig_finalize<MODE>(a, fw_nxt, T + 1u, __builtin_amdgcn_readlane(p, j), wj, readlane_u64(vis, j), mj, dj,
-                           lo, hi, accd, lmask, sc);
+                           (uint32_t)__builtin_amdgcn_readlane((int)poff, j), lo, hi, accd, lmask, sc);
     }
 }
 
-// Dependencies for the kGroup queue entries [g0, g0 + kGroup) of level l, packed
-// like sig_group.
+// Dependencies for the kGroup queue entries [g0, g0 + kGroup) of level l,
+// packed like sig_group.
 template <int MODE>
-__device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__restrict__ fb_nxt, Tagged *fb_cur, uint32_t TB,
-                          int qb, int g0, int cnt, unsigned long long dead, int sh, int shn,
-                          unsigned long long &my_larcs, unsigned long long &my_arcs) {
+__device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__restrict__ fb_nxt, Tagged *fb_cur,
+                                          uint32_t TB, int qb, int g0, int cnt, unsigned long long dead, int sh,
+                                          int shn, unsigned long long &my_larcs, unsigned long long &my_arcs,
+                                          unsigned long long &my_pairs) {
     const int32_t *__restrict__ rp = a.g.row_ptr;
     const int32_t *__restrict__ col = a.g.col;
     const int lane = lane_id();
@@ -394,7 +446,9 @@ __device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__re
     const int deg = valid ? rp[v + 1] - e0 : 0;
     const bool light = valid && deg <= kPack;
     const bool medium = valid && deg > kPack && deg <= kSeg;
-    const unsigned long long M = (light || medium) ? (a.lq_mask[p] & ~dead) : 0ull;
+    const unsigned long long Mf = (light || medium) ? a.lq_mask[p] : 0ull;
+    const uint32_t poff = (light || medium) ? a.lq_off[p] : 0u;
+    const unsigned long long M = Mf & ~dead;
     const int dl = (light && M) ? deg : 0;
     const int incl = wave_incl_scan(dl);
     const int off = incl - dl;
@@ -404,7 +458,9 @@ __device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__re
     auto finalize_upto = [&](int upto) {
         for (int e = cur; e < upto; ++e) {
             if (__builtin_amdgcn_readlane((int)light, e))
-                bwd_finalize<MODE>(a, fb_cur, TB, __builtin_amdgcn_readlane(v, e), readlane_u64(M, e), acc, sh, shn);
+                bwd_finalize<MODE>(a, fb_cur, TB, __builtin_amdgcn_readlane(v, e), readlane_u64(Mf, e),
+                                   readlane_u64(M, e), (uint32_t)__builtin_amdgcn_readlane((int)poff, e), acc, sh,
+                                   shn);
             acc = 0.0;
         }
         cur = upto;
@@ -414,42 +470,34 @@ __device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__re
         const int o = packed_owner(incl, min(ai, total - 1));
         const int e0o = __shfl(e0, o), offo = __shfl(off, o);
         const unsigned long long mo = shfl_u64(M, o);
-        int wj = 0;
-        unsigned long long xj = 0;
+        unsigned long long xj = 0, mj = 0;
+        uint32_t oj = 0;
         if (ai < total) {
-            wj = col[e0o + (ai - offo)];
-            const Tagged F = fb_nxt[wj];
-            if (F.tag == TB + 1u) xj = F.mask & mo;
+            const Tagged F = fb_nxt[col[e0o + (ai - offo)]];
+            if (F.tag == TB + 1u) {
+                xj = F.mask & mo;
+                mj = F.mask;
+                oj = F.off;
+            }
         }
         if (lane == 0) my_arcs += (unsigned)min(kWave, total - base);
         unsigned long long bal = __ballot(xj != 0ull);
         while (bal) {
-            int ww[kUnroll], own[kUnroll];
-            unsigned long long xm[kUnroll];
+            Matches mt;
+            pop_matches(bal, xj, mj, oj, o, mt);
             double val[kUnroll];
 #pragma unroll
-            for (int q = 0; q < kUnroll; ++q) {
-                if (bal) {
-                    const int j = __ffsll(bal) - 1;
-                    bal &= bal - 1;
-                    ww[q] = __builtin_amdgcn_readlane(wj, j);
-                    own[q] = __builtin_amdgcn_readlane(o, j);
-                    xm[q] = readlane_u64(xj, j);
-                } else {
-                    ww[q] = 0;
-                    own[q] = -1;
-                    xm[q] = 0ull;
-                }
-            }
-#pragma unroll
             for (int q = 0; q < kUnroll; ++q)
-                val[q] = ((xm[q] >> lane) & 1ull) ? a.chat[(size_t)ww[q] * kLanes + lane] : 0.0;
+                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.pk_chat[mt.off[q] + lanes_below(mt.mu[q])] : 0.0;
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q) {
-                if (own[q] < 0) continue;
-                if (own[q] != cur) finalize_upto(own[q]);
-                if ((xm[q] >> lane) & 1ull) acc += val[q];
-                if (lane == 0) my_larcs += (unsigned)__popcll(xm[q]);
+                if (mt.own[q] < 0) continue;
+                if (mt.own[q] != cur) finalize_upto(mt.own[q]);
+                if ((mt.x[q] >> lane) & 1ull) acc += val[q];
+                if (lane == 0) {
+                    my_larcs += (unsigned)__popcll(mt.x[q]);
+                    my_pairs += mt.x[q] ? 1u : 0u;
+                }
             }
         }
     }
@@ -461,15 +509,30 @@ __device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__re
         const int vj = __builtin_amdgcn_readlane(v, j);
         const int a0 = __builtin_amdgcn_readlane(e0, j), dj = __builtin_amdgcn_readlane(deg, j);
         const unsigned long long Mj = readlane_u64(M, j);
-        const double s = Mj ? bwd_arcs(a, fb_nxt, TB + 1u, Mj, a0, a0 + dj, col, my_larcs) : 0.0;
+        const double sm = Mj ? bwd_arcs(a, fb_nxt, TB + 1u, Mj, a0, a0 + dj, col, my_larcs, my_pairs) : 0.0;
         if (lane == 0) my_arcs += (unsigned)dj;
-        bwd_finalize<MODE>(a, fb_cur, TB, vj, Mj, s, sh, shn);
+        bwd_finalize<MODE>(a, fb_cur, TB, vj, readlane_u64(Mf, j), Mj, (uint32_t)__builtin_amdgcn_readlane((int)poff, j),
+                           sm, sh, shn);
+    }
+}
+
+// The variant of the next level; when collecting timings, every level starts
+// with variant 0 and its normalised features are kept for the sample.
+__device__ __forceinline__ void set_level_variant(Ctl *c, int v, const LevelFeatures &f, float n, float nnz) {
+    if (c->collect) {
+        float x[kMlpIn];
+        mlp_inputs(f, n, nnz, x);
+        for (int i = 0; i < kMlpIn; ++i) c->feat[i] = x[i];
+        c->cvar = 0;
+        c->variant = 0;
+    } else {
+        c->variant = v;
     }
 }
 
 template <int MODE>
 __device__ __forceinline__ void batch_begin(const BatchArgs &a, Ctl *c, int64_t b, float *lds, LevelFeatures *sf, int *s_lsrc,
-                            int *s_cnt, unsigned long long *s_tmp) {
+                            int *s_cnt, unsigned long long *s_tmp, int *s_lead) {
     const int t = threadIdx.x;
     const int64_t start = a.batch_start[b], end = a.batch_start[b + 1];
     const int lanes = (int)(end - start);
@@ -483,26 +546,37 @@ __device__ __forceinline__ void batch_begin(const BatchArgs &a, Ctl *c, int64_t 
         a.lane_src[t] = s;
     }
     __syncthreads();
+    // lanes with the same source share one level-0 entry, led by its lowest lane
+    unsigned long long m = 0;
+    int lead = t;
     if (t < lanes) {
         const int s = s_lsrc[t];
-        unsigned long long m = 0;
-        bool leader = true;
-        for (int k = 0; k < lanes; ++k) {
+        for (int k = lanes - 1; k >= 0; --k) {
             if (s_lsrc[k] == s) {
                 m |= 1ull << k;
-                if (k < t) leader = false;
+                lead = k;
             }
         }
-        a.sig[(size_t)s * kLanes + t] = MODE ? as_u64(1.0) : 1ull;
-        if (leader) {
+        s_lead[t] = lead;
+    }
+    __syncthreads();
+    if (t < lanes) {
+        const int s = s_lsrc[t];
+        // the entry's packed slots follow those of entries with a lower leader
+        int before = 0;
+        for (int k = 0; k < lanes; ++k) before += (s_lead[k] < lead) ? 1 : 0;
+        const uint32_t eoff = (uint32_t)before;
+        a.pk_sig[eoff + (uint32_t)__popcll(m & ((1ull << t) - 1ull))] = MODE ? as_u64(1.0) : 1ull;
+        if (lead == t) {
             const int j = atomicAdd(s_cnt, 1);
             a.lq_vtx[j] = s;
             a.lq_mask[j] = m;
+            a.lq_off[j] = eoff;
             a.vn[s].vis = m;
             Tagged tg;
             tg.mask = m;
             tg.tag = epoch;
-            tg.pad = 0;
+            tg.off = eoff;
             a.fw0[s] = tg;
             s_tmp[j] = (unsigned long long)(a.g.row_ptr[s + 1] - a.g.row_ptr[s]);
         }
@@ -528,6 +602,7 @@ __device__ __forceinline__ void batch_begin(const BatchArgs &a, Ctl *c, int64_t 
         a.hq.off[1] = nh;
         a.hq.nseg[0] = segs;
         c->next_hq = 0;
+        c->pk_next = (uint32_t)lanes;
         c->epoch = epoch;
         c->pos = b;
         c->lanes = lanes;
@@ -562,7 +637,7 @@ __device__ __forceinline__ void batch_begin(const BatchArgs &a, Ctl *c, int64_t 
     __syncthreads();
     const int v = choose_variant(a.p, c->policy, V_PUSH_TPV, *sf, (float)(c->range_hi - c->range_lo),
                                  (float)c->range_arcs, lds);
-    if (t == 0) c->variant = v;
+    if (t == 0) set_level_variant(c, v, *sf, (float)(c->range_hi - c->range_lo), (float)c->range_arcs);
 }
 
 template <int MODE>
@@ -576,6 +651,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
     __shared__ unsigned long long s_tot[kNCnt];
     __shared__ unsigned long long s_tmp[kLanes];
     __shared__ int s_lsrc[kLanes];
+    __shared__ int s_lead[kLanes];
     __shared__ Stage s_stage[kWavesPerBlock];
     __shared__ float s_lds[2 * kMlpH + 4];
     __shared__ LevelFeatures s_feat;
@@ -603,6 +679,9 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             if (s_phase == PH_SIG) s_qn = a.level_off[l + 2];
         } else if (s_phase == PH_DUMP_FWD || s_phase == PH_DUMP_BWD) {
             s_qe = a.level_off[s_L];
+        } else if (s_phase == PH_UNDO) {
+            s_qe = a.level_off[l + 1];
+            s_qn = (int)c->next_count;
         }
         if (s_phase == PH_FWD) {
             if (s_variant == V_PULL) {  // static heavy vertices of the batch's range
@@ -641,6 +720,8 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             items = (s_hi - s_lo + kWave - 1) / kWave;
         } else if (s_phase == PH_DUMP_FWD || s_phase == PH_DUMP_BWD) {
             items = (s_qe + kWave - 1) / kWave;
+        } else if (s_phase == PH_UNDO) {
+            items = (s_qn + kWave - 1) / kWave;
         }
         s_nblk = active_blocks(items);
     }
@@ -661,7 +742,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
     const int h0 = s_h0, h1 = s_h1, hseg = s_hseg;
 
     unsigned long long my_edges = 0, my_arcs = 0, my_larcs = 0, my_act = 0, my_ovf = 0;
-    unsigned long long my_full_n = 0, my_full_m = 0;
+    unsigned long long my_full_n = 0, my_full_m = 0, my_pairs = 0;
     int my_maxe = INT_MIN, my_mine = INT_MAX;
 
     if (!active) {
@@ -838,7 +919,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             const int a0 = e0 + s * kSeg, a1 = min(e1, a0 + kSeg);
             unsigned long long lo = 0, hi = 0;
             double accd = 0.0;
-            sig_arcs<MODE>(a, fw_cur, T, m, a0, a1, sh, col, lo, hi, accd, sc.larcs);
+            sig_arcs<MODE>(a, fw_cur, T, m, a0, a1, sh, col, lo, hi, accd, sc.larcs, sc.pairs);
             if (lane == 0) sc.arcs += (unsigned)(a1 - a0);
             const size_t slot = (size_t)(a.hq.seg[h] + s) * kLanes + lane;
             if (MODE == 0) {
@@ -863,7 +944,8 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             }
             if (lane == 0) a.hq.cnt[h] = 0;
             const VisNext x = a.vn[w];
-            sig_finalize<MODE>(a, fw_nxt, T + 1u, p, w, x.vis, x.nxt, e1 - e0, lo, hi, accd, lmask, sc);
+            const uint32_t poff = alloc_packed(a, (unsigned)__popcll(x.nxt));
+            sig_finalize<MODE>(a, fw_nxt, T + 1u, p, w, x.vis, x.nxt, e1 - e0, poff, lo, hi, accd, lmask, sc);
         }
         my_edges += sc.edges;
         my_act |= sc.act;
@@ -872,6 +954,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
         my_full_m += sc.full_m;
         my_larcs += sc.larcs;
         my_arcs += sc.arcs;
+        my_pairs += sc.pairs;
         my_maxe = max(my_maxe, sc.maxe);
         my_mine = min(my_mine, sc.mine);
     } else if (phase == PH_BWD) {
@@ -886,7 +969,8 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
         const int total = n_groups + hseg;
         for (int it = gw; it < total; it += nw) {
             if (it < n_groups) {
-                bwd_group<MODE>(a, fb_nxt, fb_cur, TB, qb, it * kGroup, cnt, dead, sh, shn, my_larcs, my_arcs);
+                bwd_group<MODE>(a, fb_nxt, fb_cur, TB, qb, it * kGroup, cnt, dead, sh, shn, my_larcs, my_arcs,
+                                my_pairs);
                 continue;
             }
             const int t = it - n_groups;
@@ -894,10 +978,11 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             const int s = t - a.hq.seg[h];
             const int p = a.hq.pos[h];
             const int v = a.lq_vtx[p];
-            const unsigned long long M = a.lq_mask[p] & ~dead;
+            const unsigned long long Mf = a.lq_mask[p];
+            const unsigned long long M = Mf & ~dead;
             const int e0 = rp[v], e1 = rp[v + 1];
             const int a0 = e0 + s * kSeg, a1 = min(e1, a0 + kSeg);
-            double acc = M ? bwd_arcs(a, fb_nxt, TB + 1u, M, a0, a1, col, my_larcs) : 0.0;
+            double acc = M ? bwd_arcs(a, fb_nxt, TB + 1u, M, a0, a1, col, my_larcs, my_pairs) : 0.0;
             if (lane == 0) my_arcs += (unsigned)(a1 - a0);
             a.hq.part_lo[(size_t)(a.hq.seg[h] + s) * kLanes + lane] = as_u64(acc);
             const int ns = n_segments(e1 - e0);
@@ -905,8 +990,13 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             acc = 0.0;
             for (int k = 0; k < ns; ++k) acc += as_f64(a.hq.part_lo[(size_t)(a.hq.seg[h] + k) * kLanes + lane]);
             if (lane == 0) a.hq.cnt[h] = 0;
-            bwd_finalize<MODE>(a, fb_cur, TB, v, M, acc, sh, shn);
+            bwd_finalize<MODE>(a, fb_cur, TB, v, Mf, M, a.lq_off[p], acc, sh, shn);
         }
+    } else if (phase == PH_UNDO) {
+        // timing collection: forget the level just discovered (its entries
+        // are the only vertices with next words set)
+        const int qs = s_qe, cnt = s_qn;
+        for (int i = blockIdx.x * kBlock + tid; i < cnt; i += (int)nblk * kBlock) a.vn[a.lq_vtx[qs + i]].nxt = 0ull;
     } else if (phase == PH_BC) {
         // dependencies -> BC in source-list order, then clear the visited words
         const int lo = s_lo, span = s_hi - s_lo;
@@ -944,12 +1034,12 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
                 else hi = mid;
             }
             const int v = a.lq_vtx[j];
-            const unsigned long long val = a.sig[(size_t)v * kLanes + k];
             if (phase == PH_DUMP_FWD) {
+                const unsigned long long mj = a.lq_mask[j];
                 a.dump_d[v] = lo;
-                a.dump_sig[v] = val;
+                a.dump_sig[v] = a.pk_sig[a.lq_off[j] + (uint32_t)__popcll(mj & ((1ull << k) - 1ull))];
             } else if (lo >= 1) {
-                a.dump_delta[v] = as_f64(val);
+                a.dump_delta[v] = as_f64(a.sig[(size_t)v * kLanes + k]);
             }
         }
         if (phase == PH_DUMP_FWD && blockIdx.x == 0)
@@ -965,6 +1055,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
     cn.v[SC_FULLM] = my_full_m;
     cn.v[SC_ACT] = my_act;
     cn.v[SC_OVF] = my_ovf;
+    cn.v[SC_PAIRS] = my_pairs;
     if (MODE == 1 && phase == PH_SIG) {  // per-lane exponent range of the new level
         if (my_maxe != INT_MIN) atomicMax(&a.maxexp[lane], my_maxe);
         if (my_mine != INT_MAX) atomicMin(&a.maxexp[kLanes + lane], my_mine);
@@ -978,14 +1069,41 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
         c->st_steps += 1;
         c->st_arcs += s_tot[SC_ARCS];
         c->st_lane_arcs += s_tot[SC_LARCS];
+        c->st_parcs[phase] += s_tot[SC_ARCS];
+        c->st_plarcs[phase] += s_tot[SC_LARCS];
+        c->st_ppairs[phase] += s_tot[SC_PAIRS];
         const unsigned long long now = wall_clock64();
+        const unsigned long long prev_tick = c->last_tick;
         if (c->last_tick) {
             const unsigned long long dt = now - c->last_tick;
             c->st_ticks[phase] += dt;
             if (phase == PH_FWD) c->st_vticks[s_variant] += dt;
         }
         c->last_tick = now;
-        if (phase == PH_FWD) {
+        bool timed_again = false;
+        if (phase == PH_FWD && c->collect) {
+            c->ct[c->cvar] = c->last_tick ? now - prev_tick : 0ull;
+            if (c->cvar < 2) {
+                timed_again = true;  // undo, then run the level with the next variant
+                c->phase = PH_UNDO;
+            } else {
+                const uint32_t k = c->n_samples;
+                if (k < a.col_cap) {
+                    for (int i = 0; i < kMlpIn; ++i) a.col_X[(size_t)k * kMlpIn + i] = c->feat[i];
+                    for (int v = 0; v < 3; ++v) a.col_Y[(size_t)k * 3 + v] = (float)c->ct[v];
+                }
+                c->n_samples = k + 1;
+                c->cvar = 0;
+            }
+        }
+        if (phase == PH_UNDO) {
+            c->next_count = 0;
+            c->next_hq = 0;
+            c->cvar += 1;
+            c->variant = c->cvar;
+            c->phase = PH_FWD;
+        } else if (timed_again) {
+        } else if (phase == PH_FWD) {
             const uint32_t cnt = ld_agent(&c->next_count);
             const unsigned long long nh = ld_agent(&c->next_hq);
             const int qe = a.level_off[l + 1];
@@ -1040,7 +1158,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
     __syncthreads();
     action = s_cnt;
     if (action == 1) {
-        batch_begin<MODE>(a, c, c->pos, s_lds, &s_feat, s_lsrc, &s_qn, s_tmp);
+        batch_begin<MODE>(a, c, c->pos, s_lds, &s_feat, s_lsrc, &s_qn, s_tmp, s_lead);
     } else if (action == 2) {
         // finish level l+1: lane deaths, FP64 shifts, features, policy
         if (tid == 0) {
@@ -1090,7 +1208,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
         __syncthreads();
         const int v = choose_variant(a.p, c->policy, c->prev_variant, s_feat, (float)(c->range_hi - c->range_lo),
                                      (float)c->range_arcs, s_lds);
-        if (tid == 0) c->variant = v;
+        if (tid == 0) set_level_variant(c, v, s_feat, (float)(c->range_hi - c->range_lo), (float)c->range_arcs);
     }
 }
 

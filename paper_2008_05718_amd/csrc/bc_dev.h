@@ -13,7 +13,7 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kLanes = 64;   // sources per batch = wavefront lanes
 constexpr int kLightDeg = 32;  // thread-per-vertex loops handle up to this many arcs
 constexpr int kSeg = 1024;     // heavy vertices (degree > kSeg) are split into kSeg-arc segments
-constexpr int kPhases = 9;
+constexpr int kPhases = 10;
 constexpr int kSlots = 32;     // per-step counters and arrivals are spread over this many slots
 
 // Counters every step kernel accumulates per workgroup into its slot.
@@ -27,6 +27,7 @@ enum : int {
     SC_OVF,        // lanes / sources whose path counts overflowed (or)
     SC_MAXE,       // max binary exponent + 4096 (max)
     SC_MINE,       // 4096 - min binary exponent (max)
+    SC_PAIRS,      // matched (vertex, neighbour) pairs whose per-source rows were read (sum)
     kNCnt
 };
 
@@ -43,6 +44,7 @@ enum : int32_t {
     PH_DUMP_FWD = 6, // copy one source's d / sigma out (detail runs only)
     PH_DUMP_BWD = 7, // copy one source's delta out (detail runs only)
     PH_DONE = 8,
+    PH_UNDO = 9,     // timing collection: clear the level just discovered
 };
 
 enum : int32_t { V_PUSH_TPV = 0, V_PUSH_WPV = 1, V_PULL = 2 };
@@ -85,9 +87,16 @@ struct Ctl {
     int32_t minexp;
     uint32_t total_queued;
     uint32_t n_ovf;       // overflowed sources recorded
+    uint32_t pk_next;     // batched: packed slots handed out in the current batch
     // --- features of the frontier at level l
     unsigned long long f_nf, f_mf, visited_n, visited_m, full_n, full_m;
     unsigned long long range_nodeg, range_arcs;  // non-isolated vertices / arcs of the range
+    // --- timing collection (policy training data)
+    int32_t collect;      // 1 = run every forward level with each variant
+    int32_t cvar;         // variant being timed
+    unsigned long long ct[3];
+    float feat[kMlpIn];   // normalised features of the level being timed
+    uint32_t n_samples;
     // --- detail dump
     int64_t dump_pos;     // source position to dump (-1 = none)
     int32_t dump_lane;    // batched: lane of the dumped source in its batch
@@ -103,6 +112,9 @@ struct Ctl {
     unsigned long long last_tick;            // wall clock at the end of the previous step
     unsigned long long st_ticks[kPhases];    // wall-clock ticks spent per phase
     unsigned long long st_vticks[3];         // forward (discover) ticks per variant
+    unsigned long long st_parcs[kPhases];    // arcs scanned per phase
+    unsigned long long st_plarcs[kPhases];   // DAG (arc, source) pairs per phase
+    unsigned long long st_ppairs[kPhases];   // matched neighbour rows per phase
 };
 
 enum : int32_t { ERR_QUEUE_CAP = 1, ERR_SIGMA_RANGE = 2, ERR_LEVEL_CAP = 4, ERR_OVF_CAP = 8 };
@@ -170,7 +182,7 @@ struct PlainArgs {
 struct __attribute__((aligned(16))) Tagged {
     unsigned long long mask;
     uint32_t tag;
-    uint32_t pad;
+    uint32_t off;  // batched engine: packed offset of the entry's per-source values
 };
 // Visited / next lane words of a vertex, one 16-byte load.
 struct __attribute__((aligned(16))) VisNext {
@@ -190,8 +202,11 @@ struct BatchArgs {
     uint32_t lq_cap;
     int32_t *level_off;          // [max_levels + 2]
     int32_t max_levels;
-    unsigned long long *sig;     // [n][64] uint64 / FP64 bits; delta after the backward
-    double *chat;                // [n][64]
+    unsigned long long *sig;     // [n][64] dense delta slab (read by PH_BC and dumps)
+    unsigned long long *pk_sig;  // packed per-entry path counts (uint64 / FP64 bits)
+    double *pk_chat;             // packed per-entry c = (1 + delta) / sigma
+    uint32_t *lq_off;            // packed offset of each level-queue entry
+    uint32_t pk_cap;
     int32_t *shift;              // [max_levels + 2][64] (mode 1)
     int32_t *maxexp;             // [128]: per-lane max (0..63) and min (64..127) exponents (mode 1)
     double *bc;                  // [n]
@@ -208,6 +223,9 @@ struct BatchArgs {
     double *dump_delta;
     int32_t *dump_shift;         // [max_levels + 2]
     HeavyQ hq;
+    float *col_X;                // collected features [cap][5]
+    float *col_Y;                // collected device ticks per variant [cap][3]
+    uint32_t col_cap;
 };
 
 }  // namespace bcx

@@ -642,6 +642,9 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
         c->st_steps += 1;
         c->st_arcs += s_tot[SC_ARCS];
         c->st_lane_arcs += s_tot[SC_LARCS];
+        c->st_parcs[phase] += s_tot[SC_ARCS];
+        c->st_plarcs[phase] += s_tot[SC_LARCS];
+        c->st_ppairs[phase] += s_tot[SC_PAIRS];
         const unsigned long long now = wall_clock64();
         if (c->last_tick) {
             const unsigned long long dt = now - c->last_tick;
