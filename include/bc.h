@@ -213,6 +213,11 @@ typedef struct bc_stats {
     int64_t phase_arcs[10];    /* arcs scanned per phase                      */
     int64_t phase_lane_arcs[10];/* DAG (arc, source) pairs per phase          */
     int64_t phase_pairs[10];   /* matched neighbours whose per-source values were read */
+    int64_t mode_launches[2];  /* step-kernel launches of the 64-bit (0) and FP64 (1)
+                                  path-count passes                            */
+    double mode_ms[2];         /* device time of those passes: HIP events on the run's
+                                  stream around each pass's launches           */
+    double mode_algo_bytes[2]; /* algorithmic bytes of those passes            */
 } bc_stats;
 
 bc_status bc_run_stats(const bc_graph *g, bc_stats *out);

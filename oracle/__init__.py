@@ -46,6 +46,8 @@ def _load():
     lib.oracle_bc.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.c_int64, P, P]
     lib.oracle_source.restype = ctypes.c_int
     lib.oracle_source.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_int32, P, P, P, P, P]
+    lib.oracle_path_excess.restype = ctypes.c_int
+    lib.oracle_path_excess.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.c_int64, P]
     lib.oracle_sizeof_long_double.restype = ctypes.c_int
     if lib.oracle_sizeof_long_double() != np.dtype(np.longdouble).itemsize:
         raise RuntimeError("long double size mismatch between gcc and numpy")
@@ -110,3 +112,38 @@ def source(g, s: int) -> SourceDetail:
     r.mode = int(mode)
     r.n_levels = int(nl[0])
     return r
+
+
+def path_excess(g, sources, threads: int = 0) -> np.ndarray:
+    """Per source, the sum over reached t != s of (d(s, t) - 1), as int64.
+
+    This equals sum_v delta_s(v), so a BC vector over ``sources`` must sum to
+    ``path_excess(g, sources).sum()``.  Only distances are computed (plain
+    BFS); slices of the source list run on ``threads`` host threads (0 = all
+    cores, at most 16), each call owning its buffers.
+    """
+    from concurrent.futures import ThreadPoolExecutor
+    lib = _load()
+    rp32, rp64 = _rp(g)
+    col = np.ascontiguousarray(g.col_idx, dtype=np.int32)
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    out = np.zeros(src.size, dtype=np.int64)
+    if src.size == 0:
+        return out
+    nt = threads or min(16, os.cpu_count() or 1)
+    nt = max(1, min(nt, src.size))
+    bounds = np.linspace(0, src.size, nt + 1).astype(np.int64)
+
+    def work(i):
+        lo, hi = int(bounds[i]), int(bounds[i + 1])
+        if hi <= lo:
+            return 0
+        s = src[lo:hi]
+        o = out[lo:hi]
+        return lib.oracle_path_excess(g.n, _ptr(rp32), _ptr(rp64), _ptr(col), _ptr(s), hi - lo, _ptr(o))
+
+    with ThreadPoolExecutor(nt) as ex:
+        rcs = list(ex.map(work, range(nt)))
+    if any(rcs):
+        raise ValueError(f"oracle_path_excess failed with codes {rcs}")
+    return out

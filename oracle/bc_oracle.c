@@ -222,3 +222,48 @@ int oracle_source(int32_t n, const int32_t *row_ptr32, const int64_t *row_ptr64,
 /* Size of long double in this build, so the loader can check it matches
  * numpy's longdouble. */
 int oracle_sizeof_long_double(void) { return (int)sizeof(long double); }
+
+/*
+ * Path-length excess per source: excess[k] = sum over vertices t reached from
+ * sources[k], t != s, of (d(s, t) - 1).  A shortest s-t path has d(s, t) - 1
+ * interior vertices and every interior vertex v of the sigma_st paths takes
+ * the share sigma_st(v) / sigma_st, so these shares sum to d(s, t) - 1 and,
+ * summed over t, sum_v delta_s(v) = excess (Eq. 1 and 2 with the readings
+ * above).  Plain queue BFS; it touches no path count, so it checks the
+ * dependency sums of any size of run independently.  Reentrant: every call
+ * owns its buffers, so disjoint source slices may run on several threads.
+ */
+int oracle_path_excess(int32_t n, const int32_t *row_ptr32, const int64_t *row_ptr64, const int32_t *col,
+                       const int32_t *sources, int64_t n_sources, int64_t *excess)
+{
+    if (n <= 0 || (!row_ptr32 && !row_ptr64) || !sources || !excess) return ORC_ERR_ARG;
+    int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    if (!d || !queue) { free(d); free(queue); return ORC_ERR_MEM; }
+    for (int32_t i = 0; i < n; ++i) d[i] = -1;
+    for (int64_t k = 0; k < n_sources; ++k) {
+        const int32_t s = sources[k];
+        if (s < 0 || s >= n) { free(d); free(queue); return ORC_ERR_ARG; }
+        int64_t head = 0, tail = 0, sum = 0;
+        queue[tail++] = s;
+        d[s] = 0;
+        while (head < tail) {
+            const int32_t v = queue[head++];
+            const int64_t e0 = row_ptr64 ? row_ptr64[v] : (int64_t)row_ptr32[v];
+            const int64_t e1 = row_ptr64 ? row_ptr64[v + 1] : (int64_t)row_ptr32[v + 1];
+            for (int64_t e = e0; e < e1; ++e) {
+                const int32_t x = col[e];
+                if (d[x] == -1) {
+                    d[x] = d[v] + 1;
+                    sum += d[x] - 1;
+                    queue[tail++] = x;
+                }
+            }
+        }
+        excess[k] = sum;
+        for (int64_t i = 0; i < tail; ++i) d[queue[i]] = -1; /* reset only what was reached */
+    }
+    free(d);
+    free(queue);
+    return ORC_OK;
+}

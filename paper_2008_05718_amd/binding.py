@@ -78,7 +78,8 @@ class Stats(ctypes.Structure):
                 ("queue_entries", ctypes.c_int64), ("algo_bytes", ctypes.c_double), ("ms", ctypes.c_double),
                 ("phase_ms", ctypes.c_double * 10), ("variant_ms", ctypes.c_double * 3),
                 ("phase_arcs", ctypes.c_int64 * 10), ("phase_lane_arcs", ctypes.c_int64 * 10),
-                ("phase_pairs", ctypes.c_int64 * 10)]
+                ("phase_pairs", ctypes.c_int64 * 10), ("mode_launches", ctypes.c_int64 * 2),
+                ("mode_ms", ctypes.c_double * 2), ("mode_algo_bytes", ctypes.c_double * 2)]
 
 
 _lib = None

@@ -540,7 +540,7 @@ static bc_status get_graph(bc_graph *g, const Args &args, void (*kern)(Args), co
 // Launch chunks of step kernels until the device state machine reports done.
 template <typename Args>
 static bc_status drive(bc_graph *g, const Args &args, void (*kern)(Args), const RunCfg &cfg, hipStream_t st,
-                       int64_t max_steps, int64_t *launches) {
+                       int64_t max_steps, int64_t *launches, double *dev_ms) {
     hipGraphExec_t exec = nullptr;
     if (cfg.use_graphs) {
         bc_status s = get_graph(g, args, kern, cfg, &exec);
@@ -549,6 +549,12 @@ static bc_status drive(bc_graph *g, const Args &args, void (*kern)(Args), const 
     const int kRing = 4;
     hipEvent_t ev[kRing];
     for (int i = 0; i < kRing; ++i) HIP_TRY(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+    // device time of the whole pass: from before the first step launch to
+    // after the last, on the launch stream
+    hipEvent_t t_ev[2];
+    HIP_TRY(hipEventCreate(&t_ev[0]));
+    HIP_TRY(hipEventCreate(&t_ev[1]));
+    HIP_TRY(hipEventRecord(t_ev[0], st));
     int64_t issued = 0, chunks = 0;
     bc_status result = BC_OK;
     g->flag_host[0] = PH_IDLE;
@@ -591,7 +597,12 @@ static bc_status drive(bc_graph *g, const Args &args, void (*kern)(Args), const 
         issued += cfg.chunk;
         ++chunks;
     }
+    (void)hipEventRecord(t_ev[1], st);
     hipError_t e = hipStreamSynchronize(st);
+    float pass_ms = 0.0f;
+    if (e == hipSuccess && hipEventElapsedTime(&pass_ms, t_ev[0], t_ev[1]) == hipSuccess) *dev_ms += pass_ms;
+    (void)hipEventDestroy(t_ev[0]);
+    (void)hipEventDestroy(t_ev[1]);
     for (int i = 0; i < kRing; ++i) (void)hipEventDestroy(ev[i]);
     if (e != hipSuccess && result == BC_OK) result = fail(BC_ERR_DEVICE, std::string("stream sync: ") + hipGetErrorString(e));
     *launches += issued;
@@ -622,6 +633,14 @@ struct DumpBufs {
     double *delta = nullptr;
     int32_t *shift = nullptr;
 };
+
+// Algorithmic bytes: every scanned arc reads its column index and a 4-8 byte
+// word of the neighbour (8 B + 8 B), every DAG (arc, source) pair moves one
+// 8-byte path count or c value, every level-queue entry costs its row
+// offsets, queue slots and per-vertex words (32 B).
+static double algo_bytes(const bc_stats &s) {
+    return 16.0 * (double)s.arcs_scanned + 8.0 * (double)s.lane_arcs + 32.0 * (double)s.queue_entries;
+}
 
 static void accumulate_stats(bc_stats *s, const Ctl &c, double clock_khz) {
     for (int i = 0; i < kPhases; ++i) s->phase_ms[i] += (double)c.st_ticks[i] / clock_khz;
@@ -682,6 +701,7 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
     ga.hv_seg = g->hv_seg;
     ga.n_heavy = g->n_heavy;
     int64_t launches = 0;
+    double dev_ms = 0.0;
     if (cfg.engine == 1) {
         s = ensure_plain(g, st);
         if (s != BC_OK) return s;
@@ -715,7 +735,7 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
         }
         const double bound = (double)ns * (2.0 * (double)g->n + 6.0) + 64.0;
         const int64_t max_steps = bound > 4e18 ? (int64_t)4e18 : (int64_t)bound;
-        s = drive(g, a, cfg.mode ? plain_step<1> : plain_step<0>, cfg, st, max_steps, &launches);
+        s = drive(g, a, cfg.mode ? plain_step<1> : plain_step<0>, cfg, st, max_steps, &launches, &dev_ms);
         if (s != BC_OK) g->plain_dirty = true;
     } else {
         s = ensure_batched(g);
@@ -813,14 +833,19 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
         }
         const int64_t maxl = std::min<int64_t>(g->n, g->b_max_levels) + 2;
         const int64_t max_steps = (nb + 1) * ((col ? 7 : 3) * maxl + 8) + 64;
-        s = drive(g, a, cfg.mode ? batch_step<1> : batch_step<0>, cfg, st, max_steps, &launches);
+        s = drive(g, a, cfg.mode ? batch_step<1> : batch_step<0>, cfg, st, max_steps, &launches, &dev_ms);
     }
     g->stats.launches += launches;
     if (s != BC_OK) return s;
     HIP_TRY(hipMemcpyAsync(hc, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     *ctl_out = *hc;
+    const double bytes0 = algo_bytes(g->stats);
     accumulate_stats(&g->stats, *hc, g->clock_khz);
+    const int mi = cfg.mode ? 1 : 0;
+    g->stats.mode_launches[mi] += launches;
+    g->stats.mode_ms[mi] += dev_ms;
+    g->stats.mode_algo_bytes[mi] += algo_bytes(g->stats) - bytes0;
     if (hc->err) {
         g->plain_dirty = true;
         return ctl_error(*hc);
@@ -986,11 +1011,7 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
         detail->n_levels = L;
     }
     g->stats.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    // algorithmic bytes: every scanned arc reads its column index and a 4-8
-    // byte word of the neighbour (8 B + 8 B), every DAG (arc, source) pair
-    // moves one 8-byte path count or c value, every level-queue entry costs
-    // its row offsets, queue slots and per-vertex words (32 B).
-    g->stats.algo_bytes = 16.0 * g->stats.arcs_scanned + 8.0 * g->stats.lane_arcs + 32.0 * g->stats.queue_entries;
+    g->stats.algo_bytes = algo_bytes(g->stats);
     return BC_OK;
 }
 

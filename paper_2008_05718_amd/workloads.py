@@ -68,7 +68,12 @@ def csr_from_edges(n: int, u: np.ndarray, v: np.ndarray, name: str = "") -> CSR:
         if u.min() < 0 or v.min() < 0 or u.max() >= n or v.max() >= n:
             raise ValueError("edge endpoint out of range")
     keys = np.concatenate([u * n + v, v * n + u])
-    keys = np.unique(keys)
+    keys.sort()
+    if keys.size:
+        keep = np.empty(keys.size, dtype=bool)
+        keep[0] = True
+        np.not_equal(keys[1:], keys[:-1], out=keep[1:])
+        keys = keys[keep]
     rows = keys // n
     cols = (keys - rows * n).astype(np.int32)
     counts = np.bincount(rows, minlength=n)

@@ -314,3 +314,28 @@ def test_planted_mistake_is_caught(name, monkeypatch):
             caught = True
         monkeypatch.setattr(oracle, "_lib", None)
     assert caught, f"mutation {name} was not detected by the pins"
+
+
+def test_path_excess_matches_scipy_and_closed_form():
+    # the BFS-only checker used for full-size runs: scipy's unweighted
+    # shortest paths (library routine) and the intact grid seen from a corner
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import shortest_path
+    g = W.union([W.rmat(10, 8, seed=8), W.erdos_renyi(300, 3.0, seed=2)])
+    A = csr_matrix((np.ones(g.nnz), g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    srcs = W.choose_sources(g, 40, seed=3)
+    D = shortest_path(A, unweighted=True, indices=srcs)
+    want = [int(np.sum(row[np.isfinite(row) & (row > 0)] - 1)) for row in D]
+    assert oracle.path_excess(g, srcs, threads=3).tolist() == want
+    L = 30
+    closed = sum(i + j - 1 for i in range(L) for j in range(L) if i + j > 0)
+    assert oracle.path_excess(W.grid(L), [0]).tolist() == [closed]
+
+
+def test_path_excess_equals_dependency_sums():
+    g = W.rmat(11, 16, seed=21)
+    srcs = W.choose_sources(g, 16, seed=5)
+    ex = oracle.path_excess(g, srcs, threads=4)
+    for s, e in zip(srcs, ex):
+        det = oracle.source(g, int(s))
+        assert _close(float(np.sum(det.delta[det.d > 0])), float(e), 1e-11)
