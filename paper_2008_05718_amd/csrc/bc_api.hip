@@ -447,6 +447,9 @@ static bc_status ensure_plain(bc_graph *g, hipStream_t st) {
 static bc_status ensure_batched(bc_graph *g) {
     if (g->batch_ready) return BC_OK;
     const int64_t n = g->n;
+    // per-(vertex, lane) slots are addressed with 32-bit offsets v * 64 + k
+    if (n * kLanes + kLanes > (int64_t)UINT32_MAX)
+        return fail(BC_ERR_NOT_SUPPORTED, "more than 2^26 - 1 vertices: use the per-source engine (batch = 1)");
     HIP_TRY(dalloc(&g->b_vn, (size_t)n, &g->bytes));
     HIP_TRY(dalloc(&g->b_fw0, (size_t)n, &g->bytes));
     HIP_TRY(dalloc(&g->b_fw1, (size_t)n, &g->bytes));
@@ -466,7 +469,7 @@ static bc_status ensure_batched(bc_graph *g) {
     HIP_TRY(dalloc(&g->b_chat, (size_t)pk, &g->bytes));
     HIP_TRY(dalloc(&g->b_lq_off, (size_t)cap, &g->bytes));
     HIP_TRY(dalloc(&g->b_shift, ((size_t)g->b_max_levels + 2) * kLanes, &g->bytes));
-    HIP_TRY(dalloc(&g->b_maxexp, (size_t)2 * kLanes, &g->bytes));
+    HIP_TRY(dalloc(&g->b_maxexp, (size_t)2 * kSlots * kLanes, &g->bytes));
     HIP_TRY(dalloc(&g->b_lane_src, (size_t)kLanes, &g->bytes));
     // a heavy vertex sits on at most 64 distinct levels of a batch (one per lane)
     bc_status s = alloc_hq(g, &g->b_hq, (int64_t)g->n_heavy * kLanes + kLanes, (int64_t)g->b_max_levels + 3, kLanes);
@@ -778,8 +781,8 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
             fill_u64<<<grid_for(2 * n, 256, 4096), 256, 0, st>>>((unsigned long long *)g->b_fw0, 2 * n, 0ull);
             fill_u64<<<grid_for(2 * n, 256, 4096), 256, 0, st>>>((unsigned long long *)g->b_fw1, 2 * n, 0ull);
         }
-        fill_i32<<<1, 128, 0, st>>>(g->b_maxexp, kLanes, INT_MIN);
-        fill_i32<<<1, 128, 0, st>>>(g->b_maxexp + kLanes, kLanes, INT_MAX);
+        fill_i32<<<8, 256, 0, st>>>(g->b_maxexp, kSlots * kLanes, INT_MIN);
+        fill_i32<<<8, 256, 0, st>>>(g->b_maxexp + kSlots * kLanes, kSlots * kLanes, INT_MAX);
         HIP_TRY(hipGetLastError());
         hc->phase = PH_BC;
         hc->pos = -1;

@@ -71,6 +71,18 @@ constexpr int kUnroll = BC_UNROLL;  // matched neighbours whose values are loade
 // slots from its offset, lane k at off + popc(M & lanes-below-k).  The
 // frontier tag of v carries (M, level tag, off), so reading a neighbour's
 // values for a subset x of M touches one short contiguous run.
+#ifndef BC_DENSE
+#define BC_DENSE 1
+#endif
+constexpr bool kDense = BC_DENSE != 0;
+
+// Slot of this lane's value in an entry with lane mask m: dense slabs keep
+// lane k of vertex v at v * 64 + k (entry offset v * 64), packed entries at
+// off + popc(m below k).
+__device__ __forceinline__ uint32_t slot_of(unsigned long long m) {
+    return kDense ? (uint32_t)lane_id() : lanes_below(m);
+}
+
 __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long x, int j) {
     const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, j);
     const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), j);
@@ -134,7 +146,7 @@ __device__ __forceinline__ void sig_arcs(const BatchArgs &a, const Tagged *__res
             unsigned long long val[kUnroll];
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q)
-                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.pk_sig[mt.off[q] + lanes_below(mt.mu[q])] : 0ull;
+                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.pk_sig[mt.off[q] + slot_of(mt.mu[q])] : 0ull;
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q) {
                 if ((mt.x[q] >> lane) & 1ull) {
@@ -180,7 +192,7 @@ __device__ __forceinline__ double bwd_arcs(const BatchArgs &a, const Tagged *__r
             double val[kUnroll];
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q)
-                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.pk_chat[mt.off[q] + lanes_below(mt.mu[q])] : 0.0;
+                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.pk_chat[mt.off[q] + slot_of(mt.mu[q])] : 0.0;
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q) {
                 if ((mt.x[q] >> lane) & 1ull) acc += val[q];
@@ -238,7 +250,7 @@ __device__ __forceinline__ void sig_finalize(const BatchArgs &a, Tagged *fw_nxt,
                                              unsigned long long lmask, SigCounters &sc) {
     const int lane = lane_id();
     if ((m >> lane) & 1ull) {
-        const uint32_t at = off + lanes_below(m);
+        const uint32_t at = off + slot_of(m);
         if (MODE == 0) a.pk_sig[at] = lo;
         else a.pk_sig[at] = as_u64(accd);
         if (MODE == 0) {
@@ -279,7 +291,7 @@ __device__ __forceinline__ void bwd_finalize(const BatchArgs &a, Tagged *fb_cur,
                                              int sh, int shn) {
     const int lane = lane_id();
     if ((M >> lane) & 1ull) {
-        const uint32_t at = off + lanes_below(Mf);
+        const uint32_t at = off + slot_of(Mf);
         const unsigned long long raw = a.pk_sig[at];
         const double sv = MODE ? ldexp(as_f64(raw), -sh) : (double)raw;
         double delta = sv * acc;
@@ -345,8 +357,8 @@ __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__re
     // packed slots of every light or medium entry of the group, one atomic
     const int need = (light || medium) ? __popcll(nxt) : 0;
     const int pincl = wave_incl_scan(need);
-    const uint32_t pbase = alloc_packed(a, (unsigned)__shfl(pincl, 63));
-    const uint32_t poff = pbase + (uint32_t)(pincl - need);
+    const uint32_t pbase = kDense ? 0u : alloc_packed(a, (unsigned)__shfl(pincl, 63));
+    const uint32_t poff = kDense ? (uint32_t)w * kLanes : pbase + (uint32_t)(pincl - need);
     const int dl = light ? deg : 0;
     const int incl = wave_incl_scan(dl);
     const int off = incl - dl;
@@ -390,7 +402,7 @@ __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__re
             unsigned long long val[kUnroll];
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q)
-                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.pk_sig[mt.off[q] + lanes_below(mt.mu[q])] : 0ull;
+                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.pk_sig[mt.off[q] + slot_of(mt.mu[q])] : 0ull;
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q) {
                 if (mt.own[q] < 0) continue;
@@ -488,7 +500,7 @@ __device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__re
             double val[kUnroll];
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q)
-                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.pk_chat[mt.off[q] + lanes_below(mt.mu[q])] : 0.0;
+                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.pk_chat[mt.off[q] + slot_of(mt.mu[q])] : 0.0;
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q) {
                 if (mt.own[q] < 0) continue;
@@ -565,8 +577,8 @@ __device__ __forceinline__ void batch_begin(const BatchArgs &a, Ctl *c, int64_t 
         // the entry's packed slots follow those of entries with a lower leader
         int before = 0;
         for (int k = 0; k < lanes; ++k) before += (s_lead[k] < lead) ? 1 : 0;
-        const uint32_t eoff = (uint32_t)before;
-        a.pk_sig[eoff + (uint32_t)__popcll(m & ((1ull << t) - 1ull))] = MODE ? as_u64(1.0) : 1ull;
+        const uint32_t eoff = kDense ? (uint32_t)s * kLanes : (uint32_t)before;
+        a.pk_sig[eoff + (kDense ? (uint32_t)t : (uint32_t)__popcll(m & ((1ull << t) - 1ull)))] = MODE ? as_u64(1.0) : 1ull;
         if (lead == t) {
             const int j = atomicAdd(s_cnt, 1);
             a.lq_vtx[j] = s;
@@ -655,6 +667,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
     __shared__ Stage s_stage[kWavesPerBlock];
     __shared__ float s_lds[2 * kMlpH + 4];
     __shared__ LevelFeatures s_feat;
+    __shared__ int s_emax[kLanes], s_emin[kLanes];
     Ctl *c = a.ctl;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     if (tid == 0) {
@@ -725,7 +738,11 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
         }
         s_nblk = active_blocks(items);
     }
-    if (tid < kLanes) s_lsrc[tid] = a.lane_src[tid];
+    if (tid < kLanes) {
+        s_lsrc[tid] = a.lane_src[tid];
+        s_emax[tid] = INT_MIN;
+        s_emin[tid] = INT_MAX;
+    }
     __syncthreads();
     const int phase = s_phase;
     if (phase == PH_DONE || phase == PH_IDLE) return;
@@ -757,7 +774,8 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
         if (variant == V_PUSH_TPV || variant == V_PUSH_WPV) {
             const int n_light = variant == V_PUSH_TPV ? (cnt + kWave - 1) / kWave : cnt;
             const int total = n_light + hseg;
-            for (int it = gw; it < total; it += nw) {
+            for (int k = gw; k < total; k += nw) {
+                const int it = k < hseg ? n_light + k : k - hseg;  // heavy segments first
                 if (it >= n_light) {  // one segment of a heavy frontier vertex
                     const int t = it - n_light;
                     const int h = seg_owner(a.hq.seg, h0, h1, t);
@@ -816,7 +834,8 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             const int n_light = (span + kWave - 1) / kWave;
             const int total = n_light + hseg;
             const int hs0 = a.g.hv_seg[h0];
-            for (int it = gw; it < total; it += nw) {
+            for (int k = gw; k < total; k += nw) {
+                const int it = k < hseg ? n_light + k : k - hseg;  // heavy segments first
                 if (it >= n_light) {  // one segment of a heavy unvisited vertex
                     const int t = hs0 + (it - n_light);
                     const int h = seg_owner(a.g.hv_seg, h0, h1, t);
@@ -903,7 +922,8 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
         const int n_groups = (cnt + kGroup - 1) / kGroup;
         const int total = n_groups + hseg;
         SigCounters sc;
-        for (int it = gw; it < total; it += nw) {
+        for (int k = gw; k < total; k += nw) {
+            const int it = k < hseg ? n_groups + k : k - hseg;  // heavy segments first
             if (it < n_groups) {
                 sig_group<MODE>(a, fw_cur, fw_nxt, T, qs, it * kGroup, cnt, sh, lmask, sc);
                 continue;
@@ -944,7 +964,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             }
             if (lane == 0) a.hq.cnt[h] = 0;
             const VisNext x = a.vn[w];
-            const uint32_t poff = alloc_packed(a, (unsigned)__popcll(x.nxt));
+            const uint32_t poff = kDense ? (uint32_t)w * kLanes : alloc_packed(a, (unsigned)__popcll(x.nxt));
             sig_finalize<MODE>(a, fw_nxt, T + 1u, p, w, x.vis, x.nxt, e1 - e0, poff, lo, hi, accd, lmask, sc);
         }
         my_edges += sc.edges;
@@ -967,7 +987,8 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
         const int shn = (MODE && l + 1 < s_L) ? a.shift[(size_t)(l + 1) * kLanes + lane] : 0;
         const int n_groups = (cnt + kGroup - 1) / kGroup;
         const int total = n_groups + hseg;
-        for (int it = gw; it < total; it += nw) {
+        for (int k = gw; k < total; k += nw) {
+            const int it = k < hseg ? n_groups + k : k - hseg;  // heavy segments first
             if (it < n_groups) {
                 bwd_group<MODE>(a, fb_nxt, fb_cur, TB, qb, it * kGroup, cnt, dead, sh, shn, my_larcs, my_arcs,
                                 my_pairs);
@@ -1037,7 +1058,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             if (phase == PH_DUMP_FWD) {
                 const unsigned long long mj = a.lq_mask[j];
                 a.dump_d[v] = lo;
-                a.dump_sig[v] = a.pk_sig[a.lq_off[j] + (uint32_t)__popcll(mj & ((1ull << k) - 1ull))];
+                a.dump_sig[v] = a.pk_sig[a.lq_off[j] + (kDense ? (uint32_t)k : (uint32_t)__popcll(mj & ((1ull << k) - 1ull)))];
             } else if (lo >= 1) {
                 a.dump_delta[v] = as_f64(a.sig[(size_t)v * kLanes + k]);
             }
@@ -1056,9 +1077,18 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
     cn.v[SC_ACT] = my_act;
     cn.v[SC_OVF] = my_ovf;
     cn.v[SC_PAIRS] = my_pairs;
-    if (MODE == 1 && phase == PH_SIG) {  // per-lane exponent range of the new level
-        if (my_maxe != INT_MIN) atomicMax(&a.maxexp[lane], my_maxe);
-        if (my_mine != INT_MAX) atomicMin(&a.maxexp[kLanes + lane], my_mine);
+    if (MODE == 1 && phase == PH_SIG) {
+        // per-lane exponent range of the new level: reduced over the
+        // workgroup in LDS, then one atomic per lane into the workgroup's slot
+        if (active) {
+            if (my_maxe != INT_MIN) atomicMax(&s_emax[lane], my_maxe);
+            if (my_mine != INT_MAX) atomicMin(&s_emin[lane], my_mine);
+        }
+        __syncthreads();
+        const int slot = blockIdx.x % kSlots;
+        if (tid < kLanes && s_emax[tid] != INT_MIN) atomicMax(&a.maxexp[slot * kLanes + tid], s_emax[tid]);
+        else if (tid >= kLanes && tid < 2 * kLanes && s_emin[tid - kLanes] != INT_MAX)
+            atomicMin(&a.maxexp[(kSlots + slot) * kLanes + tid - kLanes], s_emin[tid - kLanes]);
     }
     if (!step_epilogue(c, cn, s_red, &s_last, active)) return;
     collect_slots(c, s_tot, s_red);
@@ -1179,13 +1209,17 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             c->active = s_tot[SC_ACT] & ~c->dead;
         }
         if (MODE && tid < kLanes) {
-            const int mx = ld_agent(&a.maxexp[tid]), mn = ld_agent(&a.maxexp[kLanes + tid]);
+            int mx = INT_MIN, mn = INT_MAX;
+            for (int sl = 0; sl < kSlots; ++sl) {
+                mx = max(mx, ld_agent(&a.maxexp[sl * kLanes + tid]));
+                mn = min(mn, ld_agent(&a.maxexp[(kSlots + sl) * kLanes + tid]));
+                a.maxexp[sl * kLanes + tid] = INT_MIN;
+                a.maxexp[(kSlots + sl) * kLanes + tid] = INT_MAX;
+            }
             int sh = 0;
             if (mx != INT_MIN && mx > 960) sh = mx - 900;
             if (mn != INT_MAX && mn - sh < -1000) atomicOr(&c->err, ERR_SIGMA_RANGE);
             a.shift[(size_t)(l + 1) * kLanes + tid] = sh;
-            a.maxexp[tid] = INT_MIN;
-            a.maxexp[kLanes + tid] = INT_MAX;
         }
         if (tid == 0) {
             const uint32_t cnt = ld_agent(&c->next_count);

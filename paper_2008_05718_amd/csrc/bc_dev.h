@@ -12,7 +12,10 @@ constexpr int kWave = 64;    // CDNA wavefront width
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kLanes = 64;   // sources per batch = wavefront lanes
 constexpr int kLightDeg = 32;  // thread-per-vertex loops handle up to this many arcs
-constexpr int kSeg = 1024;     // heavy vertices (degree > kSeg) are split into kSeg-arc segments
+#ifndef BC_SEG
+#define BC_SEG 1024
+#endif
+constexpr int kSeg = BC_SEG;   // heavy vertices (degree > kSeg) are split into kSeg-arc segments
 constexpr int kPhases = 10;
 constexpr int kSlots = 32;     // per-step counters and arrivals are spread over this many slots
 
@@ -208,7 +211,7 @@ struct BatchArgs {
     uint32_t *lq_off;            // packed offset of each level-queue entry
     uint32_t pk_cap;
     int32_t *shift;              // [max_levels + 2][64] (mode 1)
-    int32_t *maxexp;             // [128]: per-lane max (0..63) and min (64..127) exponents (mode 1)
+    int32_t *maxexp;             // [2][kSlots][64]: per-slot, per-lane max then min exponents (mode 1)
     double *bc;                  // [n]
     const int32_t *srcs;         // source list of this run
     const int64_t *batch_start;  // [n_batches + 1] positions into srcs

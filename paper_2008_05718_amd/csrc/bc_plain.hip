@@ -284,7 +284,8 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
         if (variant == V_PUSH_TPV || variant == V_PUSH_WPV) {
             const int n_light = variant == V_PUSH_TPV ? (cnt + kWave - 1) / kWave : cnt;
             const int total = n_light + hseg;
-            for (int it = gw; it < total; it += nw) {
+            for (int k = gw; k < total; k += nw) {
+                const int it = k < hseg ? n_light + k : k - hseg;  // heavy segments first
                 if (it >= n_light) {  // a segment of a heavy frontier vertex
                     const int t = it - n_light;
                     const int h = seg_owner(a.hq.seg, h0, h1, t);
@@ -349,7 +350,8 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
         } else {  // V_PULL: every unvisited vertex looks for neighbours on level l
             const int n_light = (n + kWave - 1) / kWave;
             const int total = n_light + hseg;
-            for (int it = gw; it < total; it += nw) {
+            for (int k = gw; k < total; k += nw) {
+                const int it = k < hseg ? n_light + k : k - hseg;  // heavy segments first
                 if (it >= n_light) {  // a segment of a heavy vertex
                     const int t = it - n_light;
                     const int h = seg_owner(a.g.hv_seg, h0, h1, t);
@@ -478,7 +480,8 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
         const int sh = s_sh0;
         const int n_light = (cnt + kWave - 1) / kWave;
         const int total = n_light + hseg;
-        for (int it = gw; it < total; it += nw) {
+        for (int k = gw; k < total; k += nw) {
+            const int it = k < hseg ? n_light + k : k - hseg;  // heavy segments first
             if (it >= n_light) {  // a segment of a heavy new vertex
                 const int t = it - n_light;
                 const int h = seg_owner(a.hq.seg, h0, h1, t);
@@ -546,7 +549,8 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
         const bool dump = s_dump != 0;
         const int n_light = (cnt + kWave - 1) / kWave;
         const int total = n_light + hseg;
-        for (int it = gw; it < total; it += nw) {
+        for (int k = gw; k < total; k += nw) {
+            const int it = k < hseg ? n_light + k : k - hseg;  // heavy segments first
             if (it >= n_light) {  // a segment of a heavy vertex of level l
                 const int t = it - n_light;
                 const int h = seg_owner(a.hq.seg, h0, h1, t);
