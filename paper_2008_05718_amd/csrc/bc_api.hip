@@ -142,6 +142,7 @@ struct bc_graph {
     int32_t *hv_vtx = nullptr, *hv_seg = nullptr;
     int32_t n_heavy = 0;
     int64_t heavy_segs = 0;
+    int64_t cost_units = 0;         // sum of entry_cost over all vertices
     double clock_khz = 100000.0;
     int grid_plain = 1024, grid_batch = 1024;  // resident workgroups of the step kernels
     double *bc = nullptr;
@@ -165,10 +166,10 @@ struct bc_graph {
     uint32_t b_lq_cap = 0;
     int32_t *b_level_off = nullptr;
     int32_t b_max_levels = 0;
-    unsigned long long *b_sig = nullptr, *b_pk_sig = nullptr;
-    double *b_chat = nullptr;
-    uint32_t *b_lq_off = nullptr;
-    uint32_t b_pk_cap = 0;
+    unsigned long long *b_sigma = nullptr;
+    double *b_chat = nullptr, *b_delta = nullptr;
+    uint32_t *b_gstart = nullptr, *b_gbase = nullptr;
+    uint32_t b_gcap = 0;
     int32_t *b_shift = nullptr, *b_maxexp = nullptr, *b_lane_src = nullptr;
     HeavyQ b_hq{};
     // per-run buffers (grown on demand)
@@ -201,8 +202,8 @@ extern "C" void bc_destroy(bc_graph *g) {
     free_graphs(g);
     void *dev[] = {g->row_ptr, g->col, g->bc, g->ctl, g->p_d, g->p_queue, g->p_level_off, g->p_shift,
                    g->p_sig, g->p_chat, g->b_vn, g->b_fw0, g->b_fw1, g->b_lq_vtx, g->b_lq_mask,
-                   g->b_level_off, g->b_sig, g->b_chat, g->b_shift, g->b_maxexp, g->b_lane_src,
-                   g->b_pk_sig, g->b_lq_off,
+                   g->b_level_off, g->b_delta, g->b_chat, g->b_shift, g->b_maxexp, g->b_lane_src,
+                   g->b_sigma, g->b_gstart, g->b_gbase,
                    g->srcs, g->ovf, g->bstart, g->blo, g->bhi, g->mlp, g->hv_vtx, g->hv_seg,
                    g->p_hq.pos, g->p_hq.seg, g->p_hq.cnt, g->p_hq.off, g->p_hq.nseg, g->p_hq.part_lo,
                    g->p_hq.part_hi, g->b_hq.pos, g->b_hq.seg, g->b_hq.cnt, g->b_hq.off, g->b_hq.nseg,
@@ -335,8 +336,10 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
         CR_TRY(hipMemcpy(rp.data(), g->row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost));
         std::vector<int32_t> hv, hs(1, 0);
         int64_t segs = 0;
+        int64_t cost_units = 0;
         for (int32_t v = 0; v < n; ++v) {
             const int32_t deg = rp[v + 1] - rp[v];
+            cost_units += entry_cost(deg);
             if (deg > kSeg) {
                 hv.push_back(v);
                 segs += (deg + kSeg - 1) / kSeg;
@@ -345,6 +348,7 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
         }
         g->n_heavy = (int32_t)hv.size();
         g->heavy_segs = segs;
+        g->cost_units = cost_units;
         CR_TRY(dalloc(&g->hv_vtx, hv.size(), &g->bytes));
         CR_TRY(dalloc(&g->hv_seg, hs.size(), &g->bytes));
         if (!hv.empty()) CR_TRY(hipMemcpy(g->hv_vtx, hv.data(), sizeof(int32_t) * hv.size(), hipMemcpyHostToDevice));
@@ -447,9 +451,9 @@ static bc_status ensure_plain(bc_graph *g, hipStream_t st) {
 static bc_status ensure_batched(bc_graph *g) {
     if (g->batch_ready) return BC_OK;
     const int64_t n = g->n;
-    // per-(vertex, lane) slots are addressed with 32-bit offsets v * 64 + k
-    if (n * kLanes + kLanes > (int64_t)UINT32_MAX)
-        return fail(BC_ERR_NOT_SUPPORTED, "more than 2^26 - 1 vertices: use the per-source engine (batch = 1)");
+    // level cost prefixes are 32-bit; a level holds each vertex at most once
+    if (g->cost_units >= (int64_t)UINT32_MAX)
+        return fail(BC_ERR_NOT_SUPPORTED, "graph too large for the batched engine: use batch = 1");
     HIP_TRY(dalloc(&g->b_vn, (size_t)n, &g->bytes));
     HIP_TRY(dalloc(&g->b_fw0, (size_t)n, &g->bytes));
     HIP_TRY(dalloc(&g->b_fw1, (size_t)n, &g->bytes));
@@ -461,13 +465,17 @@ static bc_status ensure_batched(bc_graph *g) {
     g->b_max_levels = (int32_t)std::min<int64_t>(n + 2, 65536);
     if (g->b_max_levels < 4) g->b_max_levels = 4;
     HIP_TRY(dalloc(&g->b_level_off, (size_t)g->b_max_levels + 2, &g->bytes));
-    HIP_TRY(dalloc(&g->b_sig, (size_t)n * kLanes, &g->bytes));
-    // packed per-entry values: every (vertex, lane) pair at most once per batch
-    const int64_t pk = std::min<int64_t>((int64_t)n * kLanes + kLanes, (int64_t)UINT32_MAX);
-    g->b_pk_cap = (uint32_t)pk;
-    HIP_TRY(dalloc(&g->b_pk_sig, (size_t)pk, &g->bytes));
-    HIP_TRY(dalloc(&g->b_chat, (size_t)pk, &g->bytes));
-    HIP_TRY(dalloc(&g->b_lq_off, (size_t)cap, &g->bytes));
+    // per-(vertex, lane) slabs of path counts, c and delta
+    HIP_TRY(dalloc(&g->b_sigma, (size_t)n * kLanes, &g->bytes));
+    HIP_TRY(dalloc(&g->b_chat, (size_t)n * kLanes, &g->bytes));
+    HIP_TRY(dalloc(&g->b_delta, (size_t)n * kLanes, &g->bytes));
+    // work groups: a vertex is on at most 64 levels of a batch; each level
+    // has cost / kBudget + 1 groups and one closing slot
+    const int64_t gcap = std::min<int64_t>((int64_t)kLanes * g->cost_units / kBudget + 2 * ((int64_t)g->b_max_levels + 2) + 64,
+                                           (int64_t)UINT32_MAX);
+    g->b_gcap = (uint32_t)gcap;
+    HIP_TRY(dalloc(&g->b_gstart, (size_t)gcap, &g->bytes));
+    HIP_TRY(dalloc(&g->b_gbase, (size_t)g->b_max_levels + 2, &g->bytes));
     HIP_TRY(dalloc(&g->b_shift, ((size_t)g->b_max_levels + 2) * kLanes, &g->bytes));
     HIP_TRY(dalloc(&g->b_maxexp, (size_t)2 * kSlots * kLanes, &g->bytes));
     HIP_TRY(dalloc(&g->b_lane_src, (size_t)kLanes, &g->bytes));
@@ -806,11 +814,12 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
         a.lq_cap = g->b_lq_cap;
         a.level_off = g->b_level_off;
         a.max_levels = g->b_max_levels;
-        a.sig = g->b_sig;
-        a.pk_sig = g->b_pk_sig;
-        a.pk_chat = g->b_chat;
-        a.lq_off = g->b_lq_off;
-        a.pk_cap = g->b_pk_cap;
+        a.delta = g->b_delta;
+        a.sigma = g->b_sigma;
+        a.chat = g->b_chat;
+        a.gstart = g->b_gstart;
+        a.gbase = g->b_gbase;
+        a.gcap = g->b_gcap;
         a.shift = g->b_shift;
         a.maxexp = g->b_maxexp;
         a.bc = g->bc;

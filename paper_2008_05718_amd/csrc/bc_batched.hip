@@ -41,7 +41,7 @@ namespace bcx {
 __device__ __forceinline__ void push_arcs_wave(const BatchArgs &a, unsigned long long f, int a0, int a1,
                                                const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                uint32_t qe, uint32_t hq_base, unsigned long long &my_edges,
-                                               Stage &st, int &sn) {
+                                               Stage &st, int &sn, const GroupArgs &gr) {
     Ctl *c = a.ctl;
     for (int eb = a0; eb < a1; eb += kWave) {
         const int e = eb + lane_id();
@@ -57,7 +57,7 @@ __device__ __forceinline__ void push_arcs_wave(const BatchArgs &a, unsigned long
                 my_edges += (unsigned)dw;
             }
         }
-        stage_push(newly, w, dw, st, sn, c, a.lq_vtx, qe, a.lq_cap, a.hq, hq_base, &c->err);
+        stage_push(newly, w, dw, st, sn, c, a.lq_vtx, qe, a.lq_cap, a.hq, hq_base, &c->err, gr);
     }
 }
 
@@ -66,52 +66,38 @@ __device__ __forceinline__ void push_arcs_wave(const BatchArgs &a, unsigned long
 #endif
 constexpr int kUnroll = BC_UNROLL;  // matched neighbours whose values are loaded together
 
-// Per-source values (path counts, c) are stored packed per level-queue entry:
-// the entry of vertex v on level l with lane mask M owns popc(M) consecutive
-// slots from its offset, lane k at off + popc(M & lanes-below-k).  The
-// frontier tag of v carries (M, level tag, off), so reading a neighbour's
-// values for a subset x of M touches one short contiguous run.
-#ifndef BC_DENSE
-#define BC_DENSE 1
-#endif
-constexpr bool kDense = BC_DENSE != 0;
-
-// Slot of this lane's value in an entry with lane mask m: dense slabs keep
-// lane k of vertex v at v * 64 + k (entry offset v * 64), packed entries at
-// off + popc(m below k).
-__device__ __forceinline__ uint32_t slot_of(unsigned long long m) {
-    return kDense ? (uint32_t)lane_id() : lanes_below(m);
-}
-
+// Per-source values live in vertex-major slabs [n][64]: path count, c and
+// delta of vertex v for lane k at v * 64 + k.  Each (vertex, lane) pair is on
+// exactly one level of a batch, so the slot is written once per batch and
+// read only through a matching level tag and lane mask; nothing is cleared.
 __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long x, int j) {
     const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, j);
     const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), j);
     return ((unsigned long long)hi << 32) | lo;
 }
 
-// Up to kUnroll matches, popped in ascending lane order: lanes x, the
-// neighbour entry's full mask mu and packed offset off (all wavefront-uniform).
+// Up to kUnroll matches, popped in ascending lane order: the lanes x that
+// take the neighbour's value, the slab row of the neighbour (v * 64) and the
+// group entry the match belongs to (all wavefront-uniform).
 struct Matches {
-    unsigned long long x[kUnroll], mu[kUnroll];
-    uint32_t off[kUnroll];
+    unsigned long long x[kUnroll];
+    size_t row[kUnroll];
     int own[kUnroll];
 };
 
-__device__ __forceinline__ void pop_matches(unsigned long long &bal, unsigned long long xj, unsigned long long mj,
-                                            uint32_t oj, int ownj, Matches &mt) {
+__device__ __forceinline__ void pop_matches(unsigned long long &bal, unsigned long long xj, int uj, int ownj,
+                                            Matches &mt) {
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q) {
         if (bal) {
             const int j = __ffsll(bal) - 1;
             bal &= bal - 1;
             mt.x[q] = readlane_u64(xj, j);
-            mt.mu[q] = readlane_u64(mj, j);
-            mt.off[q] = (uint32_t)__builtin_amdgcn_readlane((int)oj, j);
+            mt.row[q] = (size_t)__builtin_amdgcn_readlane(uj, j) * kLanes;
             mt.own[q] = __builtin_amdgcn_readlane(ownj, j);
         } else {
             mt.x[q] = 0ull;
-            mt.mu[q] = 0ull;
-            mt.off[q] = 0u;
+            mt.row[q] = 0;
             mt.own[q] = -1;
         }
     }
@@ -129,24 +115,21 @@ __device__ __forceinline__ void sig_arcs(const BatchArgs &a, const Tagged *__res
     const int lane = lane_id();
     for (int eb = a0; eb < a1; eb += kWave) {
         const int e = eb + lane;
-        unsigned long long xj = 0, mj = 0;
-        uint32_t oj = 0;
+        unsigned long long xj = 0;
+        int uj = 0;
         if (e < a1) {
-            const Tagged F = fw_cur[col[e]];
-            if (F.tag == T) {
-                xj = F.mask & m;
-                mj = F.mask;
-                oj = F.off;
-            }
+            uj = col[e];
+            const Tagged F = fw_cur[uj];
+            if (F.tag == T) xj = F.mask & m;
         }
         unsigned long long bal = __ballot(xj != 0ull);
         while (bal) {
             Matches mt;
-            pop_matches(bal, xj, mj, oj, 0, mt);
+            pop_matches(bal, xj, uj, 0, mt);
             unsigned long long val[kUnroll];
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q)
-                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.pk_sig[mt.off[q] + slot_of(mt.mu[q])] : 0ull;
+                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.sigma[mt.row[q] + lane] : 0ull;
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q) {
                 if ((mt.x[q] >> lane) & 1ull) {
@@ -175,24 +158,21 @@ __device__ __forceinline__ double bwd_arcs(const BatchArgs &a, const Tagged *__r
     double acc = 0.0;
     for (int eb = a0; eb < a1; eb += kWave) {
         const int e = eb + lane;
-        unsigned long long xj = 0, mj = 0;
-        uint32_t oj = 0;
+        unsigned long long xj = 0;
+        int uj = 0;
         if (e < a1) {
-            const Tagged F = fb_nxt[col[e]];
-            if (F.tag == TB1) {
-                xj = F.mask & M;
-                mj = F.mask;
-                oj = F.off;
-            }
+            uj = col[e];
+            const Tagged F = fb_nxt[uj];
+            if (F.tag == TB1) xj = F.mask & M;
         }
         unsigned long long bal = __ballot(xj != 0ull);
         while (bal) {
             Matches mt;
-            pop_matches(bal, xj, mj, oj, 0, mt);
+            pop_matches(bal, xj, uj, 0, mt);
             double val[kUnroll];
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q)
-                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.pk_chat[mt.off[q] + slot_of(mt.mu[q])] : 0.0;
+                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.chat[mt.row[q] + lane] : 0.0;
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q) {
                 if ((mt.x[q] >> lane) & 1ull) acc += val[q];
@@ -206,33 +186,6 @@ __device__ __forceinline__ double bwd_arcs(const BatchArgs &a, const Tagged *__r
     return acc;
 }
 
-// Segment-partial protocol: every wavefront of a heavy entry stores its
-// partial, then counts itself in; the last one returns true and may read all
-// partials.
-__device__ __forceinline__ bool seg_arrive(int32_t *cnt, int nseg) {
-    __threadfence();
-    int old = 0;
-    if (lane_id() == 0) old = atomicAdd(cnt, 1);
-    old = __shfl(old, 0);
-    const bool last = (old == nseg - 1);
-    if (last) __threadfence();
-    return last;
-}
-
-// Packed slots for new entries: exactly popc(mask) per entry, taken from the
-// batch's counter by one atomic per group of entries.  Every (vertex, lane)
-// pair gets slots once per batch, so K * n slots always suffice.
-__device__ __forceinline__ uint32_t alloc_packed(const BatchArgs &a, unsigned count) {
-    uint32_t base = 0;
-    if (lane_id() == 0 && count) {
-        base = atomicAdd(&a.ctl->pk_next, count);
-        if ((unsigned long long)base + count > a.pk_cap) {  // cannot happen: K * n bound
-            atomicOr(&a.ctl->err, ERR_QUEUE_CAP);
-            base = 0;  // keep every later access in bounds; the run reports the error
-        }
-    }
-    return (uint32_t)__shfl((int)base, 0);
-}
 
 // Per-lane counters the path-count finalisation feeds.
 struct SigCounters {
@@ -241,18 +194,17 @@ struct SigCounters {
 };
 
 // Store the path counts of new vertex w (queue position p, visited/next words
-// vis/m, degree deg, packed offset off) and publish it as part of the
-// level-(l+1) frontier.
+// vis/m, degree deg) and publish it as part of the level-(l+1) frontier.
 template <int MODE>
 __device__ __forceinline__ void sig_finalize(const BatchArgs &a, Tagged *fw_nxt, uint32_t T1, int p, int w,
-                                             unsigned long long vis, unsigned long long m, int deg, uint32_t off,
+                                             unsigned long long vis, unsigned long long m, int deg,
                                              unsigned long long lo, unsigned long long hi, double accd,
                                              unsigned long long lmask, SigCounters &sc) {
     const int lane = lane_id();
     if ((m >> lane) & 1ull) {
-        const uint32_t at = off + slot_of(m);
-        if (MODE == 0) a.pk_sig[at] = lo;
-        else a.pk_sig[at] = as_u64(accd);
+        const size_t at = (size_t)w * kLanes + lane;
+        if (MODE == 0) a.sigma[at] = lo;
+        else a.sigma[at] = as_u64(accd);
         if (MODE == 0) {
             if (hi != 0 || lo > a.sigma_limit) sc.ovf |= 1ull << lane;
         } else if (accd > 0.0) {
@@ -270,10 +222,8 @@ __device__ __forceinline__ void sig_finalize(const BatchArgs &a, Tagged *fw_nxt,
         Tagged tg;
         tg.mask = m;
         tg.tag = T1;
-        tg.off = off;
         fw_nxt[w] = tg;
         a.lq_mask[p] = m;
-        a.lq_off[p] = off;
         sc.edges += (unsigned)deg;
         sc.act |= m;
         if ((y.vis & lmask) == lmask) {
@@ -283,27 +233,26 @@ __device__ __forceinline__ void sig_finalize(const BatchArgs &a, Tagged *fw_nxt,
     }
 }
 
-// Dependencies of vertex v (entry mask Mf, live lanes M, packed offset off)
-// from the sum acc; delta also goes to the dense [n][64] slab for PH_BC.
+// Dependencies of vertex v (entry mask Mf, live lanes M) from the sum acc:
+// delta into the delta slab (read by PH_BC), c into the c slab.
 template <int MODE>
 __device__ __forceinline__ void bwd_finalize(const BatchArgs &a, Tagged *fb_cur, uint32_t TB, int v,
-                                             unsigned long long Mf, unsigned long long M, uint32_t off, double acc,
-                                             int sh, int shn) {
+                                             unsigned long long Mf, unsigned long long M, double acc, int sh,
+                                             int shn) {
     const int lane = lane_id();
     if ((M >> lane) & 1ull) {
-        const uint32_t at = off + slot_of(Mf);
-        const unsigned long long raw = a.pk_sig[at];
+        const size_t at = (size_t)v * kLanes + lane;
+        const unsigned long long raw = a.sigma[at];
         const double sv = MODE ? ldexp(as_f64(raw), -sh) : (double)raw;
         double delta = sv * acc;
         if (MODE) delta = ldexp(delta, -shn);
-        a.pk_chat[at] = (1.0 + delta) / sv;
-        a.sig[(size_t)v * kLanes + lane] = as_u64(delta);
+        a.chat[at] = (1.0 + delta) / sv;
+        a.delta[at] = delta;
     }
     if (lane == 0) {
         Tagged tg;
         tg.mask = Mf;
         tg.tag = TB;
-        tg.off = off;
         fb_cur[v] = tg;
     }
 }
@@ -323,25 +272,22 @@ __device__ __forceinline__ int packed_owner(int incl, int ai) {
 #ifndef BC_PACK
 #define BC_PACK 64
 #endif
-#ifndef BC_GROUP
-#define BC_GROUP 8
-#endif
 constexpr int kPack = BC_PACK;    // entries of degree <= kPack share 64-arc scan chunks
-constexpr int kGroup = BC_GROUP;  // queue entries per packed work item
 
-// Path counts for the kGroup queue entries [g0, g0 + kGroup) of level l+1:
+// Path counts for the entries [i0, i1) of level l+1 (one group, at most 64):
 // entries of degree <= kPack have their adjacencies packed into dense 64-arc
 // chunks; entries of degree <= kSeg follow one at a time; heavier ones run as
 // segments elsewhere.  Every entry's sum keeps CSR order.
 template <int MODE>
 __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__restrict__ fw_cur, Tagged *fw_nxt,
-                                          uint32_t T, int qs, int g0, int cnt, int sh, unsigned long long lmask,
+                                          uint32_t T, int qs, int i0, int i1, int sh, unsigned long long lmask,
                                           SigCounters &sc) {
     const int32_t *__restrict__ rp = a.g.row_ptr;
     const int32_t *__restrict__ col = a.g.col;
     const int lane = lane_id();
-    const int i = g0 + lane;
-    const bool valid = lane < kGroup && i < cnt;
+    const int i = i0 + lane;
+    const int ne = i1 - i0;
+    const bool valid = i < i1;
     const int p = qs + i;
     const int w = valid ? a.lq_vtx[p] : 0;
     const int e0 = valid ? rp[w] : 0;
@@ -354,11 +300,6 @@ __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__re
         vis = x.vis;
         nxt = x.nxt;
     }
-    // packed slots of every light or medium entry of the group, one atomic
-    const int need = (light || medium) ? __popcll(nxt) : 0;
-    const int pincl = wave_incl_scan(need);
-    const uint32_t pbase = kDense ? 0u : alloc_packed(a, (unsigned)__shfl(pincl, 63));
-    const uint32_t poff = kDense ? (uint32_t)w * kLanes : pbase + (uint32_t)(pincl - need);
     const int dl = light ? deg : 0;
     const int incl = wave_incl_scan(dl);
     const int off = incl - dl;
@@ -371,8 +312,7 @@ __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__re
             if (__builtin_amdgcn_readlane((int)light, e)) {
                 sig_finalize<MODE>(a, fw_nxt, T + 1u, __builtin_amdgcn_readlane(p, e),
                                    __builtin_amdgcn_readlane(w, e), readlane_u64(vis, e), readlane_u64(nxt, e),
-                                   __builtin_amdgcn_readlane(deg, e),
-                                   (uint32_t)__builtin_amdgcn_readlane((int)poff, e), lo, hi, accd, lmask, sc);
+                                   __builtin_amdgcn_readlane(deg, e), lo, hi, accd, lmask, sc);
             }
             lo = hi = 0;
             accd = 0.0;
@@ -384,25 +324,22 @@ __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__re
         const int o = packed_owner(incl, min(ai, total - 1));
         const int e0o = __shfl(e0, o), offo = __shfl(off, o);
         const unsigned long long mo = shfl_u64(nxt, o);
-        unsigned long long xj = 0, mj = 0;
-        uint32_t oj = 0;
+        unsigned long long xj = 0;
+        int uj = 0;
         if (ai < total) {
-            const Tagged F = fw_cur[col[e0o + (ai - offo)]];
-            if (F.tag == T) {
-                xj = F.mask & mo;
-                mj = F.mask;
-                oj = F.off;
-            }
+            uj = col[e0o + (ai - offo)];
+            const Tagged F = fw_cur[uj];
+            if (F.tag == T) xj = F.mask & mo;
         }
         if (lane == 0) sc.arcs += (unsigned)min(kWave, total - base);
         unsigned long long bal = __ballot(xj != 0ull);
         while (bal) {
             Matches mt;
-            pop_matches(bal, xj, mj, oj, o, mt);
+            pop_matches(bal, xj, uj, o, mt);
             unsigned long long val[kUnroll];
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q)
-                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.pk_sig[mt.off[q] + slot_of(mt.mu[q])] : 0ull;
+                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.sigma[mt.row[q] + lane] : 0ull;
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q) {
                 if (mt.own[q] < 0) continue;
@@ -422,7 +359,7 @@ __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__re
             }
         }
     }
-    finalize_upto(kGroup);
+    finalize_upto(ne);
     // medium-degree entries: one wavefront-wide scan each
     unsigned long long mm = __ballot(medium);
     while (mm) {
@@ -436,22 +373,23 @@ __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__re
         sig_arcs<MODE>(a, fw_cur, T, mj, a0, a0 + dj, sh, col, lo, hi, accd, sc.larcs, sc.pairs);
         if (lane == 0) sc.arcs += (unsigned)dj;
         sig_finalize<MODE>(a, fw_nxt, T + 1u, __builtin_amdgcn_readlane(p, j), wj, readlane_u64(vis, j), mj, dj,
-                           (uint32_t)__builtin_amdgcn_readlane((int)poff, j), lo, hi, accd, lmask, sc);
+                           lo, hi, accd, lmask, sc);
     }
 }
 
-// Dependencies for the kGroup queue entries [g0, g0 + kGroup) of level l,
-// packed like sig_group.
+// Dependencies for the entries [i0, i1) of level l (one group), packed like
+// sig_group.
 template <int MODE>
 __device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__restrict__ fb_nxt, Tagged *fb_cur,
-                                          uint32_t TB, int qb, int g0, int cnt, unsigned long long dead, int sh,
+                                          uint32_t TB, int qb, int i0, int i1, unsigned long long dead, int sh,
                                           int shn, unsigned long long &my_larcs, unsigned long long &my_arcs,
                                           unsigned long long &my_pairs) {
     const int32_t *__restrict__ rp = a.g.row_ptr;
     const int32_t *__restrict__ col = a.g.col;
     const int lane = lane_id();
-    const int i = g0 + lane;
-    const bool valid = lane < kGroup && i < cnt;
+    const int i = i0 + lane;
+    const int ne = i1 - i0;
+    const bool valid = i < i1;
     const int p = qb + i;
     const int v = valid ? a.lq_vtx[p] : 0;
     const int e0 = valid ? rp[v] : 0;
@@ -459,7 +397,6 @@ __device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__re
     const bool light = valid && deg <= kPack;
     const bool medium = valid && deg > kPack && deg <= kSeg;
     const unsigned long long Mf = (light || medium) ? a.lq_mask[p] : 0ull;
-    const uint32_t poff = (light || medium) ? a.lq_off[p] : 0u;
     const unsigned long long M = Mf & ~dead;
     const int dl = (light && M) ? deg : 0;
     const int incl = wave_incl_scan(dl);
@@ -471,8 +408,7 @@ __device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__re
         for (int e = cur; e < upto; ++e) {
             if (__builtin_amdgcn_readlane((int)light, e))
                 bwd_finalize<MODE>(a, fb_cur, TB, __builtin_amdgcn_readlane(v, e), readlane_u64(Mf, e),
-                                   readlane_u64(M, e), (uint32_t)__builtin_amdgcn_readlane((int)poff, e), acc, sh,
-                                   shn);
+                                   readlane_u64(M, e), acc, sh, shn);
             acc = 0.0;
         }
         cur = upto;
@@ -482,25 +418,22 @@ __device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__re
         const int o = packed_owner(incl, min(ai, total - 1));
         const int e0o = __shfl(e0, o), offo = __shfl(off, o);
         const unsigned long long mo = shfl_u64(M, o);
-        unsigned long long xj = 0, mj = 0;
-        uint32_t oj = 0;
+        unsigned long long xj = 0;
+        int uj = 0;
         if (ai < total) {
-            const Tagged F = fb_nxt[col[e0o + (ai - offo)]];
-            if (F.tag == TB + 1u) {
-                xj = F.mask & mo;
-                mj = F.mask;
-                oj = F.off;
-            }
+            uj = col[e0o + (ai - offo)];
+            const Tagged F = fb_nxt[uj];
+            if (F.tag == TB + 1u) xj = F.mask & mo;
         }
         if (lane == 0) my_arcs += (unsigned)min(kWave, total - base);
         unsigned long long bal = __ballot(xj != 0ull);
         while (bal) {
             Matches mt;
-            pop_matches(bal, xj, mj, oj, o, mt);
+            pop_matches(bal, xj, uj, o, mt);
             double val[kUnroll];
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q)
-                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.pk_chat[mt.off[q] + slot_of(mt.mu[q])] : 0.0;
+                val[q] = ((mt.x[q] >> lane) & 1ull) ? a.chat[mt.row[q] + lane] : 0.0;
 #pragma unroll
             for (int q = 0; q < kUnroll; ++q) {
                 if (mt.own[q] < 0) continue;
@@ -513,7 +446,7 @@ __device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__re
             }
         }
     }
-    finalize_upto(kGroup);
+    finalize_upto(ne);
     unsigned long long mm = __ballot(medium);
     while (mm) {
         const int j = __ffsll(mm) - 1;
@@ -523,8 +456,7 @@ __device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__re
         const unsigned long long Mj = readlane_u64(M, j);
         const double sm = Mj ? bwd_arcs(a, fb_nxt, TB + 1u, Mj, a0, a0 + dj, col, my_larcs, my_pairs) : 0.0;
         if (lane == 0) my_arcs += (unsigned)dj;
-        bwd_finalize<MODE>(a, fb_cur, TB, vj, readlane_u64(Mf, j), Mj, (uint32_t)__builtin_amdgcn_readlane((int)poff, j),
-                           sm, sh, shn);
+        bwd_finalize<MODE>(a, fb_cur, TB, vj, readlane_u64(Mf, j), Mj, sm, sh, shn);
     }
 }
 
@@ -574,21 +506,15 @@ __device__ __forceinline__ void batch_begin(const BatchArgs &a, Ctl *c, int64_t 
     __syncthreads();
     if (t < lanes) {
         const int s = s_lsrc[t];
-        // the entry's packed slots follow those of entries with a lower leader
-        int before = 0;
-        for (int k = 0; k < lanes; ++k) before += (s_lead[k] < lead) ? 1 : 0;
-        const uint32_t eoff = kDense ? (uint32_t)s * kLanes : (uint32_t)before;
-        a.pk_sig[eoff + (kDense ? (uint32_t)t : (uint32_t)__popcll(m & ((1ull << t) - 1ull)))] = MODE ? as_u64(1.0) : 1ull;
+        a.sigma[(size_t)s * kLanes + t] = MODE ? as_u64(1.0) : 1ull;
         if (lead == t) {
             const int j = atomicAdd(s_cnt, 1);
             a.lq_vtx[j] = s;
             a.lq_mask[j] = m;
-            a.lq_off[j] = eoff;
             a.vn[s].vis = m;
             Tagged tg;
             tg.mask = m;
             tg.tag = epoch;
-            tg.off = eoff;
             a.fw0[s] = tg;
             s_tmp[j] = (unsigned long long)(a.g.row_ptr[s + 1] - a.g.row_ptr[s]);
         }
@@ -614,7 +540,9 @@ __device__ __forceinline__ void batch_begin(const BatchArgs &a, Ctl *c, int64_t 
         a.hq.off[1] = nh;
         a.hq.nseg[0] = segs;
         c->next_hq = 0;
-        c->pk_next = (uint32_t)lanes;
+        a.gstart[0] = 0u;  // level 0 has no groups; level 1 appends from slot 1
+        a.gbase[0] = 0u;
+        a.gbase[1] = 1u;
         c->epoch = epoch;
         c->pos = b;
         c->lanes = lanes;
@@ -632,7 +560,7 @@ __device__ __forceinline__ void batch_begin(const BatchArgs &a, Ctl *c, int64_t 
         c->n_levels = 0;
         a.level_off[0] = 0;
         a.level_off[1] = cnt;
-        c->next_count = 0;
+        c->next_qc = 0ull;
         c->next_edges = 0;
         c->next_active = 0;
         c->prev_variant = V_PUSH_TPV;
@@ -652,10 +580,16 @@ __device__ __forceinline__ void batch_begin(const BatchArgs &a, Ctl *c, int64_t 
     if (t == 0) set_level_variant(c, v, *sf, (float)(c->range_hi - c->range_lo), (float)c->range_arcs);
 }
 
+#ifndef BC_WAVES
+#define BC_WAVES 5
+#endif
+// Register budget of the step kernel: at least BC_WAVES wavefronts per SIMD
+// (memory latency is hidden by resident wavefronts).
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES))) void batch_step(BatchArgs a) {
     __shared__ int s_phase, s_level, s_variant, s_last, s_qb, s_qe, s_qn, s_L, s_lo, s_hi, s_dlane, s_cnt;
     __shared__ int s_h0, s_h1, s_hseg, s_hqb;
+    __shared__ uint32_t s_gb, s_ng;
     __shared__ unsigned s_nblk;
     __shared__ uint32_t s_epoch, s_epoch_b;
     __shared__ unsigned long long s_active, s_dead, s_lmask;
@@ -685,6 +619,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
         s_dlane = c->dump_lane;
         s_qb = s_qe = s_qn = 0;
         s_h0 = s_h1 = s_hseg = s_hqb = 0;
+        s_gb = s_ng = 0;
         const int l = s_level;
         if (s_phase == PH_FWD || s_phase == PH_SIG || s_phase == PH_BWD) {
             s_qb = a.level_off[l];
@@ -694,7 +629,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             s_qe = a.level_off[s_L];
         } else if (s_phase == PH_UNDO) {
             s_qe = a.level_off[l + 1];
-            s_qn = (int)c->next_count;
+            s_qn = (int)(uint32_t)c->next_qc;
         }
         if (s_phase == PH_FWD) {
             if (s_variant == V_PULL) {  // static heavy vertices of the batch's range
@@ -709,14 +644,19 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
                 s_hseg = a.hq.nseg[l];
             }
             s_hqb = a.hq.off[l + 1];    // heavy entries of level l+1 start here
+            s_gb = a.gbase[l + 1];      // groups of level l+1 are appended here
         } else if (s_phase == PH_SIG) {
             s_h0 = a.hq.off[l + 1];
             s_h1 = a.hq.off[l + 2];
             s_hseg = a.hq.nseg[l + 1];
+            s_gb = a.gbase[l + 1];
+            s_ng = a.gbase[l + 2] - s_gb - 1u;
         } else if (s_phase == PH_BWD) {
             s_h0 = a.hq.off[l];
             s_h1 = a.hq.off[l + 1];
             s_hseg = a.hq.nseg[l];
+            s_gb = a.gbase[l];
+            s_ng = a.gbase[l + 1] - s_gb - 1u;
         }
         // wavefront work items of this step -> workgroups taking part
         long long items = 1;
@@ -725,10 +665,8 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             if (s_variant == V_PUSH_TPV) items = (cnt + kWave - 1) / kWave + s_hseg;
             else if (s_variant == V_PUSH_WPV) items = cnt + s_hseg;
             else items = (s_hi - s_lo + kWave - 1) / kWave + s_hseg;
-        } else if (s_phase == PH_SIG) {
-            items = (s_qn - s_qe + kGroup - 1) / kGroup + s_hseg;
-        } else if (s_phase == PH_BWD) {
-            items = (cnt + kGroup - 1) / kGroup + s_hseg;
+        } else if (s_phase == PH_SIG || s_phase == PH_BWD) {
+            items = (long long)s_ng + s_hseg;
         } else if (s_phase == PH_BC) {
             items = (s_hi - s_lo + kWave - 1) / kWave;
         } else if (s_phase == PH_DUMP_FWD || s_phase == PH_DUMP_BWD) {
@@ -771,6 +709,10 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
         const int variant = s_variant;
         Stage &st = s_stage[wid];
         int sn = 0;
+        GroupArgs gr;
+        gr.gstart = a.gstart;
+        gr.gb = s_gb;
+        gr.gcap = a.gcap;
         if (variant == V_PUSH_TPV || variant == V_PUSH_WPV) {
             const int n_light = variant == V_PUSH_TPV ? (cnt + kWave - 1) / kWave : cnt;
             const int total = n_light + hseg;
@@ -786,14 +728,14 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
                     const int a0 = rp[u] + s * kSeg;
                     const int a1 = min(rp[u + 1], a0 + kSeg);
                     if (lane == 0) my_arcs += (unsigned)(a1 - a0);
-                    if (f) push_arcs_wave(a, f, a0, a1, rp, col, (uint32_t)qe, hqb, my_edges, st, sn);
+                    if (f) push_arcs_wave(a, f, a0, a1, rp, col, (uint32_t)qe, hqb, my_edges, st, sn, gr);
                 } else if (variant == V_PUSH_WPV) {
                     const int u = a.lq_vtx[qb + it];
                     const unsigned long long f = a.lq_mask[qb + it] & act;
                     const int e0 = rp[u], e1 = rp[u + 1];
                     if (!f || e1 - e0 > kSeg) continue;  // heavy ones run as segments
                     if (lane == 0) my_arcs += (unsigned)(e1 - e0);
-                    push_arcs_wave(a, f, e0, e1, rp, col, (uint32_t)qe, hqb, my_edges, st, sn);
+                    push_arcs_wave(a, f, e0, e1, rp, col, (uint32_t)qe, hqb, my_edges, st, sn, gr);
                 } else {  // TPV: 64 frontier vertices per wavefront
                     const int i = it * kWave + lane;
                     const bool valid = i < cnt;
@@ -817,7 +759,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
                                 my_edges += (unsigned)dw;
                             }
                         }
-                        stage_push(newly, w, dw, st, sn, c, a.lq_vtx, (uint32_t)qe, a.lq_cap, a.hq, hqb, &c->err);
+                        stage_push(newly, w, dw, st, sn, c, a.lq_vtx, (uint32_t)qe, a.lq_cap, a.hq, hqb, &c->err, gr);
                     }
                     // medium-degree vertices: the whole wavefront, one at a time
                     unsigned long long mm = __ballot(deg > kLightDeg && deg <= kSeg);
@@ -825,7 +767,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
                         const int j = __ffsll(mm) - 1;
                         mm &= mm - 1;
                         const int m0 = __shfl(e0, j), m1 = m0 + __shfl(deg, j);
-                        push_arcs_wave(a, shfl_u64(f, j), m0, m1, rp, col, (uint32_t)qe, hqb, my_edges, st, sn);
+                        push_arcs_wave(a, shfl_u64(f, j), m0, m1, rp, col, (uint32_t)qe, hqb, my_edges, st, sn, gr);
                     }
                 }
             }
@@ -862,7 +804,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
                     if (lane == 0 && got) newly = atomicOr(&a.vn[w].nxt, got) == 0ull;
                     const int deg = rp[w + 1] - rp[w];
                     if (newly) my_edges += (unsigned)deg;
-                    stage_push(newly, w, deg, st, sn, c, a.lq_vtx, (uint32_t)qe, a.lq_cap, a.hq, hqb, &c->err);
+                    stage_push(newly, w, deg, st, sn, c, a.lq_vtx, (uint32_t)qe, a.lq_cap, a.hq, hqb, &c->err, gr);
                     continue;
                 }
                 const int w = lo + it * kWave + lane;
@@ -909,23 +851,26 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
                     a.vn[w].nxt = got;
                     my_edges += (unsigned)deg;
                 }
-                stage_push(found, w, deg, st, sn, c, a.lq_vtx, (uint32_t)qe, a.lq_cap, a.hq, hqb, &c->err);
+                stage_push(found, w, deg, st, sn, c, a.lq_vtx, (uint32_t)qe, a.lq_cap, a.hq, hqb, &c->err, gr);
             }
         }
-        stage_flush(st, sn, c, a.lq_vtx, (uint32_t)qe, a.lq_cap, a.hq, hqb, &c->err);
+        stage_flush(st, sn, c, a.lq_vtx, (uint32_t)qe, a.lq_cap, a.hq, hqb, &c->err, gr);
     } else if (phase == PH_SIG) {
         // path counts of the new level; lane = source
         const int qs = s_qe, cnt = s_qn - s_qe;
         const uint32_t T = s_epoch + (uint32_t)l;
         const int sh = MODE ? a.shift[(size_t)l * kLanes + lane] : 0;
         const unsigned long long lmask = s_lmask;
-        const int n_groups = (cnt + kGroup - 1) / kGroup;
+        const int n_groups = (int)s_ng;
+        const uint32_t *gs = a.gstart + s_gb;
         const int total = n_groups + hseg;
         SigCounters sc;
-        for (int k = gw; k < total; k += nw) {
+        for (WorkCursor wc(c, nblk); wc.item() < total; wc.next(total)) {
+            const int k = wc.item();
             const int it = k < hseg ? n_groups + k : k - hseg;  // heavy segments first
             if (it < n_groups) {
-                sig_group<MODE>(a, fw_cur, fw_nxt, T, qs, it * kGroup, cnt, sh, lmask, sc);
+                const int i0 = (int)gs[it], i1 = min((int)gs[it + 1], cnt);
+                if (i1 > i0) sig_group<MODE>(a, fw_cur, fw_nxt, T, qs, i0, i1, sh, lmask, sc);
                 continue;
             }
             // a segment of a heavy new vertex
@@ -943,10 +888,10 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             if (lane == 0) sc.arcs += (unsigned)(a1 - a0);
             const size_t slot = (size_t)(a.hq.seg[h] + s) * kLanes + lane;
             if (MODE == 0) {
-                a.hq.part_lo[slot] = lo;
-                a.hq.part_hi[slot] = hi;
+                part_store(&a.hq.part_lo[slot], lo);
+                part_store(&a.hq.part_hi[slot], hi);
             } else {
-                a.hq.part_lo[slot] = as_u64(accd);
+                part_store(&a.hq.part_lo[slot], as_u64(accd));
             }
             const int ns = n_segments(e1 - e0);
             if (!seg_arrive(&a.hq.cnt[h], ns)) continue;
@@ -955,17 +900,16 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             for (int k = 0; k < ns; ++k) {  // combine in segment order
                 const size_t sl = (size_t)(a.hq.seg[h] + k) * kLanes + lane;
                 if (MODE == 0) {
-                    const unsigned long long x = a.hq.part_lo[sl];
+                    const unsigned long long x = part_load(&a.hq.part_lo[sl]);
                     lo += x;
-                    hi += a.hq.part_hi[sl] + ((lo < x) ? 1ull : 0ull);
+                    hi += part_load(&a.hq.part_hi[sl]) + ((lo < x) ? 1ull : 0ull);
                 } else {
-                    accd += as_f64(a.hq.part_lo[sl]);
+                    accd += as_f64(part_load(&a.hq.part_lo[sl]));
                 }
             }
             if (lane == 0) a.hq.cnt[h] = 0;
             const VisNext x = a.vn[w];
-            const uint32_t poff = kDense ? (uint32_t)w * kLanes : alloc_packed(a, (unsigned)__popcll(x.nxt));
-            sig_finalize<MODE>(a, fw_nxt, T + 1u, p, w, x.vis, x.nxt, e1 - e0, poff, lo, hi, accd, lmask, sc);
+            sig_finalize<MODE>(a, fw_nxt, T + 1u, p, w, x.vis, x.nxt, e1 - e0, lo, hi, accd, lmask, sc);
         }
         my_edges += sc.edges;
         my_act |= sc.act;
@@ -985,13 +929,16 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
         const unsigned long long dead = s_dead;
         const int sh = MODE ? a.shift[(size_t)l * kLanes + lane] : 0;
         const int shn = (MODE && l + 1 < s_L) ? a.shift[(size_t)(l + 1) * kLanes + lane] : 0;
-        const int n_groups = (cnt + kGroup - 1) / kGroup;
+        const int n_groups = (int)s_ng;
+        const uint32_t *gs = a.gstart + s_gb;
         const int total = n_groups + hseg;
-        for (int k = gw; k < total; k += nw) {
+        for (WorkCursor wc(c, nblk); wc.item() < total; wc.next(total)) {
+            const int k = wc.item();
             const int it = k < hseg ? n_groups + k : k - hseg;  // heavy segments first
             if (it < n_groups) {
-                bwd_group<MODE>(a, fb_nxt, fb_cur, TB, qb, it * kGroup, cnt, dead, sh, shn, my_larcs, my_arcs,
-                                my_pairs);
+                const int i0 = (int)gs[it], i1 = min((int)gs[it + 1], cnt);
+                if (i1 > i0)
+                    bwd_group<MODE>(a, fb_nxt, fb_cur, TB, qb, i0, i1, dead, sh, shn, my_larcs, my_arcs, my_pairs);
                 continue;
             }
             const int t = it - n_groups;
@@ -1005,13 +952,13 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             const int a0 = e0 + s * kSeg, a1 = min(e1, a0 + kSeg);
             double acc = M ? bwd_arcs(a, fb_nxt, TB + 1u, M, a0, a1, col, my_larcs, my_pairs) : 0.0;
             if (lane == 0) my_arcs += (unsigned)(a1 - a0);
-            a.hq.part_lo[(size_t)(a.hq.seg[h] + s) * kLanes + lane] = as_u64(acc);
+            part_store(&a.hq.part_lo[(size_t)(a.hq.seg[h] + s) * kLanes + lane], as_u64(acc));
             const int ns = n_segments(e1 - e0);
             if (!seg_arrive(&a.hq.cnt[h], ns)) continue;
             acc = 0.0;
-            for (int k = 0; k < ns; ++k) acc += as_f64(a.hq.part_lo[(size_t)(a.hq.seg[h] + k) * kLanes + lane]);
+            for (int k = 0; k < ns; ++k) acc += as_f64(part_load(&a.hq.part_lo[(size_t)(a.hq.seg[h] + k) * kLanes + lane]));
             if (lane == 0) a.hq.cnt[h] = 0;
-            bwd_finalize<MODE>(a, fb_cur, TB, v, Mf, M, a.lq_off[p], acc, sh, shn);
+            bwd_finalize<MODE>(a, fb_cur, TB, v, Mf, M, acc, sh, shn);
         }
     } else if (phase == PH_UNDO) {
         // timing collection: forget the level just discovered (its entries
@@ -1031,7 +978,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
                 while (vis) {
                     const int k = __ffsll(vis) - 1;
                     vis &= vis - 1;
-                    if (s_lsrc[k] != w) b += as_f64(a.sig[(size_t)w * kLanes + k]);
+                    if (s_lsrc[k] != w) b += a.delta[(size_t)w * kLanes + k];
                 }
                 a.bc[w] = b;
             }
@@ -1056,11 +1003,10 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             }
             const int v = a.lq_vtx[j];
             if (phase == PH_DUMP_FWD) {
-                const unsigned long long mj = a.lq_mask[j];
                 a.dump_d[v] = lo;
-                a.dump_sig[v] = a.pk_sig[a.lq_off[j] + (kDense ? (uint32_t)k : (uint32_t)__popcll(mj & ((1ull << k) - 1ull)))];
+                a.dump_sig[v] = a.sigma[(size_t)v * kLanes + k];
             } else if (lo >= 1) {
-                a.dump_delta[v] = as_f64(a.sig[(size_t)v * kLanes + k]);
+                a.dump_delta[v] = a.delta[(size_t)v * kLanes + k];
             }
         }
         if (phase == PH_DUMP_FWD && blockIdx.x == 0)
@@ -1127,14 +1073,15 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             }
         }
         if (phase == PH_UNDO) {
-            c->next_count = 0;
+            c->next_qc = 0ull;
             c->next_hq = 0;
             c->cvar += 1;
             c->variant = c->cvar;
             c->phase = PH_FWD;
         } else if (timed_again) {
         } else if (phase == PH_FWD) {
-            const uint32_t cnt = ld_agent(&c->next_count);
+            const unsigned long long qc = ld_agent(&c->next_qc);
+            const uint32_t cnt = (uint32_t)qc, cost = (uint32_t)(qc >> 32);
             const unsigned long long nh = ld_agent(&c->next_hq);
             const int qe = a.level_off[l + 1];
             c->st_fwd_levels += 1;
@@ -1157,7 +1104,18 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
                 c->phase = PH_DONE;
             } else {
                 a.level_off[l + 2] = qe + (int)cnt;
-                c->phase = PH_SIG;
+                // close the groups of level l+1 (every entry costs >= 2 units)
+                const uint32_t gb = a.gbase[l + 1];
+                const uint32_t ng = (cost - 1u) / (uint32_t)kBudget + 1u;
+                if ((unsigned long long)gb + ng + 1u > a.gcap) {
+                    c->err |= ERR_QUEUE_CAP;
+                    c->phase = PH_DONE;
+                } else {
+                    a.gstart[gb] = 0u;
+                    a.gstart[gb + ng] = cnt;
+                    a.gbase[l + 2] = gb + ng + 1u;
+                    c->phase = PH_SIG;
+                }
             }
         } else if (phase == PH_SIG) {
             action = 2;
@@ -1222,7 +1180,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             a.shift[(size_t)(l + 1) * kLanes + tid] = sh;
         }
         if (tid == 0) {
-            const uint32_t cnt = ld_agent(&c->next_count);
+            const uint32_t cnt = (uint32_t)ld_agent(&c->next_qc);
             const unsigned long long edges = s_tot[SC_EDGES];
             c->level = l + 1;
             c->visited_n += cnt;
@@ -1235,7 +1193,7 @@ __global__ __launch_bounds__(kBlock) void batch_step(BatchArgs a) {
             s_feat.nu = (float)((long long)c->range_nodeg - (long long)fn);
             s_feat.mu = (float)((long long)c->range_arcs - (long long)fm);
             s_feat.level = l + 1;
-            c->next_count = 0;
+            c->next_qc = 0ull;
             c->prev_variant = c->variant;
             c->phase = PH_FWD;
         }

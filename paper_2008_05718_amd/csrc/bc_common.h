@@ -95,6 +95,37 @@ __device__ __forceinline__ unsigned active_blocks(long long items) {
     return (unsigned)b;
 }
 
+// Work items of a step, [0, total), are dealt to ncls = min(nblk, kSlots)
+// classes k mod ncls; the workgroups of class r (blockIdx.x mod ncls) share
+// that class's items: each wavefront takes its first one statically, later
+// ones from the class's counter (reset by the last workgroup of the launch),
+// so a wavefront that finishes early takes the next item without all
+// wavefronts meeting on one address.  Items are independent and each sum
+// stays inside one item, so the assignment never changes a result.
+struct WorkCursor {
+    uint32_t *ctr;
+    int r, ncls, nwr, j, jn;
+    __device__ __forceinline__ WorkCursor(Ctl *c, unsigned nblk) {
+        ncls = (int)(nblk < (unsigned)kSlots ? nblk : (unsigned)kSlots);
+        r = (int)(blockIdx.x % (unsigned)ncls);
+        const int nb = ((int)nblk - r + ncls - 1) / ncls;  // workgroups of class r
+        nwr = nb * kWavesPerBlock;
+        j = (int)(blockIdx.x / (unsigned)ncls) * kWavesPerBlock + (int)(threadIdx.x >> 6);
+        ctr = &c->work[r][0];
+        jn = fetch();
+    }
+    __device__ __forceinline__ int fetch() {
+        int x = 0;
+        if ((threadIdx.x & 63) == 0) x = (int)atomicAdd(ctr, 1u);
+        return nwr + __shfl(x, 0);
+    }
+    __device__ __forceinline__ int item() const { return r + ncls * j; }
+    __device__ __forceinline__ void next(int total) {
+        j = jn;
+        if (item() < total) jn = fetch();
+    }
+};
+
 // End of a step for one workgroup: reduce the counters over the workgroup,
 // add them into the workgroup's slot, count the workgroup in (two-level
 // arrival so no single address takes one atomic per workgroup).  Returns
@@ -159,6 +190,7 @@ __device__ __forceinline__ void collect_slots(Ctl *c, unsigned long long *s_tot,
             c->slot[t][k] = 0ull;
         }
         c->arrive[t] = 0u;
+        c->work[t][0] = 0u;
     }
     __syncthreads();
     if (t < kNCnt) {
@@ -197,61 +229,54 @@ __device__ __forceinline__ unsigned long long shfl_u64(unsigned long long x, int
 
 __device__ __forceinline__ int n_segments(int deg) { return (deg + kSeg - 1) / kSeg; }
 
-// Append w, for every lane with pred, to the level queue q at absolute
-// positions qbase + i (i from the level counter c->next_count), and the heavy
-// ones (deg > kSeg) to the heavy list of that level starting at hq_base.  The
-// wavefront must be converged.
-__device__ __forceinline__ void wave_append_level(bool pred, int32_t w, int32_t deg, Ctl *c, int32_t *q,
-                                                  uint32_t qbase, uint32_t qcap, const HeavyQ &hq,
-                                                  uint32_t hq_base, int32_t *err) {
-    const unsigned long long m = __ballot(pred);
-    if (m == 0) return;
-    const int lane = lane_id();
-    const int leader = __ffsll((unsigned long long)m) - 1;
-    unsigned base = 0;
-    if (lane == leader) base = atomicAdd(&c->next_count, (unsigned)__popcll(m));
-    base = __shfl(base, leader);
-    uint32_t p = 0;
-    if (pred) {
-        p = qbase + base + lanes_below(m);
-        if (p < qcap) q[p] = w;
-        else atomicOr(err, ERR_QUEUE_CAP);
-    }
-    const bool heavy = pred && deg > kSeg;
-    const unsigned long long hm = __ballot(heavy);
-    if (hm == 0) return;
-    const int ns = heavy ? n_segments(deg) : 0;
-    const int incl = wave_incl_scan(ns);
-    const int total = __shfl(incl, 63);
-    const int hl = __ffsll((unsigned long long)hm) - 1;
-    unsigned long long old = 0;
-    if (lane == hl)
-        old = atomicAdd(&c->next_hq, (unsigned long long)__popcll(hm) | ((unsigned long long)(unsigned)total << 32));
-    old = shfl_u64(old, hl);
-    if (heavy) {
-        const uint32_t idx = hq_base + (uint32_t)old + lanes_below(hm);
-        if (idx < hq.cap) {
-            hq.pos[idx] = (int32_t)p;
-            hq.seg[idx] = (int32_t)(old >> 32) + (incl - ns);
-            hq.cnt[idx] = 0;
-        } else {
-            atomicOr(err, ERR_QUEUE_CAP);
-        }
-    }
-}
 
 // Write the n staged entries of this wavefront to the level queue (absolute
 // positions qbase + counter), heavy ones also to the level's heavy list.
+#ifndef BC_BUDGET
+#define BC_BUDGET 32
+#endif
+constexpr int kBudget = BC_BUDGET;  // cost units (8 arcs each) per work group
+static_assert(kBudget >= 2 && kBudget <= 128, "a group must fit in one wavefront (every entry costs >= 2 units)");
+
+// Work estimate of a level entry in units of 8 arcs: its adjacency plus a
+// fixed part; heavy entries (split into segments elsewhere) count 2.  Every
+// entry costs at least 2 units, so a group never holds more than
+// kBudget / 2 entries.
+__host__ __device__ __forceinline__ unsigned entry_cost(int deg) {
+    return deg > kSeg ? 2u : 1u + (unsigned)(deg + 7) / 8u;
+}
+
+// Groups of a level: the entries whose cost prefix (in append order) starts
+// in [k * kBudget, (k + 1) * kBudget) form group k, so every group carries
+// about the same work.  Groups are found through gstart: gstart[gb + k] is
+// the level-relative index of group k's first entry.  An entry whose cost
+// range (P, P + c] contains the boundary k * kBudget writes gstart[gb + k] =
+// its index + 1; gstart[gb] = 0 and the end are set when the level closes.
+struct GroupArgs {
+    uint32_t *gstart = nullptr;  // nullptr: no groups (per-source engine)
+    uint32_t gb = 0;             // first gstart slot of the level being appended
+    uint32_t gcap = 0;
+};
+
 __device__ __forceinline__ void stage_flush(Stage &st, int &n, Ctl *c, int32_t *q, uint32_t qbase, uint32_t qcap,
-                                            const HeavyQ &hq, uint32_t hq_base, int32_t *err) {
+                                            const HeavyQ &hq, uint32_t hq_base, int32_t *err,
+                                            const GroupArgs &ga) {
     if (n == 0) return;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int lane = lane_id();
-    unsigned base = 0;
-    if (lane == 0) base = atomicAdd(&c->next_count, (unsigned)n);
-    base = __shfl(base, 0);
+    // the run's entries and cost units, taken by one 64-bit atomic
+    unsigned run_cost = 0;
+    if (ga.gstart)
+        for (int i = lane; i < n; i += kWave) run_cost += entry_cost(st.deg[i]);
+    run_cost = (unsigned)wave_sum_u64(run_cost);
+    unsigned long long old = 0;
+    if (lane == 0)
+        old = atomicAdd(&c->next_qc, (unsigned long long)(unsigned)n | ((unsigned long long)run_cost << 32));
+    old = shfl_u64(old, 0);
+    const unsigned base = (unsigned)old;
+    unsigned cbase = (unsigned)(old >> 32);
     for (int i0 = 0; i0 < n; i0 += kWave) {
         const int i = i0 + lane;
         const bool on = i < n;
@@ -262,6 +287,17 @@ __device__ __forceinline__ void stage_flush(Stage &st, int &n, Ctl *c, int32_t *
             if (p < qcap) q[p] = w;
             else atomicOr(err, ERR_QUEUE_CAP);
         }
+        if (ga.gstart) {
+            const unsigned ci = on ? entry_cost(deg) : 0u;
+            const unsigned incl = (unsigned)wave_incl_scan((int)ci);
+            const unsigned P = cbase + incl - ci;
+            for (unsigned k = P / kBudget + 1; on && k <= (P + ci) / kBudget; ++k) {
+                const unsigned long long at = (unsigned long long)ga.gb + k;
+                if (at < ga.gcap) ga.gstart[at] = base + (uint32_t)i + 1u;
+                else atomicOr(err, ERR_QUEUE_CAP);
+            }
+            cbase += (unsigned)__shfl((int)incl, 63);
+        }
         const bool heavy = on && deg > kSeg;
         const unsigned long long hm = __ballot(heavy);
         if (hm) {
@@ -269,16 +305,16 @@ __device__ __forceinline__ void stage_flush(Stage &st, int &n, Ctl *c, int32_t *
             const int incl = wave_incl_scan(ns);
             const int total = __shfl(incl, 63);
             const int hl = __ffsll((unsigned long long)hm) - 1;
-            unsigned long long old = 0;
+            unsigned long long hold = 0;
             if (lane == hl)
-                old = atomicAdd(&c->next_hq,
-                                (unsigned long long)__popcll(hm) | ((unsigned long long)(unsigned)total << 32));
-            old = shfl_u64(old, hl);
+                hold = atomicAdd(&c->next_hq,
+                                 (unsigned long long)__popcll(hm) | ((unsigned long long)(unsigned)total << 32));
+            hold = shfl_u64(hold, hl);
             if (heavy) {
-                const uint32_t idx = hq_base + (uint32_t)old + lanes_below(hm);
+                const uint32_t idx = hq_base + (uint32_t)hold + lanes_below(hm);
                 if (idx < hq.cap) {
                     hq.pos[idx] = (int32_t)p;
-                    hq.seg[idx] = (int32_t)(old >> 32) + (incl - ns);
+                    hq.seg[idx] = (int32_t)(hold >> 32) + (incl - ns);
                     hq.cnt[idx] = 0;
                 } else {
                     atomicOr(err, ERR_QUEUE_CAP);
@@ -294,7 +330,7 @@ __device__ __forceinline__ void stage_flush(Stage &st, int &n, Ctl *c, int32_t *
 // converged.
 __device__ __forceinline__ void stage_push(bool pred, int32_t w, int32_t deg, Stage &st, int &n, Ctl *c, int32_t *q,
                                            uint32_t qbase, uint32_t qcap, const HeavyQ &hq, uint32_t hq_base,
-                                           int32_t *err) {
+                                           int32_t *err, const GroupArgs &ga) {
     const unsigned long long m = __ballot(pred);
     if (m == 0) return;
     if (pred) {
@@ -303,7 +339,7 @@ __device__ __forceinline__ void stage_push(bool pred, int32_t w, int32_t deg, St
         st.deg[pos] = deg;
     }
     n += __popcll(m);
-    if (n >= kWave) stage_flush(st, n, c, q, qbase, qcap, hq, hq_base, err);
+    if (n >= kWave) stage_flush(st, n, c, q, qbase, qcap, hq, hq_base, err, ga);
 }
 
 // Largest h in [h0, h1) with seg[h] <= t (seg ascending, seg[h0] = 0 <= t).
@@ -421,19 +457,27 @@ __device__ __forceinline__ int choose_variant(const PolicyArgs &p, int policy, i
     return heuristic_variant(p, prev, f, n);
 }
 
-// Last-workgroup detection: every workgroup calls this once at its end; it
-// returns true in exactly one workgroup, after all others have arrived, with
-// their memory operations visible.
-__device__ __forceinline__ bool last_block_arrive(uint32_t *counter, int *s_last) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned t = atomicAdd(counter, 1u);
-        *s_last = (t == gridDim.x - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (*s_last) __threadfence();
-    return *s_last != 0;
+// Partial sums exchanged between the wavefronts of one launch (segments of
+// a heavy vertex): stored and loaded with device-scope relaxed atomics, which
+// are written through to, and read from, the point of coherence of all
+// XCDs, so no cache-wide fence (L2 write-back / invalidate) is needed.
+// seg_arrive waits until this wavefront's partial stores have completed,
+// then counts it in; the wavefront that arrives last (returns true) reads
+// every partial with part_load.
+__device__ __forceinline__ void part_store(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long part_load(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool seg_arrive(int32_t *cnt, int nseg) {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);  // every memory operation of this wavefront has completed
+    int old = 0;
+    if (lane_id() == 0) old = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    old = __shfl(old, 0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    return old == nseg - 1;
 }
 
 template <typename T>

@@ -13,7 +13,7 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kLanes = 64;   // sources per batch = wavefront lanes
 constexpr int kLightDeg = 32;  // thread-per-vertex loops handle up to this many arcs
 #ifndef BC_SEG
-#define BC_SEG 1024
+#define BC_SEG 512
 #endif
 constexpr int kSeg = BC_SEG;   // heavy vertices (degree > kSeg) are split into kSeg-arc segments
 constexpr int kPhases = 10;
@@ -81,7 +81,7 @@ struct Ctl {
     unsigned long long dead;        // lanes that overflowed in uint64 mode
     // --- level under construction (atomics)
     uint32_t blocks_done;
-    uint32_t next_count;
+    unsigned long long next_qc;  // appends to the next level: entries (low 32 bits), cost units (high 32)
     unsigned long long next_edges;
     unsigned long long next_active;
     unsigned long long ovf_lanes;
@@ -90,7 +90,6 @@ struct Ctl {
     int32_t minexp;
     uint32_t total_queued;
     uint32_t n_ovf;       // overflowed sources recorded
-    uint32_t pk_next;     // batched: packed slots handed out in the current batch
     // --- features of the frontier at level l
     unsigned long long f_nf, f_mf, visited_n, visited_m, full_n, full_m;
     unsigned long long range_nodeg, range_arcs;  // non-isolated vertices / arcs of the range
@@ -109,6 +108,7 @@ struct Ctl {
     // --- per-slot counters and workgroup arrivals of the running step
     unsigned long long slot[kSlots][kNCnt];
     uint32_t arrive[kSlots];
+    uint32_t work[kSlots][32];  // per-slot work counters, one 128-byte line each
     // --- statistics
     unsigned long long st_steps, st_fwd_levels, st_var[3], st_arcs, st_lane_arcs, st_qentries,
         st_max_levels, st_batches;
@@ -185,7 +185,7 @@ struct PlainArgs {
 struct __attribute__((aligned(16))) Tagged {
     unsigned long long mask;
     uint32_t tag;
-    uint32_t off;  // batched engine: packed offset of the entry's per-source values
+    uint32_t pad;
 };
 // Visited / next lane words of a vertex, one 16-byte load.
 struct __attribute__((aligned(16))) VisNext {
@@ -205,11 +205,9 @@ struct BatchArgs {
     uint32_t lq_cap;
     int32_t *level_off;          // [max_levels + 2]
     int32_t max_levels;
-    unsigned long long *sig;     // [n][64] dense delta slab (read by PH_BC and dumps)
-    unsigned long long *pk_sig;  // packed per-entry path counts (uint64 / FP64 bits)
-    double *pk_chat;             // packed per-entry c = (1 + delta) / sigma
-    uint32_t *lq_off;            // packed offset of each level-queue entry
-    uint32_t pk_cap;
+    double *delta;               // [n][64] dependencies (read by PH_BC and dumps)
+    unsigned long long *sigma;   // [n][64] path counts (uint64, or FP64 bits in mode 1)
+    double *chat;                // [n][64] c = (1 + delta) / sigma
     int32_t *shift;              // [max_levels + 2][64] (mode 1)
     int32_t *maxexp;             // [2][kSlots][64]: per-slot, per-lane max then min exponents (mode 1)
     double *bc;                  // [n]
@@ -229,6 +227,9 @@ struct BatchArgs {
     float *col_X;                // collected features [cap][5]
     float *col_Y;                // collected device ticks per variant [cap][3]
     uint32_t col_cap;
+    uint32_t *gstart;            // group starts of every level of the batch (see GroupArgs)
+    uint32_t *gbase;             // [max_levels + 2]: first gstart slot of each level
+    uint32_t gcap;
 };
 
 }  // namespace bcx

@@ -65,7 +65,7 @@ __device__ __forceinline__ void plain_push_arcs(const PlainArgs &a, int l, unsig
                 my_edges += (unsigned)dw;
             }
         }
-        stage_push(newly, w, dw, st, sn, c, a.queue, qe, (uint32_t)a.g.n, a.hq, hqb, &c->err);
+        stage_push(newly, w, dw, st, sn, c, a.queue, qe, (uint32_t)a.g.n, a.hq, hqb, &c->err, GroupArgs{});
     }
 }
 
@@ -86,15 +86,6 @@ __device__ __forceinline__ double plain_wave_sum(const PlainArgs &a, int a0, int
     return wave_sum_f64(p);
 }
 
-__device__ __forceinline__ bool plain_seg_arrive(int32_t *cnt, int nseg) {
-    __threadfence();
-    int old = 0;
-    if (lane_id() == 0) old = atomicAdd(cnt, 1);
-    old = __shfl(old, 0);
-    const bool last = (old == nseg - 1);
-    if (last) __threadfence();
-    return last;
-}
 
 // Exact 128-bit wavefront sum of (lo, hi) pairs; every lane gets the total.
 __device__ __forceinline__ void wave_sum_u128(unsigned long long &lo, unsigned long long &hi) {
@@ -135,7 +126,7 @@ __device__ __forceinline__ void plain_begin_source(const PlainArgs &a, Ctl *c, i
         c->pos = pos;
         c->level = 0;
         c->overflow = 0;
-        c->next_count = 0;
+        c->next_qc = 0ull;
         c->next_edges = 0;
         c->visited_n = 1;
         c->visited_m = (unsigned long long)deg;
@@ -164,7 +155,7 @@ __device__ __forceinline__ void plain_advance_level(const PlainArgs &a, Ctl *c, 
         sf->nu = (float)((long long)a.g.n - (long long)c->visited_n);
         sf->mu = (float)((long long)a.g.nnz_lo - (long long)c->visited_m);
         sf->level = l + 1;
-        c->next_count = 0;
+        c->next_qc = 0ull;
         c->next_edges = 0;
         c->prev_variant = c->variant;
         c->phase = PH_FWD;
@@ -334,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
                                 my_edges += (unsigned)dw;
                             }
                         }
-                        stage_push(newly, w, dw, st, sn, c, a.queue, (uint32_t)qe, (uint32_t)n, a.hq, hqb, &c->err);
+                        stage_push(newly, w, dw, st, sn, c, a.queue, (uint32_t)qe, (uint32_t)n, a.hq, hqb, &c->err, GroupArgs{});
                     }
                     // medium-degree vertices: the whole wavefront, one at a time
                     unsigned long long mm = __ballot(deg > kLightDeg && deg <= kSeg);
@@ -398,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
                     }
                     const int deg = rp[w + 1] - rp[w];
                     if (newly) my_edges += (unsigned)deg;
-                    stage_push(newly, w, deg, st, sn, c, a.queue, (uint32_t)qe, (uint32_t)n, a.hq, hqb, &c->err);
+                    stage_push(newly, w, deg, st, sn, c, a.queue, (uint32_t)qe, (uint32_t)n, a.hq, hqb, &c->err, GroupArgs{});
                     continue;
                 }
                 const int w = it * kWave + lane;
@@ -470,10 +461,10 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
                     }
                     my_edges += (unsigned)deg;
                 }
-                stage_push(ok, w, deg, st, sn, c, a.queue, (uint32_t)qe, (uint32_t)n, a.hq, hqb, &c->err);
+                stage_push(ok, w, deg, st, sn, c, a.queue, (uint32_t)qe, (uint32_t)n, a.hq, hqb, &c->err, GroupArgs{});
             }
         }
-        stage_flush(st, sn, c, a.queue, (uint32_t)qe, (uint32_t)n, a.hq, hqb, &c->err);
+        stage_flush(st, sn, c, a.queue, (uint32_t)qe, (uint32_t)n, a.hq, hqb, &c->err, GroupArgs{});
     } else if (MODE == 1 && phase == PH_SIG) {
         // FP64 path counts of level l+1, pulled in CSR order
         const int qs = s_qe, cnt = s_qn - s_qe;
@@ -492,13 +483,13 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
                 const double p = plain_wave_sum(a, a0, a1, l, false, sh, my_larcs);
                 if (lane == 0) {
                     my_arcs += (unsigned)(a1 - a0);
-                    a.hq.part_lo[a.hq.seg[h] + s] = as_u64(p);
+                    part_store(&a.hq.part_lo[a.hq.seg[h] + s], as_u64(p));
                 }
                 const int ns = n_segments(e1 - e0);
-                if (!plain_seg_arrive(&a.hq.cnt[h], ns)) continue;
+                if (!seg_arrive(&a.hq.cnt[h], ns)) continue;
                 if (lane == 0) {
                     double acc = 0.0;
-                    for (int k = 0; k < ns; ++k) acc += as_f64(a.hq.part_lo[a.hq.seg[h] + k]);
+                    for (int k = 0; k < ns; ++k) acc += as_f64(part_load(&a.hq.part_lo[a.hq.seg[h] + k]));
                     sig[w] = as_u64(acc);
                     if (acc > 0.0) {
                         int ex;
@@ -561,13 +552,13 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
                 const double p = plain_wave_sum(a, a0, a1, l + 1, true, 0, my_larcs);
                 if (lane == 0) {
                     my_arcs += (unsigned)(a1 - a0);
-                    a.hq.part_lo[a.hq.seg[h] + s] = as_u64(p);
+                    part_store(&a.hq.part_lo[a.hq.seg[h] + s], as_u64(p));
                 }
                 const int ns = n_segments(e1 - e0);
-                if (!plain_seg_arrive(&a.hq.cnt[h], ns)) continue;
+                if (!seg_arrive(&a.hq.cnt[h], ns)) continue;
                 if (lane == 0) {
                     double acc = 0.0;
-                    for (int k = 0; k < ns; ++k) acc += as_f64(a.hq.part_lo[a.hq.seg[h] + k]);
+                    for (int k = 0; k < ns; ++k) acc += as_f64(part_load(&a.hq.part_lo[a.hq.seg[h] + k]));
                     const double sv = norm_sigma<MODE>(a, v, sh);
                     double delta = sv * acc;
                     if (MODE == 1) delta = ldexp(delta, -shn);
@@ -657,7 +648,7 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
         }
         c->last_tick = now;
         if (phase == PH_FWD) {
-            const uint32_t cnt = ld_agent(&c->next_count);
+            const uint32_t cnt = (uint32_t)ld_agent(&c->next_qc);
             const unsigned long long nh = ld_agent(&c->next_hq);
             const int qe = a.level_off[l + 1];
             a.level_off[l + 2] = qe + (int)cnt;
@@ -693,7 +684,7 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
             if (any && mn - sh < -1000) c->err |= ERR_SIGMA_RANGE;
             a.shift[l + 1] = sh;
             advance = 1;
-            cnt_next = ld_agent(&c->next_count);
+            cnt_next = (uint32_t)ld_agent(&c->next_qc);
             edges_next = c->next_edges;
         } else if (phase == PH_BWD) {
             if (l - 1 >= 1) {

@@ -160,7 +160,7 @@ def test_sigma_limit_and_forced_f64(engine):
 
 @pytest.mark.parametrize("engine", ENGINES)
 def test_heavy_vertices_segments(engine):
-    # RMAT scale 14: 15 vertices above one 1024-arc segment (max degree 3665);
+    # RMAT scale 14: dozens of vertices above one 512-arc segment (max degree 3665);
     # every policy must split them the same way and give identical bits
     g = W.rmat(14, 16, seed=1)
     deg = g.degrees()
