@@ -508,6 +508,7 @@ struct RunCfg {
     int grid;
     int chunk;
     bool use_graphs;
+    bool f64_check = false;  // batched FP64 pass: lanes whose counts stay below 2^65 are handed back
 };
 
 template <typename Args>
@@ -700,6 +701,7 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
     init_ctl(hc);
     hc->policy = cfg.policy;
     hc->mode = cfg.mode;
+    hc->f64_check = cfg.f64_check ? 1 : 0;
     hc->dump_pos = dump_pos;
     const unsigned long long limit = o.sigma_limit > 0 ? (unsigned long long)o.sigma_limit : ~0ull;
     GraphArgs ga;
@@ -954,38 +956,78 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
         if (db.delta) (void)hipFree(db.delta);
         if (db.shift) (void)hipFree(db.shift);
     };
-    std::vector<int64_t> ovf;
     int dump_done = 0;
     int dump_mode = 0;
     Ctl last{};
     const bool force_f64 = (o.flags & BC_RUN_FORCE_F64) != 0;
-    RunCfg c0 = cfg;
-    c0.mode = force_f64 ? 1 : 0;
-    s = run_pass(g, c0, o, src, ns, detail ? dump_index : -1, detail ? &db : nullptr, st, &ovf, &dump_done, &last);
-    if (s != BC_OK) { free_dump(); return s; }
-    if (force_f64) {
-        g->stats.f64_sources = ns;
-        dump_mode = 1;
-    }
-    if (!ovf.empty()) {
-        // second pass: the overflowed sources, in list order, with FP64 path counts
-        std::vector<int32_t> redo(ovf.size());
-        int64_t redo_dump = -1;
-        for (size_t i = 0; i < ovf.size(); ++i) {
-            redo[i] = src[ovf[i]];
-            if (detail && ovf[i] == dump_index) redo_dump = (int64_t)i;
+    // One pass over the sources at the given absolute positions; returns (in
+    // *back) the positions the pass handed back: overflowed lanes of a 64-bit
+    // pass, or lanes of a checked FP64 pass whose counts may fit in 64 bits.
+    auto pass = [&](int mode, bool check, const std::vector<int64_t> &pos, std::vector<int64_t> *back) -> bc_status {
+        back->clear();
+        if (pos.empty()) return BC_OK;
+        std::vector<int32_t> list(pos.size());
+        int64_t pdump = -1;
+        for (size_t i = 0; i < pos.size(); ++i) {
+            list[i] = src[pos[i]];
+            if (detail && pos[i] == dump_index) pdump = (int64_t)i;
         }
-        RunCfg c1 = cfg;
-        c1.mode = 1;
+        RunCfg c = cfg;
+        c.mode = mode;
+        c.f64_check = check;
+        std::vector<int64_t> rel;
         int dd = 0;
-        s = run_pass(g, c1, o, redo.data(), (int64_t)redo.size(), redo_dump, detail ? &db : nullptr, st, nullptr,
-                     &dd, &last);
-        if (s != BC_OK) { free_dump(); return s; }
-        g->stats.f64_sources = (int64_t)redo.size();
-        if (redo_dump >= 0) {
+        bc_status r = run_pass(g, c, o, list.data(), (int64_t)list.size(), pdump, detail ? &db : nullptr, st, &rel,
+                               &dd, &last);
+        if (r != BC_OK) return r;
+        if (pdump >= 0 && dd) {
             dump_done = dd;
-            dump_mode = 1;
+            dump_mode = mode;
         }
+        for (int64_t q : rel) back->push_back(pos[q]);
+        return BC_OK;
+    };
+    std::vector<int64_t> all_pos((size_t)ns);
+    for (int64_t i = 0; i < ns; ++i) all_pos[i] = i;
+    std::vector<int64_t> f64_pos;  // sources that end in FP64 mode (sorted)
+    if (force_f64) {
+        std::vector<int64_t> none;
+        s = pass(1, false, all_pos, &none);
+        if (s != BC_OK) { free_dump(); return s; }
+        g->stats.f64_sources = ns;
+    } else {
+        // 64-bit counts first.  When most of the first batch overflows, the
+        // graph's counts exceed 64 bits as a rule: the rest runs in FP64
+        // straight away (checked), and only the lanes whose counts stay below
+        // 2^65 go back to a 64-bit pass, which decides their mode exactly.
+        const int64_t probe = cfg.engine == 1 ? ns : std::min<int64_t>(ns, cfg.lanes);
+        std::vector<int64_t> head(all_pos.begin(), all_pos.begin() + probe), rest(all_pos.begin() + probe, all_pos.end());
+        std::vector<int64_t> ovf_a, ovf_b, kept_f64;
+        s = pass(0, false, head, &ovf_a);
+        if (s != BC_OK) { free_dump(); return s; }
+        if (!rest.empty() && 2 * (int64_t)ovf_a.size() >= probe) {
+            std::vector<int64_t> small;
+            s = pass(1, true, rest, &small);
+            if (s != BC_OK) { free_dump(); return s; }
+            std::vector<bool> is_small((size_t)ns, false);
+            for (int64_t q : small) is_small[q] = true;
+            for (int64_t q : rest)
+                if (!is_small[q]) kept_f64.push_back(q);
+            s = pass(0, false, small, &ovf_b);
+        } else {
+            s = pass(0, false, rest, &ovf_b);
+        }
+        if (s != BC_OK) { free_dump(); return s; }
+        std::vector<int64_t> redo(ovf_a);
+        redo.insert(redo.end(), ovf_b.begin(), ovf_b.end());
+        std::sort(redo.begin(), redo.end());
+        if (!redo.empty()) {
+            // the overflowed sources, in list order, with FP64 path counts
+            std::vector<int64_t> none;
+            s = pass(1, false, redo, &none);
+            if (s != BC_OK) { free_dump(); return s; }
+        }
+        g->stats.f64_sources = (int64_t)(redo.size() + kept_f64.size());
     }
     if (detail) {
         if (!dump_done) { free_dump(); return fail(BC_ERR_DEVICE, "detail dump did not complete"); }

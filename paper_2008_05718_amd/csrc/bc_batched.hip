@@ -488,6 +488,8 @@ __device__ __forceinline__ void batch_begin(const BatchArgs &a, Ctl *c, int64_t 
         const int s = t < lanes ? a.srcs[start + t] : -1;
         s_lsrc[t] = s;
         a.lane_src[t] = s;
+        c->lane_E[t] = 0;
+        c->lane_emax[t] = INT_MIN;
     }
     __syncthreads();
     // lanes with the same source share one level-0 entry, led by its lowest lane
@@ -1093,6 +1095,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
             if (cnt == 0) {
                 const int L = l + 1;
                 c->n_levels = L;
+                if (MODE == 1 && c->f64_check) {
+                    // counts below 2^65 might fit in 64 bits: hand the lane back
+                    // (no contribution here), a 64-bit pass decides its mode
+                    unsigned long long back = 0;
+                    for (int k = 0; k < kLanes; ++k)
+                        if (c->lane_emax[k] <= 65) back |= 1ull << k;
+                    back &= c->lane_mask & ~c->dead;
+                    const int64_t start = a.batch_start[c->pos];
+                    for (unsigned long long o = back; o; o &= o - 1) {
+                        const int k = __ffsll(o) - 1;
+                        const uint32_t q = c->n_ovf;
+                        if (q < a.ovf_cap) a.ovf_list[q] = start + k;
+                        else c->err |= ERR_OVF_CAP;
+                        c->n_ovf = q + 1;
+                    }
+                    c->dead |= back;
+                }
                 // backward tags epoch_b + 1 .. epoch_b + L lie above every forward tag
                 c->epoch_b = c->epoch + (uint32_t)L + 1u;
                 if ((unsigned long long)L > c->st_max_levels) c->st_max_levels = L;
@@ -1178,6 +1197,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
             if (mx != INT_MIN && mx > 960) sh = mx - 900;
             if (mn != INT_MAX && mn - sh < -1000) atomicOr(&c->err, ERR_SIGMA_RANGE);
             a.shift[(size_t)(l + 1) * kLanes + tid] = sh;
+            // true counts of level l+1 are the stored ones times 2^lane_E
+            if (mx != INT_MIN) c->lane_emax[tid] = max(c->lane_emax[tid], mx + c->lane_E[tid]);
+            c->lane_E[tid] += sh;
         }
         if (tid == 0) {
             const uint32_t cnt = (uint32_t)ld_agent(&c->next_qc);

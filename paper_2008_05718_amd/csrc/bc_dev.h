@@ -103,6 +103,9 @@ struct Ctl {
     int64_t dump_pos;     // source position to dump (-1 = none)
     int32_t dump_lane;    // batched: lane of the dumped source in its batch
     int32_t dump_state;   // 0 = pending, 1 = forward dumped, 2 = done
+    int32_t f64_check;    // batched FP64 pass: hand back lanes whose counts stay below 2^65
+    int32_t lane_E[64];   // batched FP64: power of two of the current level's stored counts, per lane
+    int32_t lane_emax[64];  // batched FP64: largest binary exponent of a true count so far, per lane
     // --- heavy entries of the level under construction: count | segments << 32
     unsigned long long next_hq;
     // --- per-slot counters and workgroup arrivals of the running step

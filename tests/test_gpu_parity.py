@@ -205,6 +205,30 @@ def test_multi_graph_union_equals_per_graph():
         assert_bc_close(G.scores(), ref_u)
 
 
+def test_fp64_first_pass_hands_back_small_counts():
+    # a union of an 80 x 80 grid (every source overflows 64 bits) and an R-MAT
+    # graph (no source does): the first batch is all grid sources, so the
+    # rest runs in FP64 first; R-MAT sources must come back to the 64-bit
+    # pass (their mode and integer counts exact), grid sources stay FP64
+    grid = W.grid(80, 0.05, 0.0, seed=11)
+    rm = W.rmat(10, 8, seed=12)
+    u = W.union([grid, rm])
+    gsrc = W.choose_sources(grid, 100, seed=1)
+    rsrc = W.choose_sources(rm, 40, seed=2) + grid.n
+    srcs = np.concatenate([gsrc[:64], rsrc[:20], gsrc[64:], rsrc[20:]]).astype(np.int32)
+    say("[fp64 first] grid80 + rmat10, sources", len(srcs))
+    ref, modes = oracle.bc(u, srcs)
+    assert modes[:64].all() and not modes[64:84].any()
+    with b.Graph(u) as G:
+        G.run(srcs, batch=64)
+        st = G.stats()
+        assert st["f64_sources"] == int(modes.sum())
+        assert_bc_close(G.scores(), ref)
+        for idx in (70, 90, 130):  # R-MAT in the FP64-first part, grid, R-MAT at the end
+            det = G.detail(srcs, dump_index=idx, batch=64)
+            check_detail(u, det, srcs[idx])
+
+
 def test_invalid_inputs_and_handle_survives():
     good = W.grid(4)
     bad_cases = {
