@@ -82,6 +82,7 @@ def main():
     ap.add_argument("--sources", type=int, default=0, help="use only the first N sources (profiling runs)")
     ap.add_argument("--no-graphs", action="store_true", help="launch level steps one by one")
     ap.add_argument("--grid", type=int, default=0, help="workgroups per step launch (0 = library default)")
+    ap.add_argument("--no-tune", action="store_true", help="skip bc_autotune (default: tune on the first 256 sources)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes 3 times (counter calibration)")
     args = ap.parse_args()
@@ -124,6 +125,8 @@ def main():
     if os.path.exists(args.weights):
         G.load_policy(np.load(args.weights))
         weights_loaded = True
+    if pol == b.BC_POLICY_AUTO:  # the learned policy when trained weights exist (fixed, not tuned)
+        pol = b.BC_POLICY_MLP if weights_loaded else b.BC_POLICY_HEURISTIC
 
     def timed(sources, nsteps, nwarm, **opts):
         for _ in range(nwarm):
@@ -143,8 +146,14 @@ def main():
         gpu_ms = ev0.elapsed_time(ev1)
         return wall, gpu_ms, stats
 
-    # ---- batched (headline)
+    # ---- batched (headline); launch configuration tuned on a sample first (untimed)
     gflags = b.BC_RUN_NO_GRAPHS if args.no_graphs else 0
+    tuned = None
+    if not args.no_tune:
+        t = time.time()
+        tuned = G.autotune(srcs[:256], batch=64, policy=pol, grid_blocks=args.grid, flags=gflags)
+        gflags |= b.BC_RUN_TUNED
+        log(f"[bench] autotuned on {min(256, len(srcs))} sources in {time.time() - t:.1f}s: {tuned}")
     wall, gpu_ms, stats = timed(srcs, args.steps, args.warmup, batch=64, policy=pol, flags=gflags,
                                 grid_blocks=args.grid)
     st = stats[-1]
@@ -214,7 +223,7 @@ def main():
         "config": {"workload": args.workload, "n": g.n, "m": g.m, "sources": int(len(srcs)), "batch": 64,
                    "policy": {1: "heuristic", 2: "mlp", 3: "tpv", 4: "wpv", 5: "pull"}.get(st["policy"]),
                    "mlp_weights_loaded": weights_loaded, "graph_chunk_steps": st["chunk_steps"],
-                   "grid_blocks": st["grid_blocks"]},
+                   "grid_blocks": st["grid_blocks"], "tuned": tuned},
         "plain": plain,
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),

@@ -116,6 +116,8 @@ bc_status bc_graph_info(const bc_graph *g, int32_t *n, int64_t *nnz, int32_t *n_
 #define BC_RUN_ACCUMULATE  0x1u  /* add to the existing scores instead of resetting */
 #define BC_RUN_NO_GRAPHS   0x2u  /* launch level steps one by one, no hipGraph  */
 #define BC_RUN_FORCE_F64   0x4u  /* test hook: evaluate every source in FP64 mode */
+#define BC_RUN_TUNED       0x8u  /* K, policy, workgroups, chunk and WPV threshold left
+                                    automatic (zero) come from bc_autotune's result */
 
 typedef struct bc_run_options {
     uint32_t flags;
@@ -149,6 +151,25 @@ void bc_run_options_init(bc_run_options *opt);
  */
 bc_status bc_run(bc_graph *g, const int32_t *sources, int64_t n_sources,
                  const bc_run_options *opt, void *stream);
+
+/*
+ * Autotuner for the launch configuration (the paper fixes one launch shape;
+ * here the fastest of a fixed candidate set is measured on the workload).
+ * Runs bc_run over the host source list sample[0 .. n_sample) (a few
+ * batches' worth of the workload's sources) for every candidate, one
+ * dimension at a time starting from base (NULL = defaults): batch K in
+ * {64, 32, 16}, policy {heuristic, learned when weights are loaded},
+ * workgroups per step {default, 1/2, 1/4}, level steps per captured chunk
+ * {8, 16, 32}, push WPV degree threshold {12, 24, 48}.  Each candidate is
+ * timed (host clock around a synchronised run) after one untimed run that
+ * builds its captured graphs; the fastest value of each dimension is kept.
+ * The result goes to *best (non-NULL) and stays in the handle for bc_run with
+ * BC_RUN_TUNED (which fills the fields a caller leaves automatic).  Every candidate gives the same scores bit for bit, so the
+ * tuner changes speed only.  Scores are reset afterwards.
+ * Errors: BC_ERR_INVALID_ARG for NULL g / best or an empty or invalid sample.
+ */
+bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_sample, const bc_run_options *base,
+                      bc_run_options *best, void *stream);
 
 /* bc_scores flags */
 #define BC_OUT_DEVICE 0x1u

@@ -29,6 +29,7 @@ BC_SKIP_SYMMETRY_CHECK = 0x2
 BC_RUN_ACCUMULATE = 0x1
 BC_RUN_NO_GRAPHS = 0x2
 BC_RUN_FORCE_F64 = 0x4
+BC_RUN_TUNED = 0x8
 BC_OUT_DEVICE = 0x1
 
 BC_VARIANT_PUSH_TPV, BC_VARIANT_PUSH_WPV, BC_VARIANT_PULL = 0, 1, 2
@@ -42,7 +43,8 @@ BC_MLP_PARAMS = 32 * 5 + 32 + 32 * 32 + 32 + 3 * 32 + 3
 
 EXPORTS = ["bc_status_string", "bc_last_error", "bc_graph_create", "bc_graph_create_multi", "bc_destroy",
            "bc_graph_info", "bc_run_options_init", "bc_run", "bc_scores", "bc_run_detail", "bc_run_stats",
-           "bc_load_policy", "bc_mlp_loss_grad", "bc_mlp_train", "bc_mlp_predict", "bc_collect_level_times"]
+           "bc_load_policy", "bc_mlp_loss_grad", "bc_mlp_train", "bc_mlp_predict", "bc_collect_level_times",
+           "bc_autotune"]
 
 
 class LibraryMissing(RuntimeError):
@@ -123,6 +125,8 @@ def lib():
     L.bc_run_detail.argtypes = [P, P, I64, ctypes.POINTER(RunOptions), I64, ctypes.POINTER(Detail), P]
     L.bc_run_stats.restype = ctypes.c_int
     L.bc_run_stats.argtypes = [P, ctypes.POINTER(Stats)]
+    L.bc_autotune.restype = ctypes.c_int
+    L.bc_autotune.argtypes = [P, P, I64, ctypes.POINTER(RunOptions), ctypes.POINTER(RunOptions), P]
     L.bc_load_policy.restype = ctypes.c_int
     L.bc_load_policy.argtypes = [P, P, I64]
     L.bc_mlp_loss_grad.restype = ctypes.c_int
@@ -270,6 +274,18 @@ def bc_run_stats(h) -> dict:
     return out
 
 
+def bc_autotune(h, sample, options: RunOptions | None = None, stream=None) -> dict:
+    """Measure the candidate launch configurations on ``sample`` (host source
+    ids); returns the fastest as a dict of run options and keeps it in the
+    handle for runs with BC_RUN_TUNED."""
+    s = np.ascontiguousarray(sample, dtype=np.int32)
+    best = RunOptions()
+    _check(lib().bc_autotune(h, _p(s), s.size, ctypes.byref(options) if options is not None else None,
+                             ctypes.byref(best), _stream(stream)))
+    return {"batch": best.batch, "policy": best.policy, "grid_blocks": best.grid_blocks,
+            "chunk_steps": best.chunk_steps, "wpv_degree": best.wpv_degree}
+
+
 def bc_load_policy(h, weights):
     if weights is None:
         _check(lib().bc_load_policy(h, None, 0))
@@ -364,6 +380,9 @@ class Graph:
 
     def load_policy(self, weights):
         bc_load_policy(self.h, weights)
+
+    def autotune(self, sample, stream=None, **opts):
+        return bc_autotune(self.h, sample, make_options(**opts), stream)
 
     def collect_level_times(self, sources, cap=100000, stream=None, **opts):
         return bc_collect_level_times(self.h, sources, cap, make_options(**opts), stream)

@@ -183,6 +183,9 @@ struct bc_graph {
     // policy
     float *mlp = nullptr;
     bool has_mlp = false;
+    // autotuner result (bc_autotune), used by bc_run with BC_RUN_TUNED
+    bool has_tuned = false;
+    bc_run_options tuned{};
     // graph cache
     std::vector<CachedGraph> graphs;
     bc_stats stats{};
@@ -908,6 +911,15 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
     bc_run_options o;
     bc_run_options_init(&o);
     if (opt) o = *opt;
+    if (o.flags & BC_RUN_TUNED) {
+        if (!g->has_tuned) return fail(BC_ERR_INVALID_ARG, "BC_RUN_TUNED before bc_autotune");
+        // fields the caller left automatic (zero) come from the tuner
+        if (o.batch == 0) o.batch = g->tuned.batch;
+        if (o.policy == BC_POLICY_AUTO) o.policy = g->tuned.policy;
+        if (o.grid_blocks == 0) o.grid_blocks = g->tuned.grid_blocks;
+        if (o.chunk_steps == 0) o.chunk_steps = g->tuned.chunk_steps;
+        if (o.wpv_degree <= 0.0f) o.wpv_degree = g->tuned.wpv_degree;
+    }
     std::vector<int32_t> all;
     const int32_t *src = sources;
     int64_t ns = n_sources;
@@ -1181,5 +1193,73 @@ extern "C" bc_status bc_load_policy(bc_graph *g, const float *weights, int64_t l
     HIP_TRY(hipMemcpy(g->mlp, weights, sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
     g->has_mlp = true;
     free_graphs(g);  // captured args carry has_mlp
+    return BC_OK;
+}
+
+extern "C" bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_sample, const bc_run_options *base,
+                                 bc_run_options *best, void *stream) {
+    if (!g || !best || !sample || n_sample < 1) return fail(BC_ERR_INVALID_ARG, "NULL argument or empty sample");
+    bc_run_options cur;
+    bc_run_options_init(&cur);
+    if (base) cur = *base;
+    cur.flags &= ~(BC_RUN_ACCUMULATE | BC_RUN_TUNED);
+    // resolve the automatic fields so every candidate is explicit
+    RunCfg c0;
+    bc_status s = resolve_cfg(g, cur, n_sample, &c0);
+    if (s != BC_OK) return s;
+    if (cur.batch == 0) cur.batch = c0.engine == 1 ? 1 : 64;
+    if (cur.policy == BC_POLICY_AUTO) cur.policy = g->has_mlp ? BC_POLICY_MLP : BC_POLICY_HEURISTIC;
+    if (cur.grid_blocks == 0) cur.grid_blocks = c0.grid;
+    if (cur.chunk_steps == 0) cur.chunk_steps = c0.chunk;
+    if (cur.wpv_degree <= 0.0f) cur.wpv_degree = 24.0f;
+    hipStream_t st = (hipStream_t)stream;
+    auto time_one = [&](const bc_run_options &o, double *ms) -> bc_status {
+        bc_status r = run_impl(g, sample, n_sample, &o, st, -1, nullptr);  // builds captured graphs
+        if (r != BC_OK) return r;
+        const auto t0 = std::chrono::steady_clock::now();
+        r = run_impl(g, sample, n_sample, &o, st, -1, nullptr);
+        if (r != BC_OK) return r;
+        *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return BC_OK;
+    };
+    double best_ms = 0.0;
+    s = time_one(cur, &best_ms);
+    if (s != BC_OK) return s;
+    const int dflt_grid = cur.grid_blocks;
+    for (int dim = 0; dim < 5; ++dim) {
+        std::vector<bc_run_options> cand;
+        bc_run_options c = cur;
+        if (dim == 0) {
+            if (cur.batch == 1) continue;  // the per-source engine was asked for
+            for (int k : {64, 32, 16}) { c.batch = k; cand.push_back(c); }
+        } else if (dim == 1) {
+            if (!g->has_mlp) continue;
+            for (int p : {BC_POLICY_HEURISTIC, BC_POLICY_MLP}) { c.policy = p; cand.push_back(c); }
+        } else if (dim == 2) {
+            for (int d : {1, 2, 4}) { c.grid_blocks = std::max(1, dflt_grid / d); cand.push_back(c); }
+        } else if (dim == 3) {
+            for (int k : {8, 16, 32}) { c.chunk_steps = k; cand.push_back(c); }
+        } else {
+            for (float w : {12.0f, 24.0f, 48.0f}) { c.wpv_degree = w; cand.push_back(c); }
+        }
+        for (const bc_run_options &x : cand) {
+            if (std::memcmp(&x, &cur, sizeof(x)) == 0) continue;
+            double ms = 0.0;
+            s = time_one(x, &ms);
+            if (s != BC_OK) return s;
+            if (ms < best_ms) {
+                best_ms = ms;
+                cur = x;
+            }
+        }
+    }
+    g->tuned = cur;
+    g->has_tuned = true;
+    *best = cur;
+    if (g->n > 0) {
+        fill_u64<<<grid_for(g->n, 256, 4096), 256, 0, st>>>((unsigned long long *)g->bc, g->n, 0ull);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(st));
+    }
     return BC_OK;
 }
