@@ -116,6 +116,8 @@ bc_status bc_graph_info(const bc_graph *g, int32_t *n, int64_t *nnz, int32_t *n_
 #define BC_RUN_ACCUMULATE  0x1u  /* add to the existing scores instead of resetting */
 #define BC_RUN_NO_GRAPHS   0x2u  /* launch level steps one by one, no hipGraph  */
 #define BC_RUN_FORCE_F64   0x4u  /* test hook: evaluate every source in FP64 mode */
+#define BC_RUN_ONE_QUEUE   0x10u /* a handle over many graphs: run every batch on one
+                                    level state machine instead of concurrent parts */
 #define BC_RUN_TUNED       0x8u  /* K, policy, workgroups, chunk and WPV threshold left
                                     automatic (zero) come from bc_autotune's result */
 

@@ -30,6 +30,7 @@ BC_RUN_ACCUMULATE = 0x1
 BC_RUN_NO_GRAPHS = 0x2
 BC_RUN_FORCE_F64 = 0x4
 BC_RUN_TUNED = 0x8
+BC_RUN_ONE_QUEUE = 0x10
 BC_OUT_DEVICE = 0x1
 
 BC_VARIANT_PUSH_TPV, BC_VARIANT_PUSH_WPV, BC_VARIANT_PULL = 0, 1, 2

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/bc.h"
@@ -130,6 +131,8 @@ struct CachedGraph {
     hipGraph_t graph = nullptr;
 };
 
+struct SubPart;
+
 struct bc_graph {
     int32_t n = 0;
     int64_t nnz = 0;
@@ -147,7 +150,8 @@ struct bc_graph {
     int grid_plain = 1024, grid_batch = 1024;  // resident workgroups of the step kernels
     double *bc = nullptr;
     size_t bytes = 0;
-    hipStream_t cap_stream = nullptr;
+    hipStream_t cap_stream = nullptr;  // private capture stream, created on first capture
+    bool capture_on_launch = false;    // parts capture on their own (private) launch stream
     Ctl *ctl = nullptr;
     Ctl *ctl_host = nullptr;       // pinned
     int32_t *flag_host = nullptr;  // pinned: {phase, err} polled after chunks
@@ -186,9 +190,22 @@ struct bc_graph {
     // autotuner result (bc_autotune), used by bc_run with BC_RUN_TUNED
     bool has_tuned = false;
     bc_run_options tuned{};
+    // unions of many graphs: sub-unions run concurrently (see run_parts)
+    std::vector<struct SubPart> parts;
+    std::vector<int32_t> part_of_graph, local_base;  // per parent graph
     // graph cache
     std::vector<CachedGraph> graphs;
     bc_stats stats{};
+};
+
+// One sub-union of a many-graph handle: a handle of its own over some of
+// the graphs (vertices renumbered consecutively), its stream, and the map
+// back to the parent's vertex ids.
+struct SubPart {
+    bc_graph *h = nullptr;
+    int32_t *to_parent = nullptr;           // device int32[h->n]
+    std::vector<int32_t> to_parent_host;
+    hipStream_t stream = nullptr;
 };
 
 static void free_graphs(bc_graph *g) {
@@ -199,9 +216,12 @@ static void free_graphs(bc_graph *g) {
     g->graphs.clear();
 }
 
+static void free_parts(bc_graph *g);
+
 extern "C" void bc_destroy(bc_graph *g) {
     if (!g) return;
     (void)hipDeviceSynchronize();
+    free_parts(g);
     free_graphs(g);
     void *dev[] = {g->row_ptr, g->col, g->bc, g->ctl, g->p_d, g->p_queue, g->p_level_off, g->p_shift,
                    g->p_sig, g->p_chat, g->b_vn, g->b_fw0, g->b_fw1, g->b_lq_vtx, g->b_lq_mask,
@@ -378,7 +398,6 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
     CR_TRY(dalloc(&g->ctl, 1, &g->bytes));
     CR_TRY(hipHostMalloc((void **)&g->ctl_host, sizeof(Ctl), hipHostMallocDefault));
     CR_TRY(hipHostMalloc((void **)&g->flag_host, 64 * sizeof(int32_t), hipHostMallocDefault));
-    CR_TRY(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
     CR_TRY(dalloc(&g->mlp, (size_t)kMlpParams, &g->bytes));
 #undef CR_TRY
     *out = g;
@@ -516,7 +535,7 @@ struct RunCfg {
 
 template <typename Args>
 static bc_status get_graph(bc_graph *g, const Args &args, void (*kern)(Args), const RunCfg &cfg,
-                           hipGraphExec_t *out) {
+                           hipStream_t launch_st, hipGraphExec_t *out) {
     std::vector<unsigned char> key(sizeof(Args) + 3 * sizeof(int));
     std::memcpy(key.data(), &args, sizeof(Args));
     int extra[3] = {cfg.grid, cfg.chunk, cfg.engine * 2 + cfg.mode};
@@ -528,14 +547,24 @@ static bc_status get_graph(bc_graph *g, const Args &args, void (*kern)(Args), co
         }
     CachedGraph cg;
     cg.key = key;
-    HIP_TRY(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
+    // every stream holds a hardware queue of the device's few; a part
+    // captures on its own launch stream (idle first) instead of a second one
+    hipStream_t cs = g->cap_stream;
+    if (g->capture_on_launch) {
+        cs = launch_st;
+        HIP_TRY(hipStreamSynchronize(cs));
+    } else if (!cs) {
+        HIP_TRY(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+        cs = g->cap_stream;
+    }
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     Args argcopy = args;
     void *kargs[] = {(void *)&argcopy};
     for (int i = 0; i < cfg.chunk; ++i)
-        (void)hipLaunchKernel((const void *)kern, dim3(cfg.grid), dim3(kBlock), kargs, 0, g->cap_stream);
+        (void)hipLaunchKernel((const void *)kern, dim3(cfg.grid), dim3(kBlock), kargs, 0, cs);
     // flag readback at the end of the chunk
-    (void)hipMemcpyAsync(g->flag_host, g->ctl, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, g->cap_stream);
-    hipError_t e = hipStreamEndCapture(g->cap_stream, &cg.graph);
+    (void)hipMemcpyAsync(g->flag_host, g->ctl, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, cs);
+    hipError_t e = hipStreamEndCapture(cs, &cg.graph);
     if (e != hipSuccess) return fail(BC_ERR_DEVICE, std::string("graph capture failed: ") + hipGetErrorString(e));
     e = hipGraphInstantiate(&cg.exec, cg.graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
@@ -558,7 +587,7 @@ static bc_status drive(bc_graph *g, const Args &args, void (*kern)(Args), const 
                        int64_t max_steps, int64_t *launches, double *dev_ms) {
     hipGraphExec_t exec = nullptr;
     if (cfg.use_graphs) {
-        bc_status s = get_graph(g, args, kern, cfg, &exec);
+        bc_status s = get_graph(g, args, kern, cfg, st, &exec);
         if (s != BC_OK) return s;
     }
     const int kRing = 4;
@@ -905,6 +934,267 @@ static bc_status resolve_cfg(const bc_graph *g, const bc_run_options &o, int64_t
     return BC_OK;
 }
 
+// ------------------------------------------------ concurrent sub-unions
+// A handle over many graphs (block-diagonal union) runs its batched work as
+// a few sub-unions (4; BC_PARTS overrides), each a handle of its own on its own stream, driven
+// from its own host thread, so the level steps of different graphs overlap
+// on the device (a single level state machine leaves the GPU idle between
+// the small steps of small graphs).  Graphs go to parts by largest work
+// first; a part keeps its graphs in the parent's order and a graph's sources
+// in list order, so every score is accumulated in the same order as by one
+// handle and the results are identical bit for bit.
+static int n_parts() {
+    static const int np = [] {
+        const char *e = std::getenv("BC_PARTS");
+        const int v = e ? std::atoi(e) : 4;
+        return std::min(16, std::max(2, v));
+    }();
+    return np;
+}
+
+__global__ void gather_f64(double *dst, const double *src, const int32_t *map, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[map[i]];
+}
+__global__ void scatter_f64(double *dst, const double *src, const int32_t *map, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[map[i]] = src[i];
+}
+
+static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources, const bc_run_options *opt,
+                          void *stream, int64_t dump_index, bc_detail *detail);
+
+static void free_parts(bc_graph *g) {
+    for (SubPart &pt : g->parts) {
+        if (pt.h) bc_destroy(pt.h);
+        if (pt.to_parent) (void)hipFree(pt.to_parent);
+        if (pt.stream) (void)hipStreamDestroy(pt.stream);
+    }
+    g->parts.clear();
+}
+
+static bool use_parts(const bc_graph *g, const bc_run_options &o, int64_t ns) {
+    if (g->n_graphs < 2 * n_parts() || (o.flags & BC_RUN_ONE_QUEUE) || o.batch == 1) return false;
+    if (o.batch == 0 && ns < 2) return false;  // the per-source engine would be chosen
+    return std::getenv("BC_ONE_QUEUE") == nullptr;
+}
+
+static bc_status ensure_parts(bc_graph *g) {
+    if (!g->parts.empty()) return BC_OK;
+    const int32_t n = g->n;
+    std::vector<int32_t> rp((size_t)n + 1), col((size_t)g->nnz);
+    HIP_TRY(hipMemcpy(rp.data(), g->row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost));
+    if (g->nnz) HIP_TRY(hipMemcpy(col.data(), g->col, sizeof(int32_t) * (size_t)g->nnz, hipMemcpyDeviceToHost));
+    // graphs by decreasing size (vertices x arcs), dealt to the parts in
+    // snake order (0 1 2 3 3 2 1 0 ...): every part gets about the same
+    // number of graphs (batches) and the same total size
+    const int G = g->n_graphs;
+    const int P = n_parts();
+    std::vector<int32_t> order(G);
+    std::vector<double> work(G);
+    for (int i = 0; i < G; ++i) {
+        order[i] = i;
+        const int32_t lo = g->voff[i], hi = g->voff[i + 1];
+        work[i] = (double)(hi - lo) * (double)(rp[hi] - rp[lo] + (hi - lo));
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+    g->part_of_graph.assign(G, 0);
+    for (int r = 0; r < G; ++r) {
+        const int k = r % (2 * P);
+        g->part_of_graph[order[r]] = k < P ? k : 2 * P - 1 - k;
+    }
+    g->local_base.assign(G, 0);
+    std::vector<float> w;
+    if (g->has_mlp) {
+        w.resize(kMlpParams);
+        HIP_TRY(hipMemcpy(w.data(), g->mlp, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost));
+    }
+    std::vector<SubPart> parts(P);
+    for (int p = 0; p < P; ++p) {
+        std::vector<int32_t> srp(1, 0), scol, svoff(1, 0), map;
+        for (int i = 0; i < G; ++i) {
+            if (g->part_of_graph[i] != p) continue;
+            const int32_t lo = g->voff[i], hi = g->voff[i + 1];
+            const int32_t base = (int32_t)map.size();
+            g->local_base[i] = base;
+            for (int32_t v = lo; v < hi; ++v) {
+                map.push_back(v);
+                for (int32_t e = rp[v]; e < rp[v + 1]; ++e) scol.push_back(col[e] - lo + base);
+                srp.push_back((int32_t)scol.size());
+            }
+            svoff.push_back((int32_t)map.size());
+        }
+        SubPart &pt = parts[p];
+        bc_status s = bc_graph_create_multi((int32_t)svoff.size() - 1, svoff.data(), (int32_t)map.size(),
+                                            (int64_t)scol.size(), srp.data(), scol.data(), BC_SKIP_SYMMETRY_CHECK,
+                                            &pt.h);
+        if (s == BC_OK) pt.h->capture_on_launch = true;
+        if (s == BC_OK && !w.empty()) s = bc_load_policy(pt.h, w.data(), kMlpParams);
+        if (s == BC_OK && hipMalloc((void **)&pt.to_parent, sizeof(int32_t) * std::max<size_t>(map.size(), 1)) != hipSuccess)
+            s = fail(BC_ERR_OUT_OF_MEMORY, "part vertex map");
+        if (s == BC_OK && !map.empty() &&
+            hipMemcpy(pt.to_parent, map.data(), sizeof(int32_t) * map.size(), hipMemcpyHostToDevice) != hipSuccess)
+            s = fail(BC_ERR_DEVICE, "part vertex map copy");
+        if (s == BC_OK && hipStreamCreateWithFlags(&pt.stream, hipStreamNonBlocking) != hipSuccess)
+            s = fail(BC_ERR_DEVICE, "part stream");
+        pt.to_parent_host = std::move(map);
+        if (s != BC_OK) {
+            g->parts = std::move(parts);
+            free_parts(g);
+            return s;
+        }
+    }
+    g->parts = std::move(parts);
+    return BC_OK;
+}
+
+static bc_status run_parts(bc_graph *g, const int32_t *sources, int64_t n_sources, const bc_run_options &o,
+                           void *stream, int64_t dump_index, bc_detail *detail) {
+    bc_status s = ensure_parts(g);
+    if (s != BC_OK) return s;
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t ns = sources ? n_sources : g->n;
+    if (ns < 0) return fail(BC_ERR_INVALID_ARG, "n_sources < 0");
+    if (detail && (dump_index < 0 || dump_index >= ns)) return fail(BC_ERR_INVALID_ARG, "dump_index out of range");
+    const int P = (int)g->parts.size();
+    std::vector<std::vector<int32_t>> lists(P);
+    int dump_part = -1;
+    int64_t dump_local = -1;
+    for (int64_t i = 0; i < ns; ++i) {
+        const int32_t v = sources ? sources[i] : (int32_t)i;
+        if (v < 0 || v >= g->n) return fail(BC_ERR_INVALID_ARG, "source id outside [0, n)");
+        const int gi = (int)(std::upper_bound(g->voff.begin(), g->voff.end(), v) - g->voff.begin()) - 1;
+        const int p = g->part_of_graph[gi];
+        if (detail && i == dump_index) {
+            dump_part = p;
+            dump_local = (int64_t)lists[p].size();
+        }
+        lists[p].push_back(g->local_base[gi] + (v - g->voff[gi]));
+    }
+    const bool acc = (o.flags & BC_RUN_ACCUMULATE) != 0;
+    if (!acc && g->n > 0) {
+        fill_u64<<<grid_for(g->n, 256, 4096), 256, 0, st>>>((unsigned long long *)g->bc, g->n, 0ull);
+        HIP_TRY(hipGetLastError());
+    }
+    for (SubPart &pt : g->parts) {
+        if (acc && pt.h->n > 0) {  // the parts continue from the parent's scores
+            gather_f64<<<grid_for(pt.h->n, 256, 4096), 256, 0, st>>>(pt.h->bc, g->bc, pt.to_parent, pt.h->n);
+            HIP_TRY(hipGetLastError());
+        }
+    }
+    hipEvent_t ev0;
+    HIP_TRY(hipEventCreateWithFlags(&ev0, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(ev0, st));
+    for (SubPart &pt : g->parts) HIP_TRY(hipStreamWaitEvent(pt.stream, ev0, 0));
+    (void)hipEventDestroy(ev0);
+    // sub-detail buffers for the part that holds the dumped source
+    const size_t dn = dump_part >= 0 ? (size_t)std::max<int32_t>(g->parts[dump_part].h->n, 1) : 0;
+    std::vector<int32_t> sd(dn), sexp(dn);
+    std::vector<uint64_t> su(dn);
+    std::vector<double> smant(dn), sdel(dn);
+    bc_detail sub_det{};
+    sub_det.d = sd.data();
+    sub_det.sigma_u64 = su.data();
+    sub_det.sigma_mant = smant.data();
+    sub_det.sigma_exp = sexp.data();
+    sub_det.delta = sdel.data();
+    std::vector<bc_status> res(P, BC_OK);
+    std::vector<std::string> msg(P);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::vector<std::thread> th;
+    for (int p = 0; p < P; ++p) {
+        if (lists[p].empty()) continue;
+        th.emplace_back([&, p]() {
+            (void)hipSetDevice(dev);
+            bc_run_options po = o;
+            if (!acc) po.flags &= ~BC_RUN_ACCUMULATE;
+            po.flags |= BC_RUN_ONE_QUEUE;
+            SubPart &pt = g->parts[p];
+            if (p == dump_part)
+                res[p] = run_impl(pt.h, lists[p].data(), (int64_t)lists[p].size(), &po, pt.stream, dump_local, &sub_det);
+            else
+                res[p] = run_impl(pt.h, lists[p].data(), (int64_t)lists[p].size(), &po, pt.stream, -1, nullptr);
+            if (res[p] != BC_OK) msg[p] = bc_last_error();
+        });
+    }
+    for (std::thread &t : th) t.join();
+    for (int p = 0; p < P; ++p)
+        if (res[p] != BC_OK) return fail(res[p], msg[p]);
+    // scores back to the parent, then the caller's stream waits for every part
+    for (int p = 0; p < P; ++p) {
+        SubPart &pt = g->parts[p];
+        if ((lists[p].empty() && !acc) || pt.h->n == 0) continue;
+        scatter_f64<<<grid_for(pt.h->n, 256, 4096), 256, 0, pt.stream>>>(g->bc, pt.h->bc, pt.to_parent, pt.h->n);
+        HIP_TRY(hipGetLastError());
+        hipEvent_t ev;
+        HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(ev, pt.stream));
+        HIP_TRY(hipStreamWaitEvent(st, ev, 0));
+        (void)hipEventDestroy(ev);
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    // statistics: sums over the parts (device times overlap), wall time of the whole
+    std::memset(&g->stats, 0, sizeof(g->stats));
+    bc_stats &S = g->stats;
+    for (int p = 0; p < P; ++p) {
+        if (lists[p].empty()) continue;
+        const bc_stats &x = g->parts[p].h->stats;
+        S.n_sources += x.n_sources;
+        S.n_batches += x.n_batches;
+        S.batch = x.batch;
+        S.policy = x.policy;
+        S.grid_blocks = x.grid_blocks;
+        S.chunk_steps = x.chunk_steps;
+        S.steps += x.steps;
+        S.launches += x.launches;
+        S.forward_levels += x.forward_levels;
+        S.max_levels = std::max(S.max_levels, x.max_levels);
+        for (int k = 0; k < 3; ++k) S.variant_levels[k] += x.variant_levels[k];
+        S.f64_sources += x.f64_sources;
+        S.arcs_scanned += x.arcs_scanned;
+        S.lane_arcs += x.lane_arcs;
+        S.queue_entries += x.queue_entries;
+        S.algo_bytes += x.algo_bytes;
+        for (int k = 0; k < 10; ++k) {
+            S.phase_ms[k] += x.phase_ms[k];
+            S.phase_arcs[k] += x.phase_arcs[k];
+            S.phase_lane_arcs[k] += x.phase_lane_arcs[k];
+            S.phase_pairs[k] += x.phase_pairs[k];
+        }
+        for (int k = 0; k < 3; ++k) S.variant_ms[k] += x.variant_ms[k];
+        for (int k = 0; k < 2; ++k) {
+            S.mode_launches[k] += x.mode_launches[k];
+            S.mode_ms[k] += x.mode_ms[k];
+            S.mode_algo_bytes[k] += x.mode_algo_bytes[k];
+        }
+    }
+    S.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (detail) {
+        // the dumped source's graph lies in one part; every other vertex is unreached
+        const SubPart &pt = g->parts[dump_part];
+        for (int32_t v = 0; v < g->n; ++v) {
+            if (detail->d) detail->d[v] = -1;
+            if (detail->sigma_u64) detail->sigma_u64[v] = 0;
+            if (detail->sigma_mant) detail->sigma_mant[v] = 0.0;
+            if (detail->sigma_exp) detail->sigma_exp[v] = 0;
+            if (detail->delta) detail->delta[v] = 0.0;
+        }
+        for (size_t i = 0; i < pt.to_parent_host.size(); ++i) {
+            const int32_t v = pt.to_parent_host[i];
+            if (detail->d) detail->d[v] = sd[i];
+            if (detail->sigma_u64) detail->sigma_u64[v] = su[i];
+            if (detail->sigma_mant) detail->sigma_mant[v] = smant[i];
+            if (detail->sigma_exp) detail->sigma_exp[v] = sexp[i];
+            if (detail->delta) detail->delta[v] = sdel[i];
+        }
+        detail->mode = sub_det.mode;
+        detail->n_levels = sub_det.n_levels;
+    }
+    return BC_OK;
+}
+
 static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources, const bc_run_options *opt,
                           void *stream, int64_t dump_index, bc_detail *detail) {
     if (!g) return fail(BC_ERR_INVALID_ARG, "NULL handle");
@@ -919,7 +1209,10 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
         if (o.grid_blocks == 0) o.grid_blocks = g->tuned.grid_blocks;
         if (o.chunk_steps == 0) o.chunk_steps = g->tuned.chunk_steps;
         if (o.wpv_degree <= 0.0f) o.wpv_degree = g->tuned.wpv_degree;
+        o.flags &= ~BC_RUN_TUNED;
     }
+    if (use_parts(g, o, sources ? n_sources : g->n))
+        return run_parts(g, sources, n_sources, o, stream, dump_index, detail);
     std::vector<int32_t> all;
     const int32_t *src = sources;
     int64_t ns = n_sources;
@@ -1183,13 +1476,19 @@ extern "C" bc_status bc_run_stats(const bc_graph *g, bc_stats *out) {
 
 extern "C" bc_status bc_load_policy(bc_graph *g, const float *weights, int64_t len) {
     if (!g) return fail(BC_ERR_INVALID_ARG, "NULL handle");
+    if (weights) {
+        if (len != kMlpParams) return fail(BC_ERR_INVALID_ARG, "weights length must be BC_MLP_PARAMS");
+        for (int64_t i = 0; i < len; ++i)
+            if (!std::isfinite(weights[i])) return fail(BC_ERR_INVALID_ARG, "non-finite policy weight");
+    }
+    for (SubPart &pt : g->parts) {
+        bc_status s = bc_load_policy(pt.h, weights, len);
+        if (s != BC_OK) return s;
+    }
     if (!weights) {
         g->has_mlp = false;  // unload
         return BC_OK;
     }
-    if (len != kMlpParams) return fail(BC_ERR_INVALID_ARG, "weights length must be BC_MLP_PARAMS");
-    for (int64_t i = 0; i < len; ++i)
-        if (!std::isfinite(weights[i])) return fail(BC_ERR_INVALID_ARG, "non-finite policy weight");
     HIP_TRY(hipMemcpy(g->mlp, weights, sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
     g->has_mlp = true;
     free_graphs(g);  // captured args carry has_mlp

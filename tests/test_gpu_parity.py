@@ -229,6 +229,33 @@ def test_fp64_first_pass_hands_back_small_counts():
             check_detail(u, det, srcs[idx])
 
 
+def test_many_graph_union_parts_bit_identical():
+    # 12 graphs of uneven size: the handle runs them as concurrent parts; the
+    # scores must equal one state machine's bit for bit and each graph's oracle
+    sizes = [50, 700, 120, 3000, 90, 400, 1500, 60, 250, 800, 30, 2200]
+    gs = [W.barabasi_albert(n, 4, seed=200 + i) for i, n in enumerate(sizes)]
+    gs[5] = W.grid(20, 0.1, 0.0, seed=3)
+    u = W.union(gs)
+    srcs = np.concatenate([W.choose_sources(u, 600, seed=9), np.arange(0, u.n, 7)]).astype(np.int32)
+    say("[parts] union of", len(gs), "graphs, sources", len(srcs))
+    with b.Graph(u) as G:
+        G.run(srcs, batch=64, flags=b.BC_RUN_ONE_QUEUE)
+        one = G.scores().copy()
+        G.run(srcs, batch=64)
+        parts = G.scores().copy()
+        assert np.array_equal(one.view(np.uint64), parts.view(np.uint64))
+        G.run(srcs[:300], batch=64)
+        G.run(srcs[300:], batch=64, flags=b.BC_RUN_ACCUMULATE)
+        acc = G.scores().copy()
+        for idx in (0, 333, len(srcs) - 1):
+            det = G.detail(srcs, dump_index=idx, batch=64)
+            check_detail(u, det, srcs[idx])
+        assert np.array_equal(G.scores().view(np.uint64), parts.view(np.uint64))
+    ref, _ = oracle.bc(u, srcs)
+    assert_bc_close(parts, ref)
+    assert_bc_close(acc, ref)
+
+
 def test_invalid_inputs_and_handle_survives():
     good = W.grid(4)
     bad_cases = {
