@@ -936,17 +936,18 @@ static bc_status resolve_cfg(const bc_graph *g, const bc_run_options &o, int64_t
 
 // ------------------------------------------------ concurrent sub-unions
 // A handle over many graphs (block-diagonal union) runs its batched work as
-// a few sub-unions (4; BC_PARTS overrides), each a handle of its own on its own stream, driven
-// from its own host thread, so the level steps of different graphs overlap
-// on the device (a single level state machine leaves the GPU idle between
-// the small steps of small graphs).  Graphs go to parts by largest work
-// first; a part keeps its graphs in the parent's order and a graph's sources
-// in list order, so every score is accumulated in the same order as by one
-// handle and the results are identical bit for bit.
+// up to 8 sub-unions (environment BC_PARTS overrides, at least two graphs
+// per part), each a handle of its own on its own stream with a dedicated
+// hardware queue, driven from its own host thread, so the level steps of
+// different graphs overlap on the device (one level state machine leaves
+// the GPU idle during the small steps of small graphs).  Graphs are dealt
+// by size; a part keeps its graphs in the parent's order and a graph's
+// sources in list order, so every score is accumulated in the same order as
+// by one handle and the results are identical bit for bit.
 static int n_parts() {
     static const int np = [] {
         const char *e = std::getenv("BC_PARTS");
-        const int v = e ? std::atoi(e) : 4;
+        const int v = e ? std::atoi(e) : 8;
         return std::min(16, std::max(2, v));
     }();
     return np;
@@ -974,7 +975,7 @@ static void free_parts(bc_graph *g) {
 }
 
 static bool use_parts(const bc_graph *g, const bc_run_options &o, int64_t ns) {
-    if (g->n_graphs < 2 * n_parts() || (o.flags & BC_RUN_ONE_QUEUE) || o.batch == 1) return false;
+    if (g->n_graphs < 4 || (o.flags & BC_RUN_ONE_QUEUE) || o.batch == 1) return false;
     if (o.batch == 0 && ns < 2) return false;  // the per-source engine would be chosen
     return std::getenv("BC_ONE_QUEUE") == nullptr;
 }
@@ -989,7 +990,7 @@ static bc_status ensure_parts(bc_graph *g) {
     // snake order (0 1 2 3 3 2 1 0 ...): every part gets about the same
     // number of graphs (batches) and the same total size
     const int G = g->n_graphs;
-    const int P = n_parts();
+    const int P = std::min(n_parts(), G / 2);  // at least two graphs per part
     std::vector<int32_t> order(G);
     std::vector<double> work(G);
     for (int i = 0; i < G; ++i) {
@@ -1010,6 +1011,13 @@ static bc_status ensure_parts(bc_graph *g) {
         HIP_TRY(hipMemcpy(w.data(), g->mlp, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost));
     }
     std::vector<SubPart> parts(P);
+    // each part needs a hardware queue of its own: ordinary streams share the
+    // device's few queues with other streams of the process, a stream with
+    // a CU mask gets a dedicated queue (here the mask enables every CU)
+    int cus = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    std::vector<uint32_t> cu_mask((size_t)std::max(1, (cus + 31) / 32), 0xffffffffu);
     for (int p = 0; p < P; ++p) {
         std::vector<int32_t> srp(1, 0), scol, svoff(1, 0), map;
         for (int i = 0; i < G; ++i) {
@@ -1035,7 +1043,10 @@ static bc_status ensure_parts(bc_graph *g) {
         if (s == BC_OK && !map.empty() &&
             hipMemcpy(pt.to_parent, map.data(), sizeof(int32_t) * map.size(), hipMemcpyHostToDevice) != hipSuccess)
             s = fail(BC_ERR_DEVICE, "part vertex map copy");
-        if (s == BC_OK && hipStreamCreateWithFlags(&pt.stream, hipStreamNonBlocking) != hipSuccess)
+        if (s == BC_OK && std::getenv("BC_PART_PLAIN_STREAMS") == nullptr &&
+            hipExtStreamCreateWithCUMask(&pt.stream, (uint32_t)cu_mask.size(), cu_mask.data()) != hipSuccess)
+            pt.stream = nullptr;
+        if (s == BC_OK && !pt.stream && hipStreamCreateWithFlags(&pt.stream, hipStreamNonBlocking) != hipSuccess)
             s = fail(BC_ERR_DEVICE, "part stream");
         pt.to_parent_host = std::move(map);
         if (s != BC_OK) {
