@@ -150,8 +150,7 @@ struct bc_graph {
     int grid_plain = 1024, grid_batch = 1024;  // resident workgroups of the step kernels
     double *bc = nullptr;
     size_t bytes = 0;
-    hipStream_t cap_stream = nullptr;  // private capture stream, created on first capture
-    bool capture_on_launch = false;    // parts capture on their own (private) launch stream
+    hipStream_t cap_stream = nullptr;  // private non-blocking capture stream, created on first capture
     Ctl *ctl = nullptr;
     Ctl *ctl_host = nullptr;       // pinned
     int32_t *flag_host = nullptr;  // pinned: {phase, err} polled after chunks
@@ -193,6 +192,7 @@ struct bc_graph {
     // unions of many graphs: sub-unions run concurrently (see run_parts)
     std::vector<struct SubPart> parts;
     std::vector<int32_t> part_of_graph, local_base;  // per parent graph
+    bool replicas = false;  // parts are full copies of a single graph (see ensure_replicas)
     // graph cache
     std::vector<CachedGraph> graphs;
     bc_stats stats{};
@@ -547,16 +547,11 @@ static bc_status get_graph(bc_graph *g, const Args &args, void (*kern)(Args), co
         }
     CachedGraph cg;
     cg.key = key;
-    // every stream holds a hardware queue of the device's few; a part
-    // captures on its own launch stream (idle first) instead of a second one
+    // capture on a private non-blocking stream: capturing a blocking stream
+    // would forbid legacy-stream work in other threads (concurrent parts)
+    (void)launch_st;
+    if (!g->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
     hipStream_t cs = g->cap_stream;
-    if (g->capture_on_launch) {
-        cs = launch_st;
-        HIP_TRY(hipStreamSynchronize(cs));
-    } else if (!cs) {
-        HIP_TRY(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
-        cs = g->cap_stream;
-    }
     HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     Args argcopy = args;
     void *kargs[] = {(void *)&argcopy};
@@ -900,7 +895,8 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
     if (dump_done) *dump_done = hc->dump_state == 2;
     if (ovf_positions && hc->n_ovf) {
         std::vector<int64_t> tmp(hc->n_ovf);
-        HIP_TRY(hipMemcpy(tmp.data(), g->ovf, sizeof(int64_t) * hc->n_ovf, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpyAsync(tmp.data(), g->ovf, sizeof(int64_t) * hc->n_ovf, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
         std::sort(tmp.begin(), tmp.end());
         *ovf_positions = tmp;
     }
@@ -962,6 +958,19 @@ __global__ void scatter_f64(double *dst, const double *src, const int32_t *map, 
         dst[map[i]] = src[i];
 }
 
+struct PartScores {
+    const double *p[16];
+    int n;
+};
+// dst[v] = (acc ? dst[v] : 0) + the parts' scores added in part order
+__global__ void sum_parts_f64(double *dst, PartScores ps, int acc, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double t = ps.p[0][i];
+        for (int k = 1; k < ps.n; ++k) t += ps.p[k][i];
+        dst[i] = acc ? dst[i] + t : t;
+    }
+}
+
 static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources, const bc_run_options *opt,
                           void *stream, int64_t dump_index, bc_detail *detail);
 
@@ -974,10 +983,58 @@ static void free_parts(bc_graph *g) {
     g->parts.clear();
 }
 
+static int n_replicas() {
+    static const int nr = [] {
+        const char *e = std::getenv("BC_REPLICAS");
+        const int v = e ? std::atoi(e) : 4;
+        return std::min(8, std::max(1, v));
+    }();
+    return nr;
+}
+
 static bool use_parts(const bc_graph *g, const bc_run_options &o, int64_t ns) {
-    if (g->n_graphs < 4 || (o.flags & BC_RUN_ONE_QUEUE) || o.batch == 1) return false;
+    if ((o.flags & BC_RUN_ONE_QUEUE) || o.batch == 1 || std::getenv("BC_ONE_QUEUE")) return false;
     if (o.batch == 0 && ns < 2) return false;  // the per-source engine would be chosen
-    return std::getenv("BC_ONE_QUEUE") == nullptr;
+    if (g->n_graphs >= 4) return true;
+    const int K = o.batch >= 8 ? o.batch : 64;
+    return n_replicas() >= 2 && ns >= 2 * (int64_t)K;
+}
+
+// Single graph: parts are full copies of the graph (own per-vertex state);
+// batches of K sources are dealt to them in turn, and the parts' score
+// vectors are added in part order.  Deterministic for a given K, but the
+// additions are grouped differently from one state machine.
+static bc_status ensure_replicas(bc_graph *g) {
+    if (!g->parts.empty()) return BC_OK;
+    const int R = n_replicas();
+    int cus = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    std::vector<uint32_t> cu_mask((size_t)std::max(1, (cus + 31) / 32), 0xffffffffu);
+    std::vector<float> w;
+    if (g->has_mlp) {
+        w.resize(kMlpParams);
+        HIP_TRY(hipMemcpy(w.data(), g->mlp, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost));
+    }
+    std::vector<SubPart> parts(R);
+    for (int r = 0; r < R; ++r) {
+        SubPart &pt = parts[r];
+        bc_status s = bc_graph_create(g->n, g->nnz, g->row_ptr, g->col, BC_INPUT_DEVICE | BC_SKIP_SYMMETRY_CHECK,
+                                      &pt.h);
+        if (s == BC_OK && !w.empty()) s = bc_load_policy(pt.h, w.data(), kMlpParams);
+        if (s == BC_OK && hipExtStreamCreateWithCUMask(&pt.stream, (uint32_t)cu_mask.size(), cu_mask.data()) != hipSuccess)
+            pt.stream = nullptr;
+        if (s == BC_OK && !pt.stream && hipStreamCreateWithFlags(&pt.stream, hipStreamNonBlocking) != hipSuccess)
+            s = fail(BC_ERR_DEVICE, "replica stream");
+        if (s != BC_OK) {
+            g->parts = std::move(parts);
+            free_parts(g);
+            return s;
+        }
+    }
+    g->parts = std::move(parts);
+    g->replicas = true;
+    return BC_OK;
 }
 
 static bc_status ensure_parts(bc_graph *g) {
@@ -1036,7 +1093,6 @@ static bc_status ensure_parts(bc_graph *g) {
         bc_status s = bc_graph_create_multi((int32_t)svoff.size() - 1, svoff.data(), (int32_t)map.size(),
                                             (int64_t)scol.size(), srp.data(), scol.data(), BC_SKIP_SYMMETRY_CHECK,
                                             &pt.h);
-        if (s == BC_OK) pt.h->capture_on_launch = true;
         if (s == BC_OK && !w.empty()) s = bc_load_policy(pt.h, w.data(), kMlpParams);
         if (s == BC_OK && hipMalloc((void **)&pt.to_parent, sizeof(int32_t) * std::max<size_t>(map.size(), 1)) != hipSuccess)
             s = fail(BC_ERR_OUT_OF_MEMORY, "part vertex map");
@@ -1061,8 +1117,10 @@ static bc_status ensure_parts(bc_graph *g) {
 
 static bc_status run_parts(bc_graph *g, const int32_t *sources, int64_t n_sources, const bc_run_options &o,
                            void *stream, int64_t dump_index, bc_detail *detail) {
-    bc_status s = ensure_parts(g);
+    bc_status s = g->n_graphs >= 4 ? ensure_parts(g) : ensure_replicas(g);
     if (s != BC_OK) return s;
+    const bool repl = g->replicas;
+    const int64_t K = o.batch >= 8 ? o.batch : 64;
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = (hipStream_t)stream;
     const int64_t ns = sources ? n_sources : g->n;
@@ -1075,21 +1133,29 @@ static bc_status run_parts(bc_graph *g, const int32_t *sources, int64_t n_source
     for (int64_t i = 0; i < ns; ++i) {
         const int32_t v = sources ? sources[i] : (int32_t)i;
         if (v < 0 || v >= g->n) return fail(BC_ERR_INVALID_ARG, "source id outside [0, n)");
-        const int gi = (int)(std::upper_bound(g->voff.begin(), g->voff.end(), v) - g->voff.begin()) - 1;
-        const int p = g->part_of_graph[gi];
+        int p;
+        int32_t local;
+        if (repl) {
+            p = (int)((i / K) % P);
+            local = v;
+        } else {
+            const int gi = (int)(std::upper_bound(g->voff.begin(), g->voff.end(), v) - g->voff.begin()) - 1;
+            p = g->part_of_graph[gi];
+            local = g->local_base[gi] + (v - g->voff[gi]);
+        }
         if (detail && i == dump_index) {
             dump_part = p;
             dump_local = (int64_t)lists[p].size();
         }
-        lists[p].push_back(g->local_base[gi] + (v - g->voff[gi]));
+        lists[p].push_back(local);
     }
     const bool acc = (o.flags & BC_RUN_ACCUMULATE) != 0;
-    if (!acc && g->n > 0) {
+    if (!acc && g->n > 0 && !repl) {
         fill_u64<<<grid_for(g->n, 256, 4096), 256, 0, st>>>((unsigned long long *)g->bc, g->n, 0ull);
         HIP_TRY(hipGetLastError());
     }
     for (SubPart &pt : g->parts) {
-        if (acc && pt.h->n > 0) {  // the parts continue from the parent's scores
+        if (acc && pt.h->n > 0 && !repl) {  // the parts continue from the parent's scores
             gather_f64<<<grid_for(pt.h->n, 256, 4096), 256, 0, st>>>(pt.h->bc, g->bc, pt.to_parent, pt.h->n);
             HIP_TRY(hipGetLastError());
         }
@@ -1120,7 +1186,7 @@ static bc_status run_parts(bc_graph *g, const int32_t *sources, int64_t n_source
         th.emplace_back([&, p]() {
             (void)hipSetDevice(dev);
             bc_run_options po = o;
-            if (!acc) po.flags &= ~BC_RUN_ACCUMULATE;
+            if (!acc || repl) po.flags &= ~BC_RUN_ACCUMULATE;
             po.flags |= BC_RUN_ONE_QUEUE;
             SubPart &pt = g->parts[p];
             if (p == dump_part)
@@ -1134,16 +1200,24 @@ static bc_status run_parts(bc_graph *g, const int32_t *sources, int64_t n_source
     for (int p = 0; p < P; ++p)
         if (res[p] != BC_OK) return fail(res[p], msg[p]);
     // scores back to the parent, then the caller's stream waits for every part
+    PartScores ps{};
     for (int p = 0; p < P; ++p) {
         SubPart &pt = g->parts[p];
-        if ((lists[p].empty() && !acc) || pt.h->n == 0) continue;
-        scatter_f64<<<grid_for(pt.h->n, 256, 4096), 256, 0, pt.stream>>>(g->bc, pt.h->bc, pt.to_parent, pt.h->n);
-        HIP_TRY(hipGetLastError());
+        if (repl) {
+            if (!lists[p].empty()) ps.p[ps.n++] = pt.h->bc;
+        } else if (!(lists[p].empty() && !acc) && pt.h->n > 0) {
+            scatter_f64<<<grid_for(pt.h->n, 256, 4096), 256, 0, pt.stream>>>(g->bc, pt.h->bc, pt.to_parent, pt.h->n);
+            HIP_TRY(hipGetLastError());
+        }
         hipEvent_t ev;
         HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         HIP_TRY(hipEventRecord(ev, pt.stream));
         HIP_TRY(hipStreamWaitEvent(st, ev, 0));
         (void)hipEventDestroy(ev);
+    }
+    if (repl && g->n > 0 && ps.n > 0) {
+        sum_parts_f64<<<grid_for(g->n, 256, 4096), 256, 0, st>>>(g->bc, ps, acc ? 1 : 0, g->n);
+        HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipStreamSynchronize(st));
     // statistics: sums over the parts (device times overlap), wall time of the whole
@@ -1185,14 +1259,23 @@ static bc_status run_parts(bc_graph *g, const int32_t *sources, int64_t n_source
     if (detail) {
         // the dumped source's graph lies in one part; every other vertex is unreached
         const SubPart &pt = g->parts[dump_part];
-        for (int32_t v = 0; v < g->n; ++v) {
+        if (repl) {
+            for (int32_t v = 0; v < g->n; ++v) {
+                if (detail->d) detail->d[v] = sd[v];
+                if (detail->sigma_u64) detail->sigma_u64[v] = su[v];
+                if (detail->sigma_mant) detail->sigma_mant[v] = smant[v];
+                if (detail->sigma_exp) detail->sigma_exp[v] = sexp[v];
+                if (detail->delta) detail->delta[v] = sdel[v];
+            }
+        }
+        for (int32_t v = 0; v < g->n && !repl; ++v) {
             if (detail->d) detail->d[v] = -1;
             if (detail->sigma_u64) detail->sigma_u64[v] = 0;
             if (detail->sigma_mant) detail->sigma_mant[v] = 0.0;
             if (detail->sigma_exp) detail->sigma_exp[v] = 0;
             if (detail->delta) detail->delta[v] = 0.0;
         }
-        for (size_t i = 0; i < pt.to_parent_host.size(); ++i) {
+        for (size_t i = 0; i < pt.to_parent_host.size() && !repl; ++i) {
             const int32_t v = pt.to_parent_host[i];
             if (detail->d) detail->d[v] = sd[i];
             if (detail->sigma_u64) detail->sigma_u64[v] = su[i];
@@ -1351,10 +1434,11 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
         std::vector<int32_t> hd(n), hsh(n + 2);
         std::vector<unsigned long long> hs(n);
         std::vector<double> hdel(n);
-        HIP_TRY(hipMemcpy(hd.data(), db.d, n * sizeof(int32_t), hipMemcpyDeviceToHost));
-        HIP_TRY(hipMemcpy(hs.data(), db.sig, n * sizeof(unsigned long long), hipMemcpyDeviceToHost));
-        HIP_TRY(hipMemcpy(hdel.data(), db.delta, n * sizeof(double), hipMemcpyDeviceToHost));
-        HIP_TRY(hipMemcpy(hsh.data(), db.shift, (n + 2) * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpyAsync(hd.data(), db.d, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hs.data(), db.sig, n * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hdel.data(), db.delta, n * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(hsh.data(), db.shift, (n + 2) * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
         free_dump();
         // sigma(v) = raw * 2^(shift_0 + ... + shift_{d-1}) in mode 1
         std::vector<int64_t> E(n + 2, 0);

@@ -89,19 +89,32 @@ def test_policies_and_capture_bit_identical(engine):
 
 
 def test_batch_widths_bit_identical():
+    # one state machine: every width adds the same terms in the same order;
+    # the default (batches dealt to concurrent replicas, whose score vectors
+    # are added at the end) groups the additions per replica instead
     g = W.rmat(12, 16, seed=22)
     srcs = W.choose_sources(g, 150, seed=6)
     say("[widths] rmat12")
     outs = []
     with b.Graph(g) as G:
         for K in (8, 16, 32, 64):
-            G.run(srcs, batch=K)
+            G.run(srcs, batch=K, flags=b.BC_RUN_ONE_QUEUE)
             outs.append(G.scores().copy())
             assert G.stats()["n_batches"] == -(-150 // K)
+        reps = {}
+        for K in (16, 64):
+            G.run(srcs, batch=K)
+            reps[K] = G.scores().copy()
+            assert G.stats()["n_batches"] == -(-150 // K)
+            G.run(srcs, batch=K)  # run to run: same bits
+            assert np.array_equal(G.scores().view(np.uint64), reps[K].view(np.uint64))
     for o in outs[1:]:
         assert np.array_equal(o.view(np.uint64), outs[0].view(np.uint64))
     ref, _ = oracle.bc(g, srcs)
     assert_bc_close(outs[0], ref)
+    for r in reps.values():
+        assert_bc_close(r, ref)
+        assert_bc_close(r, outs[0], 1e-13)
 
 
 @pytest.mark.parametrize("engine", ENGINES)
@@ -220,13 +233,15 @@ def test_fp64_first_pass_hands_back_small_counts():
     ref, modes = oracle.bc(u, srcs)
     assert modes[:64].all() and not modes[64:84].any()
     with b.Graph(u) as G:
-        G.run(srcs, batch=64)
+        G.run(srcs, batch=64, flags=b.BC_RUN_ONE_QUEUE)  # one list, so the FP64-first pass runs
         st = G.stats()
         assert st["f64_sources"] == int(modes.sum())
         assert_bc_close(G.scores(), ref)
         for idx in (70, 90, 130):  # R-MAT in the FP64-first part, grid, R-MAT at the end
-            det = G.detail(srcs, dump_index=idx, batch=64)
+            det = G.detail(srcs, dump_index=idx, batch=64, flags=b.BC_RUN_ONE_QUEUE)
             check_detail(u, det, srcs[idx])
+        G.run(srcs, batch=64)  # default path (replicas)
+        assert_bc_close(G.scores(), ref)
 
 
 def test_many_graph_union_parts_bit_identical():
