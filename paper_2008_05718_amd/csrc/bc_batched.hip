@@ -62,7 +62,7 @@ __device__ __forceinline__ void push_arcs_wave(const BatchArgs &a, unsigned long
 }
 
 #ifndef BC_UNROLL
-#define BC_UNROLL 8
+#define BC_UNROLL 4
 #endif
 constexpr int kUnroll = BC_UNROLL;  // matched neighbours whose values are loaded together
 
@@ -583,7 +583,7 @@ __device__ __forceinline__ void batch_begin(const BatchArgs &a, Ctl *c, int64_t 
 }
 
 #ifndef BC_WAVES
-#define BC_WAVES 5
+#define BC_WAVES 6
 #endif
 // Register budget of the step kernel: at least BC_WAVES wavefronts per SIMD
 // (memory latency is hidden by resident wavefronts).
