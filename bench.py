@@ -31,6 +31,7 @@ def log(*a):
 
 
 KERNEL_SOURCES = ["paper_2008_05718_amd/csrc/bc_batched.hip", "paper_2008_05718_amd/csrc/bc_common.h",
+                  "paper_2008_05718_amd/csrc/bc_api.hip",
                   "paper_2008_05718_amd/csrc/bc_dev.h", "paper_2008_05718_amd/build.py"]
 
 
@@ -128,9 +129,10 @@ def main():
     if pol == b.BC_POLICY_AUTO:  # the learned policy when trained weights exist (fixed, not tuned)
         pol = b.BC_POLICY_MLP if weights_loaded else b.BC_POLICY_HEURISTIC
 
-    def timed(sources, nsteps, nwarm, **opts):
+    def timed(sources, nsteps, nwarm, H=None, **opts):
+        H = H or G
         for _ in range(nwarm):
-            G.run(sources, stream=stream, **opts)
+            H.run(sources, stream=stream, **opts)
         torch.cuda.synchronize()
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
@@ -138,8 +140,8 @@ def main():
         t = time.perf_counter()
         stats = []
         for _ in range(nsteps):
-            G.run(sources, stream=stream, **opts)
-            stats.append(G.stats())
+            H.run(sources, stream=stream, **opts)
+            stats.append(H.stats())
         ev1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t
@@ -190,7 +192,14 @@ def main():
     plain = None
     if not args.no_plain:
         ps = srcs if args.plain_sources <= 0 else srcs[:args.plain_sources]
-        pw, pg, pst = timed(ps, 1, 1, batch=1, policy=pol, flags=gflags)
+        # the caller's vertex order and the library's default launch shape
+        # (the tuned shape and the hub-first renumbering belong to the
+        # batched path)
+        with b.Graph(g, flags=b.BC_KEEP_ORDER) as P:
+            if weights_loaded:
+                P.load_policy(np.load(args.weights))
+            pw, pg, pst = timed(ps, 1, 1, H=P, batch=1, policy=pol,
+                                flags=b.BC_RUN_NO_GRAPHS if args.no_graphs else 0)
         plain = {"value": round(g.m * len(ps) / pw / 1e9, 4), "unit": "GTEPS", "ms_per_step": round(pw * 1e3, 2),
                  "sources": int(len(ps)), "variants": pst[-1]["variant_levels"]}
         log(f"[bench] plain: {pw * 1e3:.1f} ms for {len(ps)} sources, {plain['value']} GTEPS; phase ms",

@@ -55,6 +55,7 @@ const char *bc_last_error(void);
 /* bc_graph_create flags */
 #define BC_INPUT_DEVICE        0x1u  /* row_ptr / col_idx are device pointers   */
 #define BC_SKIP_SYMMETRY_CHECK 0x2u  /* caller guarantees symmetric arcs        */
+#define BC_KEEP_ORDER          0x4u  /* no internal hub-first relabelling        */
 
 /*
  * Build a graph handle from a CSR adjacency (Section "Space Complexity":
@@ -67,9 +68,15 @@ const char *bc_last_error(void);
  *            row_ptr[v+1]), strictly ascending (no duplicates), in [0, n),
  *            never v itself (no self-loops), and symmetric: w is a neighbour
  *            of v iff v is a neighbour of w.
- *   flags    BC_INPUT_* bits above.
+ *   flags    bits above.
  * Ownership: the arrays are copied into library-owned device memory; the
  * caller may free them on return.  Validation runs on the device.
+ * Internally the vertices of each graph are renumbered hub-first (degree at
+ * least twice the graph's mean, by decreasing degree; the others keep their
+ * order) unless BC_KEEP_ORDER is given, so that the frontier words and
+ * rows of the most-read vertices share cache lines.  Every call of this
+ * interface takes and returns the caller's vertex ids; only the order in
+ * which floating-point terms of a sum are added can differ.
  * Errors: BC_ERR_INVALID_ARG (NULL pointers, negative sizes),
  * BC_ERR_INVALID_GRAPH (validation failure; bc_last_error names the rule),
  * BC_ERR_OUT_OF_MEMORY, BC_ERR_DEVICE.  *out is set only on success.

@@ -26,6 +26,7 @@ STATUS = {0: "BC_OK", 1: "BC_ERR_INVALID_ARG", 2: "BC_ERR_INVALID_GRAPH", 3: "BC
 
 BC_INPUT_DEVICE = 0x1
 BC_SKIP_SYMMETRY_CHECK = 0x2
+BC_KEEP_ORDER = 0x4
 BC_RUN_ACCUMULATE = 0x1
 BC_RUN_NO_GRAPHS = 0x2
 BC_RUN_FORCE_F64 = 0x4

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/bc.h"
@@ -186,6 +187,10 @@ struct bc_graph {
     // policy
     float *mlp = nullptr;
     bool has_mlp = false;
+    // hub-first relabelling (empty = identity): perm[new] = old, inv[old] = new
+    std::vector<int32_t> perm, inv;
+    int32_t *inv_dev = nullptr;
+    double *bc_out = nullptr;  // scores gathered back to the caller's order
     // autotuner result (bc_autotune), used by bc_run with BC_RUN_TUNED
     bool has_tuned = false;
     bc_run_options tuned{};
@@ -226,7 +231,7 @@ extern "C" void bc_destroy(bc_graph *g) {
     void *dev[] = {g->row_ptr, g->col, g->bc, g->ctl, g->p_d, g->p_queue, g->p_level_off, g->p_shift,
                    g->p_sig, g->p_chat, g->b_vn, g->b_fw0, g->b_fw1, g->b_lq_vtx, g->b_lq_mask,
                    g->b_level_off, g->b_delta, g->b_chat, g->b_shift, g->b_maxexp, g->b_lane_src,
-                   g->b_sigma, g->b_gstart, g->b_gbase,
+                   g->b_sigma, g->b_gstart, g->b_gbase, g->inv_dev, g->bc_out,
                    g->srcs, g->ovf, g->bstart, g->blo, g->bhi, g->mlp, g->hv_vtx, g->hv_seg,
                    g->p_hq.pos, g->p_hq.seg, g->p_hq.cnt, g->p_hq.off, g->p_hq.nseg, g->p_hq.part_lo,
                    g->p_hq.part_hi, g->b_hq.pos, g->b_hq.seg, g->b_hq.cnt, g->b_hq.off, g->b_hq.nseg,
@@ -354,9 +359,63 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
     }
     g->nonisolated = (int64_t)hcnt;
     {
-        // vertices heavier than one segment, for the split load balancing
         std::vector<int32_t> rp((size_t)n + 1);
         CR_TRY(hipMemcpy(rp.data(), g->row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost));
+        if (!(flags & BC_KEEP_ORDER) && n > 0 && nnz > 0) {
+            // hub-first renumbering inside each graph: vertices of degree at
+            // least twice the graph's mean (over vertices with arcs) first, by
+            // decreasing degree, the rest in their order
+            std::vector<int32_t> order((size_t)n);
+            bool moved = false;
+            for (int gi = 0; gi < n_graphs; ++gi) {
+                const int32_t lo = voff[gi], hi = voff[gi + 1];
+                int64_t arcs = 0, with = 0;
+                for (int32_t v = lo; v < hi; ++v) {
+                    const int32_t d = rp[v + 1] - rp[v];
+                    arcs += d;
+                    with += d > 0;
+                }
+                const double thr = with ? 2.0 * (double)arcs / (double)with : 1e300;
+                std::vector<int32_t> hubs, rest;
+                for (int32_t v = lo; v < hi; ++v) ((double)(rp[v + 1] - rp[v]) >= thr ? hubs : rest).push_back(v);
+                std::stable_sort(hubs.begin(), hubs.end(),
+                                 [&](int32_t a, int32_t b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
+                int32_t k = lo;
+                for (int32_t v : hubs) order[k++] = v;
+                for (int32_t v : rest) order[k++] = v;
+                for (int32_t i = lo; i < hi && !moved; ++i) moved = order[i] != i;
+            }
+            if (moved) {
+                std::vector<int32_t> col((size_t)nnz), ncol((size_t)nnz), nrp((size_t)n + 1);
+                CR_TRY(hipMemcpy(col.data(), g->col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToHost));
+                g->perm = order;
+                g->inv.assign((size_t)n, 0);
+                for (int32_t i = 0; i < n; ++i) g->inv[order[i]] = i;
+                nrp[0] = 0;
+                for (int32_t i = 0; i < n; ++i) nrp[i + 1] = nrp[i] + (rp[order[i] + 1] - rp[order[i]]);
+                // rows are independent: renumber and sort them on a few host threads
+                const int nt = (int)std::min<int64_t>(16, std::max<int64_t>(1, nnz >> 20));
+                std::vector<std::thread> pool;
+                for (int t = 0; t < nt; ++t)
+                    pool.emplace_back([&, t] {
+                        for (int32_t i = (int32_t)((int64_t)n * t / nt); i < (int32_t)((int64_t)n * (t + 1) / nt); ++i) {
+                            const int32_t v = order[i];
+                            int32_t *dst = ncol.data() + nrp[i];
+                            const int32_t d = rp[v + 1] - rp[v];
+                            for (int32_t e = 0; e < d; ++e) dst[e] = g->inv[col[rp[v] + e]];
+                            std::sort(dst, dst + d);
+                        }
+                    });
+                for (std::thread &th : pool) th.join();
+                rp = nrp;
+                CR_TRY(hipMemcpy(g->row_ptr, rp.data(), sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice));
+                CR_TRY(hipMemcpy(g->col, ncol.data(), sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice));
+                CR_TRY(dalloc(&g->inv_dev, (size_t)n, &g->bytes));
+                CR_TRY(hipMemcpy(g->inv_dev, g->inv.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
+                CR_TRY(dalloc(&g->bc_out, (size_t)n, &g->bytes));
+            }
+        }
+        // vertices heavier than one segment, for the split load balancing
         std::vector<int32_t> hv, hs(1, 0);
         int64_t segs = 0;
         int64_t cost_units = 0;
@@ -1019,8 +1078,8 @@ static bc_status ensure_replicas(bc_graph *g) {
     std::vector<SubPart> parts(R);
     for (int r = 0; r < R; ++r) {
         SubPart &pt = parts[r];
-        bc_status s = bc_graph_create(g->n, g->nnz, g->row_ptr, g->col, BC_INPUT_DEVICE | BC_SKIP_SYMMETRY_CHECK,
-                                      &pt.h);
+        bc_status s = bc_graph_create(g->n, g->nnz, g->row_ptr, g->col,
+                                      BC_INPUT_DEVICE | BC_SKIP_SYMMETRY_CHECK | BC_KEEP_ORDER, &pt.h);
         if (s == BC_OK && !w.empty()) s = bc_load_policy(pt.h, w.data(), kMlpParams);
         if (s == BC_OK && hipExtStreamCreateWithCUMask(&pt.stream, (uint32_t)cu_mask.size(), cu_mask.data()) != hipSuccess)
             pt.stream = nullptr;
@@ -1091,8 +1150,8 @@ static bc_status ensure_parts(bc_graph *g) {
         }
         SubPart &pt = parts[p];
         bc_status s = bc_graph_create_multi((int32_t)svoff.size() - 1, svoff.data(), (int32_t)map.size(),
-                                            (int64_t)scol.size(), srp.data(), scol.data(), BC_SKIP_SYMMETRY_CHECK,
-                                            &pt.h);
+                                            (int64_t)scol.size(), srp.data(), scol.data(),
+                                            BC_SKIP_SYMMETRY_CHECK | BC_KEEP_ORDER, &pt.h);
         if (s == BC_OK && !w.empty()) s = bc_load_policy(pt.h, w.data(), kMlpParams);
         if (s == BC_OK && hipMalloc((void **)&pt.to_parent, sizeof(int32_t) * std::max<size_t>(map.size(), 1)) != hipSuccess)
             s = fail(BC_ERR_OUT_OF_MEMORY, "part vertex map");
@@ -1469,15 +1528,53 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
     return BC_OK;
 }
 
+// Caller ids -> internal ids (hub-first renumbering).  A NULL list means
+// every vertex in the caller's order.  Ids are checked by the run itself.
+static const int32_t *to_internal(const bc_graph *g, const int32_t *sources, int64_t *n_sources,
+                                  std::vector<int32_t> *buf) {
+    if (!g || g->perm.empty()) return sources;
+    if (!sources) {
+        *n_sources = g->n;
+        buf->assign(g->inv.begin(), g->inv.end());
+    } else {
+        if (*n_sources < 0) return sources;
+        buf->resize((size_t)*n_sources);
+        for (int64_t i = 0; i < *n_sources; ++i) {
+            const int32_t v = sources[i];
+            (*buf)[i] = (v >= 0 && v < g->n) ? g->inv[v] : v;  // out-of-range ids stay out of range
+        }
+    }
+    return buf->data();
+}
+
 extern "C" bc_status bc_run(bc_graph *g, const int32_t *sources, int64_t n_sources, const bc_run_options *opt,
                             void *stream) {
-    return run_impl(g, sources, n_sources, opt, stream, -1, nullptr);
+    std::vector<int32_t> buf;
+    const int32_t *src = to_internal(g, sources, &n_sources, &buf);
+    return run_impl(g, src, n_sources, opt, stream, -1, nullptr);
 }
 
 extern "C" bc_status bc_run_detail(bc_graph *g, const int32_t *sources, int64_t n_sources,
                                    const bc_run_options *opt, int64_t dump_index, bc_detail *out, void *stream) {
     if (!out) return fail(BC_ERR_INVALID_ARG, "out is NULL");
-    return run_impl(g, sources, n_sources, opt, stream, dump_index, out);
+    std::vector<int32_t> buf;
+    const int32_t *src = to_internal(g, sources, &n_sources, &buf);
+    bc_status s = run_impl(g, src, n_sources, opt, stream, dump_index, out);
+    if (s != BC_OK || !g || g->perm.empty()) return s;
+    // per-vertex outputs back to the caller's ids
+    const size_t n = (size_t)g->n;
+    auto unperm = [&](auto *a) {
+        if (!a) return;
+        using T = std::remove_reference_t<decltype(a[0])>;
+        std::vector<T> t(a, a + n);
+        for (size_t v = 0; v < n; ++v) a[v] = t[g->inv[v]];
+    };
+    unperm(out->d);
+    unperm(out->sigma_u64);
+    unperm(out->sigma_mant);
+    unperm(out->sigma_exp);
+    unperm(out->delta);
+    return BC_OK;
 }
 
 extern "C" bc_status bc_collect_level_times(bc_graph *g, const int32_t *sources, int64_t n_sources,
@@ -1487,6 +1584,8 @@ extern "C" bc_status bc_collect_level_times(bc_graph *g, const int32_t *sources,
         return fail(BC_ERR_INVALID_ARG, "NULL argument, empty source list or cap < 1");
     for (int64_t i = 0; i < n_sources; ++i)
         if (sources[i] < 0 || sources[i] >= g->n) return fail(BC_ERR_INVALID_ARG, "source id outside [0, n)");
+    std::vector<int32_t> sbuf;
+    sources = to_internal(g, sources, &n_sources, &sbuf);
     bc_run_options o;
     bc_run_options_init(&o);
     if (opt) o = *opt;
@@ -1557,7 +1656,13 @@ extern "C" bc_status bc_scores(const bc_graph *g, double *out, int64_t len, uint
     if (len < g->n) return fail(BC_ERR_INVALID_ARG, "len < n");
     if (g->n == 0) return BC_OK;
     hipStream_t st = (hipStream_t)stream;
-    HIP_TRY(hipMemcpyAsync(out, g->bc, sizeof(double) * g->n,
+    const double *src = g->bc;
+    if (!g->perm.empty()) {  // back to the caller's ids: out[v] = bc[inv[v]]
+        gather_f64<<<grid_for(g->n, 256, 4096), 256, 0, st>>>(g->bc_out, g->bc, g->inv_dev, g->n);
+        HIP_TRY(hipGetLastError());
+        src = g->bc_out;
+    }
+    HIP_TRY(hipMemcpyAsync(out, src, sizeof(double) * g->n,
                            (flags & BC_OUT_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     return BC_OK;
@@ -1593,6 +1698,8 @@ extern "C" bc_status bc_load_policy(bc_graph *g, const float *weights, int64_t l
 extern "C" bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_sample, const bc_run_options *base,
                                  bc_run_options *best, void *stream) {
     if (!g || !best || !sample || n_sample < 1) return fail(BC_ERR_INVALID_ARG, "NULL argument or empty sample");
+    std::vector<int32_t> sbuf;
+    sample = to_internal(g, sample, &n_sample, &sbuf);
     bc_run_options cur;
     bc_run_options_init(&cur);
     if (base) cur = *base;

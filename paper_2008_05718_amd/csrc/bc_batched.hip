@@ -1155,10 +1155,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
             c->dump_state = 2;
             c->phase = PH_BC;
         } else if (phase == PH_BC) {
+            // the next batch is set up by the last workgroup of a launch of
+            // its own: this launch's workgroups have just cleared visited
+            // words that the set-up writes again
             const int64_t next = c->pos + 1;
             c->pos = next;
-            if (next < c->n_items) action = 1;
-            else c->phase = PH_DONE;
+            c->phase = next < c->n_items ? PH_FIN : PH_DONE;
+        } else if (phase == PH_FIN) {
+            action = 1;
         }
         s_cnt = action;
     }

@@ -136,7 +136,10 @@ struct WorkCursor {
 //
 // No fences: within a launch, workgroups exchange only device-scope atomics
 // here (slot counters, arrival counts, queue counters); plain stores are
-// consumed by later launches, which kernel boundaries order.  s_red needs
+// consumed by later launches, which kernel boundaries order.  The last
+// workgroup must therefore never store to a word that another workgroup of
+// the same launch stored to: each XCD's L2 would hold its own dirty copy
+// until the launch ends and write it back in no fixed order.  s_red needs
 // kWavesPerBlock * kNCnt entries.
 __device__ __forceinline__ bool step_epilogue(Ctl *c, Counters &cn, unsigned long long *s_red, int *s_last,
                                               bool active) {

@@ -42,7 +42,7 @@ enum : int32_t {
     PH_FWD = 1,      // discover level l+1 from the frontier at level l
     PH_SIG = 2,      // path counts of level l+1 (pull, fixed summation order)
     PH_BWD = 3,      // dependencies of level l (pull from level l+1)
-    PH_FIN = 4,      // plain: reset the visited set, start the next source
+    PH_FIN = 4,      // plain: reset the visited set, start the next source; batched: set up the next batch
     PH_BC = 5,       // batched: add dependencies to BC in source order, reset
     PH_DUMP_FWD = 6, // copy one source's d / sigma out (detail runs only)
     PH_DUMP_BWD = 7, // copy one source's delta out (detail runs only)

@@ -207,6 +207,10 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
             s_sh1 = (MODE && s_phase == PH_BWD && l + 1 < c->n_levels) ? a.shift[l + 1] : 0;
         } else if (s_phase == PH_FIN) {
             s_qe = (int)c->total_queued;
+            // the next source's words are left to the last workgroup, which
+            // sets them: a word stored by two workgroups of one launch ends
+            // with whichever L2 writes it back last
+            s_sh0 = c->pos + 1 < c->n_items ? a.srcs[c->pos + 1] : -1;
         }
         if (s_phase == PH_FWD) {
             if (s_variant == V_PULL) {  // static heavy vertices
@@ -602,9 +606,10 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
             }
         }
     } else if (phase == PH_FIN) {
-        const int total = s_qe;
+        const int total = s_qe, next_src = s_sh0;
         for (int i = blockIdx.x * kBlock + tid; i < total; i += (int)nblk * kBlock) {
             const int v = a.queue[i];
+            if (v == next_src) continue;
             d[v] = -1;
             sig[v] = 0ull;
         }

@@ -131,6 +131,60 @@ def test_rmat_details(engine):
 
 
 @pytest.mark.parametrize("engine", ENGINES)
+def test_hub_first_relabelling_keeps_caller_ids(engine):
+    # hubs placed last in the caller's numbering, so the internal renumbering
+    # moves them; every output must still be in the caller's ids
+    base = W.rmat(12, 16, seed=31)
+    deg = np.diff(base.row_ptr)
+    order = np.argsort(deg, kind="stable")  # caller id i -> vertex order[i]: hubs get the largest ids
+    inv = np.empty_like(order)
+    inv[order] = np.arange(base.n)
+    src_v = np.repeat(np.arange(base.n), deg)
+    g = W.csr_from_edges(base.n, inv[src_v], inv[base.col_idx.astype(np.int64)])
+    srcs = W.choose_sources(g, 100, seed=5)
+    srcs[3] = base.n - 1  # the largest hub as a source
+    say(f"[relabel] engine={engine} n={g.n} max degree {deg.max()}")
+    with b.Graph(g) as G, b.Graph(g, flags=b.BC_KEEP_ORDER) as H:
+        G.run(srcs, batch=engine)
+        got = G.scores()
+        H.run(srcs, batch=engine)
+        kept = H.scores()
+        for idx in (0, 3, 99):
+            det = G.detail(srcs, dump_index=idx, batch=engine)
+            check_detail(g, det, srcs[idx])
+            det_k = H.detail(srcs, dump_index=idx, batch=engine)
+            assert np.array_equal(det["d"], det_k["d"])
+        G.run(None, batch=engine)
+        all_src = G.scores()
+    ref, _ = oracle.bc(g, srcs)
+    assert_bc_close(got, ref)
+    assert_bc_close(kept, ref)
+    assert np.max(np.abs(got - kept) / np.maximum(np.abs(kept), 1e-300)) <= 1e-13
+    ref_all, _ = oracle.bc(g)
+    assert_bc_close(all_src, ref_all)
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_source_transitions_repeatable(engine):
+    # every source (plain) or batch (batched) ends with a launch whose last
+    # workgroup sets up the next one over words the other workgroups have
+    # just reset; repeated runs over many such transitions must agree bit
+    # for bit and with the oracle
+    g = W.rmat(11, 16, seed=41)
+    say(f"[transitions] rmat11 engine={engine} sources={g.n}")
+    ref, _ = oracle.bc(g)
+    with b.Graph(g) as G:
+        first = None
+        for rep in range(3):
+            G.run(None, batch=engine, flags=b.BC_RUN_ONE_QUEUE)
+            x = G.scores().copy()
+            assert_bc_close(x, ref)
+            if first is None:
+                first = x
+            assert np.array_equal(x.view(np.uint64), first.view(np.uint64)), f"run {rep} differs"
+
+
+@pytest.mark.parametrize("engine", ENGINES)
 def test_grid_uint64_overflow_fallback(engine):
     L = 40
     g = W.grid(L)
