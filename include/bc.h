@@ -74,9 +74,13 @@ const char *bc_last_error(void);
  * Internally the vertices of each graph are renumbered hub-first (degree at
  * least twice the graph's mean, by decreasing degree; the others keep their
  * order) unless BC_KEEP_ORDER is given, so that the frontier words and
- * rows of the most-read vertices share cache lines.  Every call of this
- * interface takes and returns the caller's vertex ids; only the order in
- * which floating-point terms of a sum are added can differ.
+ * rows of the most-read vertices share cache lines.  Such a handle also
+ * takes the sources of a run in its own order: by graph, then by hop
+ * distance from the graph's vertex of largest degree, then by decreasing
+ * degree (stable), so that the sources of one batch reach most vertices at
+ * the same depth.  Every call of this interface takes and returns the
+ * caller's vertex ids and source positions; only the order in which
+ * floating-point terms of a sum are added can differ.
  * Errors: BC_ERR_INVALID_ARG (NULL pointers, negative sizes),
  * BC_ERR_INVALID_GRAPH (validation failure; bc_last_error names the rule),
  * BC_ERR_OUT_OF_MEMORY, BC_ERR_DEVICE.  *out is set only on success.

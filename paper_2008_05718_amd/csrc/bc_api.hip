@@ -191,6 +191,9 @@ struct bc_graph {
     std::vector<int32_t> perm, inv;
     int32_t *inv_dev = nullptr;
     double *bc_out = nullptr;  // scores gathered back to the caller's order
+    // source order key per internal vertex (empty = keep the caller's order):
+    // graph index, distance from the graph's top hub, decreasing degree
+    std::vector<uint64_t> skey;
     // autotuner result (bc_autotune), used by bc_run with BC_RUN_TUNED
     bool has_tuned = false;
     bc_run_options tuned{};
@@ -264,6 +267,42 @@ static int grid_for(int64_t work, int per_block, int cap) {
     if (b < 1) b = 1;
     if (b > cap) b = cap;
     return (int)b;
+}
+
+// Order key of every vertex as a source: graph index, then hop distance from
+// the graph's vertex of largest degree, then decreasing degree.  Sources
+// equally far from the hub see most vertices at the same depth, so a batch
+// of them shares frontier entries (fewer level-queue entries, neighbour rows
+// read for more lanes at once).
+static void source_keys(int32_t n_graphs, const std::vector<int32_t> &voff, const std::vector<int32_t> &rp,
+                        const std::vector<int32_t> &col, std::vector<uint64_t> *key) {
+    const int32_t n = (int32_t)rp.size() - 1;
+    std::vector<int32_t> dist((size_t)n, -1), q;
+    q.reserve((size_t)n);
+    key->assign((size_t)n, 0);
+    for (int gi = 0; gi < n_graphs; ++gi) {
+        const int32_t lo = voff[gi], hi = voff[gi + 1];
+        if (lo == hi) continue;
+        int32_t hub = lo;
+        for (int32_t v = lo; v < hi; ++v)
+            if (rp[v + 1] - rp[v] > rp[hub + 1] - rp[hub]) hub = v;
+        q.clear();
+        q.push_back(hub);
+        dist[hub] = 0;
+        for (size_t h = 0; h < q.size(); ++h) {
+            const int32_t v = q[h];
+            for (int32_t e = rp[v]; e < rp[v + 1]; ++e)
+                if (dist[col[e]] < 0) {
+                    dist[col[e]] = dist[v] + 1;
+                    q.push_back(col[e]);
+                }
+        }
+        for (int32_t v = lo; v < hi; ++v) {
+            const uint64_t d = dist[v] < 0 ? 0xFFFFFu : (uint64_t)std::min(dist[v], 0xFFFFE);
+            const uint64_t deg = (uint64_t)std::min(rp[v + 1] - rp[v], 0xFFFFF);
+            (*key)[v] = ((uint64_t)gi << 40) | (d << 20) | (0xFFFFFu - deg);
+        }
+    }
 }
 
 static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n, int64_t nnz,
@@ -413,6 +452,7 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
                 CR_TRY(dalloc(&g->inv_dev, (size_t)n, &g->bytes));
                 CR_TRY(hipMemcpy(g->inv_dev, g->inv.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
                 CR_TRY(dalloc(&g->bc_out, (size_t)n, &g->bytes));
+                source_keys(n_graphs, voff, rp, ncol, &g->skey);
             }
         }
         // vertices heavier than one segment, for the split load balancing
@@ -1528,10 +1568,14 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
     return BC_OK;
 }
 
-// Caller ids -> internal ids (hub-first renumbering).  A NULL list means
-// every vertex in the caller's order.  Ids are checked by the run itself.
+// Caller ids -> internal ids (hub-first renumbering), and the sources in
+// the order the run takes them (by source_keys; stable, so equal keys keep
+// the caller's order).  A NULL list means every vertex.  *pos_of (if given)
+// receives, for each run position, the caller's position.  Out-of-range ids
+// are passed through unchanged (and rejected by the run).
 static const int32_t *to_internal(const bc_graph *g, const int32_t *sources, int64_t *n_sources,
-                                  std::vector<int32_t> *buf) {
+                                  std::vector<int32_t> *buf, std::vector<int64_t> *pos_of = nullptr) {
+    if (pos_of) pos_of->clear();
     if (!g || g->perm.empty()) return sources;
     if (!sources) {
         *n_sources = g->n;
@@ -1541,8 +1585,21 @@ static const int32_t *to_internal(const bc_graph *g, const int32_t *sources, int
         buf->resize((size_t)*n_sources);
         for (int64_t i = 0; i < *n_sources; ++i) {
             const int32_t v = sources[i];
-            (*buf)[i] = (v >= 0 && v < g->n) ? g->inv[v] : v;  // out-of-range ids stay out of range
+            if (v < 0 || v >= g->n) return sources;
+            (*buf)[i] = g->inv[v];
         }
+    }
+    if (!g->skey.empty()) {
+        const int64_t ns = *n_sources;
+        std::vector<int64_t> order((size_t)ns);
+        for (int64_t i = 0; i < ns; ++i) order[i] = i;
+        const std::vector<int32_t> &b = *buf;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int64_t x, int64_t y) { return g->skey[b[x]] < g->skey[b[y]]; });
+        std::vector<int32_t> sorted((size_t)ns);
+        for (int64_t i = 0; i < ns; ++i) sorted[i] = b[order[i]];
+        buf->swap(sorted);
+        if (pos_of) pos_of->swap(order);
     }
     return buf->data();
 }
@@ -1558,7 +1615,15 @@ extern "C" bc_status bc_run_detail(bc_graph *g, const int32_t *sources, int64_t 
                                    const bc_run_options *opt, int64_t dump_index, bc_detail *out, void *stream) {
     if (!out) return fail(BC_ERR_INVALID_ARG, "out is NULL");
     std::vector<int32_t> buf;
-    const int32_t *src = to_internal(g, sources, &n_sources, &buf);
+    std::vector<int64_t> pos_of;
+    const int32_t *src = to_internal(g, sources, &n_sources, &buf, &pos_of);
+    if (!pos_of.empty() && dump_index >= 0 && dump_index < n_sources) {
+        for (int64_t i = 0; i < n_sources; ++i)
+            if (pos_of[i] == dump_index) {
+                dump_index = i;
+                break;
+            }
+    }
     bc_status s = run_impl(g, src, n_sources, opt, stream, dump_index, out);
     if (s != BC_OK || !g || g->perm.empty()) return s;
     // per-vertex outputs back to the caller's ids
