@@ -76,9 +76,9 @@ const char *bc_last_error(void);
  * order) unless BC_KEEP_ORDER is given, so that the frontier words and
  * rows of the most-read vertices share cache lines.  Such a handle also
  * takes the sources of a run in its own order: by graph, then by hop
- * distance from the graph's vertex of largest degree, then by decreasing
- * degree (stable), so that the sources of one batch reach most vertices at
- * the same depth.  Every call of this interface takes and returns the
+ * distance from the graph's vertex of largest degree, then by parent in
+ * that vertex's BFS tree, then by decreasing degree (stable), so that the
+ * sources of one batch reach most vertices at the same depth.  Every call of this interface takes and returns the
  * caller's vertex ids and source positions; only the order in which
  * floating-point terms of a sum are added can differ.
  * Errors: BC_ERR_INVALID_ARG (NULL pointers, negative sizes),

@@ -191,9 +191,9 @@ struct bc_graph {
     std::vector<int32_t> perm, inv;
     int32_t *inv_dev = nullptr;
     double *bc_out = nullptr;  // scores gathered back to the caller's order
-    // source order key per internal vertex (empty = keep the caller's order):
-    // graph index, distance from the graph's top hub, decreasing degree
-    std::vector<uint64_t> skey;
+    // rank of each internal vertex as a source (empty = keep the caller's
+    // order; see source_ranks)
+    std::vector<int32_t> srank;
     // autotuner result (bc_autotune), used by bc_run with BC_RUN_TUNED
     bool has_tuned = false;
     bc_run_options tuned{};
@@ -269,40 +269,65 @@ static int grid_for(int64_t work, int per_block, int cap) {
     return (int)b;
 }
 
-// Order key of every vertex as a source: graph index, then hop distance from
-// the graph's vertex of largest degree, then decreasing degree.  Sources
-// equally far from the hub see most vertices at the same depth, so a batch
-// of them shares frontier entries (fewer level-queue entries, neighbour rows
-// read for more lanes at once).
-static void source_keys(int32_t n_graphs, const std::vector<int32_t> &voff, const std::vector<int32_t> &rp,
-                        const std::vector<int32_t> &col, std::vector<uint64_t> *key) {
+// Rank of every vertex as a source.  Within each graph, sources are taken
+// by hop distance from the graph's vertex of largest degree (the hub), then
+// by their parent in the hub's BFS tree (the neighbour one hop closer, of
+// largest degree; parents of larger degree first), then by decreasing
+// degree.  Sources equally far from the hub that hang off the same parent
+// reach most vertices at the same depth, so a batch of them shares frontier
+// entries: fewer level-queue entries, and neighbour rows read for more lanes
+// at once.
+static void source_ranks(int32_t n_graphs, const std::vector<int32_t> &voff, const std::vector<int32_t> &rp,
+                         const std::vector<int32_t> &col, std::vector<int32_t> *rank) {
     const int32_t n = (int32_t)rp.size() - 1;
-    std::vector<int32_t> dist((size_t)n, -1), q;
+    const int32_t kFar = INT32_MAX;
+    std::vector<int32_t> dist((size_t)n, kFar), par((size_t)n, -1), q;
     q.reserve((size_t)n);
-    key->assign((size_t)n, 0);
+    auto deg = [&](int32_t v) { return v < 0 ? INT32_MAX : rp[v + 1] - rp[v]; };
     for (int gi = 0; gi < n_graphs; ++gi) {
         const int32_t lo = voff[gi], hi = voff[gi + 1];
         if (lo == hi) continue;
         int32_t hub = lo;
         for (int32_t v = lo; v < hi; ++v)
-            if (rp[v + 1] - rp[v] > rp[hub + 1] - rp[hub]) hub = v;
+            if (deg(v) > deg(hub)) hub = v;
         q.clear();
         q.push_back(hub);
         dist[hub] = 0;
         for (size_t h = 0; h < q.size(); ++h) {
             const int32_t v = q[h];
             for (int32_t e = rp[v]; e < rp[v + 1]; ++e)
-                if (dist[col[e]] < 0) {
+                if (dist[col[e]] == kFar) {
                     dist[col[e]] = dist[v] + 1;
                     q.push_back(col[e]);
                 }
         }
-        for (int32_t v = lo; v < hi; ++v) {
-            const uint64_t d = dist[v] < 0 ? 0xFFFFFu : (uint64_t)std::min(dist[v], 0xFFFFE);
-            const uint64_t deg = (uint64_t)std::min(rp[v + 1] - rp[v], 0xFFFFF);
-            (*key)[v] = ((uint64_t)gi << 40) | (d << 20) | (0xFFFFFu - deg);
+        for (int32_t v : q) {
+            if (v == hub) continue;
+            int32_t p = -1;
+            for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+                const int32_t u = col[e];
+                if (dist[u] == dist[v] - 1 && (p < 0 || deg(u) > deg(p))) p = u;
+            }
+            par[v] = p;
         }
     }
+    std::vector<int32_t> order((size_t)n), gidx((size_t)n);
+    for (int gi = 0; gi < n_graphs; ++gi)
+        for (int32_t v = voff[gi]; v < voff[gi + 1]; ++v) gidx[v] = gi;
+    for (int32_t v = 0; v < n; ++v) order[v] = v;
+    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        if (gidx[a] != gidx[b]) return gidx[a] < gidx[b];
+        if (dist[a] != dist[b]) return dist[a] < dist[b];
+        const int32_t pa = par[a], pb = par[b];
+        if (pa != pb) {
+            if (deg(pa) != deg(pb)) return deg(pa) > deg(pb);
+            return pa < pb;
+        }
+        if (deg(a) != deg(b)) return deg(a) > deg(b);
+        return a < b;
+    });
+    rank->assign((size_t)n, 0);
+    for (int32_t i = 0; i < n; ++i) (*rank)[order[i]] = i;
 }
 
 static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n, int64_t nnz,
@@ -452,7 +477,7 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
                 CR_TRY(dalloc(&g->inv_dev, (size_t)n, &g->bytes));
                 CR_TRY(hipMemcpy(g->inv_dev, g->inv.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
                 CR_TRY(dalloc(&g->bc_out, (size_t)n, &g->bytes));
-                source_keys(n_graphs, voff, rp, ncol, &g->skey);
+                source_ranks(n_graphs, voff, rp, ncol, &g->srank);
             }
         }
         // vertices heavier than one segment, for the split load balancing
@@ -1569,7 +1594,7 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
 }
 
 // Caller ids -> internal ids (hub-first renumbering), and the sources in
-// the order the run takes them (by source_keys; stable, so equal keys keep
+// the order the run takes them (by source_ranks; stable, so duplicates keep
 // the caller's order).  A NULL list means every vertex.  *pos_of (if given)
 // receives, for each run position, the caller's position.  Out-of-range ids
 // are passed through unchanged (and rejected by the run).
@@ -1589,13 +1614,13 @@ static const int32_t *to_internal(const bc_graph *g, const int32_t *sources, int
             (*buf)[i] = g->inv[v];
         }
     }
-    if (!g->skey.empty()) {
+    if (!g->srank.empty()) {
         const int64_t ns = *n_sources;
         std::vector<int64_t> order((size_t)ns);
         for (int64_t i = 0; i < ns; ++i) order[i] = i;
         const std::vector<int32_t> &b = *buf;
         std::stable_sort(order.begin(), order.end(),
-                         [&](int64_t x, int64_t y) { return g->skey[b[x]] < g->skey[b[y]]; });
+                         [&](int64_t x, int64_t y) { return g->srank[b[x]] < g->srank[b[y]]; });
         std::vector<int32_t> sorted((size_t)ns);
         for (int64_t i = 0; i < ns; ++i) sorted[i] = b[order[i]];
         buf->swap(sorted);
