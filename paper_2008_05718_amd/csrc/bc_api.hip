@@ -430,7 +430,7 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
             // least twice the graph's mean (over vertices with arcs) first, by
             // decreasing degree, the rest in their order
             std::vector<int32_t> order((size_t)n);
-            bool moved = false;
+            bool moved = false, any_hubs = false;
             for (int gi = 0; gi < n_graphs; ++gi) {
                 const int32_t lo = voff[gi], hi = voff[gi + 1];
                 int64_t arcs = 0, with = 0;
@@ -444,6 +444,7 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
                 for (int32_t v = lo; v < hi; ++v) ((double)(rp[v + 1] - rp[v]) >= thr ? hubs : rest).push_back(v);
                 std::stable_sort(hubs.begin(), hubs.end(),
                                  [&](int32_t a, int32_t b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
+                any_hubs = any_hubs || !hubs.empty();
                 int32_t k = lo;
                 for (int32_t v : hubs) order[k++] = v;
                 for (int32_t v : rest) order[k++] = v;
@@ -478,6 +479,10 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
                 CR_TRY(hipMemcpy(g->inv_dev, g->inv.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
                 CR_TRY(dalloc(&g->bc_out, (size_t)n, &g->bytes));
                 source_ranks(n_graphs, voff, rp, ncol, &g->srank);
+            } else if (any_hubs) {  // hubs already first: keep the numbering, still order the sources
+                std::vector<int32_t> col((size_t)nnz);
+                CR_TRY(hipMemcpy(col.data(), g->col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToHost));
+                source_ranks(n_graphs, voff, rp, col, &g->srank);
             }
         }
         // vertices heavier than one segment, for the split load balancing
@@ -1601,17 +1606,19 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
 static const int32_t *to_internal(const bc_graph *g, const int32_t *sources, int64_t *n_sources,
                                   std::vector<int32_t> *buf, std::vector<int64_t> *pos_of = nullptr) {
     if (pos_of) pos_of->clear();
-    if (!g || g->perm.empty()) return sources;
+    if (!g || (g->perm.empty() && g->srank.empty())) return sources;
+    const bool map = !g->perm.empty();
     if (!sources) {
         *n_sources = g->n;
-        buf->assign(g->inv.begin(), g->inv.end());
+        buf->resize((size_t)g->n);
+        for (int32_t v = 0; v < g->n; ++v) (*buf)[v] = map ? g->inv[v] : v;
     } else {
         if (*n_sources < 0) return sources;
         buf->resize((size_t)*n_sources);
         for (int64_t i = 0; i < *n_sources; ++i) {
             const int32_t v = sources[i];
             if (v < 0 || v >= g->n) return sources;
-            (*buf)[i] = g->inv[v];
+            (*buf)[i] = map ? g->inv[v] : v;
         }
     }
     if (!g->srank.empty()) {
