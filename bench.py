@@ -30,6 +30,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TUNE_SOURCES = 512  # autotuner sample: the first sources of the list (untimed)
 KERNEL_SOURCES = ["paper_2008_05718_amd/csrc/bc_batched.hip", "paper_2008_05718_amd/csrc/bc_common.h",
                   "paper_2008_05718_amd/csrc/bc_api.hip",
                   "paper_2008_05718_amd/csrc/bc_dev.h", "paper_2008_05718_amd/build.py"]
@@ -83,7 +84,7 @@ def main():
     ap.add_argument("--sources", type=int, default=0, help="use only the first N sources (profiling runs)")
     ap.add_argument("--no-graphs", action="store_true", help="launch level steps one by one")
     ap.add_argument("--grid", type=int, default=0, help="workgroups per step launch (0 = library default)")
-    ap.add_argument("--no-tune", action="store_true", help="skip bc_autotune (default: tune on the first 256 sources)")
+    ap.add_argument("--no-tune", action="store_true", help="skip bc_autotune (default: tune on the first 512 sources)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes 3 times (counter calibration)")
     args = ap.parse_args()
@@ -153,9 +154,9 @@ def main():
     tuned = None
     if not args.no_tune:
         t = time.time()
-        tuned = G.autotune(srcs[:256], batch=64, policy=pol, grid_blocks=args.grid, flags=gflags)
+        tuned = G.autotune(srcs[:TUNE_SOURCES], batch=64, policy=pol, grid_blocks=args.grid, flags=gflags)
         gflags |= b.BC_RUN_TUNED
-        log(f"[bench] autotuned on {min(256, len(srcs))} sources in {time.time() - t:.1f}s: {tuned}")
+        log(f"[bench] autotuned on {min(TUNE_SOURCES, len(srcs))} sources in {time.time() - t:.1f}s: {tuned}")
     wall, gpu_ms, stats = timed(srcs, args.steps, args.warmup, batch=64, policy=pol, flags=gflags,
                                 grid_blocks=args.grid)
     st = stats[-1]

@@ -174,11 +174,15 @@ bc_status bc_run(bc_graph *g, const int32_t *sources, int64_t n_sources,
  * {64, 32, 16}, policy {heuristic, learned when weights are loaded},
  * workgroups per step {default, 1/2, 1/4}, level steps per captured chunk
  * {8, 16, 32}, push WPV degree threshold {12, 24, 48}.  Each candidate is
- * timed (host clock around a synchronised run) after one untimed run that
- * builds its captured graphs; the fastest value of each dimension is kept.
- * The result goes to *best (non-NULL) and stays in the handle for bc_run with
- * BC_RUN_TUNED (which fills the fields a caller leaves automatic).  Every candidate gives the same scores bit for bit, so the
- * tuner changes speed only.  Scores are reset afterwards.
+ * timed (host clock around a synchronised run, best of two) after one
+ * untimed run that builds its captured graphs; a value replaces the current
+ * one only when it is at least 2 % faster.  The result goes to *best
+ * (non-NULL) and stays in the handle for bc_run with BC_RUN_TUNED (which
+ * fills the fields a caller leaves automatic).  Candidates with the same K
+ * give the same scores bit for bit; another K may group the additions of
+ * concurrent replicas differently (agreement to rounding; see
+ * BC_RUN_ONE_QUEUE), so the tuner changes speed only.  Scores are reset
+ * afterwards.
  * Errors: BC_ERR_INVALID_ARG for NULL g / best or an empty or invalid sample.
  */
 bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_sample, const bc_run_options *base,

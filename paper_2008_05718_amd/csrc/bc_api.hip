@@ -1811,15 +1811,20 @@ extern "C" bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_s
     if (cur.chunk_steps == 0) cur.chunk_steps = c0.chunk;
     if (cur.wpv_degree <= 0.0f) cur.wpv_degree = 24.0f;
     hipStream_t st = (hipStream_t)stream;
+    // a warm-up run (builds the captured graphs), then the best of two timed runs
     auto time_one = [&](const bc_run_options &o, double *ms) -> bc_status {
-        bc_status r = run_impl(g, sample, n_sample, &o, st, -1, nullptr);  // builds captured graphs
+        bc_status r = run_impl(g, sample, n_sample, &o, st, -1, nullptr);
         if (r != BC_OK) return r;
-        const auto t0 = std::chrono::steady_clock::now();
-        r = run_impl(g, sample, n_sample, &o, st, -1, nullptr);
-        if (r != BC_OK) return r;
-        *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        *ms = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+            const auto t0 = std::chrono::steady_clock::now();
+            r = run_impl(g, sample, n_sample, &o, st, -1, nullptr);
+            if (r != BC_OK) return r;
+            *ms = std::min(*ms, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+        }
         return BC_OK;
     };
+    const double kGain = 0.98;  // a candidate must be 2 % faster to replace the current choice
     double best_ms = 0.0;
     s = time_one(cur, &best_ms);
     if (s != BC_OK) return s;
@@ -1845,7 +1850,7 @@ extern "C" bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_s
             double ms = 0.0;
             s = time_one(x, &ms);
             if (s != BC_OK) return s;
-            if (ms < best_ms) {
+            if (ms < kGain * best_ms) {
                 best_ms = ms;
                 cur = x;
             }
