@@ -1112,13 +1112,17 @@ static void free_parts(bc_graph *g) {
     g->parts.clear();
 }
 
-static int n_replicas() {
-    static const int nr = [] {
+// Replicas of a single graph: 8 while one batch's steps are small (up to
+// 2^19 vertices), 4 above, where fewer, larger state machines measured
+// faster (R-MAT 18: 8 replicas +3 % over 4; R-MAT 22: -3 %).  BC_REPLICAS
+// overrides (1 .. 8).
+static int n_replicas(const bc_graph *g) {
+    static const int env = [] {
         const char *e = std::getenv("BC_REPLICAS");
-        const int v = e ? std::atoi(e) : 4;
-        return std::min(8, std::max(1, v));
+        return e ? std::min(8, std::max(1, std::atoi(e))) : 0;
     }();
-    return nr;
+    if (env) return env;
+    return g->n <= (1 << 19) ? 8 : 4;
 }
 
 static bool use_parts(const bc_graph *g, const bc_run_options &o, int64_t ns) {
@@ -1126,7 +1130,7 @@ static bool use_parts(const bc_graph *g, const bc_run_options &o, int64_t ns) {
     if (o.batch == 0 && ns < 2) return false;  // the per-source engine would be chosen
     if (g->n_graphs >= 4) return true;
     const int K = o.batch >= 8 ? o.batch : 64;
-    return n_replicas() >= 2 && ns >= 2 * (int64_t)K;
+    return n_replicas(g) >= 2 && ns >= 2 * (int64_t)K;
 }
 
 // Single graph: parts are full copies of the graph (own per-vertex state);
@@ -1135,7 +1139,7 @@ static bool use_parts(const bc_graph *g, const bc_run_options &o, int64_t ns) {
 // additions are grouped differently from one state machine.
 static bc_status ensure_replicas(bc_graph *g) {
     if (!g->parts.empty()) return BC_OK;
-    const int R = n_replicas();
+    const int R = n_replicas(g);
     int cus = 0, dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
