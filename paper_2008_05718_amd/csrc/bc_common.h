@@ -236,7 +236,7 @@ __device__ __forceinline__ int n_segments(int deg) { return (deg + kSeg - 1) / k
 // Write the n staged entries of this wavefront to the level queue (absolute
 // positions qbase + counter), heavy ones also to the level's heavy list.
 #ifndef BC_BUDGET
-#define BC_BUDGET 32
+#define BC_BUDGET 64
 #endif
 constexpr int kBudget = BC_BUDGET;  // cost units (8 arcs each) per work group
 static_assert(kBudget >= 2 && kBudget <= 128, "a group must fit in one wavefront (every entry costs >= 2 units)");

@@ -13,7 +13,7 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kLanes = 64;   // sources per batch = wavefront lanes
 constexpr int kLightDeg = 32;  // thread-per-vertex loops handle up to this many arcs
 #ifndef BC_SEG
-#define BC_SEG 512
+#define BC_SEG 1024
 #endif
 constexpr int kSeg = BC_SEG;   // heavy vertices (degree > kSeg) are split into kSeg-arc segments
 constexpr int kPhases = 10;

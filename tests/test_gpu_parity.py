@@ -164,6 +164,33 @@ def test_hub_first_relabelling_keeps_caller_ids(engine):
     assert_bc_close(all_src, ref_all)
 
 
+def test_ranked_sources_make_list_order_irrelevant():
+    # a handle with hubs takes the sources in its own rank order, so any
+    # permutation of the same list gives the same bits; a caller-order handle
+    # (BC_KEEP_ORDER) agrees to rounding
+    g = W.rmat(12, 16, seed=43)
+    srcs = W.choose_sources(g, 300, seed=9)
+    rng = np.random.default_rng(4)
+    say(f"[ranked] rmat12 sources={len(srcs)}")
+    ref, _ = oracle.bc(g, srcs)
+    with b.Graph(g) as G, b.Graph(g, flags=b.BC_KEEP_ORDER) as H:
+        G.run(srcs, batch=64, flags=b.BC_RUN_ONE_QUEUE)
+        first = G.scores().copy()
+        for _ in range(2):
+            G.run(rng.permutation(srcs), batch=64, flags=b.BC_RUN_ONE_QUEUE)
+            assert np.array_equal(G.scores().view(np.uint64), first.view(np.uint64))
+        G.run(rng.permutation(srcs), batch=64)  # concurrent replicas: same K, same bits
+        again = G.scores().copy()
+        G.run(rng.permutation(srcs), batch=64)
+        assert np.array_equal(G.scores().view(np.uint64), again.view(np.uint64))
+        H.run(srcs, batch=64)
+        kept = H.scores()
+        det = G.detail(srcs, dump_index=123, batch=64)  # position in the caller's list
+        check_detail(g, det, srcs[123])
+    assert_bc_close(first, ref)
+    assert np.max(np.abs(first - kept) / np.maximum(np.abs(kept), 1e-300)) <= 1e-13
+
+
 @pytest.mark.parametrize("engine", ENGINES)
 def test_source_transitions_repeatable(engine):
     # every source (plain) or batch (batched) ends with a launch whose last
@@ -227,7 +254,7 @@ def test_sigma_limit_and_forced_f64(engine):
 
 @pytest.mark.parametrize("engine", ENGINES)
 def test_heavy_vertices_segments(engine):
-    # RMAT scale 14: dozens of vertices above one 512-arc segment (max degree 3665);
+    # RMAT scale 14: vertices above one 1024-arc segment (max degree 3665);
     # every policy must split them the same way and give identical bits
     g = W.rmat(14, 16, seed=1)
     deg = g.degrees()
