@@ -142,10 +142,14 @@ struct bc_graph {
     std::vector<int32_t> vgraph;   // not kept (large); block lookups use voff
     int32_t *row_ptr = nullptr, *col = nullptr;
     int64_t nonisolated = 0;
-    // vertices of degree > kSeg (ascending) and their segment prefix sums
+    // vertices of degree > kSegBatched (ascending) and their segment prefix
+    // sums; p_*: the same for the plain engine's kSegPlain
     int32_t *hv_vtx = nullptr, *hv_seg = nullptr;
     int32_t n_heavy = 0;
     int64_t heavy_segs = 0;
+    int32_t *p_hv_vtx = nullptr, *p_hv_seg = nullptr;
+    int32_t p_n_heavy = 0;
+    int64_t p_heavy_segs = 0;
     int64_t cost_units = 0;         // sum of entry_cost over all vertices
     double clock_khz = 100000.0;
     int grid_plain = 1024, grid_batch = 1024;  // resident workgroups of the step kernels
@@ -235,7 +239,7 @@ extern "C" void bc_destroy(bc_graph *g) {
                    g->p_sig, g->p_chat, g->b_vn, g->b_fw0, g->b_fw1, g->b_lq_vtx, g->b_lq_mask,
                    g->b_level_off, g->b_delta, g->b_chat, g->b_shift, g->b_maxexp, g->b_lane_src,
                    g->b_sigma, g->b_gstart, g->b_gbase, g->inv_dev, g->bc_out,
-                   g->srcs, g->ovf, g->bstart, g->blo, g->bhi, g->mlp, g->hv_vtx, g->hv_seg,
+                   g->srcs, g->ovf, g->bstart, g->blo, g->bhi, g->mlp, g->hv_vtx, g->hv_seg, g->p_hv_vtx, g->p_hv_seg,
                    g->p_hq.pos, g->p_hq.seg, g->p_hq.cnt, g->p_hq.off, g->p_hq.nseg, g->p_hq.part_lo,
                    g->p_hq.part_hi, g->b_hq.pos, g->b_hq.seg, g->b_hq.cnt, g->b_hq.off, g->b_hq.nseg,
                    g->b_hq.part_lo, g->b_hq.part_hi};
@@ -486,25 +490,30 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
             }
         }
         // vertices heavier than one segment, for the split load balancing
-        std::vector<int32_t> hv, hs(1, 0);
-        int64_t segs = 0;
+        // (one list per engine segment size)
         int64_t cost_units = 0;
-        for (int32_t v = 0; v < n; ++v) {
-            const int32_t deg = rp[v + 1] - rp[v];
-            cost_units += entry_cost(deg);
-            if (deg > kSeg) {
-                hv.push_back(v);
-                segs += (deg + kSeg - 1) / kSeg;
-                hs.push_back((int32_t)segs);
-            }
-        }
-        g->n_heavy = (int32_t)hv.size();
-        g->heavy_segs = segs;
+        for (int32_t v = 0; v < n; ++v) cost_units += entry_cost(rp[v + 1] - rp[v]);
         g->cost_units = cost_units;
-        CR_TRY(dalloc(&g->hv_vtx, hv.size(), &g->bytes));
-        CR_TRY(dalloc(&g->hv_seg, hs.size(), &g->bytes));
-        if (!hv.empty()) CR_TRY(hipMemcpy(g->hv_vtx, hv.data(), sizeof(int32_t) * hv.size(), hipMemcpyHostToDevice));
-        CR_TRY(hipMemcpy(g->hv_seg, hs.data(), sizeof(int32_t) * hs.size(), hipMemcpyHostToDevice));
+        for (int which = 0; which < 2; ++which) {
+            const int seg = which == 0 ? kSegBatched : kSegPlain;
+            std::vector<int32_t> hv, hs(1, 0);
+            int64_t segs = 0;
+            for (int32_t v = 0; v < n; ++v) {
+                const int32_t deg = rp[v + 1] - rp[v];
+                if (deg > seg) {
+                    hv.push_back(v);
+                    segs += (deg + seg - 1) / seg;
+                    hs.push_back((int32_t)segs);
+                }
+            }
+            int32_t **pv = which == 0 ? &g->hv_vtx : &g->p_hv_vtx, **ps = which == 0 ? &g->hv_seg : &g->p_hv_seg;
+            (which == 0 ? g->n_heavy : g->p_n_heavy) = (int32_t)hv.size();
+            (which == 0 ? g->heavy_segs : g->p_heavy_segs) = segs;
+            CR_TRY(dalloc(pv, hv.size(), &g->bytes));
+            CR_TRY(dalloc(ps, hs.size(), &g->bytes));
+            if (!hv.empty()) CR_TRY(hipMemcpy(*pv, hv.data(), sizeof(int32_t) * hv.size(), hipMemcpyHostToDevice));
+            CR_TRY(hipMemcpy(*ps, hs.data(), sizeof(int32_t) * hs.size(), hipMemcpyHostToDevice));
+        }
         int dev = 0, khz = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
@@ -560,13 +569,13 @@ extern "C" void bc_run_options_init(bc_run_options *opt) {
 }
 
 // ------------------------------------------------------------ engine setup
-static bc_status alloc_hq(bc_graph *g, HeavyQ *q, int64_t entries, int64_t levels, int lanes) {
+static bc_status alloc_hq(bc_graph *g, HeavyQ *q, int64_t entries, int64_t levels, int lanes, int64_t heavy_segs) {
     HIP_TRY(dalloc(&q->pos, (size_t)entries, &g->bytes));
     HIP_TRY(dalloc(&q->seg, (size_t)entries, &g->bytes));
     HIP_TRY(dalloc(&q->cnt, (size_t)entries, &g->bytes));
     HIP_TRY(dalloc(&q->off, (size_t)levels, &g->bytes));
     HIP_TRY(dalloc(&q->nseg, (size_t)levels, &g->bytes));
-    const int64_t segs = g->heavy_segs + 1;
+    const int64_t segs = heavy_segs + 1;
     HIP_TRY(dalloc(&q->part_lo, (size_t)segs * lanes, &g->bytes));
     HIP_TRY(dalloc(&q->part_hi, (size_t)segs * lanes, &g->bytes));
     q->cap = (uint32_t)std::min<int64_t>(entries, UINT32_MAX);
@@ -578,7 +587,7 @@ static bc_status ensure_plain(bc_graph *g, hipStream_t st) {
     const int64_t n = g->n;
     if (!g->plain_ready) {
         // each heavy vertex enters a source's level queues once
-        bc_status s = alloc_hq(g, &g->p_hq, (int64_t)g->n_heavy + 1, n + 3, 1);
+        bc_status s = alloc_hq(g, &g->p_hq, (int64_t)g->p_n_heavy + 1, n + 3, 1, g->p_heavy_segs);
         if (s != BC_OK) return s;
         HIP_TRY(dalloc(&g->p_d, (size_t)n, &g->bytes));
         HIP_TRY(dalloc(&g->p_queue, (size_t)n, &g->bytes));
@@ -631,7 +640,8 @@ static bc_status ensure_batched(bc_graph *g) {
     HIP_TRY(dalloc(&g->b_maxexp, (size_t)2 * kSlots * kLanes, &g->bytes));
     HIP_TRY(dalloc(&g->b_lane_src, (size_t)kLanes, &g->bytes));
     // a heavy vertex sits on at most 64 distinct levels of a batch (one per lane)
-    bc_status s = alloc_hq(g, &g->b_hq, (int64_t)g->n_heavy * kLanes + kLanes, (int64_t)g->b_max_levels + 3, kLanes);
+    bc_status s = alloc_hq(g, &g->b_hq, (int64_t)g->n_heavy * kLanes + kLanes, (int64_t)g->b_max_levels + 3, kLanes,
+                           g->heavy_segs);
     if (s != BC_OK) return s;
     g->batch_ready = true;
     return BC_OK;
@@ -872,6 +882,9 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
     int64_t launches = 0;
     double dev_ms = 0.0;
     if (cfg.engine == 1) {
+        ga.hv_vtx = g->p_hv_vtx;
+        ga.hv_seg = g->p_hv_seg;
+        ga.n_heavy = g->p_n_heavy;
         s = ensure_plain(g, st);
         if (s != BC_OK) return s;
         hc->phase = PH_FIN;

@@ -245,7 +245,7 @@ static_assert(kBudget >= 2 && kBudget <= 128, "a group must fit in one wavefront
 // fixed part; heavy entries (split into segments elsewhere) count 2.  Every
 // entry costs at least 2 units, so a group never holds more than
 // kBudget / 2 entries.
-__host__ __device__ __forceinline__ unsigned entry_cost(int deg) {
+static __host__ __device__ __forceinline__ unsigned entry_cost(int deg) {
     return deg > kSeg ? 2u : 1u + (unsigned)(deg + 7) / 8u;
 }
 

@@ -15,7 +15,18 @@ constexpr int kLightDeg = 32;  // thread-per-vertex loops handle up to this many
 #ifndef BC_SEG
 #define BC_SEG 1024
 #endif
-constexpr int kSeg = BC_SEG;   // heavy vertices (degree > kSeg) are split into kSeg-arc segments
+#ifndef BC_SEG_PLAIN
+#define BC_SEG_PLAIN 512
+#endif
+// heavy vertices (degree > kSeg) are split into kSeg-arc segments; each
+// engine has its own size (the plain engine is compiled with BC_PLAIN_TU)
+constexpr int kSegBatched = BC_SEG;
+constexpr int kSegPlain = BC_SEG_PLAIN;
+#ifdef BC_PLAIN_TU
+constexpr int kSeg = kSegPlain;
+#else
+constexpr int kSeg = kSegBatched;
+#endif
 constexpr int kPhases = 10;
 constexpr int kSlots = 32;     // per-step counters and arrivals are spread over this many slots
 

@@ -23,6 +23,7 @@
 // wavefront (<= kSeg) or kSeg-arc segments combined in segment order by the
 // last segment to finish; no floating-point atomics, so results are bitwise
 // reproducible.
+#define BC_PLAIN_TU 1  // this engine's segment size: kSegPlain
 #include "bc_common.h"
 
 namespace bcx {
