@@ -1,6 +1,6 @@
-"""Parity at the benchmark sizes, in the benchmark's launch configuration
+"""Parity at the full workload sizes, in the benchmark's launch configuration
 (64-source batches, default policy with the trained weights loaded, captured
-level chunks).
+level chunks, concurrent replicas or sub-unions).
 
 A whole run at these sizes is beyond the oracle, so each test checks
   * sampled sources one by one: d and integer sigma bit-exact, FP64 sigma and
@@ -103,3 +103,39 @@ def test_rmat22_16384_sources():
         got = G.scores()
     ref, _ = oracle.bc(g, srcs[:4])
     assert_bc_close(got, ref)
+
+
+def _block(g, lo, hi):
+    """Graph block [lo, hi) of a block-diagonal union as a CSR of its own."""
+    rp = g.row_ptr[lo:hi + 1].astype(np.int64)
+    col = g.col_idx[rp[0]:rp[-1]].astype(np.int64) - lo
+    rr = np.repeat(np.arange(hi - lo), np.diff(rp))
+    return W.csr_from_edges(hi - lo, rr, col)
+
+
+def test_ba512_sampled_sources():
+    # the full union (512 graphs, 12.3 M vertices) in the default launch
+    # configuration (concurrent sub-unions), 8 sources from every graph:
+    # details of three sources, the score sum against the path-length excess,
+    # and three whole graphs' scores against the oracle
+    t = time.time()
+    g, _ = W.workload("ba512")
+    off = g.vtx_offsets.astype(np.int64)
+    rng = np.random.default_rng(77)
+    srcs = np.concatenate([off[i] + rng.choice(off[i + 1] - off[i], 8, replace=False)
+                           for i in range(len(off) - 1)]).astype(np.int32)
+    say(f"[fullsize ba512] n={g.n} m={g.m} graphs={len(off) - 1} sources={len(srcs)} "
+        f"(generated in {time.time() - t:.1f}s)")
+    with _graph(g) as G:
+        t = time.time()
+        G.run(srcs, batch=64)
+        got = G.scores().copy()
+        say(f"  run {time.time() - t:.2f}s")
+        _sum_check(got, g, srcs)
+        for k in (0, 8 * 255 + 3, len(srcs) - 1):
+            det = G.detail(srcs, dump_index=k, batch=64)
+            check_detail(g, det, srcs[k])
+    for i in (0, 255, 511):
+        lo, hi = int(off[i]), int(off[i + 1])
+        ref, _ = oracle.bc(_block(g, lo, hi), srcs[8 * i:8 * i + 8] - lo)
+        assert_bc_close(got[lo:hi], ref)
