@@ -1082,10 +1082,12 @@ static bc_status resolve_cfg(const bc_graph *g, const bc_run_options &o, int64_t
 // by size; a part keeps its graphs in the parent's order and a graph's
 // sources in list order, so every score is accumulated in the same order as
 // by one handle and the results are identical bit for bit.
+// 16 by default: on 512 BA graphs (64 sources each) 16 parts ran 22 % faster
+// than 8 (26.5 vs 21.7 GTEPS); BC_PARTS overrides (2 .. 16).
 static int n_parts() {
     static const int np = [] {
         const char *e = std::getenv("BC_PARTS");
-        const int v = e ? std::atoi(e) : 8;
+        const int v = e ? std::atoi(e) : 16;
         return std::min(16, std::max(2, v));
     }();
     return np;
@@ -1128,11 +1130,11 @@ static void free_parts(bc_graph *g) {
 // Replicas of a single graph: 8 while one batch's steps are small (up to
 // 2^19 vertices), 4 above, where fewer, larger state machines measured
 // faster (R-MAT 18: 8 replicas +3 % over 4; R-MAT 22: -3 %).  BC_REPLICAS
-// overrides (1 .. 8).
+// overrides (1 .. 16).
 static int n_replicas(const bc_graph *g) {
     static const int env = [] {
         const char *e = std::getenv("BC_REPLICAS");
-        return e ? std::min(8, std::max(1, std::atoi(e))) : 0;
+        return e ? std::min(16, std::max(1, std::atoi(e))) : 0;
     }();
     if (env) return env;
     return g->n <= (1 << 19) ? 8 : 4;
