@@ -36,12 +36,26 @@ KERNEL_SOURCES = ["paper_2008_05718_amd/csrc/bc_batched.hip", "paper_2008_05718_
                   "paper_2008_05718_amd/csrc/bc_dev.h", "paper_2008_05718_amd/build.py"]
 
 
+def _code_only(text: str) -> str:
+    """C/C++ source without comments and with whitespace collapsed."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_sources_sha256() -> str:
+    """Hash of the sources the step kernel is built from; comments and
+    whitespace of the HIP sources are ignored, so an edit of comments only
+    keeps the recorded counters valid."""
     import hashlib
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            text = f.read()
+        if rel.endswith((".hip", ".h")):
+            text = _code_only(text)
+        h.update(text.encode())
     return h.hexdigest()
 
 

@@ -1074,7 +1074,7 @@ static bc_status resolve_cfg(const bc_graph *g, const bc_run_options &o, int64_t
 
 // ------------------------------------------------ concurrent sub-unions
 // A handle over many graphs (block-diagonal union) runs its batched work as
-// up to 8 sub-unions (environment BC_PARTS overrides, at least two graphs
+// up to 16 sub-unions (environment BC_PARTS overrides, at least two graphs
 // per part), each a handle of its own on its own stream with a dedicated
 // hardware queue, driven from its own host thread, so the level steps of
 // different graphs overlap on the device (one level state machine leaves

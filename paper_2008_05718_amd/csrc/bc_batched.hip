@@ -968,7 +968,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
         const int qs = s_qe, cnt = s_qn;
         for (int i = blockIdx.x * kBlock + tid; i < cnt; i += (int)nblk * kBlock) a.vn[a.lq_vtx[qs + i]].nxt = 0ull;
     } else if (phase == PH_BC) {
-        // dependencies -> BC in source-list order, then clear the visited words
+        // dependencies -> BC in lane order (the run's source order), then
+        // clear the visited words
         const int lo = s_lo, span = s_hi - s_lo;
         const unsigned long long keep = s_lmask & ~s_dead;
         for (int i = blockIdx.x * kBlock + tid; i < span; i += (int)nblk * kBlock) {
