@@ -113,8 +113,8 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": n * 4, "copies": 3}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part "
-                                   "of this build (sources would shard across GPUs with one BC reduction)"}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; a multi-GPU run (sources "
+                                   "sharded across GPUs, one reduction of the BC vectors) is not implemented"}))
         sys.exit(2)
 
     import torch

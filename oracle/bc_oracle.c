@@ -219,8 +219,8 @@ int oracle_source(int32_t n, const int32_t *row_ptr32, const int64_t *row_ptr64,
     return mode;
 }
 
-/* Size of long double in this build, so the loader can check it matches
- * numpy's longdouble. */
+/* Size of long double in the compiled oracle, so the loader can check it
+ * matches numpy's longdouble. */
 int oracle_sizeof_long_double(void) { return (int)sizeof(long double); }
 
 /*
