@@ -4,11 +4,12 @@ Only the test suite, ``__graft_entry__.smoke()`` and the benchmark's
 ``cpu_baseline`` leg may import this package.  The GPU library never loads it
 and shares no code with it.
 
-``bc_oracle.c`` is a plain single-threaded C implementation of the paper's
-sequential algorithm (Section "Background", Eq. 1-2 and the algorithm figure
-"Betweenness Centrality Algorithm").  This module compiles it with gcc and
-wraps it with ctypes.  ``brute.py`` holds definition-level checkers (path
-enumeration, walk counting) used to pin the oracle.
+``bc_oracle.c`` is a plain single-threaded C implementation of Eq. 1-2 of
+the paper's Section "Background", written out from their definitions:
+breadth-first distances, the path-count recurrence over predecessors, and
+Eq. 2 as a sum over each vertex's successors.  This module compiles it with
+gcc and wraps it with ctypes.  ``tests/brute.py`` holds definition-level
+checkers (path enumeration, walk counting) used to pin the oracle.
 """
 from __future__ import annotations
 
@@ -86,6 +87,41 @@ def bc(g, sources=None):
     rc = lib.oracle_bc(g.n, _ptr(rp32), _ptr(rp64), _ptr(col), _ptr(src), ns, _ptr(out), _ptr(modes))
     if rc != 0:
         raise ValueError(f"oracle_bc failed with code {rc}")
+    return out, modes
+
+
+def bc_sliced(g, sources, threads: int = 0):
+    """``bc(g, sources)`` with the source list cut into ``threads`` contiguous
+    slices (0 = all cores, at most 16), each run by the single-threaded oracle
+    on its own host thread with its own buffers; the partial score vectors
+    are added in slice order.  Same terms as ``bc``, grouped per slice, so
+    the result agrees with ``bc`` to rounding.  Returns (bc, modes)."""
+    from concurrent.futures import ThreadPoolExecutor
+    lib = _load()
+    rp32, rp64 = _rp(g)
+    col = np.ascontiguousarray(g.col_idx, dtype=np.int32)
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    modes = np.zeros(src.size, dtype=np.int32)
+    nt = threads or min(16, os.cpu_count() or 1)
+    nt = max(1, min(nt, src.size))
+    bounds = np.linspace(0, src.size, nt + 1).astype(np.int64)
+    parts = [np.zeros(g.n, dtype=np.float64) for _ in range(nt)]
+
+    def work(i):
+        lo, hi = int(bounds[i]), int(bounds[i + 1])
+        if hi <= lo:
+            return 0
+        s = src[lo:hi]
+        m = modes[lo:hi]
+        return lib.oracle_bc(g.n, _ptr(rp32), _ptr(rp64), _ptr(col), _ptr(s), hi - lo, _ptr(parts[i]), _ptr(m))
+
+    with ThreadPoolExecutor(nt) as ex:
+        rcs = list(ex.map(work, range(nt)))
+    if any(rcs):
+        raise ValueError(f"oracle_bc failed with codes {rcs}")
+    out = np.zeros(g.n, dtype=np.float64)
+    for p in parts:
+        out += p
     return out, modes
 
 

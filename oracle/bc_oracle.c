@@ -11,9 +11,17 @@
  *   Eq. 2    delta_s(v) = sum over u with v in P_s(u) of
  *                         sigma_sv / sigma_su * (1 + delta_s(u))
  *            BC[v] = sum over s != v of delta_s(v)
- *   Algorithm "Betweenness Centrality Algorithm" (Fig. seq-BC): a
- *   level-synchronous forward phase that records level sets, distances and
- *   path counts, and a backward phase over the levels in descending order.
+ * written out from those definitions, one source at a time:
+ *   1. distances d(s, .) by breadth-first search (the graphs are unweighted);
+ *   2. path counts from the recurrence sigma_ss = 1 and, for t != s,
+ *      sigma_st = sum of sigma_sv over the neighbours v of t with
+ *      d(s, v) = d(s, t) - 1 (every shortest s-t path enters t from such a
+ *      v, and each of them continues exactly the sigma_sv shortest s-v
+ *      paths), taking vertices in non-decreasing distance;
+ *   3. Eq. 2 for each vertex v as a sum over its successors u (neighbours
+ *      with d(s, u) = d(s, v) + 1), taking vertices in non-increasing
+ *      distance so that every delta_s(u) on the right is final;
+ *   4. BC[v] += delta_s(v) for every reached v != s.
  *
  * Readings where the paper is silent or loose (each one is listed in the
  * design notes of the repository):
@@ -21,17 +29,17 @@
  *     pair is counted twice.  The raw sum over the given sources is returned.
  *   - v = s is excluded from BC (Eq. 2's outer sum has s != v); vertices not
  *     reached from s receive nothing (pairs with sigma_st = 0 contribute 0).
- *   - Predecessor sets are not stored: v is a predecessor of u exactly when
- *     (v, u) is an edge and d[v] = d[u] - 1, which is the set the forward
- *     phase would have built.
+ *   - The predecessor set P_s(u) of Eq. 2 is the set of neighbours v of u
+ *     with d(s, v) = d(s, u) - 1; it is not stored.
  *   - Path counts use uint64.  A source whose exact count exceeds 2^64 - 1 is
  *     flagged F64 and recomputed entirely in x87 long double (64-bit
  *     mantissa, 15-bit exponent); its dependencies are rounded to double at
- *     the end.  Since all partial sums of a path count are non-negative and
- *     increasing, the first carry out of 64 bits is detected exactly.
- *   - The backward update is evaluated as written,
- *     delta[v] = delta[v] + sigma[v] / sigma[u] * (1 + delta[u]),
- *     left to right, in double (U64 mode) or long double (F64 mode).
+ *     the end.  Every partial sum of a path count is a sum of non-negative
+ *     terms no larger than the final count, so a carry out of 64 bits occurs
+ *     exactly when some count exceeds 2^64 - 1.
+ *   - Each term of Eq. 2 is evaluated as (sigma_sv / sigma_su) *
+ *     (1 + delta_s(u)) and the terms of one vertex are added in adjacency
+ *     order, in double (U64 mode) or long double (F64 mode).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -46,79 +54,78 @@ typedef struct {
     int32_t n;
     const int64_t *row_ptr; /* int64 copy for uniform indexing */
     const int32_t *col;
-    int32_t *d;
-    int32_t *queue;          /* all levels, concatenated in discovery order */
-    int64_t *level_start;    /* level l occupies queue[level_start[l] .. level_start[l+1]) */
-    int32_t n_levels;        /* number of non-empty levels */
-    uint64_t *sig_u;
-    long double *sig_l;
-    double *del_d;
-    long double *del_l;
+    int32_t *dist;           /* d(s, v), -1 = not reached */
+    int32_t *order;          /* reached vertices in breadth-first order (non-decreasing d) */
+    int64_t n_reached;
+    uint64_t *sig_u;         /* sigma_sv, U64 mode */
+    long double *sig_l;      /* sigma_sv, F64 mode */
+    double *dep_d;           /* delta_s(v), U64 mode */
+    long double *dep_l;      /* delta_s(v), F64 mode */
 } orc_ws;
 
-/* Forward phase (Algorithm, forward loop).  Returns 1 when a path count
- * overflowed uint64 (only possible when use_ld == 0). */
-static int forward(orc_ws *w, int32_t s, int use_ld)
+/* Step 1: breadth-first search from s.  The FIFO order is kept: it lists
+ * the reached vertices by non-decreasing distance. */
+static void distances(orc_ws *w, int32_t s)
 {
-    const int32_t n = w->n;
-    for (int32_t i = 0; i < n; ++i) w->d[i] = -1;
-    if (use_ld) { for (int32_t i = 0; i < n; ++i) w->sig_l[i] = 0.0L; }
-    else        { for (int32_t i = 0; i < n; ++i) w->sig_u[i] = 0; }
-    int64_t tail = 0;
-    w->queue[tail++] = s;
-    w->d[s] = 0;
-    if (use_ld) w->sig_l[s] = 1.0L; else w->sig_u[s] = 1;
-    w->level_start[0] = 0;
-    w->level_start[1] = 1;
-    int32_t cur = 0;
-    int overflow = 0;
-    while (w->level_start[cur + 1] > w->level_start[cur]) {
-        const int64_t lo = w->level_start[cur], hi = w->level_start[cur + 1];
-        for (int64_t qi = lo; qi < hi; ++qi) {
-            const int32_t v = w->queue[qi];
-            for (int64_t e = w->row_ptr[v]; e < w->row_ptr[v + 1]; ++e) {
-                const int32_t x = w->col[e];
-                if (w->d[x] == -1) {
-                    w->queue[tail++] = x;
-                    w->d[x] = w->d[v] + 1;
-                }
-                if (w->d[x] == w->d[v] + 1) {
-                    if (use_ld) {
-                        w->sig_l[x] = w->sig_l[x] + w->sig_l[v];
-                    } else {
-                        uint64_t r;
-                        if (__builtin_add_overflow(w->sig_u[x], w->sig_u[v], &r)) overflow = 1;
-                        w->sig_u[x] = r;
-                    }
-                }
+    for (int32_t i = 0; i < w->n; ++i) w->dist[i] = -1;
+    int64_t head = 0, tail = 0;
+    w->order[tail++] = s;
+    w->dist[s] = 0;
+    while (head < tail) {
+        const int32_t v = w->order[head++];
+        for (int64_t e = w->row_ptr[v]; e < w->row_ptr[v + 1]; ++e) {
+            const int32_t x = w->col[e];
+            if (w->dist[x] < 0) {
+                w->dist[x] = w->dist[v] + 1;
+                w->order[tail++] = x;
             }
         }
-        ++cur;
-        w->level_start[cur + 1] = tail;
     }
-    w->n_levels = cur; /* levels 0 .. cur-1 are non-empty */
+    w->n_reached = tail;
+}
+
+/* Step 2: sigma_st = sum over the neighbours one step closer to s.  Returns
+ * 1 when a count does not fit in uint64 (use_ld == 0 only). */
+static int path_counts(orc_ws *w, int use_ld)
+{
+    int overflow = 0;
+    for (int64_t k = 0; k < w->n_reached; ++k) {
+        const int32_t t = w->order[k];
+        if (k == 0) { /* t = s */
+            if (use_ld) w->sig_l[t] = 1.0L; else w->sig_u[t] = 1;
+            continue;
+        }
+        uint64_t su = 0;
+        long double sl = 0.0L;
+        for (int64_t e = w->row_ptr[t]; e < w->row_ptr[t + 1]; ++e) {
+            const int32_t v = w->col[e];
+            if (w->dist[v] != w->dist[t] - 1) continue;
+            if (use_ld) {
+                sl += w->sig_l[v];
+            } else if (__builtin_add_overflow(su, w->sig_u[v], &su)) {
+                overflow = 1;
+            }
+        }
+        if (use_ld) w->sig_l[t] = sl; else w->sig_u[t] = su;
+    }
     return overflow;
 }
 
-/* Backward phase (Algorithm, backward loop): levels L..1 in descending
- * order, every vertex u of the level pushes into its predecessors. */
-static void backward(orc_ws *w, int use_ld)
+/* Step 3: Eq. 2, delta_s(v) = sum over successors u of
+ * sigma_sv / sigma_su * (1 + delta_s(u)), vertices by non-increasing distance. */
+static void dependencies(orc_ws *w, int use_ld)
 {
-    const int32_t n = w->n;
-    if (use_ld) { for (int32_t i = 0; i < n; ++i) w->del_l[i] = 0.0L; }
-    else        { for (int32_t i = 0; i < n; ++i) w->del_d[i] = 0.0; }
-    for (int32_t l = w->n_levels - 1; l > 0; --l) {
-        for (int64_t qi = w->level_start[l]; qi < w->level_start[l + 1]; ++qi) {
-            const int32_t u = w->queue[qi];
-            for (int64_t e = w->row_ptr[u]; e < w->row_ptr[u + 1]; ++e) {
-                const int32_t v = w->col[e];
-                if (w->d[v] != l - 1) continue; /* v not in pred[u] */
-                if (use_ld)
-                    w->del_l[v] = w->del_l[v] + w->sig_l[v] / w->sig_l[u] * (1.0L + w->del_l[u]);
-                else
-                    w->del_d[v] = w->del_d[v] + (double)w->sig_u[v] / (double)w->sig_u[u] * (1.0 + w->del_d[u]);
-            }
+    for (int64_t k = w->n_reached - 1; k >= 0; --k) {
+        const int32_t v = w->order[k];
+        double dd = 0.0;
+        long double dl = 0.0L;
+        for (int64_t e = w->row_ptr[v]; e < w->row_ptr[v + 1]; ++e) {
+            const int32_t u = w->col[e];
+            if (w->dist[u] != w->dist[v] + 1) continue; /* u is not a successor of v */
+            if (use_ld) dl += (w->sig_l[v] / w->sig_l[u]) * (1.0L + w->dep_l[u]);
+            else dd += ((double)w->sig_u[v] / (double)w->sig_u[u]) * (1.0 + w->dep_d[u]);
         }
+        if (use_ld) w->dep_l[v] = dl; else w->dep_d[v] = dd;
     }
 }
 
@@ -132,43 +139,44 @@ static int ws_init(orc_ws *w, int32_t n, const int32_t *row_ptr32, const int64_t
     for (int64_t i = 0; i <= n; ++i) rp[i] = row_ptr64 ? row_ptr64[i] : (int64_t)row_ptr32[i];
     w->row_ptr = rp;
     w->col = col;
-    w->d = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    w->queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    w->level_start = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 2));
-    w->sig_u = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
-    w->sig_l = (long double *)malloc(sizeof(long double) * (size_t)(n > 0 ? n : 1));
-    w->del_d = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-    w->del_l = (long double *)malloc(sizeof(long double) * (size_t)(n > 0 ? n : 1));
-    if (!w->d || !w->queue || !w->level_start || !w->sig_u || !w->sig_l || !w->del_d || !w->del_l)
-        return ORC_ERR_MEM;
+    const size_t m = (size_t)(n > 0 ? n : 1);
+    w->dist = (int32_t *)malloc(sizeof(int32_t) * m);
+    w->order = (int32_t *)malloc(sizeof(int32_t) * m);
+    w->sig_u = (uint64_t *)calloc(m, sizeof(uint64_t));
+    w->sig_l = (long double *)calloc(m, sizeof(long double));
+    w->dep_d = (double *)calloc(m, sizeof(double));
+    w->dep_l = (long double *)calloc(m, sizeof(long double));
+    if (!w->dist || !w->order || !w->sig_u || !w->sig_l || !w->dep_d || !w->dep_l) return ORC_ERR_MEM;
     return ORC_OK;
 }
 
 static void ws_free(orc_ws *w)
 {
     free((void *)w->row_ptr);
-    free(w->d); free(w->queue); free(w->level_start);
-    free(w->sig_u); free(w->sig_l); free(w->del_d); free(w->del_l);
+    free(w->dist); free(w->order);
+    free(w->sig_u); free(w->sig_l); free(w->dep_d); free(w->dep_l);
 }
 
-/* One source: forward, overflow fallback, backward.  Returns the mode
- * (0 = U64, 1 = F64). */
+/* One source: distances, path counts (uint64, else long double), Eq. 2.
+ * Returns the mode (0 = U64, 1 = F64). */
 static int one_source(orc_ws *w, int32_t s)
 {
+    distances(w, s);
     int mode = 0;
-    if (forward(w, s, 0)) {
+    if (path_counts(w, 0)) {
         mode = 1;
-        forward(w, s, 1);
+        path_counts(w, 1);
     }
-    backward(w, mode);
+    dependencies(w, mode);
     return mode;
 }
 
 /*
  * BC over a source list.  sources == NULL means every vertex 0..n-1 in
  * order.  bc[0..n) receives the raw ordered-pair sums (it is overwritten, not
- * accumulated).  modes (nullable) receives 0/1 per source.  row_ptr is given
- * either as int32 (row_ptr32) or int64 (row_ptr64); pass NULL for the other.
+ * accumulated), sources taken in list order.  modes (nullable) receives 0/1
+ * per source.  row_ptr is given either as int32 (row_ptr32) or int64
+ * (row_ptr64); pass NULL for the other.
  */
 int oracle_bc(int32_t n, const int32_t *row_ptr32, const int64_t *row_ptr64, const int32_t *col,
               const int32_t *sources, int64_t n_sources, double *bc, int32_t *modes)
@@ -183,9 +191,9 @@ int oracle_bc(int32_t n, const int32_t *row_ptr32, const int64_t *row_ptr64, con
         if (s < 0 || s >= n) { ws_free(&w); return ORC_ERR_ARG; }
         const int mode = one_source(&w, s);
         if (modes) modes[k] = mode;
-        for (int32_t v = 0; v < n; ++v) {
-            if (w.d[v] <= 0) continue; /* unreached, or v == s */
-            bc[v] += mode ? (double)w.del_l[v] : w.del_d[v];
+        for (int64_t i = 1; i < w.n_reached; ++i) { /* order[0] is s itself */
+            const int32_t v = w.order[i];
+            bc[v] += mode ? (double)w.dep_l[v] : w.dep_d[v];
         }
     }
     ws_free(&w);
@@ -196,9 +204,10 @@ int oracle_bc(int32_t n, const int32_t *row_ptr32, const int64_t *row_ptr64, con
  * Per-source detail.  d: int32[n] (-1 = unreached).  sigma_u64: uint64[n]
  * (valid in U64 mode; zero in F64 mode).  sigma_ld: long double[n] (the F64
  * mode counts; in U64 mode the exact counts converted).  delta: double[n],
- * the backward loop's values; the source's own entry is what the loop leaves
- * there (BC excludes it).  Any output pointer may be NULL.  Returns the mode
- * (0/1) or a negative error.
+ * delta_s(v) from Eq. 2 for reached v (for v = s the same sum over its
+ * successors, which BC excludes), 0 for unreached v.  n_levels: number of
+ * distinct distances (largest d + 1).  Any output pointer may be NULL.
+ * Returns the mode (0/1) or a negative error.
  */
 int oracle_source(int32_t n, const int32_t *row_ptr32, const int64_t *row_ptr64, const int32_t *col,
                   int32_t s, int32_t *d, uint64_t *sigma_u64, long double *sigma_ld, double *delta,
@@ -209,12 +218,13 @@ int oracle_source(int32_t n, const int32_t *row_ptr32, const int64_t *row_ptr64,
     if (ws_init(&w, n, row_ptr32, row_ptr64, col) != ORC_OK) { ws_free(&w); return -ORC_ERR_MEM; }
     const int mode = one_source(&w, s);
     for (int32_t v = 0; v < n; ++v) {
-        if (d) d[v] = w.d[v];
-        if (sigma_u64) sigma_u64[v] = mode ? 0 : w.sig_u[v];
-        if (sigma_ld) sigma_ld[v] = mode ? w.sig_l[v] : (long double)w.sig_u[v];
-        if (delta) delta[v] = mode ? (double)w.del_l[v] : w.del_d[v];
+        const int reached = w.dist[v] >= 0;
+        if (d) d[v] = w.dist[v];
+        if (sigma_u64) sigma_u64[v] = (mode || !reached) ? 0 : w.sig_u[v];
+        if (sigma_ld) sigma_ld[v] = !reached ? 0.0L : (mode ? w.sig_l[v] : (long double)w.sig_u[v]);
+        if (delta) delta[v] = !reached ? 0.0 : (mode ? (double)w.dep_l[v] : w.dep_d[v]);
     }
-    if (n_levels) *n_levels = w.n_levels;
+    if (n_levels) *n_levels = w.dist[w.order[w.n_reached - 1]] + 1;
     ws_free(&w);
     return mode;
 }
