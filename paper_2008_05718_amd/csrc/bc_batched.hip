@@ -1038,6 +1038,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
         if (tid < kLanes && s_emax[tid] != INT_MIN) atomicMax(&a.maxexp[slot * kLanes + tid], s_emax[tid]);
         else if (tid >= kLanes && tid < 2 * kLanes && s_emin[tid - kLanes] != INT_MAX)
             atomicMin(&a.maxexp[(kSlots + slot) * kLanes + tid - kLanes], s_emin[tid - kLanes]);
+        // completed before this workgroup arrives (the last one reads them)
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
     if (!step_epilogue(c, cn, s_red, &s_last, active)) return;
     collect_slots(c, s_tot, s_red);

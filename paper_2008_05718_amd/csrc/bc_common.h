@@ -139,8 +139,11 @@ struct WorkCursor {
 // consumed by later launches, which kernel boundaries order.  The last
 // workgroup must therefore never store to a word that another workgroup of
 // the same launch stored to: each XCD's L2 would hold its own dirty copy
-// until the launch ends and write it back in no fixed order.  s_red needs
-// kWavesPerBlock * kNCnt entries.
+// until the launch ends and write it back in no fixed order.  Device-scope
+// atomics that a workgroup issues before calling this (the slot counters
+// here, a caller's exponent ranges) must have completed before it counts
+// itself in: each wave that issued one waits for its memory counters first.
+// s_red needs kWavesPerBlock * kNCnt entries.
 __device__ __forceinline__ bool step_epilogue(Ctl *c, Counters &cn, unsigned long long *s_red, int *s_last,
                                               bool active) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -165,6 +168,12 @@ __device__ __forceinline__ bool step_epilogue(Ctl *c, Counters &cn, unsigned lon
                 else atomicMax(&c->slot[slot][k], t);
             }
         }
+        // The slot atomics return nothing, so nothing has waited for them;
+        // the last workgroup reads the slots once every arrival is counted,
+        // so they must have completed before this workgroup arrives.
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __syncthreads();
     }
     if (threadIdx.x == 0) {
