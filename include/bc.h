@@ -38,7 +38,7 @@ typedef enum bc_status {
     BC_OK = 0,
     BC_ERR_INVALID_ARG = 1,    /* bad pointer, size, source id or option   */
     BC_ERR_INVALID_GRAPH = 2,  /* CSR fails validation (see bc_graph_create) */
-    BC_ERR_OUT_OF_MEMORY = 3,  /* device allocation failed or over max_device_bytes */
+    BC_ERR_OUT_OF_MEMORY = 3,  /* device allocation failed, or over bc_set_device_limit's cap */
     BC_ERR_DEVICE = 4,         /* a HIP call failed; destroy the handle     */
     BC_ERR_SIGMA_RANGE = 5,    /* scaled FP64 path counts left the double range */
     BC_ERR_NOT_SUPPORTED = 6
@@ -104,9 +104,24 @@ bc_status bc_graph_create_multi(int32_t n_graphs, const int32_t *vtx_offsets, in
 /* NULL-safe.  Frees every device and host resource of the handle. */
 void bc_destroy(bc_graph *g);
 
-/* Basic facts: n, nnz, number of graphs, bytes of device memory held. */
+/* Basic facts: n, nnz, number of graphs, bytes of device memory held (the
+ * handle and the concurrent replicas or sub-unions it created). */
 bc_status bc_graph_info(const bc_graph *g, int32_t *n, int64_t *nnz, int32_t *n_graphs,
                         int64_t *device_bytes);
+
+/*
+ * Cap on the device memory the handle may hold: its graph arrays, engine
+ * state (allocated at the first run of each engine, then kept), per-run
+ * buffers, and the concurrent replicas or sub-unions a run would create.
+ * max_device_bytes = 0 removes the cap (the default).  An allocation that
+ * would take the handle past the cap fails with BC_ERR_OUT_OF_MEMORY before
+ * any device memory is requested (the handle stays usable); concurrent
+ * replicas or sub-unions that would not fit are not created, and the run
+ * uses one level state machine instead (same results to rounding; see
+ * BC_RUN_ONE_QUEUE).  Concurrent parts already created that exceed a new
+ * cap are released.  Errors: BC_ERR_INVALID_ARG (NULL g, negative cap).
+ */
+bc_status bc_set_device_limit(bc_graph *g, int64_t max_device_bytes);
 
 /* -------------------------------------------------------------------- run */
 
@@ -241,7 +256,8 @@ typedef struct bc_stats {
     int64_t lane_arcs;         /* (arc, source) pairs on shortest-path DAGs, both phases */
     int64_t queue_entries;     /* level-queue entries written                  */
     double algo_bytes;         /* algorithmic bytes: 16 per scanned arc, 8 per DAG
-                                  (arc, source) pair, 32 per level-queue entry  */
+                                  (arc, source) pair, 32 per level-queue entry,
+                                  40 per reached (vertex, source) pair         */
     double ms;                 /* wall time of the run, host clock            */
     double phase_ms[10];       /* device time per phase (index = internal phase id:
                                   1 discover, 2 path counts, 3 backward,
@@ -256,9 +272,32 @@ typedef struct bc_stats {
     double mode_ms[2];         /* device time of those passes: HIP events on the run's
                                   stream around each pass's launches           */
     double mode_algo_bytes[2]; /* algorithmic bytes of those passes            */
+    int64_t reached_pairs;     /* (vertex, source) pairs reached, sources included */
+    double algo_bytes_arcs;    /* algo_bytes without the 40 B per reached pair  */
 } bc_stats;
 
 bc_status bc_run_stats(const bc_graph *g, bc_stats *out);
+
+/*
+ * Per-level records of the last bc_run / bc_run_detail on this handle, one
+ * per distance l from the source (the level loop of the forward and
+ * backward phases, Section "Background"), summed over every batch (K > 1)
+ * or source (K = 1) of the run and over both path-count modes.  Levels at
+ * or beyond 65537 share the last record.
+ *   out        host array of cap records (may be NULL when cap == 0).
+ *   *n_levels  number of levels the run reached (records available).
+ * Copies min(cap, *n_levels) records.  Errors: BC_ERR_INVALID_ARG for NULL
+ * g / n_levels, cap < 0, or out == NULL with cap > 0.
+ */
+typedef struct bc_level_stats {
+    int64_t visits;      /* forward steps at this level: batches (or sources) whose traversal reached it */
+    int64_t entries;     /* level-queue entries: vertices on this level, each with its lane mask (the frontier size) */
+    int64_t arcs;        /* adjacency entries scanned by this level's steps, all phases */
+    int64_t variant[3];  /* forward steps of this level run with each BC_VARIANT_* */
+    double ms;           /* device time of this level's steps, all phases */
+} bc_level_stats;
+
+bc_status bc_run_level_stats(const bc_graph *g, bc_level_stats *out, int64_t cap, int64_t *n_levels);
 
 /* ---------------------------------------------------------- learned policy */
 

@@ -17,8 +17,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# BC_LIBRARY may point at another build of libbc.so (tuning experiments).
-LIB_PATH = os.environ.get("BC_LIBRARY") or os.path.join(_HERE, "libbc.so")
+LIB_PATH = os.path.join(_HERE, "libbc.so")  # the in-tree build; no override
 
 BC_OK = 0
 STATUS = {0: "BC_OK", 1: "BC_ERR_INVALID_ARG", 2: "BC_ERR_INVALID_GRAPH", 3: "BC_ERR_OUT_OF_MEMORY",
@@ -46,7 +45,7 @@ BC_MLP_PARAMS = 32 * 5 + 32 + 32 * 32 + 32 + 3 * 32 + 3
 EXPORTS = ["bc_status_string", "bc_last_error", "bc_graph_create", "bc_graph_create_multi", "bc_destroy",
            "bc_graph_info", "bc_run_options_init", "bc_run", "bc_scores", "bc_run_detail", "bc_run_stats",
            "bc_load_policy", "bc_mlp_loss_grad", "bc_mlp_train", "bc_mlp_predict", "bc_collect_level_times",
-           "bc_autotune"]
+           "bc_autotune", "bc_set_device_limit", "bc_run_level_stats"]
 
 
 class LibraryMissing(RuntimeError):
@@ -83,7 +82,13 @@ class Stats(ctypes.Structure):
                 ("phase_ms", ctypes.c_double * 10), ("variant_ms", ctypes.c_double * 3),
                 ("phase_arcs", ctypes.c_int64 * 10), ("phase_lane_arcs", ctypes.c_int64 * 10),
                 ("phase_pairs", ctypes.c_int64 * 10), ("mode_launches", ctypes.c_int64 * 2),
-                ("mode_ms", ctypes.c_double * 2), ("mode_algo_bytes", ctypes.c_double * 2)]
+                ("mode_ms", ctypes.c_double * 2), ("mode_algo_bytes", ctypes.c_double * 2),
+                ("reached_pairs", ctypes.c_int64), ("algo_bytes_arcs", ctypes.c_double)]
+
+
+class LevelStats(ctypes.Structure):
+    _fields_ = [("visits", ctypes.c_int64), ("entries", ctypes.c_int64), ("arcs", ctypes.c_int64),
+                ("variant", ctypes.c_int64 * 3), ("ms", ctypes.c_double)]
 
 
 _lib = None
@@ -137,6 +142,10 @@ def lib():
     L.bc_mlp_train.argtypes = [P, P, P, P, I64, I32, ctypes.c_float, P, P]
     L.bc_mlp_predict.restype = ctypes.c_int
     L.bc_mlp_predict.argtypes = [P, P, I64, P, P]
+    L.bc_set_device_limit.restype = ctypes.c_int
+    L.bc_set_device_limit.argtypes = [P, I64]
+    L.bc_run_level_stats.restype = ctypes.c_int
+    L.bc_run_level_stats.argtypes = [P, P, I64, P]
     L.bc_collect_level_times.restype = ctypes.c_int
     L.bc_collect_level_times.argtypes = [P, P, I64, ctypes.POINTER(RunOptions), P, P, I64, P, P]
     _lib = L
@@ -276,6 +285,24 @@ def bc_run_stats(h) -> dict:
     return out
 
 
+def bc_set_device_limit(h, max_device_bytes: int):
+    _check(lib().bc_set_device_limit(h, int(max_device_bytes)))
+
+
+def bc_run_level_stats(h) -> dict:
+    """Per-level records of the last run as arrays indexed by level."""
+    nl = ctypes.c_int64()
+    _check(lib().bc_run_level_stats(h, None, 0, ctypes.byref(nl)))
+    k = nl.value
+    recs = (LevelStats * max(k, 1))()
+    _check(lib().bc_run_level_stats(h, ctypes.cast(recs, ctypes.c_void_p), k, ctypes.byref(nl)))
+    return {"visits": np.array([r.visits for r in recs[:k]], np.int64),
+            "entries": np.array([r.entries for r in recs[:k]], np.int64),
+            "arcs": np.array([r.arcs for r in recs[:k]], np.int64),
+            "variant": np.array([list(r.variant) for r in recs[:k]], np.int64).reshape(k, 3),
+            "ms": np.array([r.ms for r in recs[:k]], np.float64)}
+
+
 def bc_autotune(h, sample, options: RunOptions | None = None, stream=None) -> dict:
     """Measure the candidate launch configurations on ``sample`` (host source
     ids); returns the fastest as a dict of run options and keeps it in the
@@ -379,6 +406,12 @@ class Graph:
 
     def stats(self):
         return bc_run_stats(self.h)
+
+    def level_stats(self):
+        return bc_run_level_stats(self.h)
+
+    def set_device_limit(self, max_device_bytes: int):
+        bc_set_device_limit(self.h, max_device_bytes)
 
     def load_policy(self, weights):
         bc_load_policy(self.h, weights)

@@ -32,13 +32,12 @@ static bc_status fail(bc_status st, const std::string &msg) {
 
 bc_status bc_set_error(bc_status s, const char *msg) { return fail(s, msg ? msg : ""); }
 
+static bc_status hip_fail(hipError_t e, const char *what);
+
 #define HIP_TRY(expr)                                                                         \
     do {                                                                                      \
         hipError_t _e = (expr);                                                               \
-        if (_e != hipSuccess) {                                                               \
-            return fail(_e == hipErrorOutOfMemory ? BC_ERR_OUT_OF_MEMORY : BC_ERR_DEVICE,     \
-                        std::string(#expr) + ": " + hipGetErrorString(_e));                   \
-        }                                                                                     \
+        if (_e != hipSuccess) return hip_fail(_e, #expr);                                     \
     } while (0)
 
 // ----------------------------------------------------------- small kernels
@@ -116,13 +115,36 @@ __global__ void validate_arcs(int32_t n, const int32_t *rp, const int32_t *col, 
 }  // namespace
 
 // ------------------------------------------------------------------ handle
+// Device bytes a handle holds and its cap (bc_set_device_limit; 0 = none).
+struct ByteAcct {
+    size_t bytes = 0;
+    size_t limit = 0;
+};
+static thread_local bool t_cap_refused = false;  // the last refusal came from the cap, not the device
+
+static bool over_cap(const ByteAcct *a, size_t more) { return a && a->limit && a->bytes + more > a->limit; }
+
+static bc_status hip_fail(hipError_t e, const char *what) {
+    if (e == hipErrorOutOfMemory && t_cap_refused) {
+        t_cap_refused = false;
+        return fail(BC_ERR_OUT_OF_MEMORY, std::string(what) + ": over the handle's max_device_bytes");
+    }
+    return fail(e == hipErrorOutOfMemory ? BC_ERR_OUT_OF_MEMORY : BC_ERR_DEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
 template <typename T>
-static hipError_t dalloc(T **p, size_t count, size_t *acc) {
+static hipError_t dalloc(T **p, size_t count, ByteAcct *acc) {
     *p = nullptr;
     if (count == 0) count = 1;
     const size_t bytes = count * sizeof(T);
+    t_cap_refused = false;
+    if (over_cap(acc, bytes)) {  // refused before any device memory is requested
+        t_cap_refused = true;
+        return hipErrorOutOfMemory;
+    }
     hipError_t e = hipMalloc((void **)p, bytes);
-    if (e == hipSuccess && acc) *acc += bytes;
+    if (e == hipSuccess && acc) acc->bytes += bytes;
     return e;
 }
 
@@ -154,7 +176,10 @@ struct bc_graph {
     double clock_khz = 100000.0;
     int grid_plain = 1024, grid_batch = 1024;  // resident workgroups of the step kernels
     double *bc = nullptr;
-    size_t bytes = 0;
+    LevelRec *lvl = nullptr;       // per-level records of the last run [kLevelRecs]
+    bool last_parts = false;       // the last run ran on concurrent parts
+    ByteAcct acct;                 // device bytes held by this handle itself, and the cap
+    size_t create_bytes = 0;       // bytes held right after creation
     hipStream_t cap_stream = nullptr;  // private non-blocking capture stream, created on first capture
     Ctl *ctl = nullptr;
     Ctl *ctl_host = nullptr;       // pinned
@@ -187,7 +212,7 @@ struct bc_graph {
     int64_t ovf_cap = 0;
     int64_t *bstart = nullptr;
     int32_t *blo = nullptr, *bhi = nullptr;
-    int64_t bcap = 0;
+    int64_t bcap[3] = {0, 0, 0};   // capacities of bstart, blo, bhi
     // policy
     float *mlp = nullptr;
     bool has_mlp = false;
@@ -205,6 +230,7 @@ struct bc_graph {
     std::vector<struct SubPart> parts;
     std::vector<int32_t> part_of_graph, local_base;  // per parent graph
     bool replicas = false;  // parts are full copies of a single graph (see ensure_replicas)
+    bool parts_refused = false;  // concurrent parts would not fit under the cap (see parts_fit)
     // graph cache
     std::vector<CachedGraph> graphs;
     bc_stats stats{};
@@ -242,7 +268,7 @@ extern "C" void bc_destroy(bc_graph *g) {
                    g->srcs, g->ovf, g->bstart, g->blo, g->bhi, g->mlp, g->hv_vtx, g->hv_seg, g->p_hv_vtx, g->p_hv_seg,
                    g->p_hq.pos, g->p_hq.seg, g->p_hq.cnt, g->p_hq.off, g->p_hq.nseg, g->p_hq.part_lo,
                    g->p_hq.part_hi, g->b_hq.pos, g->b_hq.seg, g->b_hq.cnt, g->b_hq.off, g->b_hq.nseg,
-                   g->b_hq.part_lo, g->b_hq.part_hi};
+                   g->b_hq.part_lo, g->b_hq.part_hi, g->lvl};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (g->ctl_host) (void)hipHostFree(g->ctl_host);
@@ -371,13 +397,11 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
             if (derr) (void)hipFree(derr);                                                     \
             if (dcnt) (void)hipFree(dcnt);                                                     \
             if (dvoff) (void)hipFree(dvoff);                                                   \
-            fail(e == hipErrorOutOfMemory ? BC_ERR_OUT_OF_MEMORY : BC_ERR_DEVICE,              \
-                 std::string(#expr) + ": " + hipGetErrorString(e));                            \
-            return bail(e == hipErrorOutOfMemory ? BC_ERR_OUT_OF_MEMORY : BC_ERR_DEVICE);      \
+            return bail(hip_fail(e, #expr));                                                   \
         }                                                                                      \
     } while (0)
-    CR_TRY(dalloc(&g->row_ptr, (size_t)n + 1, &g->bytes));
-    CR_TRY(dalloc(&g->col, (size_t)nnz, &g->bytes));
+    CR_TRY(dalloc(&g->row_ptr, (size_t)n + 1, &g->acct));
+    CR_TRY(dalloc(&g->col, (size_t)nnz, &g->acct));
     const hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     CR_TRY(hipMemcpy(g->row_ptr, row_ptr, sizeof(int32_t) * ((size_t)n + 1), kind));
     if (nnz) CR_TRY(hipMemcpy(g->col, col_idx, sizeof(int32_t) * (size_t)nnz, kind));
@@ -479,9 +503,9 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
                 rp = nrp;
                 CR_TRY(hipMemcpy(g->row_ptr, rp.data(), sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice));
                 CR_TRY(hipMemcpy(g->col, ncol.data(), sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice));
-                CR_TRY(dalloc(&g->inv_dev, (size_t)n, &g->bytes));
+                CR_TRY(dalloc(&g->inv_dev, (size_t)n, &g->acct));
                 CR_TRY(hipMemcpy(g->inv_dev, g->inv.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
-                CR_TRY(dalloc(&g->bc_out, (size_t)n, &g->bytes));
+                CR_TRY(dalloc(&g->bc_out, (size_t)n, &g->acct));
                 source_ranks(n_graphs, voff, rp, ncol, &g->srank);
             } else if (any_hubs) {  // hubs already first: keep the numbering, still order the sources
                 std::vector<int32_t> col((size_t)nnz);
@@ -509,8 +533,8 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
             int32_t **pv = which == 0 ? &g->hv_vtx : &g->p_hv_vtx, **ps = which == 0 ? &g->hv_seg : &g->p_hv_seg;
             (which == 0 ? g->n_heavy : g->p_n_heavy) = (int32_t)hv.size();
             (which == 0 ? g->heavy_segs : g->p_heavy_segs) = segs;
-            CR_TRY(dalloc(pv, hv.size(), &g->bytes));
-            CR_TRY(dalloc(ps, hs.size(), &g->bytes));
+            CR_TRY(dalloc(pv, hv.size(), &g->acct));
+            CR_TRY(dalloc(ps, hs.size(), &g->acct));
             if (!hv.empty()) CR_TRY(hipMemcpy(*pv, hv.data(), sizeof(int32_t) * hv.size(), hipMemcpyHostToDevice));
             CR_TRY(hipMemcpy(*ps, hs.data(), sizeof(int32_t) * hs.size(), hipMemcpyHostToDevice));
         }
@@ -531,13 +555,16 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
                 g->grid_batch = cus * bb;
         }
     }
-    CR_TRY(dalloc(&g->bc, (size_t)n, &g->bytes));
+    CR_TRY(dalloc(&g->bc, (size_t)n, &g->acct));
     CR_TRY(hipMemset(g->bc, 0, sizeof(double) * (size_t)(n > 0 ? n : 1)));
-    CR_TRY(dalloc(&g->ctl, 1, &g->bytes));
+    CR_TRY(dalloc(&g->ctl, 1, &g->acct));
     CR_TRY(hipHostMalloc((void **)&g->ctl_host, sizeof(Ctl), hipHostMallocDefault));
     CR_TRY(hipHostMalloc((void **)&g->flag_host, 64 * sizeof(int32_t), hipHostMallocDefault));
-    CR_TRY(dalloc(&g->mlp, (size_t)kMlpParams, &g->bytes));
+    CR_TRY(dalloc(&g->mlp, (size_t)kMlpParams, &g->acct));
+    CR_TRY(dalloc(&g->lvl, (size_t)kLevelRecs, &g->acct));
+    CR_TRY(hipMemset(g->lvl, 0, sizeof(LevelRec) * kLevelRecs));
 #undef CR_TRY
+    g->create_bytes = g->acct.bytes;
     *out = g;
     return BC_OK;
 }
@@ -554,13 +581,34 @@ extern "C" bc_status bc_graph_create_multi(int32_t n_graphs, const int32_t *vtx_
     return create_impl(n_graphs, vtx_offsets, n, nnz, row_ptr, col_idx, flags, out);
 }
 
+// Device bytes of the handle and of the concurrent parts it created.
+static size_t total_bytes(const bc_graph *g) {
+    size_t t = g->acct.bytes;
+    for (const SubPart &pt : g->parts) t += total_bytes(pt.h) + pt.to_parent_host.size() * sizeof(int32_t);
+    return t;
+}
+
 extern "C" bc_status bc_graph_info(const bc_graph *g, int32_t *n, int64_t *nnz, int32_t *n_graphs,
                                    int64_t *device_bytes) {
     if (!g) return fail(BC_ERR_INVALID_ARG, "NULL handle");
     if (n) *n = g->n;
     if (nnz) *nnz = g->nnz;
     if (n_graphs) *n_graphs = g->n_graphs;
-    if (device_bytes) *device_bytes = (int64_t)g->bytes;
+    if (device_bytes) *device_bytes = (int64_t)total_bytes(g);
+    return BC_OK;
+}
+
+extern "C" bc_status bc_set_device_limit(bc_graph *g, int64_t max_device_bytes) {
+    if (!g) return fail(BC_ERR_INVALID_ARG, "NULL handle");
+    if (max_device_bytes < 0) return fail(BC_ERR_INVALID_ARG, "max_device_bytes < 0");
+    g->acct.limit = (size_t)max_device_bytes;
+    g->parts_refused = false;  // decided again at the next run
+    if (g->acct.limit && !g->parts.empty() && total_bytes(g) > g->acct.limit) {
+        // the parts already made do not fit under the new cap: drop them
+        (void)hipDeviceSynchronize();
+        free_parts(g);
+        g->replicas = false;
+    }
     return BC_OK;
 }
 
@@ -570,14 +618,14 @@ extern "C" void bc_run_options_init(bc_run_options *opt) {
 
 // ------------------------------------------------------------ engine setup
 static bc_status alloc_hq(bc_graph *g, HeavyQ *q, int64_t entries, int64_t levels, int lanes, int64_t heavy_segs) {
-    HIP_TRY(dalloc(&q->pos, (size_t)entries, &g->bytes));
-    HIP_TRY(dalloc(&q->seg, (size_t)entries, &g->bytes));
-    HIP_TRY(dalloc(&q->cnt, (size_t)entries, &g->bytes));
-    HIP_TRY(dalloc(&q->off, (size_t)levels, &g->bytes));
-    HIP_TRY(dalloc(&q->nseg, (size_t)levels, &g->bytes));
+    HIP_TRY(dalloc(&q->pos, (size_t)entries, &g->acct));
+    HIP_TRY(dalloc(&q->seg, (size_t)entries, &g->acct));
+    HIP_TRY(dalloc(&q->cnt, (size_t)entries, &g->acct));
+    HIP_TRY(dalloc(&q->off, (size_t)levels, &g->acct));
+    HIP_TRY(dalloc(&q->nseg, (size_t)levels, &g->acct));
     const int64_t segs = heavy_segs + 1;
-    HIP_TRY(dalloc(&q->part_lo, (size_t)segs * lanes, &g->bytes));
-    HIP_TRY(dalloc(&q->part_hi, (size_t)segs * lanes, &g->bytes));
+    HIP_TRY(dalloc(&q->part_lo, (size_t)segs * lanes, &g->acct));
+    HIP_TRY(dalloc(&q->part_hi, (size_t)segs * lanes, &g->acct));
     q->cap = (uint32_t)std::min<int64_t>(entries, UINT32_MAX);
     q->part_cap = (uint32_t)std::min<int64_t>(segs, UINT32_MAX);
     return BC_OK;
@@ -586,15 +634,20 @@ static bc_status alloc_hq(bc_graph *g, HeavyQ *q, int64_t entries, int64_t level
 static bc_status ensure_plain(bc_graph *g, hipStream_t st) {
     const int64_t n = g->n;
     if (!g->plain_ready) {
+        const size_t need = (size_t)(g->p_n_heavy + 1) * 12 + (size_t)(n + 3) * 8 + (size_t)(g->p_heavy_segs + 1) * 16 +
+                            (size_t)std::max<int64_t>(n, 1) * 24 + (size_t)(n + 2) * 8;
+        if (over_cap(&g->acct, need))
+            return fail(BC_ERR_OUT_OF_MEMORY, "per-source engine state (" + std::to_string(need) +
+                                                  " bytes) is over the handle's max_device_bytes");
         // each heavy vertex enters a source's level queues once
         bc_status s = alloc_hq(g, &g->p_hq, (int64_t)g->p_n_heavy + 1, n + 3, 1, g->p_heavy_segs);
         if (s != BC_OK) return s;
-        HIP_TRY(dalloc(&g->p_d, (size_t)n, &g->bytes));
-        HIP_TRY(dalloc(&g->p_queue, (size_t)n, &g->bytes));
-        HIP_TRY(dalloc(&g->p_level_off, (size_t)n + 2, &g->bytes));
-        HIP_TRY(dalloc(&g->p_shift, (size_t)n + 2, &g->bytes));
-        HIP_TRY(dalloc(&g->p_sig, (size_t)n, &g->bytes));
-        HIP_TRY(dalloc(&g->p_chat, (size_t)n, &g->bytes));
+        HIP_TRY(dalloc(&g->p_d, (size_t)n, &g->acct));
+        HIP_TRY(dalloc(&g->p_queue, (size_t)n, &g->acct));
+        HIP_TRY(dalloc(&g->p_level_off, (size_t)n + 2, &g->acct));
+        HIP_TRY(dalloc(&g->p_shift, (size_t)n + 2, &g->acct));
+        HIP_TRY(dalloc(&g->p_sig, (size_t)n, &g->acct));
+        HIP_TRY(dalloc(&g->p_chat, (size_t)n, &g->acct));
         g->plain_ready = true;
         g->plain_dirty = true;
     }
@@ -608,54 +661,77 @@ static bc_status ensure_plain(bc_graph *g, hipStream_t st) {
     return BC_OK;
 }
 
+// Sizes of the batched engine's state for a graph (shared by the allocation
+// and by the estimates the device-memory cap is checked against).
+struct BatchedSizes {
+    int64_t lq_cap, max_levels, gcap, hq_entries, hq_levels;
+    size_t bytes;
+};
+static BatchedSizes batched_sizes(int64_t n, int64_t cost_units, int64_t n_heavy, int64_t heavy_segs) {
+    BatchedSizes z;
+    // every (vertex, lane) pair enters the level queues at most once
+    z.lq_cap = std::min<int64_t>((int64_t)kLanes * std::max<int64_t>(n, 1) + 64, (int64_t)INT32_MAX);
+    z.max_levels = std::max<int64_t>(std::min<int64_t>(n + 2, 65536), 4);
+    // work groups: a vertex is on at most 64 levels of a batch; each level
+    // has cost / kBudget + 1 groups and one closing slot
+    z.gcap = std::min<int64_t>((int64_t)kLanes * cost_units / kBudget + 2 * (z.max_levels + 2) + 64,
+                               (int64_t)UINT32_MAX);
+    // a heavy vertex sits on at most 64 distinct levels of a batch (one per lane)
+    z.hq_entries = n_heavy * kLanes + kLanes;
+    z.hq_levels = z.max_levels + 3;
+    const size_t nn = (size_t)std::max<int64_t>(n, 1);
+    z.bytes = nn * (sizeof(VisNext) + 2 * sizeof(Tagged)) + (size_t)z.lq_cap * (sizeof(int32_t) + 8) +
+              (size_t)(z.max_levels + 2) * sizeof(int32_t) * 2 + nn * kLanes * 3 * 8 + (size_t)z.gcap * 4 +
+              (size_t)(z.max_levels + 2) * kLanes * 4 + (size_t)2 * kSlots * kLanes * 4 + kLanes * 4 +
+              (size_t)z.hq_entries * 12 + (size_t)z.hq_levels * 8 + (size_t)(heavy_segs + 1) * kLanes * 16;
+    return z;
+}
+
 static bc_status ensure_batched(bc_graph *g) {
     if (g->batch_ready) return BC_OK;
     const int64_t n = g->n;
     // level cost prefixes are 32-bit; a level holds each vertex at most once
     if (g->cost_units >= (int64_t)UINT32_MAX)
         return fail(BC_ERR_NOT_SUPPORTED, "graph too large for the batched engine: use batch = 1");
-    HIP_TRY(dalloc(&g->b_vn, (size_t)n, &g->bytes));
-    HIP_TRY(dalloc(&g->b_fw0, (size_t)n, &g->bytes));
-    HIP_TRY(dalloc(&g->b_fw1, (size_t)n, &g->bytes));
-    // every (vertex, lane) pair enters the level queues at most once
-    const int64_t cap = std::min<int64_t>((int64_t)kLanes * std::max<int64_t>(n, 1) + 64, (int64_t)INT32_MAX);
-    g->b_lq_cap = (uint32_t)cap;
-    HIP_TRY(dalloc(&g->b_lq_vtx, (size_t)cap, &g->bytes));
-    HIP_TRY(dalloc(&g->b_lq_mask, (size_t)cap, &g->bytes));
-    g->b_max_levels = (int32_t)std::min<int64_t>(n + 2, 65536);
-    if (g->b_max_levels < 4) g->b_max_levels = 4;
-    HIP_TRY(dalloc(&g->b_level_off, (size_t)g->b_max_levels + 2, &g->bytes));
+    const BatchedSizes z = batched_sizes(n, g->cost_units, g->n_heavy, g->heavy_segs);
+    if (over_cap(&g->acct, z.bytes))
+        return fail(BC_ERR_OUT_OF_MEMORY, "batched engine state (" + std::to_string(z.bytes) +
+                                              " bytes) is over the handle's max_device_bytes");
+    HIP_TRY(dalloc(&g->b_vn, (size_t)n, &g->acct));
+    HIP_TRY(dalloc(&g->b_fw0, (size_t)n, &g->acct));
+    HIP_TRY(dalloc(&g->b_fw1, (size_t)n, &g->acct));
+    g->b_lq_cap = (uint32_t)z.lq_cap;
+    HIP_TRY(dalloc(&g->b_lq_vtx, (size_t)z.lq_cap, &g->acct));
+    HIP_TRY(dalloc(&g->b_lq_mask, (size_t)z.lq_cap, &g->acct));
+    g->b_max_levels = (int32_t)z.max_levels;
+    HIP_TRY(dalloc(&g->b_level_off, (size_t)g->b_max_levels + 2, &g->acct));
     // per-(vertex, lane) slabs of path counts, c and delta
-    HIP_TRY(dalloc(&g->b_sigma, (size_t)n * kLanes, &g->bytes));
-    HIP_TRY(dalloc(&g->b_chat, (size_t)n * kLanes, &g->bytes));
-    HIP_TRY(dalloc(&g->b_delta, (size_t)n * kLanes, &g->bytes));
-    // work groups: a vertex is on at most 64 levels of a batch; each level
-    // has cost / kBudget + 1 groups and one closing slot
-    const int64_t gcap = std::min<int64_t>((int64_t)kLanes * g->cost_units / kBudget + 2 * ((int64_t)g->b_max_levels + 2) + 64,
-                                           (int64_t)UINT32_MAX);
-    g->b_gcap = (uint32_t)gcap;
-    HIP_TRY(dalloc(&g->b_gstart, (size_t)gcap, &g->bytes));
-    HIP_TRY(dalloc(&g->b_gbase, (size_t)g->b_max_levels + 2, &g->bytes));
-    HIP_TRY(dalloc(&g->b_shift, ((size_t)g->b_max_levels + 2) * kLanes, &g->bytes));
-    HIP_TRY(dalloc(&g->b_maxexp, (size_t)2 * kSlots * kLanes, &g->bytes));
-    HIP_TRY(dalloc(&g->b_lane_src, (size_t)kLanes, &g->bytes));
-    // a heavy vertex sits on at most 64 distinct levels of a batch (one per lane)
-    bc_status s = alloc_hq(g, &g->b_hq, (int64_t)g->n_heavy * kLanes + kLanes, (int64_t)g->b_max_levels + 3, kLanes,
-                           g->heavy_segs);
+    HIP_TRY(dalloc(&g->b_sigma, (size_t)n * kLanes, &g->acct));
+    HIP_TRY(dalloc(&g->b_chat, (size_t)n * kLanes, &g->acct));
+    HIP_TRY(dalloc(&g->b_delta, (size_t)n * kLanes, &g->acct));
+    g->b_gcap = (uint32_t)z.gcap;
+    HIP_TRY(dalloc(&g->b_gstart, (size_t)z.gcap, &g->acct));
+    HIP_TRY(dalloc(&g->b_gbase, (size_t)g->b_max_levels + 2, &g->acct));
+    HIP_TRY(dalloc(&g->b_shift, ((size_t)g->b_max_levels + 2) * kLanes, &g->acct));
+    HIP_TRY(dalloc(&g->b_maxexp, (size_t)2 * kSlots * kLanes, &g->acct));
+    HIP_TRY(dalloc(&g->b_lane_src, (size_t)kLanes, &g->acct));
+    bc_status s = alloc_hq(g, &g->b_hq, z.hq_entries, z.hq_levels, kLanes, g->heavy_segs);
     if (s != BC_OK) return s;
     g->batch_ready = true;
     return BC_OK;
 }
 
 template <typename T>
-static bc_status grow(T **p, int64_t *cap, int64_t need, size_t *bytes) {
+static bc_status grow(T **p, int64_t *cap, int64_t need, ByteAcct *acct) {
     if (need <= *cap && *p) return BC_OK;
     if (*p) {
         HIP_TRY(hipFree(*p));
-        *bytes -= (size_t)(*cap) * sizeof(T);
+        *p = nullptr;
+        acct->bytes -= (size_t)(*cap) * sizeof(T);
+        *cap = 0;
     }
     int64_t c = std::max<int64_t>(need, 16);
-    HIP_TRY(dalloc(p, (size_t)c, bytes));
+    HIP_TRY(dalloc(p, (size_t)c, acct));
     *cap = c;
     return BC_OK;
 }
@@ -815,10 +891,14 @@ struct DumpBufs {
 // Algorithmic bytes: every scanned arc reads its column index and a 4-8 byte
 // word of the neighbour (8 B + 8 B), every DAG (arc, source) pair moves one
 // 8-byte path count or c value, every level-queue entry costs its row
-// offsets, queue slots and per-vertex words (32 B).
-static double algo_bytes(const bc_stats &s) {
+// offsets, queue slots and per-vertex words (32 B), and every reached
+// (vertex, source) pair moves five 8-byte slab values: its path count written
+// (forward) and read (backward), c and delta written (backward), delta read
+// (score accumulation).  algo_bytes_arcs leaves the last term out.
+static double algo_bytes_arcs(const bc_stats &s) {
     return 16.0 * (double)s.arcs_scanned + 8.0 * (double)s.lane_arcs + 32.0 * (double)s.queue_entries;
 }
+static double algo_bytes(const bc_stats &s) { return algo_bytes_arcs(s) + 40.0 * (double)s.reached_pairs; }
 
 static void accumulate_stats(bc_stats *s, const Ctl &c, double clock_khz) {
     for (int i = 0; i < kPhases; ++i) s->phase_ms[i] += (double)c.st_ticks[i] / clock_khz;
@@ -834,6 +914,7 @@ static void accumulate_stats(bc_stats *s, const Ctl &c, double clock_khz) {
     s->arcs_scanned += (int64_t)c.st_arcs;
     s->lane_arcs += (int64_t)c.st_lane_arcs;
     s->queue_entries += (int64_t)c.st_qentries;
+    s->reached_pairs += (int64_t)c.st_lane_entries;
     s->max_levels = std::max<int64_t>(s->max_levels, (int64_t)c.st_max_levels);
     s->n_batches += (int64_t)c.st_batches;
 }
@@ -858,9 +939,13 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
                           std::vector<int64_t> *ovf_positions, int *dump_done, Ctl *ctl_out,
                           const CollectBufs *col = nullptr) {
     bc_status s;
-    s = grow(&g->srcs, &g->srcs_cap, ns, &g->bytes);
+    // engine state first: it is by far the largest allocation, so a run
+    // refused under the device-memory cap allocates nothing
+    s = cfg.engine == 1 ? ensure_plain(g, st) : ensure_batched(g);
     if (s != BC_OK) return s;
-    s = grow(&g->ovf, &g->ovf_cap, ns, &g->bytes);
+    s = grow(&g->srcs, &g->srcs_cap, ns, &g->acct);
+    if (s != BC_OK) return s;
+    s = grow(&g->ovf, &g->ovf_cap, ns, &g->acct);
     if (s != BC_OK) return s;
     if (ns) HIP_TRY(hipMemcpyAsync(g->srcs, h_srcs, sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
     Ctl *hc = g->ctl_host;
@@ -885,8 +970,6 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
         ga.hv_vtx = g->p_hv_vtx;
         ga.hv_seg = g->p_hv_seg;
         ga.n_heavy = g->p_n_heavy;
-        s = ensure_plain(g, st);
-        if (s != BC_OK) return s;
         hc->phase = PH_FIN;
         hc->pos = -1;
         hc->n_items = ns;
@@ -909,6 +992,7 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
         a.ovf_cap = (uint32_t)std::min<int64_t>(g->ovf_cap, UINT32_MAX);
         a.sigma_limit = limit;
         a.hq = g->p_hq;
+        a.lvl = g->lvl;
         if (dump) {
             a.dump_d = dump->d;
             a.dump_sig = dump->sig;
@@ -920,8 +1004,6 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
         s = drive(g, a, cfg.mode ? plain_step<1> : plain_step<0>, cfg, st, max_steps, &launches, &dev_ms);
         if (s != BC_OK) g->plain_dirty = true;
     } else {
-        s = ensure_batched(g);
-        if (s != BC_OK) return s;
         // batches of up to 64 sources that never cross a graph boundary
         std::vector<int64_t> bs;
         std::vector<int32_t> lo, hi;
@@ -939,15 +1021,12 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
         }
         bs.push_back(ns);
         const int64_t nb = (int64_t)lo.size();
-        int64_t cap64 = g->bcap;
-        s = grow(&g->bstart, &cap64, nb + 1, &g->bytes);
+        s = grow(&g->bstart, &g->bcap[0], nb + 1, &g->acct);
         if (s != BC_OK) return s;
-        int64_t c1 = g->bcap, c2 = g->bcap;
-        s = grow(&g->blo, &c1, nb + 1, &g->bytes);
+        s = grow(&g->blo, &g->bcap[1], nb + 1, &g->acct);
         if (s != BC_OK) return s;
-        s = grow(&g->bhi, &c2, nb + 1, &g->bytes);
+        s = grow(&g->bhi, &g->bcap[2], nb + 1, &g->acct);
         if (s != BC_OK) return s;
-        g->bcap = std::min(cap64, std::min(c1, c2));
         HIP_TRY(hipMemcpyAsync(g->bstart, bs.data(), sizeof(int64_t) * bs.size(), hipMemcpyHostToDevice, st));
         if (nb) {
             HIP_TRY(hipMemcpyAsync(g->blo, lo.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
@@ -1000,6 +1079,7 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
         a.batch_hi = g->bhi;
         a.lane_src = g->b_lane_src;
         a.hq = g->b_hq;
+        a.lvl = g->lvl;
         if (col) {
             a.col_X = col->X;
             a.col_Y = col->Y;
@@ -1142,6 +1222,7 @@ static int n_replicas(const bc_graph *g) {
 
 static bool use_parts(const bc_graph *g, const bc_run_options &o, int64_t ns) {
     if ((o.flags & BC_RUN_ONE_QUEUE) || o.batch == 1 || std::getenv("BC_ONE_QUEUE")) return false;
+    if (g->parts_refused) return false;
     if (o.batch == 0 && ns < 2) return false;  // the per-source engine would be chosen
     if (g->n_graphs >= 4) return true;
     const int K = o.batch >= 8 ? o.batch : 64;
@@ -1152,9 +1233,31 @@ static bool use_parts(const bc_graph *g, const bc_run_options &o, int64_t ns) {
 // batches of K sources are dealt to them in turn, and the parts' score
 // vectors are added in part order.  Deterministic for a given K, but the
 // additions are grouped differently from one state machine.
+// Under a device-memory cap, concurrent parts are created only when the
+// state they would allocate fits beside what the handle holds; otherwise the
+// handle runs on its own level state machine (same results to rounding).
+static bool parts_fit(bc_graph *g, size_t need) {
+    if (!g->acct.limit) return true;
+    const size_t have = g->acct.bytes;
+    if (have + need <= g->acct.limit) return true;
+    g->parts_refused = true;
+    return false;
+}
+
+// Per-run buffers of a handle running ns sources: source list, overflow
+// list, batch bounds.
+static size_t run_buffer_bytes(int64_t ns) { return (size_t)(ns + 16) * 12 + (size_t)(ns + 17) * 16; }
+
 static bc_status ensure_replicas(bc_graph *g) {
     if (!g->parts.empty()) return BC_OK;
     const int R = n_replicas(g);
+    {
+        // a replica holds the graph (created with the parent's internal
+        // numbering) and its own batched engine state
+        const BatchedSizes z = batched_sizes(g->n, g->cost_units, g->n_heavy, g->heavy_segs);
+        if (!parts_fit(g, (size_t)R * (g->create_bytes + z.bytes + run_buffer_bytes(g->n))))
+            return fail(BC_ERR_OUT_OF_MEMORY, "concurrent replicas do not fit under max_device_bytes");
+    }
     int cus = 0, dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -1208,6 +1311,32 @@ static bc_status ensure_parts(bc_graph *g) {
     for (int r = 0; r < G; ++r) {
         const int k = r % (2 * P);
         g->part_of_graph[order[r]] = k < P ? k : 2 * P - 1 - k;
+    }
+    if (g->acct.limit) {
+        // what the parts would hold: their graphs and batched engine state
+        std::vector<int64_t> pn(P, 0), pnnz(P, 0), pcost(P, 0), pheavy(P, 0), psegs(P, 0);
+        for (int i = 0; i < G; ++i) {
+            const int p = g->part_of_graph[i];
+            for (int32_t v = g->voff[i]; v < g->voff[i + 1]; ++v) {
+                const int32_t d = rp[v + 1] - rp[v];
+                pn[p] += 1;
+                pnnz[p] += d;
+                pcost[p] += entry_cost(d);
+                if (d > kSegBatched) {
+                    pheavy[p] += 1;
+                    psegs[p] += (d + kSegBatched - 1) / kSegBatched;
+                }
+            }
+        }
+        size_t need = 0;
+        for (int p = 0; p < P; ++p)
+            need += (size_t)(pn[p] + 1) * 24 + (size_t)pnnz[p] * 4 + sizeof(Ctl) + (size_t)kLevelRecs * sizeof(LevelRec) +
+                    (size_t)pheavy[p] * 16 + 4096 + batched_sizes(pn[p], pcost[p], pheavy[p], psegs[p]).bytes +
+                    run_buffer_bytes(pn[p]);
+        if (!parts_fit(g, need)) {
+            g->part_of_graph.clear();
+            return fail(BC_ERR_OUT_OF_MEMORY, "concurrent sub-unions do not fit under max_device_bytes");
+        }
     }
     g->local_base.assign(G, 0);
     std::vector<float> w;
@@ -1390,6 +1519,8 @@ static bc_status run_parts(bc_graph *g, const int32_t *sources, int64_t n_source
         S.lane_arcs += x.lane_arcs;
         S.queue_entries += x.queue_entries;
         S.algo_bytes += x.algo_bytes;
+        S.algo_bytes_arcs += x.algo_bytes_arcs;
+        S.reached_pairs += x.reached_pairs;
         for (int k = 0; k < 10; ++k) {
             S.phase_ms[k] += x.phase_ms[k];
             S.phase_arcs[k] += x.phase_arcs[k];
@@ -1453,8 +1584,13 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
         if (o.wpv_degree <= 0.0f) o.wpv_degree = g->tuned.wpv_degree;
         o.flags &= ~BC_RUN_TUNED;
     }
-    if (use_parts(g, o, sources ? n_sources : g->n))
-        return run_parts(g, sources, n_sources, o, stream, dump_index, detail);
+    if (use_parts(g, o, sources ? n_sources : g->n)) {
+        g->last_parts = true;
+        const bc_status ps = run_parts(g, sources, n_sources, o, stream, dump_index, detail);
+        if (!(ps == BC_ERR_OUT_OF_MEMORY && g->parts_refused)) return ps;
+        // the parts were refused under the cap before anything ran: one state machine
+    }
+    g->last_parts = false;
     std::vector<int32_t> all;
     const int32_t *src = sources;
     int64_t ns = n_sources;
@@ -1475,6 +1611,9 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
     hipStream_t st = (hipStream_t)stream;
     const auto t0 = std::chrono::steady_clock::now();
     std::memset(&g->stats, 0, sizeof(g->stats));
+    fill_u64<<<grid_for((int64_t)kLevelRecs * 8, 256, 4096), 256, 0, st>>>((unsigned long long *)g->lvl,
+                                                                           (int64_t)kLevelRecs * 8, 0ull);
+    HIP_TRY(hipGetLastError());
     g->stats.n_sources = ns;
     g->stats.batch = cfg.engine;
     g->stats.policy = cfg.policy;
@@ -1487,6 +1626,8 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
     DumpBufs db;
     if (detail) {
         const size_t n = (size_t)std::max<int32_t>(g->n, 1);
+        if (over_cap(&g->acct, n * 24 + 8))
+            return fail(BC_ERR_OUT_OF_MEMORY, "detail buffers are over the handle's max_device_bytes");
         HIP_TRY(hipMalloc((void **)&db.d, n * sizeof(int32_t)));
         HIP_TRY(hipMalloc((void **)&db.sig, n * sizeof(unsigned long long)));
         HIP_TRY(hipMalloc((void **)&db.delta, n * sizeof(double)));
@@ -1614,6 +1755,7 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
     }
     g->stats.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     g->stats.algo_bytes = algo_bytes(g->stats);
+    g->stats.algo_bytes_arcs = algo_bytes_arcs(g->stats);
     return BC_OK;
 }
 
@@ -1713,6 +1855,8 @@ extern "C" bc_status bc_collect_level_times(bc_graph *g, const int32_t *sources,
     hipStream_t st = (hipStream_t)stream;
     CollectBufs cb;
     cb.cap = (uint32_t)std::min<int64_t>(cap, UINT32_MAX);
+    if (over_cap(&g->acct, (size_t)cb.cap * (kMlpIn + 3) * sizeof(float)))
+        return fail(BC_ERR_OUT_OF_MEMORY, "collection buffers are over the handle's max_device_bytes");
     HIP_TRY(hipMalloc((void **)&cb.X, (size_t)cb.cap * kMlpIn * sizeof(float)));
     hipError_t e = hipMalloc((void **)&cb.Y, (size_t)cb.cap * 3 * sizeof(float));
     if (e != hipSuccess) {
@@ -1720,6 +1864,9 @@ extern "C" bc_status bc_collect_level_times(bc_graph *g, const int32_t *sources,
         return fail(BC_ERR_OUT_OF_MEMORY, "collection buffers");
     }
     std::memset(&g->stats, 0, sizeof(g->stats));
+    g->last_parts = false;
+    fill_u64<<<grid_for((int64_t)kLevelRecs * 8, 256, 4096), 256, 0, st>>>((unsigned long long *)g->lvl,
+                                                                           (int64_t)kLevelRecs * 8, 0ull);
     if (!(o.flags & BC_RUN_ACCUMULATE) && g->n > 0) {
         fill_u64<<<grid_for(g->n, 256, 4096), 256, 0, st>>>((unsigned long long *)g->bc, g->n, 0ull);
     }
@@ -1787,6 +1934,49 @@ extern "C" bc_status bc_scores(const bc_graph *g, double *out, int64_t len, uint
 extern "C" bc_status bc_run_stats(const bc_graph *g, bc_stats *out) {
     if (!g || !out) return fail(BC_ERR_INVALID_ARG, "NULL argument");
     *out = g->stats;
+    return BC_OK;
+}
+
+// Level records of the last run, summed over the concurrent parts it ran on.
+static bc_status level_records(const bc_graph *g, std::vector<LevelRec> *acc) {
+    if (g->last_parts) {
+        for (const SubPart &pt : g->parts) {
+            bc_status s = level_records(pt.h, acc);
+            if (s != BC_OK) return s;
+        }
+        return BC_OK;
+    }
+    std::vector<LevelRec> r((size_t)kLevelRecs);
+    HIP_TRY(hipMemcpy(r.data(), g->lvl, sizeof(LevelRec) * kLevelRecs, hipMemcpyDeviceToHost));
+    for (int i = 0; i < kLevelRecs; ++i) {
+        LevelRec &a = (*acc)[(size_t)i];
+        a.visits += r[i].visits;
+        a.entries += r[i].entries;
+        a.arcs += r[i].arcs;
+        for (int k = 0; k < 3; ++k) a.var[k] += r[i].var[k];
+        a.ticks += r[i].ticks;
+    }
+    return BC_OK;
+}
+
+extern "C" bc_status bc_run_level_stats(const bc_graph *g, bc_level_stats *out, int64_t cap, int64_t *n_levels) {
+    if (!g || !n_levels || cap < 0 || (cap > 0 && !out)) return fail(BC_ERR_INVALID_ARG, "NULL argument or cap < 0");
+    std::vector<LevelRec> acc((size_t)kLevelRecs);
+    std::memset(acc.data(), 0, sizeof(LevelRec) * acc.size());
+    bc_status s = level_records(g, &acc);
+    if (s != BC_OK) return s;
+    int64_t used = 0;
+    for (int i = 0; i < kLevelRecs; ++i)
+        if (acc[i].visits || acc[i].entries) used = i + 1;
+    *n_levels = used;
+    for (int64_t i = 0; i < std::min(cap, used); ++i) {
+        bc_level_stats &o = out[i];
+        o.visits = (int64_t)acc[i].visits;
+        o.entries = (int64_t)acc[i].entries;
+        o.arcs = (int64_t)acc[i].arcs;
+        for (int k = 0; k < 3; ++k) o.variant[k] = (int64_t)acc[i].var[k];
+        o.ms = (double)acc[i].ticks / g->clock_khz;
+    }
     return BC_OK;
 }
 

@@ -189,7 +189,7 @@ __device__ __forceinline__ double bwd_arcs(const BatchArgs &a, const Tagged *__r
 
 // Per-lane counters the path-count finalisation feeds.
 struct SigCounters {
-    unsigned long long edges = 0, act = 0, ovf = 0, full_n = 0, full_m = 0, larcs = 0, arcs = 0, pairs = 0;
+    unsigned long long edges = 0, act = 0, ovf = 0, full_n = 0, full_m = 0, larcs = 0, arcs = 0, pairs = 0, lent = 0;
     int maxe = INT_MIN, mine = INT_MAX;
 };
 
@@ -226,6 +226,7 @@ __device__ __forceinline__ void sig_finalize(const BatchArgs &a, Tagged *fw_nxt,
         a.lq_mask[p] = m;
         sc.edges += (unsigned)deg;
         sc.act |= m;
+        sc.lent += (unsigned)__popcll(m);
         if ((y.vis & lmask) == lmask) {
             sc.full_n += 1;
             sc.full_m += (unsigned)deg;
@@ -568,6 +569,8 @@ __device__ __forceinline__ void batch_begin(const BatchArgs &a, Ctl *c, int64_t 
         c->prev_variant = V_PUSH_TPV;
         c->phase = PH_FWD;
         c->st_batches += 1;
+        c->st_lane_entries += (unsigned long long)lanes;
+        level_rec(a.lvl, 0).entries += (unsigned long long)cnt;
         const int64_t dp = c->dump_pos;
         c->dump_lane = (dp >= start && dp < end && c->dump_state == 0) ? (int)(dp - start) : -1;
         sf->nf = (float)cnt;
@@ -699,7 +702,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
     const int h0 = s_h0, h1 = s_h1, hseg = s_hseg;
 
     unsigned long long my_edges = 0, my_arcs = 0, my_larcs = 0, my_act = 0, my_ovf = 0;
-    unsigned long long my_full_n = 0, my_full_m = 0, my_pairs = 0;
+    unsigned long long my_full_n = 0, my_full_m = 0, my_pairs = 0, my_lent = 0;
     int my_maxe = INT_MIN, my_mine = INT_MAX;
 
     if (!active) {
@@ -921,6 +924,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
         my_larcs += sc.larcs;
         my_arcs += sc.arcs;
         my_pairs += sc.pairs;
+        my_lent += sc.lent;
         my_maxe = max(my_maxe, sc.maxe);
         my_mine = min(my_mine, sc.mine);
     } else if (phase == PH_BWD) {
@@ -1026,6 +1030,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
     cn.v[SC_ACT] = my_act;
     cn.v[SC_OVF] = my_ovf;
     cn.v[SC_PAIRS] = my_pairs;
+    cn.v[SC_LENT] = my_lent;
     if (MODE == 1 && phase == PH_SIG) {
         // per-lane exponent range of the new level: reduced over the
         // workgroup in LDS, then one atomic per lane into the workgroup's slot
@@ -1052,17 +1057,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
         c->st_steps += 1;
         c->st_arcs += s_tot[SC_ARCS];
         c->st_lane_arcs += s_tot[SC_LARCS];
+        c->st_lane_entries += s_tot[SC_LENT];
         c->st_parcs[phase] += s_tot[SC_ARCS];
         c->st_plarcs[phase] += s_tot[SC_LARCS];
         c->st_ppairs[phase] += s_tot[SC_PAIRS];
         const unsigned long long now = wall_clock64();
         const unsigned long long prev_tick = c->last_tick;
-        if (c->last_tick) {
-            const unsigned long long dt = now - c->last_tick;
-            c->st_ticks[phase] += dt;
-            if (phase == PH_FWD) c->st_vticks[s_variant] += dt;
-        }
+        const unsigned long long dt = prev_tick ? now - prev_tick : 0ull;
+        c->st_ticks[phase] += dt;
+        if (phase == PH_FWD) c->st_vticks[s_variant] += dt;
         c->last_tick = now;
+        const int rl = (phase == PH_FWD || phase == PH_BWD) ? l : (phase == PH_SIG ? l + 1 : -1);
+        if (rl >= 0) {
+            LevelRec &r = level_rec(a.lvl, rl);
+            r.arcs += s_tot[SC_ARCS];
+            r.ticks += dt;
+            if (phase == PH_FWD) {
+                r.visits += 1;
+                r.var[s_variant] += 1;
+            }
+        }
         bool timed_again = false;
         if (phase == PH_FWD && c->collect) {
             c->ct[c->cvar] = c->last_tick ? now - prev_tick : 0ull;
@@ -1094,6 +1108,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
             c->st_fwd_levels += 1;
             c->st_var[s_variant] += 1;
             c->st_qentries += cnt;
+            level_rec(a.lvl, l + 1).entries += cnt;
             a.hq.off[l + 2] = a.hq.off[l + 1] + (int)(uint32_t)nh;
             a.hq.nseg[l + 1] = (int)(nh >> 32);
             c->next_hq = 0;
@@ -1203,8 +1218,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
                 a.maxexp[(kSlots + sl) * kLanes + tid] = INT_MAX;
             }
             int sh = 0;
-            if (mx != INT_MIN && mx > 960) sh = mx - 900;
-            if (mn != INT_MAX && mn - sh < -1000) atomicOr(&c->err, ERR_SIGMA_RANGE);
+            if (mx != INT_MIN && mx > kExpHigh) sh = mx - kExpTarget;
+            if (mn != INT_MAX && mn - sh < kExpLow) atomicOr(&c->err, ERR_SIGMA_RANGE);
             a.shift[(size_t)(l + 1) * kLanes + tid] = sh;
             // true counts of level l+1 are the stored ones times 2^lane_E
             if (mx != INT_MIN) c->lane_emax[tid] = max(c->lane_emax[tid], mx + c->lane_E[tid]);

@@ -78,7 +78,7 @@ struct Counters {
 };
 
 __device__ __forceinline__ int cnt_op(int k) {  // 0 sum, 1 or, 2 max
-    return k == SC_PAIRS ? 0 : (k >= SC_MAXE ? 2 : (k >= SC_ACT ? 1 : 0));
+    return k >= SC_PAIRS ? 0 : (k >= SC_MAXE ? 2 : (k >= SC_ACT ? 1 : 0));
 }
 
 __device__ __forceinline__ unsigned long long cnt_combine(int k, unsigned long long a, unsigned long long b) {

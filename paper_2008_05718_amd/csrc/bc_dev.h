@@ -28,6 +28,13 @@ constexpr int kSeg = kSegPlain;
 constexpr int kSeg = kSegBatched;
 #endif
 constexpr int kPhases = 10;
+// Scaled FP64 path counts (mode 1): a level whose largest binary exponent
+// exceeds kExpHigh is divided by a power of two that brings it to kExpTarget,
+// so a sum over fewer than 2^31 predecessors stays below 2^932.  Its
+// smallest count must then stay at or above 2^kExpLow: c = (1 + delta) /
+// sigma with delta < 2^31 then stays below 2^1021 (a wider spread within
+// one level is reported as a range error).
+constexpr int kExpHigh = 960, kExpTarget = 900, kExpLow = -990;
 constexpr int kSlots = 32;     // per-step counters and arrivals are spread over this many slots
 
 // Counters every step kernel accumulates per workgroup into its slot.
@@ -42,6 +49,7 @@ enum : int {
     SC_MAXE,       // max binary exponent + 4096 (max)
     SC_MINE,       // 4096 - min binary exponent (max)
     SC_PAIRS,      // matched (vertex, neighbour) pairs whose per-source rows were read (sum)
+    SC_LENT,       // (vertex, source) pairs of the entries appended (sum)
     kNCnt
 };
 
@@ -126,6 +134,7 @@ struct Ctl {
     // --- statistics
     unsigned long long st_steps, st_fwd_levels, st_var[3], st_arcs, st_lane_arcs, st_qentries,
         st_max_levels, st_batches;
+    unsigned long long st_lane_entries;      // (vertex, source) pairs reached, level 0 included
     unsigned long long last_tick;            // wall clock at the end of the previous step
     unsigned long long st_ticks[kPhases];    // wall-clock ticks spent per phase
     unsigned long long st_vticks[3];         // forward (discover) ticks per variant
@@ -135,6 +144,20 @@ struct Ctl {
 };
 
 enum : int32_t { ERR_QUEUE_CAP = 1, ERR_SIGMA_RANGE = 2, ERR_LEVEL_CAP = 4, ERR_OVF_CAP = 8 };
+
+// Per-level record of a run (statistics): index = distance from the source;
+// levels at or beyond kLevelRecs - 1 share the last record.  Written only by
+// the last workgroup of a step launch.
+constexpr int kLevelRecs = 65538;
+struct LevelRec {
+    unsigned long long visits;   // forward steps at this level (batches or sources that reached it)
+    unsigned long long entries;  // level-queue entries of this level
+    unsigned long long arcs;     // adjacency entries scanned by this level's steps, all phases
+    unsigned long long var[3];   // forward steps of this level per discover variant
+    unsigned long long ticks;    // device clock ticks of this level's steps, all phases
+    unsigned long long pad;
+};
+__device__ __forceinline__ LevelRec &level_rec(LevelRec *r, int l) { return r[l < kLevelRecs ? l : kLevelRecs - 1]; }
 
 // Read-only graph description passed to every kernel.
 struct GraphArgs {
@@ -193,6 +216,7 @@ struct PlainArgs {
     double *dump_delta;
     int32_t *dump_shift;     // per-level shifts of the dumped source
     HeavyQ hq;
+    LevelRec *lvl;           // [kLevelRecs]
 };
 
 // Tagged frontier word: lanes of vertex v that sit on level (tag - epoch).
@@ -244,6 +268,7 @@ struct BatchArgs {
     uint32_t *gstart;            // group starts of every level of the batch (see GroupArgs)
     uint32_t *gbase;             // [max_levels + 2]: first gstart slot of each level
     uint32_t gcap;
+    LevelRec *lvl;               // [kLevelRecs]
 };
 
 }  // namespace bcx

@@ -133,6 +133,8 @@ __device__ __forceinline__ void plain_begin_source(const PlainArgs &a, Ctl *c, i
         c->visited_m = (unsigned long long)deg;
         c->prev_variant = V_PUSH_TPV;
         c->phase = PH_FWD;
+        level_rec(a.lvl, 0).entries += 1;
+        c->st_lane_entries += 1;
         sf->nf = 1.0f;
         sf->mf = (float)deg;
         sf->nu = (float)(a.g.n - 1);
@@ -647,12 +649,20 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
         c->st_plarcs[phase] += s_tot[SC_LARCS];
         c->st_ppairs[phase] += s_tot[SC_PAIRS];
         const unsigned long long now = wall_clock64();
-        if (c->last_tick) {
-            const unsigned long long dt = now - c->last_tick;
-            c->st_ticks[phase] += dt;
-            if (phase == PH_FWD) c->st_vticks[s_variant] += dt;
-        }
+        const unsigned long long dt = c->last_tick ? now - c->last_tick : 0ull;
+        c->st_ticks[phase] += dt;
+        if (phase == PH_FWD) c->st_vticks[s_variant] += dt;
         c->last_tick = now;
+        const int rl = (phase == PH_FWD || phase == PH_BWD) ? l : (phase == PH_SIG ? l + 1 : -1);
+        if (rl >= 0) {
+            LevelRec &r = level_rec(a.lvl, rl);
+            r.arcs += s_tot[SC_ARCS];
+            r.ticks += dt;
+            if (phase == PH_FWD) {
+                r.visits += 1;
+                r.var[s_variant] += 1;
+            }
+        }
         if (phase == PH_FWD) {
             const uint32_t cnt = (uint32_t)ld_agent(&c->next_qc);
             const unsigned long long nh = ld_agent(&c->next_hq);
@@ -664,6 +674,8 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
             c->st_fwd_levels += 1;
             c->st_var[s_variant] += 1;
             c->st_qentries += cnt;
+            c->st_lane_entries += cnt;
+            level_rec(a.lvl, l + 1).entries += cnt;
             if (MODE == 0 && s_tot[SC_OVF]) {
                 const uint32_t k = c->n_ovf;
                 if (k < a.ovf_cap) a.ovf_list[k] = c->pos;
@@ -686,8 +698,8 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
             const bool any = s_tot[SC_MAXE] != 0;
             const int mx = (int)s_tot[SC_MAXE] - 4096, mn = 4096 - (int)s_tot[SC_MINE];
             int sh = 0;
-            if (any && mx > 960) sh = mx - 900;
-            if (any && mn - sh < -1000) c->err |= ERR_SIGMA_RANGE;
+            if (any && mx > kExpHigh) sh = mx - kExpTarget;
+            if (any && mn - sh < kExpLow) c->err |= ERR_SIGMA_RANGE;
             a.shift[l + 1] = sh;
             advance = 1;
             cnt_next = (uint32_t)ld_agent(&c->next_qc);

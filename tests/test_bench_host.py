@@ -54,3 +54,60 @@ def test_summaries_are_read_only_for_their_sources():
         assert (t is not None and t > 0) if rec == cur else t is None, name
     assert found >= 1
     assert bench.measured_traffic("batch_step<0>", "no_such_workload") is None
+
+
+def _write_csv(path, header, rows):
+    import csv
+    path.parent.mkdir(parents=True, exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_profile_summary_reduces_rocprof_csvs(tmp_path):
+    # fixture shaped like rocprofv3 output: a kernel trace with stats, one
+    # FETCH_SIZE and one WRITE_SIZE counter run, and the copy calibration
+    import argparse
+    import json
+    K = "void bcx::batch_step<0>(bcx::BatchArgs)"
+    _write_csv(tmp_path / "kt/h/1_kernel_stats.csv",
+               ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs", "StdDev"],
+               [[K, 5, 5000, 1000, 90.0, 900, 1100, 1.0], ["fill_u64", 2, 100, 50, 10.0, 40, 60, 1.0]])
+    # 5 dispatches; the last 4 are the timed step: 1000 ns each, two at a time
+    starts = [0, 10000, 10000, 11000, 11000]
+    _write_csv(tmp_path / "kt/h/1_kernel_trace.csv",
+               ["Kind", "Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"],
+               [["KERNEL_DISPATCH", i + 1, K, t, t + 1000] for i, t in enumerate(starts)])
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    _write_csv(tmp_path / "f/h/1_counter_collection.csv", hdr,
+               [[i + 1, K, "FETCH_SIZE", 999999 if i == 0 else 100.0] for i in range(5)])
+    _write_csv(tmp_path / "w/h/1_counter_collection.csv", hdr,
+               [[i + 1, K, "WRITE_SIZE", 50.0] for i in range(5)])
+    _write_csv(tmp_path / "cf/h/1_counter_collection.csv", hdr, [[1, "copy", "FETCH_SIZE", 524288.0]])
+    _write_csv(tmp_path / "cw/h/1_counter_collection.csv", hdr, [[1, "copy", "WRITE_SIZE", 1048576.0]])
+    line = {"value": 1.0, "roofline": {"launches": 4, "kernel": "batch_step<0>", "algo_bytes_per_launch": 1e5,
+                                       "avg_launch_us": 0.5, "achieved": 1.0, "frac": 0.1, "peak": 8000.0}}
+    (tmp_path / "bench.log").write_text("noise\n" + json.dumps(line) + "\n")
+    args = argparse.Namespace(kernel="batch_step<0>", workload="fixture", bench_json=str(tmp_path / "bench.log"),
+                              command=["cmd a", "cmd b"], trace_dir=str(tmp_path / "kt"),
+                              fetch_dir=str(tmp_path / "f"), write_dir=str(tmp_path / "w"),
+                              cal_fetch_dir=str(tmp_path / "cf"), cal_write_dir=str(tmp_path / "cw"))
+    text = bench.profile_summary(args)
+    # factors: a 1 GiB copy reads as 524288 KiB of FETCH_SIZE (x2) and 1048576 KiB of WRITE_SIZE (x1)
+    want = 100.0 * 1024 * 2.0 + 50.0 * 1024 * 1.0
+    assert f"- traffic_bytes_per_launch: {want:.0f}" in text
+    assert "- avg_launch_us_trace: 1.000" in text
+    assert "- launches_in_flight: 2.000" in text
+    assert "cmd a" in text and f"- kernel_sources_sha256: {bench.kernel_sources_sha256()}" in text
+    # read back the way the bench line reads it
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "batch_step_u64_fixture.md").write_text(text)
+    old = bench.ROOT
+    try:
+        _copy_sources(tmp_path)
+        bench.ROOT = str(tmp_path)
+        assert bench.measured_traffic("batch_step<0>", "fixture") == want
+    finally:
+        bench.ROOT = old

@@ -60,7 +60,7 @@ def _c_sizeof(struct_src: str, name: str) -> int:
 
 
 @pytest.mark.parametrize("cname,pyt", [("bc_run_options", b.RunOptions), ("bc_detail", b.Detail),
-                                       ("bc_stats", b.Stats)])
+                                       ("bc_stats", b.Stats), ("bc_level_stats", b.LevelStats)])
 def test_struct_layouts_match_header(cname, pyt):
     assert _c_sizeof("", cname) == ctypes.sizeof(pyt)
 
@@ -104,3 +104,55 @@ def test_grid_full_size_recipe_counts():
     assert 1_040_000 < g.n < 1_048_576
     lcc_m = g.m - round(0.001 * (g.m / 1.001))
     assert abs(g.m - lcc_m) > 1000
+
+
+def test_null_handles_and_pointers_are_argument_errors():
+    # every entry point rejects a NULL handle or a NULL required pointer with
+    # BC_ERR_INVALID_ARG before touching the device (no GPU needed)
+    L = b.lib()
+    INV = 1
+    P = ctypes.c_void_p
+    out = P()
+    rp = np.array([0, 1, 2], np.int32)
+    ci = np.array([1, 0], np.int32)
+    prp, pci = rp.ctypes.data_as(P), ci.ctypes.data_as(P)
+    o = b.make_options()
+    st = b.Stats()
+    det = b.Detail()
+    lv = b.LevelStats()
+    nl = ctypes.c_int64()
+    cnt = ctypes.c_int64()
+    src = np.array([0], np.int32)
+    ps = src.ctypes.data_as(P)
+    f = np.zeros(4096, np.float32)
+    pf = f.ctypes.data_as(P)
+    mask = np.ones(4096, np.uint8)
+    calls = {
+        "create out NULL": lambda: L.bc_graph_create(2, 2, prp, pci, 0, None),
+        "create row_ptr NULL": lambda: L.bc_graph_create(2, 2, None, pci, 0, ctypes.byref(out)),
+        "create col NULL": lambda: L.bc_graph_create(2, 2, prp, None, 0, ctypes.byref(out)),
+        "create n < 0": lambda: L.bc_graph_create(-1, 2, prp, pci, 0, ctypes.byref(out)),
+        "create nnz < 0": lambda: L.bc_graph_create(2, -2, prp, pci, 0, ctypes.byref(out)),
+        "multi offsets NULL": lambda: L.bc_graph_create_multi(1, None, 2, 2, prp, pci, 0, ctypes.byref(out)),
+        "info": lambda: L.bc_graph_info(None, None, None, None, None),
+        "limit": lambda: L.bc_set_device_limit(None, 0),
+        "run": lambda: L.bc_run(None, ps, 1, ctypes.byref(o), None),
+        "run all": lambda: L.bc_run(None, None, 0, None, None),
+        "detail": lambda: L.bc_run_detail(None, ps, 1, ctypes.byref(o), 0, ctypes.byref(det), None),
+        "detail out NULL": lambda: L.bc_run_detail(None, ps, 1, ctypes.byref(o), 0, None, None),
+        "scores": lambda: L.bc_scores(None, pf, 10, 0, None),
+        "stats": lambda: L.bc_run_stats(None, ctypes.byref(st)),
+        "level stats": lambda: L.bc_run_level_stats(None, ctypes.byref(lv), 1, ctypes.byref(nl)),
+        "autotune": lambda: L.bc_autotune(None, ps, 1, None, ctypes.byref(o), None),
+        "load policy": lambda: L.bc_load_policy(None, pf, b.BC_MLP_PARAMS),
+        "collect": lambda: L.bc_collect_level_times(None, ps, 1, None, pf, pf, 10, ctypes.byref(cnt), None),
+        "mlp grad NULL X": lambda: L.bc_mlp_loss_grad(pf, None, pf, mask.ctypes.data_as(P), 1, None, pf, None),
+        "mlp train NULL w": lambda: L.bc_mlp_train(None, pf, pf, mask.ctypes.data_as(P), 1, 1, ctypes.c_float(0.01),
+                                                   None, None),
+        "mlp predict NULL Y": lambda: L.bc_mlp_predict(pf, pf, 1, None, None),
+    }
+    for name, call in calls.items():
+        assert call() == INV, name
+        assert L.bc_last_error().decode(), name
+    assert out.value is None  # never set on failure
+    L.bc_destroy(None)  # NULL-safe

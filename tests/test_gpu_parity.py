@@ -436,3 +436,59 @@ def test_torch_device_interop():
             G.scores(out, stream=stream)
     stream.synchronize()
     assert_bc_close(out.cpu().numpy(), ref)
+
+
+def test_level_records_add_up_to_run_stats():
+    g = W.rmat(12, 16, seed=44)
+    srcs = W.choose_sources(g, 300, seed=12)
+    say("[level stats] rmat12")
+    with b.Graph(g) as G:
+        for opts in ({"batch": 64}, {"batch": 64, "flags": b.BC_RUN_ONE_QUEUE}, {"batch": 1}):
+            G.run(srcs, **opts)
+            st = G.stats()
+            lv = G.level_stats()
+            L = len(lv["visits"])
+            say(f"  {opts}: {L} levels, entries {lv['entries'][:8].tolist()}")
+            assert L == st["max_levels"]
+            assert int(lv["visits"].sum()) == st["forward_levels"]
+            assert int(lv["entries"][1:].sum()) == st["queue_entries"]
+            assert lv["variant"].sum(axis=0).tolist() == st["variant_levels"]
+            assert int(lv["arcs"].sum()) == st["arcs_scanned"]
+            # one forward step per batch (or source) at level 0; K = 1 has one entry per source
+            assert int(lv["visits"][0]) == (st["n_batches"] if opts["batch"] > 1 else len(srcs))
+            if opts["batch"] == 1:
+                assert int(lv["entries"][0]) == len(srcs)
+            assert (np.diff(lv["visits"]) <= 0).all()  # every batch that reaches l + 1 reached l
+            assert (lv["ms"] >= 0).all() and lv["ms"].sum() > 0
+
+
+def test_device_limit_refuses_before_allocating_and_falls_back():
+    g = W.rmat(12, 16, seed=45)
+    srcs = W.choose_sources(g, 400, seed=13)
+    say("[device limit] rmat12")
+    ref, _ = oracle.bc(g, srcs)
+    with b.Graph(g) as G:
+        G.run(srcs, batch=64, flags=b.BC_RUN_ONE_QUEUE)
+        one = G.scores().copy()
+        need = G.info()["device_bytes"]  # graph + one batched engine
+    with b.Graph(g) as H:
+        base = H.info()["device_bytes"]
+        H.set_device_limit(base + (1 << 20))  # far too small for the batched engine
+        with pytest.raises(b.BCError) as e:
+            H.run(srcs, batch=64)
+        assert e.value.status == 3 and "max_device_bytes" in e.value.message
+        assert H.info()["device_bytes"] == base  # nothing was allocated
+        H.set_device_limit(need + (4 << 20))  # one engine fits, concurrent replicas do not
+        H.run(srcs, batch=64)
+        assert H.info()["device_bytes"] <= need + (4 << 20)
+        assert np.array_equal(H.scores().view(np.uint64), one.view(np.uint64))  # one state machine
+        H.set_device_limit(0)
+        H.run(srcs, batch=64)  # replicas now
+        many = H.scores().copy()
+        assert H.info()["device_bytes"] > need + (4 << 20)
+        H.set_device_limit(need + (4 << 20))  # the replicas no longer fit: released
+        assert H.info()["device_bytes"] <= need + (4 << 20)
+        H.run(srcs, batch=64)
+        assert np.array_equal(H.scores().view(np.uint64), one.view(np.uint64))
+    assert_bc_close(one, ref)
+    assert_bc_close(many, ref)
