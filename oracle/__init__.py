@@ -43,10 +43,10 @@ def _load():
         build(force=True)
     lib = ctypes.CDLL(_LIB)
     P = ctypes.c_void_p
-    lib.oracle_bc.restype = ctypes.c_int
-    lib.oracle_bc.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.c_int64, P, P]
-    lib.oracle_source.restype = ctypes.c_int
-    lib.oracle_source.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_int32, P, P, P, P, P]
+    lib.oracle_bc_dir.restype = ctypes.c_int
+    lib.oracle_bc_dir.argtypes = [ctypes.c_int32, P, P, P, P, P, P, P, ctypes.c_int64, P, P]
+    lib.oracle_source_dir.restype = ctypes.c_int
+    lib.oracle_source_dir.argtypes = [ctypes.c_int32, P, P, P, P, P, P, ctypes.c_int32, P, P, P, P, P]
     lib.oracle_path_excess.restype = ctypes.c_int
     lib.oracle_path_excess.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.c_int64, P]
     lib.oracle_sizeof_long_double.restype = ctypes.c_int
@@ -60,15 +60,30 @@ def _ptr(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
-def _rp(g):
-    rp = np.ascontiguousarray(g.row_ptr)
+def _rp_arr(rp):
+    rp = np.ascontiguousarray(rp)
     if rp.dtype == np.int64:
         return None, rp
     return np.ascontiguousarray(rp, dtype=np.int32), None
 
 
+def _rp(g):
+    return _rp_arr(g.row_ptr)
+
+
+def _in_arcs(g):
+    """(in_rp32, in_rp64, in_col) pointers' arrays of a directed graph, or
+    Nones for an undirected one (its adjacency serves as both)."""
+    if getattr(g, "in_row_ptr", None) is None:
+        return None, None, None
+    irp32, irp64 = _rp_arr(g.in_row_ptr)
+    return irp32, irp64, np.ascontiguousarray(g.in_col_idx, dtype=np.int32)
+
+
 def bc(g, sources=None):
-    """Raw ordered-pair BC sums over ``sources`` (None = all vertices).
+    """Raw ordered-pair BC sums over ``sources`` (None = all vertices).  A
+    graph with ``in_row_ptr`` / ``in_col_idx`` is directed (paths follow
+    arcs); otherwise its symmetric adjacency is used both ways.
 
     Returns (bc float64[n], modes int32[len(sources)]) where mode 1 marks a
     source whose path counts exceed uint64 and were evaluated in long double.
@@ -84,7 +99,9 @@ def bc(g, sources=None):
         src = np.ascontiguousarray(sources, dtype=np.int32)
         ns = src.size
     modes = np.zeros(ns, dtype=np.int32)
-    rc = lib.oracle_bc(g.n, _ptr(rp32), _ptr(rp64), _ptr(col), _ptr(src), ns, _ptr(out), _ptr(modes))
+    irp32, irp64, icol = _in_arcs(g)
+    rc = lib.oracle_bc_dir(g.n, _ptr(rp32), _ptr(rp64), _ptr(col), _ptr(irp32), _ptr(irp64), _ptr(icol),
+                           _ptr(src), ns, _ptr(out), _ptr(modes))
     if rc != 0:
         raise ValueError(f"oracle_bc failed with code {rc}")
     return out, modes
@@ -106,6 +123,7 @@ def bc_sliced(g, sources, threads: int = 0):
     nt = max(1, min(nt, src.size))
     bounds = np.linspace(0, src.size, nt + 1).astype(np.int64)
     parts = [np.zeros(g.n, dtype=np.float64) for _ in range(nt)]
+    irp32, irp64, icol = _in_arcs(g)
 
     def work(i):
         lo, hi = int(bounds[i]), int(bounds[i + 1])
@@ -113,7 +131,8 @@ def bc_sliced(g, sources, threads: int = 0):
             return 0
         s = src[lo:hi]
         m = modes[lo:hi]
-        return lib.oracle_bc(g.n, _ptr(rp32), _ptr(rp64), _ptr(col), _ptr(s), hi - lo, _ptr(parts[i]), _ptr(m))
+        return lib.oracle_bc_dir(g.n, _ptr(rp32), _ptr(rp64), _ptr(col), _ptr(irp32), _ptr(irp64), _ptr(icol),
+                                 _ptr(s), hi - lo, _ptr(parts[i]), _ptr(m))
 
     with ThreadPoolExecutor(nt) as ex:
         rcs = list(ex.map(work, range(nt)))
@@ -141,8 +160,9 @@ def source(g, s: int) -> SourceDetail:
     r.sigma_ld = np.empty(n, np.longdouble)
     r.delta = np.empty(n, np.float64)
     nl = np.zeros(1, np.int32)
-    mode = lib.oracle_source(n, _ptr(rp32), _ptr(rp64), _ptr(col), int(s), _ptr(r.d),
-                             _ptr(r.sigma_u64), _ptr(r.sigma_ld), _ptr(r.delta), _ptr(nl))
+    irp32, irp64, icol = _in_arcs(g)
+    mode = lib.oracle_source_dir(n, _ptr(rp32), _ptr(rp64), _ptr(col), _ptr(irp32), _ptr(irp64), _ptr(icol),
+                                 int(s), _ptr(r.d), _ptr(r.sigma_u64), _ptr(r.sigma_ld), _ptr(r.delta), _ptr(nl))
     if mode < 0:
         raise ValueError(f"oracle_source failed with code {mode}")
     r.mode = int(mode)

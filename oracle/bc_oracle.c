@@ -12,16 +12,20 @@
  *                         sigma_sv / sigma_su * (1 + delta_s(u))
  *            BC[v] = sum over s != v of delta_s(v)
  * written out from those definitions, one source at a time:
- *   1. distances d(s, .) by breadth-first search (the graphs are unweighted);
+ *   1. distances d(s, .) by breadth-first search along arcs (the graphs are
+ *      unweighted);
  *   2. path counts from the recurrence sigma_ss = 1 and, for t != s,
- *      sigma_st = sum of sigma_sv over the neighbours v of t with
- *      d(s, v) = d(s, t) - 1 (every shortest s-t path enters t from such a
- *      v, and each of them continues exactly the sigma_sv shortest s-v
+ *      sigma_st = sum of sigma_sv over the in-neighbours v of t (arcs v -> t)
+ *      with d(s, v) = d(s, t) - 1 (every shortest s-t path enters t from such
+ *      a v, and each of them continues exactly the sigma_sv shortest s-v
  *      paths), taking vertices in non-decreasing distance;
- *   3. Eq. 2 for each vertex v as a sum over its successors u (neighbours
+ *   3. Eq. 2 for each vertex v as a sum over its successors u (out-neighbours
  *      with d(s, u) = d(s, v) + 1), taking vertices in non-increasing
  *      distance so that every delta_s(u) on the right is final;
  *   4. BC[v] += delta_s(v) for every reached v != s.
+ * An undirected graph is the directed graph with both arcs of every edge
+ * (the paper converts every input to that form, Section "Experiments and
+ * Results"): its adjacency serves as both the out- and the in-adjacency.
  *
  * Readings where the paper is silent or loose (each one is listed in the
  * design notes of the repository):
@@ -52,8 +56,10 @@
 
 typedef struct {
     int32_t n;
-    const int64_t *row_ptr; /* int64 copy for uniform indexing */
+    const int64_t *row_ptr; /* out-arcs: int64 copy for uniform indexing */
     const int32_t *col;
+    const int64_t *in_row_ptr; /* in-arcs (the same arrays for an undirected graph) */
+    const int32_t *in_col;
     int32_t *dist;           /* d(s, v), -1 = not reached */
     int32_t *order;          /* reached vertices in breadth-first order (non-decreasing d) */
     int64_t n_reached;
@@ -97,8 +103,8 @@ static int path_counts(orc_ws *w, int use_ld)
         }
         uint64_t su = 0;
         long double sl = 0.0L;
-        for (int64_t e = w->row_ptr[t]; e < w->row_ptr[t + 1]; ++e) {
-            const int32_t v = w->col[e];
+        for (int64_t e = w->in_row_ptr[t]; e < w->in_row_ptr[t + 1]; ++e) {
+            const int32_t v = w->in_col[e];
             if (w->dist[v] != w->dist[t] - 1) continue;
             if (use_ld) {
                 sl += w->sig_l[v];
@@ -129,16 +135,31 @@ static void dependencies(orc_ws *w, int use_ld)
     }
 }
 
+static int64_t *rp_copy(int32_t n, const int32_t *rp32, const int64_t *rp64)
+{
+    int64_t *rp = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    if (rp)
+        for (int64_t i = 0; i <= n; ++i) rp[i] = rp64 ? rp64[i] : (int64_t)rp32[i];
+    return rp;
+}
+
+/* in_* == NULL: undirected, the out-adjacency is also the in-adjacency. */
 static int ws_init(orc_ws *w, int32_t n, const int32_t *row_ptr32, const int64_t *row_ptr64,
-                   const int32_t *col)
+                   const int32_t *col, const int32_t *in_rp32, const int64_t *in_rp64, const int32_t *in_col)
 {
     memset(w, 0, sizeof(*w));
     w->n = n;
-    int64_t *rp = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
-    if (!rp) return ORC_ERR_MEM;
-    for (int64_t i = 0; i <= n; ++i) rp[i] = row_ptr64 ? row_ptr64[i] : (int64_t)row_ptr32[i];
-    w->row_ptr = rp;
+    w->row_ptr = rp_copy(n, row_ptr32, row_ptr64);
+    if (!w->row_ptr) return ORC_ERR_MEM;
     w->col = col;
+    if (in_rp32 || in_rp64) {
+        w->in_row_ptr = rp_copy(n, in_rp32, in_rp64);
+        if (!w->in_row_ptr) return ORC_ERR_MEM;
+        w->in_col = in_col;
+    } else {
+        w->in_row_ptr = w->row_ptr;
+        w->in_col = col;
+    }
     const size_t m = (size_t)(n > 0 ? n : 1);
     w->dist = (int32_t *)malloc(sizeof(int32_t) * m);
     w->order = (int32_t *)malloc(sizeof(int32_t) * m);
@@ -152,6 +173,7 @@ static int ws_init(orc_ws *w, int32_t n, const int32_t *row_ptr32, const int64_t
 
 static void ws_free(orc_ws *w)
 {
+    if (w->in_row_ptr != w->row_ptr) free((void *)w->in_row_ptr);
     free((void *)w->row_ptr);
     free(w->dist); free(w->order);
     free(w->sig_u); free(w->sig_l); free(w->dep_d); free(w->dep_l);
@@ -172,18 +194,21 @@ static int one_source(orc_ws *w, int32_t s)
 }
 
 /*
- * BC over a source list.  sources == NULL means every vertex 0..n-1 in
- * order.  bc[0..n) receives the raw ordered-pair sums (it is overwritten, not
- * accumulated), sources taken in list order.  modes (nullable) receives 0/1
- * per source.  row_ptr is given either as int32 (row_ptr32) or int64
- * (row_ptr64); pass NULL for the other.
+ * BC over a source list of a directed graph: out-arcs (row_ptr*, col) and
+ * in-arcs (in_row_ptr*, in_col, the transpose; both NULL for an undirected
+ * graph, whose adjacency is used for both).  sources == NULL means every
+ * vertex 0..n-1 in order.  bc[0..n) receives the raw ordered-pair sums (it
+ * is overwritten, not accumulated), sources taken in list order.  modes
+ * (nullable) receives 0/1 per source.  Row offsets are given either as int32
+ * or int64; pass NULL for the other.
  */
-int oracle_bc(int32_t n, const int32_t *row_ptr32, const int64_t *row_ptr64, const int32_t *col,
-              const int32_t *sources, int64_t n_sources, double *bc, int32_t *modes)
+int oracle_bc_dir(int32_t n, const int32_t *row_ptr32, const int64_t *row_ptr64, const int32_t *col,
+                  const int32_t *in_rp32, const int64_t *in_rp64, const int32_t *in_col,
+                  const int32_t *sources, int64_t n_sources, double *bc, int32_t *modes)
 {
     if (n < 0 || (!row_ptr32 && !row_ptr64) || !bc) return ORC_ERR_ARG;
     orc_ws w;
-    if (ws_init(&w, n, row_ptr32, row_ptr64, col) != ORC_OK) { ws_free(&w); return ORC_ERR_MEM; }
+    if (ws_init(&w, n, row_ptr32, row_ptr64, col, in_rp32, in_rp64, in_col) != ORC_OK) { ws_free(&w); return ORC_ERR_MEM; }
     for (int32_t i = 0; i < n; ++i) bc[i] = 0.0;
     const int64_t ns = sources ? n_sources : n;
     for (int64_t k = 0; k < ns; ++k) {
@@ -200,8 +225,16 @@ int oracle_bc(int32_t n, const int32_t *row_ptr32, const int64_t *row_ptr64, con
     return ORC_OK;
 }
 
+/* Undirected graphs: the adjacency is both the out- and the in-adjacency. */
+int oracle_bc(int32_t n, const int32_t *row_ptr32, const int64_t *row_ptr64, const int32_t *col,
+              const int32_t *sources, int64_t n_sources, double *bc, int32_t *modes)
+{
+    return oracle_bc_dir(n, row_ptr32, row_ptr64, col, NULL, NULL, NULL, sources, n_sources, bc, modes);
+}
+
 /*
- * Per-source detail.  d: int32[n] (-1 = unreached).  sigma_u64: uint64[n]
+ * Per-source detail (in-arcs as in oracle_bc_dir; NULL = undirected).
+ * d: int32[n] (-1 = unreached).  sigma_u64: uint64[n]
  * (valid in U64 mode; zero in F64 mode).  sigma_ld: long double[n] (the F64
  * mode counts; in U64 mode the exact counts converted).  delta: double[n],
  * delta_s(v) from Eq. 2 for reached v (for v = s the same sum over its
@@ -209,13 +242,14 @@ int oracle_bc(int32_t n, const int32_t *row_ptr32, const int64_t *row_ptr64, con
  * distinct distances (largest d + 1).  Any output pointer may be NULL.
  * Returns the mode (0/1) or a negative error.
  */
-int oracle_source(int32_t n, const int32_t *row_ptr32, const int64_t *row_ptr64, const int32_t *col,
-                  int32_t s, int32_t *d, uint64_t *sigma_u64, long double *sigma_ld, double *delta,
-                  int32_t *n_levels)
+int oracle_source_dir(int32_t n, const int32_t *row_ptr32, const int64_t *row_ptr64, const int32_t *col,
+                      const int32_t *in_rp32, const int64_t *in_rp64, const int32_t *in_col,
+                      int32_t s, int32_t *d, uint64_t *sigma_u64, long double *sigma_ld, double *delta,
+                      int32_t *n_levels)
 {
     if (n <= 0 || s < 0 || s >= n || (!row_ptr32 && !row_ptr64)) return -ORC_ERR_ARG;
     orc_ws w;
-    if (ws_init(&w, n, row_ptr32, row_ptr64, col) != ORC_OK) { ws_free(&w); return -ORC_ERR_MEM; }
+    if (ws_init(&w, n, row_ptr32, row_ptr64, col, in_rp32, in_rp64, in_col) != ORC_OK) { ws_free(&w); return -ORC_ERR_MEM; }
     const int mode = one_source(&w, s);
     for (int32_t v = 0; v < n; ++v) {
         const int reached = w.dist[v] >= 0;
@@ -229,13 +263,21 @@ int oracle_source(int32_t n, const int32_t *row_ptr32, const int64_t *row_ptr64,
     return mode;
 }
 
+int oracle_source(int32_t n, const int32_t *row_ptr32, const int64_t *row_ptr64, const int32_t *col,
+                  int32_t s, int32_t *d, uint64_t *sigma_u64, long double *sigma_ld, double *delta,
+                  int32_t *n_levels)
+{
+    return oracle_source_dir(n, row_ptr32, row_ptr64, col, NULL, NULL, NULL, s, d, sigma_u64, sigma_ld, delta,
+                             n_levels);
+}
+
 /* Size of long double in the compiled oracle, so the loader can check it
  * matches numpy's longdouble. */
 int oracle_sizeof_long_double(void) { return (int)sizeof(long double); }
 
 /*
  * Path-length excess per source: excess[k] = sum over vertices t reached from
- * sources[k], t != s, of (d(s, t) - 1).  A shortest s-t path has d(s, t) - 1
+ * sources[k] (along out-arcs), t != s, of (d(s, t) - 1).  A shortest s-t path has d(s, t) - 1
  * interior vertices and every interior vertex v of the sigma_st paths takes
  * the share sigma_st(v) / sigma_st, so these shares sum to d(s, t) - 1 and,
  * summed over t, sum_v delta_s(v) = excess (Eq. 1 and 2 with the readings

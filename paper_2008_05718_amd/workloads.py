@@ -37,6 +37,15 @@ class CSR:
     # (int32[n_graphs+1]); a single graph has [0, n].
     vtx_offsets: np.ndarray | None = None
     meta: dict = field(default_factory=dict)
+    # Directed graphs: row_ptr / col_idx hold the out-arcs and these the
+    # in-arcs (the transpose, rows ascending).  None for undirected graphs,
+    # whose symmetric adjacency is both.
+    in_row_ptr: np.ndarray | None = None
+    in_col_idx: np.ndarray | None = None
+
+    @property
+    def directed(self) -> bool:
+        return self.in_row_ptr is not None
 
     @property
     def n(self) -> int:
@@ -48,8 +57,9 @@ class CSR:
 
     @property
     def m(self) -> int:
-        """Undirected edge count (each edge is stored as two arcs)."""
-        return self.nnz // 2
+        """Edge count: undirected edges (each stored as two arcs), or arcs of
+        a directed graph."""
+        return self.nnz if self.directed else self.nnz // 2
 
     def degrees(self) -> np.ndarray:
         return np.diff(self.row_ptr.astype(np.int64))
@@ -86,6 +96,46 @@ def csr_from_edges(n: int, u: np.ndarray, v: np.ndarray, name: str = "") -> CSR:
     return g
 
 
+def _rows(n: int, keys: np.ndarray):
+    rows = keys // n
+    cols = (keys - rows * n).astype(np.int32)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=row_ptr[1:])
+    if row_ptr[-1] < 2**31:
+        row_ptr = row_ptr.astype(np.int32)
+    return row_ptr, cols
+
+
+def digraph_from_arcs(n: int, u: np.ndarray, v: np.ndarray, name: str = "") -> CSR:
+    """Directed graph from arcs u -> v: self-loops and duplicate arcs
+    dropped, out-rows and in-rows sorted ascending."""
+    u = np.asarray(u, dtype=np.int64)
+    v = np.asarray(v, dtype=np.int64)
+    keep = u != v
+    u, v = u[keep], v[keep]
+    if u.size and (u.min() < 0 or v.min() < 0 or u.max() >= n or v.max() >= n):
+        raise ValueError("arc endpoint out of range")
+    out_keys = np.unique(u * n + v)
+    uu, vv = out_keys // n, out_keys % n
+    in_keys = np.sort(vv * n + uu)
+    rp, ci = _rows(n, out_keys)
+    irp, ici = _rows(n, in_keys)
+    g = CSR(rp, ci, name=name, in_row_ptr=irp, in_col_idx=ici)
+    g.vtx_offsets = np.array([0, n], dtype=np.int32)
+    return g
+
+
+def rmat_directed(scale: int, edgefactor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+                  seed: int = 1) -> CSR:
+    """R-MAT arcs (the sampled edges kept as directed arcs, not symmetrised),
+    seeded random relabelling, duplicates and self-loops dropped."""
+    und = rmat(scale, edgefactor, a, b, c, seed=seed, relabel=True, keep_arcs=True)
+    u, v = und.meta.pop("arcs")
+    g = digraph_from_arcs(1 << scale, u, v, name=f"rmatdir{scale}_ef{edgefactor}_s{seed}")
+    g.meta.update(family="rmat_directed", scale=scale, edgefactor=edgefactor, seed=seed)
+    return g
+
+
 def csr_from_networkx(G) -> CSR:
     """Small helper for tests: relabel a networkx graph 0..n-1 in sorted order."""
     nodes = sorted(G.nodes())
@@ -115,7 +165,7 @@ def erdos_renyi(n: int, avg_degree: float, seed: int) -> CSR:
 
 # ---------------------------------------------------------------------- R-MAT
 def rmat(scale: int, edgefactor: int = 16, a: float = 0.57, b: float = 0.19,
-         c: float = 0.19, seed: int = 1, relabel: bool = True) -> CSR:
+         c: float = 0.19, seed: int = 1, relabel: bool = True, keep_arcs: bool = False) -> CSR:
     """R-MAT (Chakrabarti et al.) with a seeded random vertex relabelling.
 
     edgefactor * 2**scale edges are sampled bit by bit from the quadrant
@@ -147,6 +197,8 @@ def rmat(scale: int, edgefactor: int = 16, a: float = 0.57, b: float = 0.19,
     g = csr_from_edges(n, src, dst, name=f"rmat{scale}_ef{edgefactor}_s{seed}")
     g.meta.update(family="rmat", scale=scale, edgefactor=edgefactor,
                   abcd=(a, b, c, 1 - a - b - c), seed=seed)
+    if keep_arcs:
+        g.meta["arcs"] = (src, dst)
     return g
 
 

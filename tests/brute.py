@@ -16,24 +16,26 @@ Neither function uses the Brandes recursion; both evaluate Eq. 1 of the paper
   Python integers keep every count exact.
 
 Both return exact Fractions (ordered-pair convention), the distance matrix
-(-1 = unreachable) and the path-count matrix.
+(-1 = unreachable) and the path-count matrix.  With directed=True an edge
+(a, b) is the arc a -> b only, and paths follow arcs.
 """
 from __future__ import annotations
 
 from fractions import Fraction
 
 
-def _adj_lists(n, edges):
+def _adj_lists(n, edges, directed=False):
     adj = [set() for _ in range(n)]
     for a, b in edges:
         if a != b:
             adj[a].add(b)
-            adj[b].add(a)
+            if not directed:
+                adj[b].add(a)
     return [sorted(x) for x in adj]
 
 
-def bc_by_paths(n, edges):
-    adj = _adj_lists(n, edges)
+def bc_by_paths(n, edges, directed=False):
+    adj = _adj_lists(n, edges, directed)
     # best[s][t] = (length, count, through-count list)
     dist = [[-1] * n for _ in range(n)]
     cnt = [[0] * n for _ in range(n)]
@@ -69,12 +71,13 @@ def bc_by_paths(n, edges):
     return bc, dist, cnt
 
 
-def bc_by_walks(n, edges):
+def bc_by_walks(n, edges, directed=False):
     A = [[0] * n for _ in range(n)]
     for a, b in edges:
         if a != b:
             A[a][b] = 1
-            A[b][a] = 1
+            if not directed:
+                A[b][a] = 1
     dist = [[-1] * n for _ in range(n)]
     cnt = [[0] * n for _ in range(n)]
     P = [[1 if i == j else 0 for j in range(n)] for i in range(n)]  # A^0

@@ -290,6 +290,8 @@ MUTATIONS = {
     "sigma_one_term": ("} else if (__builtin_add_overflow(su, w->sig_u[v], &su)) {",
                        "} else if ((su = w->sig_u[v]), 0) {"),
     "forward_order": ("for (int64_t k = w->n_reached - 1; k >= 0; --k) {", "for (int64_t k = 0; k < w->n_reached; ++k) {"),
+    "sigma_over_out_arcs": ("for (int64_t e = w->in_row_ptr[t]; e < w->in_row_ptr[t + 1]; ++e) {\n            const int32_t v = w->in_col[e];",
+                            "for (int64_t e = w->row_ptr[t]; e < w->row_ptr[t + 1]; ++e) {\n            const int32_t v = w->col[e];"),
     "distance_step": ("w->dist[x] = w->dist[v] + 1;\n                w->order", "w->dist[x] = w->dist[v] + 2;\n                w->order"),
 }
 
@@ -314,6 +316,11 @@ def test_planted_mistake_is_caught(name, monkeypatch):
                 edges = [(a, b) for a, b in itertools.combinations(range(n), 2) if rng.random() < 0.45]
                 bcx, dist, cnt = bc_by_walks(n, edges)
                 _check_against_exact(n, edges, bcx, dist, cnt)
+            # the directed pins (some mistakes only show when arcs are one-way)
+            from test_oracle_directed import check_directed_against_exact, random_digraph_trials
+            for n, arcs in random_digraph_trials(60, seed=7, nmax=8):
+                bcx, dist, cnt = bc_by_walks(n, arcs, directed=True)
+                check_directed_against_exact(n, arcs, bcx, dist, cnt)
         except AssertionError:
             caught = True
         monkeypatch.setattr(oracle, "_lib", None)
