@@ -211,6 +211,19 @@ def profile_summary(args) -> str:
     return "\n".join(lines) + "\n"
 
 
+def traversed_edges(g, srcs) -> float:
+    """Work of a run in edges x sources: the edge count of each source's own
+    graph (a block-diagonal union counts only the block the source is in)."""
+    off = getattr(g, "vtx_offsets", None)
+    if off is None or len(off) <= 2:
+        return float(g.m) * len(srcs)
+    off = np.asarray(off, dtype=np.int64)
+    rp = np.asarray(g.row_ptr, dtype=np.int64)
+    m_g = (rp[off[1:]] - rp[off[:-1]]) // 2
+    gi = np.searchsorted(off, np.asarray(srcs, dtype=np.int64), side="right") - 1
+    return float(m_g[gi].sum())
+
+
 def _cpu_info():
     model = ""
     try:
@@ -243,7 +256,7 @@ def cpu_baseline(g, srcs, workload, seconds):
         oracle.bc(g, srcs[k:k + 1])
         k += 1
     el1 = time.perf_counter() - t
-    one = g.m * k / el1 / 1e9
+    one = traversed_edges(g, srcs[:k]) / el1 / 1e9
     # all threads: rounds of `threads` sources (one per thread) while time remains
     per = el1 / k
     rounds = max(1, int((seconds / 2) / max(per, 1e-9)))
@@ -254,7 +267,7 @@ def cpu_baseline(g, srcs, workload, seconds):
     t = time.perf_counter()
     oracle.bc_sliced(g, srcs[lo:hi], threads=threads)
     elp = time.perf_counter() - t
-    many = g.m * (hi - lo) / elp / 1e9
+    many = traversed_edges(g, srcs[lo:hi]) / elp / 1e9
     log(f"[bench] oracle: 1 core {k} sources in {el1:.1f}s -> {one:.4f} GTEPS; {threads} threads {hi - lo} "
         f"sources in {elp:.1f}s -> {many:.4f} GTEPS ({model}, {ncpu} CPUs, {avail} usable)")
     return {"value": round(many, 6), "unit": "GTEPS", "cores": threads, "kind": "oracle",
@@ -283,6 +296,8 @@ def main():
     ap.add_argument("--sources", type=int, default=0, help="use only the first N sources (profiling runs)")
     ap.add_argument("--no-graphs", action="store_true", help="launch level steps one by one")
     ap.add_argument("--grid", type=int, default=0, help="workgroups per step launch (0 = library default)")
+    ap.add_argument("--lanes-per-entry", type=float, default=0.0,
+                    help="entry-by-source summation threshold of the batched engine (0 = library default, <0 = off)")
     ap.add_argument("--no-tune", action="store_true", help="skip bc_autotune (default: tune on the first 512 sources)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes 3 times (counter calibration)")
@@ -371,15 +386,17 @@ def main():
     tuned = None
     if not args.no_tune:
         t = time.time()
-        tuned = G.autotune(srcs[:TUNE_SOURCES], batch=64, policy=pol, grid_blocks=args.grid, flags=gflags)
+        tuned = G.autotune(srcs[:TUNE_SOURCES], batch=64, policy=pol, grid_blocks=args.grid, flags=gflags,
+                           lanes_per_entry=args.lanes_per_entry)
         gflags |= b.BC_RUN_TUNED
         log(f"[bench] autotuned on {min(TUNE_SOURCES, len(srcs))} sources in {time.time() - t:.1f}s: {tuned}")
     wall, gpu_ms, stats = timed(srcs, args.steps, args.warmup, batch=64, policy=pol, flags=gflags,
-                                grid_blocks=args.grid)
+                                grid_blocks=args.grid, lanes_per_entry=args.lanes_per_entry)
     st = stats[-1]
     headline_bits = G.scores().copy()
     ms_step = wall * 1e3 / args.steps
-    gteps = g.m * len(srcs) * args.steps / wall / 1e9
+    work = traversed_edges(g, srcs)
+    gteps = work * args.steps / wall / 1e9
     launches = sum(s["launches"] for s in stats)
     # dominant kernel: the 64-bit (batch_step<0>) or FP64 (batch_step<1>)
     # path-count pass with more device time.  The library times each pass
@@ -413,9 +430,9 @@ def main():
     heur = None
     if args.heuristic_steps > 0 and pol == b.BC_POLICY_MLP:
         hw, _, hst = timed(srcs, args.heuristic_steps, 1, batch=64, policy=b.BC_POLICY_HEURISTIC, flags=gflags,
-                           grid_blocks=args.grid)
+                           grid_blocks=args.grid, lanes_per_entry=args.lanes_per_entry)
         same = bool(np.array_equal(G.scores().view(np.uint64), headline_bits.view(np.uint64)))
-        hg = g.m * len(srcs) * args.heuristic_steps / hw / 1e9
+        hg = work * args.heuristic_steps / hw / 1e9
         heur = {"value": round(hg, 4), "unit": "GTEPS", "steps": args.heuristic_steps,
                 "ms_per_step": round(hw * 1e3 / args.heuristic_steps, 3), "same_score_bits": same,
                 "learned_over_heuristic": round(gteps / hg, 4), "variants": hst[-1]["variant_levels"]}
@@ -435,9 +452,10 @@ def main():
                 P.load_policy(np.load(args.weights))
             pw, pg, pst = timed(ps, 1, 1, H=P, batch=1, policy=pol,
                                 flags=b.BC_RUN_NO_GRAPHS if args.no_graphs else 0)
-        plain = {"value": round(g.m * len(ps) / pw / 1e9, 4), "unit": "GTEPS", "ms_per_step": round(pw * 1e3, 2),
+        pg_teps = traversed_edges(g, ps) / pw / 1e9
+        plain = {"value": round(pg_teps, 4), "unit": "GTEPS", "ms_per_step": round(pw * 1e3, 2),
                  "sources": int(len(ps)), "variants": pst[-1]["variant_levels"],
-                 "batched_over_plain": round(gteps / (g.m * len(ps) / pw / 1e9), 2)}
+                 "batched_over_plain": round(gteps / pg_teps, 2)}
         log(f"[bench] plain: {pw * 1e3:.1f} ms for {len(ps)} sources, {plain['value']} GTEPS; phase ms",
             [round(x, 1) for x in pst[-1]["phase_ms"][1:6]], "variant ms", [round(x, 1) for x in pst[-1]["variant_ms"]])
 

@@ -56,6 +56,7 @@ const char *bc_last_error(void);
 #define BC_INPUT_DEVICE        0x1u  /* row_ptr / col_idx are device pointers   */
 #define BC_SKIP_SYMMETRY_CHECK 0x2u  /* caller guarantees symmetric arcs        */
 #define BC_KEEP_ORDER          0x4u  /* no internal hub-first relabelling        */
+#define BC_DIRECTED            0x8u  /* arcs are directed (see below)            */
 
 /*
  * Build a graph handle from a CSR adjacency (Section "Space Complexity":
@@ -81,6 +82,17 @@ const char *bc_last_error(void);
  * sources of one batch reach most vertices at the same depth.  Every call of this interface takes and returns the
  * caller's vertex ids and source positions; only the order in which
  * floating-point terms of a sum are added can differ.
+ * Directed graphs (BC_DIRECTED): the paper converts every input to an
+ * undirected graph (Section "Experiments and Results"), but Eq. 1 and Eq. 2
+ * are defined for paths that follow arcs, so a directed graph is accepted
+ * as well: col_idx[row_ptr[v] .. row_ptr[v+1]) are the heads of the arcs
+ * leaving v (strictly ascending, no self-loops, no symmetry required).  The
+ * library builds the in-arcs itself; the forward phase pushes over out-arcs
+ * and pulls (discovery, path counts) over in-arcs, the backward phase pulls
+ * dependencies from successors over out-arcs.  Such a handle keeps the
+ * caller's numbering and source order (BC_KEEP_ORDER is implied) and always
+ * runs the batched engine (batch = 1 means one source per traversal there).
+ * Scores are raw sums over ordered pairs, as for undirected graphs.
  * Errors: BC_ERR_INVALID_ARG (NULL pointers, negative sizes),
  * BC_ERR_INVALID_GRAPH (validation failure; bc_last_error names the rule),
  * BC_ERR_OUT_OF_MEMORY, BC_ERR_DEVICE.  *out is set only on success.
@@ -95,7 +107,8 @@ bc_status bc_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr,
  * No arc may cross a block boundary (BC_ERR_INVALID_GRAPH otherwise).  Since
  * the components are independent, the BC of the union restricted to block g
  * equals the BC of graph g; batches of sources never mix graphs.  Other
- * arguments as in bc_graph_create.
+ * arguments as in bc_graph_create, except that BC_DIRECTED is refused
+ * (BC_ERR_NOT_SUPPORTED) when n_graphs > 1.
  */
 bc_status bc_graph_create_multi(int32_t n_graphs, const int32_t *vtx_offsets, int32_t n,
                                 int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
@@ -159,7 +172,13 @@ typedef struct bc_run_options {
     int32_t chunk_steps;  /* level steps per captured hipGraph (0 = default) */
     int64_t sigma_limit;  /* test hook: treat path counts above this as overflow
                              (0 = none, i.e. 2^64 - 1)                       */
-    int32_t reserved[8];
+    float lanes_per_entry;/* batched path-count and backward steps: a group of level
+                             entries whose entries carry at most this many sources
+                             on average is summed one thread per (entry, source)
+                             pair instead of one wavefront lane per source
+                             (0 = default 4; negative = never).  Same results bit
+                             for bit either way; speed only.                */
+    int32_t reserved[7];
 } bc_run_options;
 
 /* Fill *opt with defaults (all zero fields, i.e. autotuned/automatic). */
@@ -188,7 +207,9 @@ bc_status bc_run(bc_graph *g, const int32_t *sources, int64_t n_sources,
  * dimension at a time starting from base (NULL = defaults): batch K in
  * {64, 32, 16}, policy {heuristic, learned when weights are loaded},
  * workgroups per step {default, 1/2, 1/4}, level steps per captured chunk
- * {8, 16, 32}, push WPV degree threshold {12, 24, 48}.  Each candidate is
+ * {8, 16, 32}, push WPV degree threshold {12, 24, 48}, sources per entry
+ * below which groups are summed by (entry, source) pairs {never, 2, 4, 12}.
+ * Each candidate is
  * timed (host clock around a synchronised run, best of two) after one
  * untimed run that builds its captured graphs; a value replaces the current
  * one only when it is at least 2 % faster.  The result goes to *best

@@ -26,6 +26,7 @@ STATUS = {0: "BC_OK", 1: "BC_ERR_INVALID_ARG", 2: "BC_ERR_INVALID_GRAPH", 3: "BC
 BC_INPUT_DEVICE = 0x1
 BC_SKIP_SYMMETRY_CHECK = 0x2
 BC_KEEP_ORDER = 0x4
+BC_DIRECTED = 0x8
 BC_RUN_ACCUMULATE = 0x1
 BC_RUN_NO_GRAPHS = 0x2
 BC_RUN_FORCE_F64 = 0x4
@@ -63,7 +64,8 @@ class RunOptions(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("batch", ctypes.c_int32), ("policy", ctypes.c_int32),
                 ("alpha", ctypes.c_float), ("beta", ctypes.c_float), ("wpv_degree", ctypes.c_float),
                 ("grid_blocks", ctypes.c_int32), ("chunk_steps", ctypes.c_int32),
-                ("sigma_limit", ctypes.c_int64), ("reserved", ctypes.c_int32 * 8)]
+                ("sigma_limit", ctypes.c_int64), ("lanes_per_entry", ctypes.c_float),
+                ("reserved", ctypes.c_int32 * 7)]
 
 
 class Detail(ctypes.Structure):
@@ -182,12 +184,13 @@ def _stream(stream):
 
 
 def make_options(batch=0, policy=BC_POLICY_AUTO, flags=0, alpha=0.0, beta=0.0, wpv_degree=0.0,
-                 grid_blocks=0, chunk_steps=0, sigma_limit=0) -> RunOptions:
+                 grid_blocks=0, chunk_steps=0, sigma_limit=0, lanes_per_entry=0.0) -> RunOptions:
     o = RunOptions()
     lib().bc_run_options_init(ctypes.byref(o))
     o.flags, o.batch, o.policy = flags, batch, policy
     o.alpha, o.beta, o.wpv_degree = alpha, beta, wpv_degree
     o.grid_blocks, o.chunk_steps, o.sigma_limit = grid_blocks, chunk_steps, sigma_limit
+    o.lanes_per_entry = lanes_per_entry
     return o
 
 
@@ -312,7 +315,8 @@ def bc_autotune(h, sample, options: RunOptions | None = None, stream=None) -> di
     _check(lib().bc_autotune(h, _p(s), s.size, ctypes.byref(options) if options is not None else None,
                              ctypes.byref(best), _stream(stream)))
     return {"batch": best.batch, "policy": best.policy, "grid_blocks": best.grid_blocks,
-            "chunk_steps": best.chunk_steps, "wpv_degree": best.wpv_degree}
+            "chunk_steps": best.chunk_steps, "wpv_degree": best.wpv_degree,
+            "lanes_per_entry": best.lanes_per_entry}
 
 
 def bc_load_policy(h, weights):
@@ -386,6 +390,8 @@ class Graph:
     def __init__(self, csr=None, row_ptr=None, col_idx=None, vtx_offsets=None, flags: int = 0):
         if csr is not None:
             row_ptr, col_idx = csr.row_ptr, csr.col_idx
+            if getattr(csr, "directed", False):
+                flags |= BC_DIRECTED
             if vtx_offsets is None and getattr(csr, "vtx_offsets", None) is not None and len(csr.vtx_offsets) > 2:
                 vtx_offsets = csr.vtx_offsets
         if vtx_offsets is not None:

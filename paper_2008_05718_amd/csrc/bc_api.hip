@@ -163,6 +163,9 @@ struct bc_graph {
     std::vector<int32_t> voff;     // host copy of vertex offsets
     std::vector<int32_t> vgraph;   // not kept (large); block lookups use voff
     int32_t *row_ptr = nullptr, *col = nullptr;
+    // directed graphs: row_ptr / col are the out-arcs, these the in-arcs
+    bool directed = false;
+    int32_t *in_row_ptr = nullptr, *in_col = nullptr;
     int64_t nonisolated = 0;
     // vertices of degree > kSegBatched (ascending) and their segment prefix
     // sums; p_*: the same for the plain engine's kSegPlain
@@ -261,7 +264,7 @@ extern "C" void bc_destroy(bc_graph *g) {
     (void)hipDeviceSynchronize();
     free_parts(g);
     free_graphs(g);
-    void *dev[] = {g->row_ptr, g->col, g->bc, g->ctl, g->p_d, g->p_queue, g->p_level_off, g->p_shift,
+    void *dev[] = {g->row_ptr, g->col, g->in_row_ptr, g->in_col, g->bc, g->ctl, g->p_d, g->p_queue, g->p_level_off, g->p_shift,
                    g->p_sig, g->p_chat, g->b_vn, g->b_fw0, g->b_fw1, g->b_lq_vtx, g->b_lq_mask,
                    g->b_level_off, g->b_delta, g->b_chat, g->b_shift, g->b_maxexp, g->b_lane_src,
                    g->b_sigma, g->b_gstart, g->b_gbase, g->inv_dev, g->bc_out,
@@ -377,7 +380,12 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
         voff = {0, n};
     }
     const bool on_dev = flags & BC_INPUT_DEVICE;
+    const bool directed = flags & BC_DIRECTED;
+    if (directed && n_graphs > 1)
+        return fail(BC_ERR_NOT_SUPPORTED, "directed graphs are supported one per handle (bc_graph_create)");
+    if (directed) flags |= BC_SKIP_SYMMETRY_CHECK | BC_KEEP_ORDER;
     bc_graph *g = new bc_graph();
+    g->directed = directed;
     g->n = n;
     g->nnz = nnz;
     g->n_graphs = n_graphs;
@@ -453,6 +461,24 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
     {
         std::vector<int32_t> rp((size_t)n + 1);
         CR_TRY(hipMemcpy(rp.data(), g->row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost));
+        // directed: the in-arcs (transpose), rows ascending; a vertex is
+        // classified by the larger of its out- and in-degree
+        std::vector<int32_t> cdeg((size_t)n);
+        for (int32_t v = 0; v < n; ++v) cdeg[v] = rp[v + 1] - rp[v];
+        if (directed) {
+            std::vector<int32_t> col((size_t)nnz), irp((size_t)n + 1, 0), icol((size_t)nnz);
+            if (nnz) CR_TRY(hipMemcpy(col.data(), g->col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToHost));
+            for (int64_t k = 0; k < nnz; ++k) ++irp[(size_t)col[k] + 1];
+            for (int32_t v = 0; v < n; ++v) irp[v + 1] += irp[v];
+            std::vector<int32_t> fill(irp.begin(), irp.end() - 1);
+            for (int32_t u = 0; u < n; ++u)  // sources in ascending order: every in-row comes out sorted
+                for (int32_t k = rp[u]; k < rp[u + 1]; ++k) icol[fill[col[k]]++] = u;
+            for (int32_t v = 0; v < n; ++v) cdeg[v] = std::max(cdeg[v], irp[v + 1] - irp[v]);
+            CR_TRY(dalloc(&g->in_row_ptr, (size_t)n + 1, &g->acct));
+            CR_TRY(dalloc(&g->in_col, (size_t)nnz, &g->acct));
+            CR_TRY(hipMemcpy(g->in_row_ptr, irp.data(), sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice));
+            if (nnz) CR_TRY(hipMemcpy(g->in_col, icol.data(), sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice));
+        }
         if (!(flags & BC_KEEP_ORDER) && n > 0 && nnz > 0) {
             // hub-first renumbering inside each graph: vertices of degree at
             // least twice the graph's mean (over vertices with arcs) first, by
@@ -515,15 +541,17 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
         }
         // vertices heavier than one segment, for the split load balancing
         // (one list per engine segment size)
+        if (!directed)  // after any renumbering
+            for (int32_t v = 0; v < n; ++v) cdeg[v] = rp[v + 1] - rp[v];
         int64_t cost_units = 0;
-        for (int32_t v = 0; v < n; ++v) cost_units += entry_cost(rp[v + 1] - rp[v]);
+        for (int32_t v = 0; v < n; ++v) cost_units += entry_cost(cdeg[v]);
         g->cost_units = cost_units;
         for (int which = 0; which < 2; ++which) {
             const int seg = which == 0 ? kSegBatched : kSegPlain;
             std::vector<int32_t> hv, hs(1, 0);
             int64_t segs = 0;
             for (int32_t v = 0; v < n; ++v) {
-                const int32_t deg = rp[v + 1] - rp[v];
+                const int32_t deg = cdeg[v];
                 if (deg > seg) {
                     hv.push_back(v);
                     segs += (deg + seg - 1) / seg;
@@ -876,6 +904,7 @@ static PolicyArgs policy_args(const bc_graph *g, const bc_run_options &o) {
     p.alpha = o.alpha > 0 ? o.alpha : 14.0f;
     p.beta = o.beta > 0 ? o.beta : 24.0f;
     p.wpv_degree = o.wpv_degree > 0 ? o.wpv_degree : 24.0f;
+    p.item_lanes = o.lanes_per_entry > 0 ? o.lanes_per_entry : (o.lanes_per_entry < 0 ? -1.0f : 4.0f);
     p.has_mlp = g->has_mlp ? 1 : 0;
     p.mlp = g->mlp;
     return p;
@@ -960,6 +989,9 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
     ga.nnz_lo = (int32_t)g->nnz;
     ga.row_ptr = g->row_ptr;
     ga.col = g->col;
+    ga.directed = g->directed ? 1 : 0;
+    ga.in_row_ptr = g->directed ? g->in_row_ptr : g->row_ptr;
+    ga.in_col = g->directed ? g->in_col : g->col;
     ga.nonisolated = g->nonisolated;
     ga.hv_vtx = g->hv_vtx;
     ga.hv_seg = g->hv_seg;
@@ -1131,6 +1163,10 @@ static bc_status resolve_cfg(const bc_graph *g, const bc_run_options &o, int64_t
     cfg->engine = o.batch == 1 ? 1 : 64;
     if (o.batch == 0) cfg->engine = ns >= 2 ? 64 : 1;
     cfg->lanes = (o.batch >= 8) ? o.batch : 64;
+    if (g->directed && cfg->engine == 1) {  // one source per traversal on the batched engine
+        cfg->engine = 64;
+        cfg->lanes = 1;
+    }
     switch (o.policy) {
     case BC_POLICY_AUTO: cfg->policy = g->has_mlp ? POL_MLP : POL_HEUR; break;
     case BC_POLICY_HEURISTIC: cfg->policy = POL_HEUR; break;
@@ -1271,7 +1307,9 @@ static bc_status ensure_replicas(bc_graph *g) {
     for (int r = 0; r < R; ++r) {
         SubPart &pt = parts[r];
         bc_status s = bc_graph_create(g->n, g->nnz, g->row_ptr, g->col,
-                                      BC_INPUT_DEVICE | BC_SKIP_SYMMETRY_CHECK | BC_KEEP_ORDER, &pt.h);
+                                      BC_INPUT_DEVICE | BC_SKIP_SYMMETRY_CHECK | BC_KEEP_ORDER |
+                                          (g->directed ? BC_DIRECTED : 0u),
+                                      &pt.h);
         if (s == BC_OK && !w.empty()) s = bc_load_policy(pt.h, w.data(), kMlpParams);
         if (s == BC_OK && hipExtStreamCreateWithCUMask(&pt.stream, (uint32_t)cu_mask.size(), cu_mask.data()) != hipSuccess)
             pt.stream = nullptr;
@@ -1582,6 +1620,7 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
         if (o.grid_blocks == 0) o.grid_blocks = g->tuned.grid_blocks;
         if (o.chunk_steps == 0) o.chunk_steps = g->tuned.chunk_steps;
         if (o.wpv_degree <= 0.0f) o.wpv_degree = g->tuned.wpv_degree;
+        if (o.lanes_per_entry == 0.0f) o.lanes_per_entry = g->tuned.lanes_per_entry;
         o.flags &= ~BC_RUN_TUNED;
     }
     if (use_parts(g, o, sources ? n_sources : g->n)) {
@@ -2019,6 +2058,7 @@ extern "C" bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_s
     if (cur.grid_blocks == 0) cur.grid_blocks = c0.grid;
     if (cur.chunk_steps == 0) cur.chunk_steps = c0.chunk;
     if (cur.wpv_degree <= 0.0f) cur.wpv_degree = 24.0f;
+    if (cur.lanes_per_entry == 0.0f) cur.lanes_per_entry = 4.0f;
     hipStream_t st = (hipStream_t)stream;
     // a warm-up run (builds the captured graphs), then the best of two timed runs
     auto time_one = [&](const bc_run_options &o, double *ms) -> bc_status {
@@ -2038,7 +2078,7 @@ extern "C" bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_s
     s = time_one(cur, &best_ms);
     if (s != BC_OK) return s;
     const int dflt_grid = cur.grid_blocks;
-    for (int dim = 0; dim < 5; ++dim) {
+    for (int dim = 0; dim < 6; ++dim) {
         std::vector<bc_run_options> cand;
         bc_run_options c = cur;
         if (dim == 0) {
@@ -2051,8 +2091,11 @@ extern "C" bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_s
             for (int d : {1, 2, 4}) { c.grid_blocks = std::max(1, dflt_grid / d); cand.push_back(c); }
         } else if (dim == 3) {
             for (int k : {8, 16, 32}) { c.chunk_steps = k; cand.push_back(c); }
-        } else {
+        } else if (dim == 4) {
             for (float w : {12.0f, 24.0f, 48.0f}) { c.wpv_degree = w; cand.push_back(c); }
+        } else {
+            if (cur.batch == 1) continue;
+            for (float x : {-1.0f, 2.0f, 4.0f, 12.0f}) { c.lanes_per_entry = x; cand.push_back(c); }
         }
         for (const bc_run_options &x : cand) {
             if (std::memcmp(&x, &cur, sizeof(x)) == 0) continue;

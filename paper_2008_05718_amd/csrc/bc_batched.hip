@@ -46,18 +46,19 @@ __device__ __forceinline__ void push_arcs_wave(const BatchArgs &a, unsigned long
     for (int eb = a0; eb < a1; eb += kWave) {
         const int e = eb + lane_id();
         bool newly = false;
-        int w = 0, dw = 0;
+        int w = 0, cw = 0;
         if (e < a1) {
             w = col[e];
             const VisNext x = a.vn[w];
             const unsigned long long add = f & ~x.vis & ~x.nxt;
             if (add) newly = atomicOr(&a.vn[w].nxt, add) == 0ull;
             if (newly) {
-                dw = rp[w + 1] - rp[w];
+                const int dw = rp[w + 1] - rp[w];
                 my_edges += (unsigned)dw;
+                cw = class_deg(a.g, w, dw);
             }
         }
-        stage_push(newly, w, dw, st, sn, c, a.lq_vtx, qe, a.lq_cap, a.hq, hq_base, &c->err, gr);
+        stage_push(newly, w, cw, st, sn, c, a.lq_vtx, qe, a.lq_cap, a.hq, hq_base, &c->err, gr);
     }
 }
 
@@ -193,6 +194,29 @@ struct SigCounters {
     int maxe = INT_MIN, mine = INT_MAX;
 };
 
+// New vertex w (queue position p, visited/next words vis/m, degree deg)
+// joins the level-(l+1) frontier; called by one thread per entry.
+__device__ __forceinline__ void sig_publish(const BatchArgs &a, Tagged *fw_nxt, uint32_t T1, int p, int w,
+                                            unsigned long long vis, unsigned long long m, int deg,
+                                            unsigned long long lmask, SigCounters &sc) {
+    VisNext y;
+    y.vis = vis | m;
+    y.nxt = 0ull;
+    a.vn[w] = y;
+    Tagged tg;
+    tg.mask = m;
+    tg.tag = T1;
+    fw_nxt[w] = tg;
+    a.lq_mask[p] = m;
+    sc.edges += (unsigned)deg;
+    sc.act |= m;
+    sc.lent += (unsigned)__popcll(m);
+    if ((y.vis & lmask) == lmask) {
+        sc.full_n += 1;
+        sc.full_m += (unsigned)deg;
+    }
+}
+
 // Store the path counts of new vertex w (queue position p, visited/next words
 // vis/m, degree deg) and publish it as part of the level-(l+1) frontier.
 template <int MODE>
@@ -214,24 +238,7 @@ __device__ __forceinline__ void sig_finalize(const BatchArgs &a, Tagged *fw_nxt,
             sc.mine = min(sc.mine, ex);
         }
     }
-    if (lane == 0) {
-        VisNext y;
-        y.vis = vis | m;
-        y.nxt = 0ull;
-        a.vn[w] = y;
-        Tagged tg;
-        tg.mask = m;
-        tg.tag = T1;
-        fw_nxt[w] = tg;
-        a.lq_mask[p] = m;
-        sc.edges += (unsigned)deg;
-        sc.act |= m;
-        sc.lent += (unsigned)__popcll(m);
-        if ((y.vis & lmask) == lmask) {
-            sc.full_n += 1;
-            sc.full_m += (unsigned)deg;
-        }
-    }
+    if (lane == 0) sig_publish(a, fw_nxt, T1, p, w, vis, m, deg, lmask, sc);
 }
 
 // Dependencies of vertex v (entry mask Mf, live lanes M) from the sum acc:
@@ -270,6 +277,27 @@ __device__ __forceinline__ int packed_owner(int incl, int ai) {
     return o;
 }
 
+// Index of the j-th set bit (j counted from 0) of m; m has more than j bits.
+__device__ __forceinline__ int nth_set_bit(unsigned long long m, int j) {
+    for (; j > 0; --j) m &= m - 1;
+    return __ffsll(m) - 1;
+}
+
+// Entry-lane items: when the entries of a group carry few sources each, the
+// per-source sums run one thread per (entry, source) pair instead of one
+// wavefront lane per source.  Each thread then scans its entry's adjacency
+// on its own and reads only its source's value of each matched neighbour, so
+// the matched neighbours of single-source entries are no longer visited one
+// after another by the whole wavefront.  Every sum is still taken over the
+// entry's arcs in CSR order with the same operations, so the results are the
+// same bits as in the per-lane form.
+//   cnt   this lane's entry's item count (0 for entries handled elsewhere)
+// Returns the group's items; item it belongs to entry packed_owner(incl, it).
+__device__ __forceinline__ int group_items(int cnt, int &incl) {
+    incl = wave_incl_scan(cnt);
+    return __shfl(incl, 63);
+}
+
 #ifndef BC_PACK
 #define BC_PACK 64
 #endif
@@ -282,9 +310,10 @@ constexpr int kPack = BC_PACK;    // entries of degree <= kPack share 64-arc sca
 template <int MODE>
 __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__restrict__ fw_cur, Tagged *fw_nxt,
                                           uint32_t T, int qs, int i0, int i1, int sh, unsigned long long lmask,
-                                          SigCounters &sc) {
-    const int32_t *__restrict__ rp = a.g.row_ptr;
-    const int32_t *__restrict__ col = a.g.col;
+                                          SigCounters &sc, int l, int *s_emax, int *s_emin) {
+    // predecessors: the in-arcs (the adjacency itself for undirected graphs)
+    const int32_t *__restrict__ rp = a.g.in_row_ptr;
+    const int32_t *__restrict__ col = a.g.in_col;
     const int lane = lane_id();
     const int i = i0 + lane;
     const int ne = i1 - i0;
@@ -292,7 +321,9 @@ __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__re
     const int p = qs + i;
     const int w = valid ? a.lq_vtx[p] : 0;
     const int e0 = valid ? rp[w] : 0;
-    const int deg = valid ? rp[w + 1] - e0 : 0;
+    const int na = valid ? rp[w + 1] - e0 : 0;  // arcs to scan
+    const int od = (valid && a.g.directed) ? a.g.row_ptr[w + 1] - a.g.row_ptr[w] : na;  // out-degree
+    const int deg = a.g.directed ? (valid ? max(na, od) : 0) : na;  // class degree
     const bool light = valid && deg <= kPack;
     const bool medium = valid && deg > kPack && deg <= kSeg;
     unsigned long long vis = 0, nxt = 0;
@@ -301,7 +332,57 @@ __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__re
         vis = x.vis;
         nxt = x.nxt;
     }
-    const int dl = light ? deg : 0;
+    // few sources per light entry: one thread per (entry, source) pair
+    int iincl = 0;
+    const int n_items = group_items(light ? __popcll(nxt) : 0, iincl);
+    const int n_light = __popcll(__ballot(light));
+    if (n_light > 0 && (float)n_items <= a.p.item_lanes * (float)n_light) {
+        for (int base = 0; base < n_items; base += kWave) {
+            const int it = base + lane;
+            const int o = packed_owner(iincl, min(it, n_items - 1));
+            const int wo = __shfl(w, o), e0o = __shfl(e0, o), dgo = __shfl(na, o), io = __shfl(iincl, o);
+            const unsigned long long mo = shfl_u64(nxt, o);
+            if (it < n_items) {
+                const int k = nth_set_bit(mo, it - (io - __popcll(mo)));
+                const int shk = MODE ? a.shift[(size_t)l * kLanes + k] : 0;
+                unsigned long long ilo = 0, ihi = 0;
+                double iacc = 0.0;
+                unsigned matched = 0;
+                for (int e = e0o; e < e0o + dgo; ++e) {
+                    const int u = col[e];
+                    const Tagged F = fw_cur[u];
+                    if (F.tag == T && ((F.mask >> k) & 1ull)) {
+                        const unsigned long long v = a.sigma[(size_t)u * kLanes + k];
+                        if (MODE == 0) {
+                            ilo += v;
+                            ihi += (ilo < v) ? 1ull : 0ull;
+                        } else {
+                            iacc += ldexp(as_f64(v), -shk);
+                        }
+                        ++matched;
+                    }
+                }
+                sc.larcs += matched;
+                sc.pairs += matched;
+                sc.arcs += (unsigned)dgo;
+                const size_t at = (size_t)wo * kLanes + k;
+                if (MODE == 0) {
+                    a.sigma[at] = ilo;
+                    if (ihi != 0 || ilo > a.sigma_limit) sc.ovf |= 1ull << k;
+                } else {
+                    a.sigma[at] = as_u64(iacc);
+                    if (iacc > 0.0) {
+                        int ex;
+                        frexp(iacc, &ex);
+                        atomicMax(&s_emax[k], ex);
+                        atomicMin(&s_emin[k], ex);
+                    }
+                }
+            }
+        }
+        if (light) sig_publish(a, fw_nxt, T + 1u, p, w, vis, nxt, od, lmask, sc);
+    } else {
+    const int dl = light ? na : 0;
     const int incl = wave_incl_scan(dl);
     const int off = incl - dl;
     const int total = __shfl(incl, 63);
@@ -313,7 +394,7 @@ __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__re
             if (__builtin_amdgcn_readlane((int)light, e)) {
                 sig_finalize<MODE>(a, fw_nxt, T + 1u, __builtin_amdgcn_readlane(p, e),
                                    __builtin_amdgcn_readlane(w, e), readlane_u64(vis, e), readlane_u64(nxt, e),
-                                   __builtin_amdgcn_readlane(deg, e), lo, hi, accd, lmask, sc);
+                                   __builtin_amdgcn_readlane(od, e), lo, hi, accd, lmask, sc);
             }
             lo = hi = 0;
             accd = 0.0;
@@ -361,20 +442,21 @@ __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__re
         }
     }
     finalize_upto(ne);
+    }
     // medium-degree entries: one wavefront-wide scan each
     unsigned long long mm = __ballot(medium);
     while (mm) {
         const int j = __ffsll(mm) - 1;
         mm &= mm - 1;
         const int wj = __builtin_amdgcn_readlane(w, j);
-        const int a0 = __builtin_amdgcn_readlane(e0, j), dj = __builtin_amdgcn_readlane(deg, j);
+        const int a0 = __builtin_amdgcn_readlane(e0, j), dj = __builtin_amdgcn_readlane(na, j);
         const unsigned long long mj = readlane_u64(nxt, j);
-        lo = hi = 0;
-        accd = 0.0;
+        unsigned long long lo = 0, hi = 0;
+        double accd = 0.0;
         sig_arcs<MODE>(a, fw_cur, T, mj, a0, a0 + dj, sh, col, lo, hi, accd, sc.larcs, sc.pairs);
         if (lane == 0) sc.arcs += (unsigned)dj;
-        sig_finalize<MODE>(a, fw_nxt, T + 1u, __builtin_amdgcn_readlane(p, j), wj, readlane_u64(vis, j), mj, dj,
-                           lo, hi, accd, lmask, sc);
+        sig_finalize<MODE>(a, fw_nxt, T + 1u, __builtin_amdgcn_readlane(p, j), wj, readlane_u64(vis, j), mj,
+                           __builtin_amdgcn_readlane(od, j), lo, hi, accd, lmask, sc);
     }
 }
 
@@ -384,7 +466,7 @@ template <int MODE>
 __device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__restrict__ fb_nxt, Tagged *fb_cur,
                                           uint32_t TB, int qb, int i0, int i1, unsigned long long dead, int sh,
                                           int shn, unsigned long long &my_larcs, unsigned long long &my_arcs,
-                                          unsigned long long &my_pairs) {
+                                          unsigned long long &my_pairs, int l, bool has_next) {
     const int32_t *__restrict__ rp = a.g.row_ptr;
     const int32_t *__restrict__ col = a.g.col;
     const int lane = lane_id();
@@ -394,12 +476,56 @@ __device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__re
     const int p = qb + i;
     const int v = valid ? a.lq_vtx[p] : 0;
     const int e0 = valid ? rp[v] : 0;
-    const int deg = valid ? rp[v + 1] - e0 : 0;
+    const int na = valid ? rp[v + 1] - e0 : 0;  // successors: the out-arcs
+    const int deg = valid ? class_deg(a.g, v, na) : 0;
     const bool light = valid && deg <= kPack;
     const bool medium = valid && deg > kPack && deg <= kSeg;
     const unsigned long long Mf = (light || medium) ? a.lq_mask[p] : 0ull;
     const unsigned long long M = Mf & ~dead;
-    const int dl = (light && M) ? deg : 0;
+    // few sources per light entry: one thread per (entry, source) pair
+    int iincl = 0;
+    const int n_items = group_items(light ? __popcll(M) : 0, iincl);
+    const int n_light = __popcll(__ballot(light));
+    if (n_light > 0 && (float)n_items <= a.p.item_lanes * (float)n_light) {
+        for (int base = 0; base < n_items; base += kWave) {
+            const int it = base + lane;
+            const int o = packed_owner(iincl, min(it, n_items - 1));
+            const int vo = __shfl(v, o), e0o = __shfl(e0, o), dgo = __shfl(na, o), io = __shfl(iincl, o);
+            const unsigned long long mo = shfl_u64(M, o);
+            if (it < n_items) {
+                const int k = nth_set_bit(mo, it - (io - __popcll(mo)));
+                double iacc = 0.0;
+                unsigned matched = 0;
+                for (int e = e0o; e < e0o + dgo; ++e) {
+                    const int u = col[e];
+                    const Tagged F = fb_nxt[u];
+                    if (F.tag == TB + 1u && ((F.mask >> k) & 1ull)) {
+                        iacc += a.chat[(size_t)u * kLanes + k];
+                        ++matched;
+                    }
+                }
+                my_larcs += matched;
+                my_pairs += matched;
+                my_arcs += (unsigned)dgo;
+                const size_t at = (size_t)vo * kLanes + k;
+                const int shk = MODE ? a.shift[(size_t)l * kLanes + k] : 0;
+                const int shnk = (MODE && has_next) ? a.shift[(size_t)(l + 1) * kLanes + k] : 0;
+                const unsigned long long raw = a.sigma[at];
+                const double sv = MODE ? ldexp(as_f64(raw), -shk) : (double)raw;
+                double delta = sv * iacc;
+                if (MODE) delta = ldexp(delta, -shnk);
+                a.chat[at] = (1.0 + delta) / sv;
+                a.delta[at] = delta;
+            }
+        }
+        if (light) {
+            Tagged tg;
+            tg.mask = Mf;
+            tg.tag = TB;
+            fb_cur[v] = tg;
+        }
+    } else {
+    const int dl = (light && M) ? na : 0;
     const int incl = wave_incl_scan(dl);
     const int off = incl - dl;
     const int total = __shfl(incl, 63);
@@ -448,12 +574,13 @@ __device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__re
         }
     }
     finalize_upto(ne);
+    }
     unsigned long long mm = __ballot(medium);
     while (mm) {
         const int j = __ffsll(mm) - 1;
         mm &= mm - 1;
         const int vj = __builtin_amdgcn_readlane(v, j);
-        const int a0 = __builtin_amdgcn_readlane(e0, j), dj = __builtin_amdgcn_readlane(deg, j);
+        const int a0 = __builtin_amdgcn_readlane(e0, j), dj = __builtin_amdgcn_readlane(na, j);
         const unsigned long long Mj = readlane_u64(M, j);
         const double sm = Mj ? bwd_arcs(a, fb_nxt, TB + 1u, Mj, a0, a0 + dj, col, my_larcs, my_pairs) : 0.0;
         if (lane == 0) my_arcs += (unsigned)dj;
@@ -519,7 +646,8 @@ __device__ __forceinline__ void batch_begin(const BatchArgs &a, Ctl *c, int64_t 
             tg.mask = m;
             tg.tag = epoch;
             a.fw0[s] = tg;
-            s_tmp[j] = (unsigned long long)(a.g.row_ptr[s + 1] - a.g.row_ptr[s]);
+            const int od = a.g.row_ptr[s + 1] - a.g.row_ptr[s];
+            s_tmp[j] = (unsigned long long)(unsigned)od | ((unsigned long long)(unsigned)class_deg(a.g, s, od) << 32);
         }
     }
     if (MODE && t < kLanes) a.shift[t] = 0;
@@ -529,13 +657,13 @@ __device__ __forceinline__ void batch_begin(const BatchArgs &a, Ctl *c, int64_t 
         unsigned long long mf = 0;
         int nh = 0, segs = 0;
         for (int j = 0; j < cnt; ++j) {
-            const int deg = (int)s_tmp[j];
+            const int deg = (int)(uint32_t)s_tmp[j], cdeg = (int)(s_tmp[j] >> 32);
             mf += (unsigned long long)deg;
-            if (deg > kSeg) {  // heavy source: level-0 segments for the push
+            if (cdeg > kSeg) {  // heavy source: level-0 segments for the push
                 a.hq.pos[nh] = j;
                 a.hq.seg[nh] = segs;
                 a.hq.cnt[nh] = 0;
-                segs += n_segments(deg);
+                segs += n_segments(cdeg);
                 ++nh;
             }
         }
@@ -731,14 +859,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
                     const int u = a.lq_vtx[p];
                     const unsigned long long f = a.lq_mask[p] & act;
                     const int a0 = rp[u] + s * kSeg;
-                    const int a1 = min(rp[u + 1], a0 + kSeg);
+                    const int a1 = max(a0, min(rp[u + 1], a0 + kSeg));
                     if (lane == 0) my_arcs += (unsigned)(a1 - a0);
                     if (f) push_arcs_wave(a, f, a0, a1, rp, col, (uint32_t)qe, hqb, my_edges, st, sn, gr);
                 } else if (variant == V_PUSH_WPV) {
                     const int u = a.lq_vtx[qb + it];
                     const unsigned long long f = a.lq_mask[qb + it] & act;
                     const int e0 = rp[u], e1 = rp[u + 1];
-                    if (!f || e1 - e0 > kSeg) continue;  // heavy ones run as segments
+                    if (!f || class_deg(a.g, u, e1 - e0) > kSeg) continue;  // heavy ones run as segments
                     if (lane == 0) my_arcs += (unsigned)(e1 - e0);
                     push_arcs_wave(a, f, e0, e1, rp, col, (uint32_t)qe, hqb, my_edges, st, sn, gr);
                 } else {  // TPV: 64 frontier vertices per wavefront
@@ -747,36 +875,40 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
                     const int u = valid ? a.lq_vtx[qb + i] : 0;
                     const unsigned long long f = valid ? (a.lq_mask[qb + i] & act) : 0ull;
                     const int e0 = f ? rp[u] : 0;
-                    const int deg = f ? rp[u + 1] - e0 : 0;
-                    const int len = deg <= kLightDeg ? deg : 0;
-                    my_arcs += (unsigned)(deg <= kSeg ? deg : 0);
+                    const int od = f ? rp[u + 1] - e0 : 0;  // out-arcs to push over
+                    const int deg = f ? class_deg(a.g, u, od) : 0;
+                    const int len = deg <= kLightDeg ? od : 0;
+                    my_arcs += (unsigned)(deg <= kSeg ? od : 0);
                     const int maxlen = wave_max_i(len);
                     for (int t = 0; t < maxlen; ++t) {
                         bool newly = false;
-                        int w = 0, dw = 0;
+                        int w = 0, cw = 0;
                         if (t < len) {
                             w = col[e0 + t];
                             const VisNext x = a.vn[w];
                             const unsigned long long add = f & ~x.vis & ~x.nxt;
                             if (add) newly = atomicOr(&a.vn[w].nxt, add) == 0ull;
                             if (newly) {
-                                dw = rp[w + 1] - rp[w];
+                                const int dw = rp[w + 1] - rp[w];
                                 my_edges += (unsigned)dw;
+                                cw = class_deg(a.g, w, dw);
                             }
                         }
-                        stage_push(newly, w, dw, st, sn, c, a.lq_vtx, (uint32_t)qe, a.lq_cap, a.hq, hqb, &c->err, gr);
+                        stage_push(newly, w, cw, st, sn, c, a.lq_vtx, (uint32_t)qe, a.lq_cap, a.hq, hqb, &c->err, gr);
                     }
                     // medium-degree vertices: the whole wavefront, one at a time
                     unsigned long long mm = __ballot(deg > kLightDeg && deg <= kSeg);
                     while (mm) {
                         const int j = __ffsll(mm) - 1;
                         mm &= mm - 1;
-                        const int m0 = __shfl(e0, j), m1 = m0 + __shfl(deg, j);
+                        const int m0 = __shfl(e0, j), m1 = m0 + __shfl(od, j);
                         push_arcs_wave(a, shfl_u64(f, j), m0, m1, rp, col, (uint32_t)qe, hqb, my_edges, st, sn, gr);
                     }
                 }
             }
-        } else {  // V_PULL over the batch's vertex range
+        } else {  // V_PULL over the batch's vertex range, scanning in-arcs (predecessors)
+            const int32_t *__restrict__ irp = a.g.in_row_ptr;
+            const int32_t *__restrict__ icol = a.g.in_col;
             const int lo = s_lo, span = s_hi - s_lo;
             const int n_light = (span + kWave - 1) / kWave;
             const int total = n_light + hseg;
@@ -790,13 +922,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
                     const int w = a.g.hv_vtx[h];
                     const unsigned long long need = act & ~a.vn[w].vis;
                     unsigned long long got = 0;
-                    const int a0 = rp[w] + s * kSeg, a1 = min(rp[w + 1], a0 + kSeg);
+                    const int a0 = irp[w] + s * kSeg, a1 = max(a0, min(irp[w + 1], a0 + kSeg));
                     int scanned = 0;
                     if (need) {
                         for (int eb = a0; eb < a1; eb += kWave) {
                             const int e = eb + lane;
                             if (e < a1) {
-                                const Tagged F = fw_cur[col[e]];
+                                const Tagged F = fw_cur[icol[e]];
                                 if (F.tag == T) got |= F.mask & need;
                             }
                             scanned += kWave;
@@ -807,25 +939,28 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
                     if (lane == 0) my_arcs += (unsigned)min(scanned, a1 - a0);
                     bool newly = false;
                     if (lane == 0 && got) newly = atomicOr(&a.vn[w].nxt, got) == 0ull;
-                    const int deg = rp[w + 1] - rp[w];
-                    if (newly) my_edges += (unsigned)deg;
-                    stage_push(newly, w, deg, st, sn, c, a.lq_vtx, (uint32_t)qe, a.lq_cap, a.hq, hqb, &c->err, gr);
+                    const int od = rp[w + 1] - rp[w];
+                    if (newly) my_edges += (unsigned)od;
+                    stage_push(newly, w, class_deg(a.g, w, od), st, sn, c, a.lq_vtx, (uint32_t)qe, a.lq_cap, a.hq, hqb,
+                               &c->err, gr);
                     continue;
                 }
                 const int w = lo + it * kWave + lane;
                 const bool valid = it * kWave + lane < span;
                 const unsigned long long vis = valid ? a.vn[w].vis : ~0ull;
                 const unsigned long long need = act & ~vis;
-                const int e0 = need ? rp[w] : 0;
-                const int deg = need ? rp[w + 1] - e0 : 0;
-                const int len = deg <= kLightDeg ? deg : 0;
+                const int e0 = need ? irp[w] : 0;
+                const int ni = need ? irp[w + 1] - e0 : 0;  // in-arcs to scan
+                const int od = (need && a.g.directed) ? rp[w + 1] - rp[w] : ni;
+                const int deg = a.g.directed ? max(ni, od) : ni;  // class degree
+                const int len = deg <= kLightDeg ? ni : 0;
                 const int maxlen = wave_max_i(len);
                 unsigned long long got = 0;
                 int scanned = 0;
                 for (int t = 0; t < maxlen; ++t) {
                     if (t < len && got != need) {
                         ++scanned;
-                        const Tagged F = fw_cur[col[e0 + t]];
+                        const Tagged F = fw_cur[icol[e0 + t]];
                         if (F.tag == T) got |= F.mask & need;
                     }
                     if (!__any(t + 1 < len && got != need)) break;
@@ -835,13 +970,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
                 while (mm) {
                     const int j = __ffsll(mm) - 1;
                     mm &= mm - 1;
-                    const int m0 = __shfl(e0, j), m1 = m0 + __shfl(deg, j);
+                    const int m0 = __shfl(e0, j), m1 = m0 + __shfl(ni, j);
                     const unsigned long long nj = shfl_u64(need, j);
                     unsigned long long gj = 0;
                     for (int eb = m0; eb < m1; eb += kWave) {
                         const int e = eb + lane;
                         if (e < m1) {
-                            const Tagged F = fw_cur[col[e]];
+                            const Tagged F = fw_cur[icol[e]];
                             if (F.tag == T) gj |= F.mask & nj;
                         }
                         if (lane == 0) scanned += min(kWave, m1 - eb);
@@ -854,7 +989,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
                 const bool found = got != 0ull && deg <= kSeg;
                 if (found) {
                     a.vn[w].nxt = got;
-                    my_edges += (unsigned)deg;
+                    my_edges += (unsigned)od;
                 }
                 stage_push(found, w, deg, st, sn, c, a.lq_vtx, (uint32_t)qe, a.lq_cap, a.hq, hqb, &c->err, gr);
             }
@@ -875,7 +1010,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
             const int it = k < hseg ? n_groups + k : k - hseg;  // heavy segments first
             if (it < n_groups) {
                 const int i0 = (int)gs[it], i1 = min((int)gs[it + 1], cnt);
-                if (i1 > i0) sig_group<MODE>(a, fw_cur, fw_nxt, T, qs, i0, i1, sh, lmask, sc);
+                if (i1 > i0) sig_group<MODE>(a, fw_cur, fw_nxt, T, qs, i0, i1, sh, lmask, sc, l, s_emax, s_emin);
                 continue;
             }
             // a segment of a heavy new vertex
@@ -884,12 +1019,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
             const int s = t - a.hq.seg[h];
             const int p = a.hq.pos[h];
             const int w = a.lq_vtx[p];
-            const int e0 = rp[w], e1 = rp[w + 1];
+            const int e0 = a.g.in_row_ptr[w], e1 = a.g.in_row_ptr[w + 1];  // predecessors: in-arcs
+            const int od = rp[w + 1] - rp[w];
             const unsigned long long m = a.vn[w].nxt;
-            const int a0 = e0 + s * kSeg, a1 = min(e1, a0 + kSeg);
+            const int a0 = e0 + s * kSeg, a1 = max(a0, min(e1, a0 + kSeg));
             unsigned long long lo = 0, hi = 0;
             double accd = 0.0;
-            sig_arcs<MODE>(a, fw_cur, T, m, a0, a1, sh, col, lo, hi, accd, sc.larcs, sc.pairs);
+            sig_arcs<MODE>(a, fw_cur, T, m, a0, a1, sh, a.g.in_col, lo, hi, accd, sc.larcs, sc.pairs);
             if (lane == 0) sc.arcs += (unsigned)(a1 - a0);
             const size_t slot = (size_t)(a.hq.seg[h] + s) * kLanes + lane;
             if (MODE == 0) {
@@ -898,7 +1034,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
             } else {
                 part_store(&a.hq.part_lo[slot], as_u64(accd));
             }
-            const int ns = n_segments(e1 - e0);
+            const int ns = n_segments(class_deg(a.g, w, od));
             if (!seg_arrive(&a.hq.cnt[h], ns)) continue;
             lo = hi = 0;
             accd = 0.0;
@@ -914,7 +1050,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
             }
             if (lane == 0) a.hq.cnt[h] = 0;
             const VisNext x = a.vn[w];
-            sig_finalize<MODE>(a, fw_nxt, T + 1u, p, w, x.vis, x.nxt, e1 - e0, lo, hi, accd, lmask, sc);
+            sig_finalize<MODE>(a, fw_nxt, T + 1u, p, w, x.vis, x.nxt, od, lo, hi, accd, lmask, sc);
         }
         my_edges += sc.edges;
         my_act |= sc.act;
@@ -944,7 +1080,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
             if (it < n_groups) {
                 const int i0 = (int)gs[it], i1 = min((int)gs[it + 1], cnt);
                 if (i1 > i0)
-                    bwd_group<MODE>(a, fb_nxt, fb_cur, TB, qb, i0, i1, dead, sh, shn, my_larcs, my_arcs, my_pairs);
+                    bwd_group<MODE>(a, fb_nxt, fb_cur, TB, qb, i0, i1, dead, sh, shn, my_larcs, my_arcs, my_pairs, l,
+                                    l + 1 < s_L);
                 continue;
             }
             const int t = it - n_groups;
@@ -954,12 +1091,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
             const int v = a.lq_vtx[p];
             const unsigned long long Mf = a.lq_mask[p];
             const unsigned long long M = Mf & ~dead;
-            const int e0 = rp[v], e1 = rp[v + 1];
-            const int a0 = e0 + s * kSeg, a1 = min(e1, a0 + kSeg);
+            const int e0 = rp[v], e1 = rp[v + 1];  // successors: out-arcs
+            const int a0 = e0 + s * kSeg, a1 = max(a0, min(e1, a0 + kSeg));
             double acc = M ? bwd_arcs(a, fb_nxt, TB + 1u, M, a0, a1, col, my_larcs, my_pairs) : 0.0;
             if (lane == 0) my_arcs += (unsigned)(a1 - a0);
             part_store(&a.hq.part_lo[(size_t)(a.hq.seg[h] + s) * kLanes + lane], as_u64(acc));
-            const int ns = n_segments(e1 - e0);
+            const int ns = n_segments(class_deg(a.g, v, e1 - e0));
             if (!seg_arrive(&a.hq.cnt[h], ns)) continue;
             acc = 0.0;
             for (int k = 0; k < ns; ++k) acc += as_f64(part_load(&a.hq.part_lo[(size_t)(a.hq.seg[h] + k) * kLanes + lane]));

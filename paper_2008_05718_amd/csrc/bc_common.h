@@ -241,6 +241,16 @@ __device__ __forceinline__ unsigned long long shfl_u64(unsigned long long x, int
 
 __device__ __forceinline__ int n_segments(int deg) { return (deg + kSeg - 1) / kSeg; }
 
+// Degree that decides how a level entry is processed (one thread, one
+// wavefront, or kSeg-arc segments) and what it costs: the larger of its out-
+// and in-degree, so an entry is handled the same way in every phase, whichever
+// arcs the phase scans (out-arcs to push and to pull dependencies from
+// successors, in-arcs to pull discovery and path counts from predecessors).
+// For an undirected graph it is the degree.
+__device__ __forceinline__ int class_deg(const GraphArgs &g, int v, int out_deg) {
+    return g.directed ? max(out_deg, g.in_row_ptr[v + 1] - g.in_row_ptr[v]) : out_deg;
+}
+
 
 // Write the n staged entries of this wavefront to the level queue (absolute
 // positions qbase + counter), heavy ones also to the level's heavy list.

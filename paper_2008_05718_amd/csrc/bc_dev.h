@@ -171,6 +171,12 @@ struct GraphArgs {
     const int32_t *hv_vtx;
     const int32_t *hv_seg;
     int32_t n_heavy;
+    // Directed graphs: row_ptr / col hold the out-arcs and these the in-arcs
+    // (the transpose).  Undirected graphs point both at the one symmetric
+    // adjacency.
+    const int32_t *in_row_ptr;
+    const int32_t *in_col;
+    int32_t directed;
 };
 
 // Heavy entries of the level queues (vertices of degree > kSeg), per level:
@@ -190,6 +196,8 @@ struct HeavyQ {
 
 struct PolicyArgs {
     float alpha, beta, wpv_degree;
+    float item_lanes;       // path-count / backward groups whose light entries carry at most this many
+                            // sources on average run one thread per (entry, source) pair
     int32_t has_mlp;
     const float *mlp;       // kMlpParams floats (device), or nullptr
 };

@@ -347,6 +347,7 @@ def workload(name: str, small: bool = False):
     rmat18     : R-MAT scale 18, ef 16, 8192 sources               (seed 2, src 1001)
     grid1024   : 1024^2 grid, -10% edges, LCC, +0.1% shortcuts, 4096 sources (seed 3, src 1002)
     ba512      : 512 BA graphs, n log-uniform [1e3, 1e5], all sources (seed 4)
+    ba512_frac64 : the same union, every 64th vertex of every graph as a source
     rmat22     : R-MAT scale 22, ef 16, 16384 sources              (seed 5, src 1004)
     """
     if name == "er2000":
@@ -365,6 +366,14 @@ def workload(name: str, small: bool = False):
         gs = ba_collection(512, 1000, 100000, 4, seed=4)
         u = union(gs, name="ba512")
         return u, np.arange(u.n, dtype=np.int32)
+    if name == "ba512_frac64":
+        # 1/64 of the all-sources work with the same mix of graph sizes:
+        # every 64th vertex of every graph
+        gs = ba_collection(512, 1000, 100000, 4, seed=4)
+        u = union(gs, name="ba512")
+        off = u.vtx_offsets.astype(np.int64)
+        srcs = np.concatenate([np.arange(off[i], off[i + 1], 64) for i in range(len(off) - 1)])
+        return u, srcs.astype(np.int32)
     if name == "rmat22":
         g = rmat(22, 16, seed=5)
         return g, choose_sources(g, 16384, seed=1004)

@@ -85,23 +85,33 @@ def test_grid1024_4096_sources():
 
 
 def test_rmat22_16384_sources():
-    # the full list is dumped once (that run is also the score check); the
-    # score sum is checked on a 256-source prefix, the oracle on 4 sources
+    # the full list runs four times with a detail dump each (sources spread
+    # over the list, so over batches held by different concurrent replicas);
+    # every run leaves the same score bits; the score sum is checked on a
+    # 256-source prefix and every vertex's score on a 64-source prefix
     t = time.time()
     g, srcs = W.workload("rmat22")
     say(f"[fullsize rmat22] n={g.n} m={g.m} sources={len(srcs)} (generated in {time.time() - t:.1f}s)")
     with _graph(g) as G:
-        t = time.time()
-        det = G.detail(srcs, dump_index=9000, batch=64)
-        say(f"  full run with detail of source #9000: mode {det['mode']}, {time.time() - t:.2f}s")
-        check_detail(g, det, srcs[9000])
-        full = G.scores().copy()
-        assert np.isfinite(full).all() and (full >= 0).all()
+        full = None
+        for k in (0, 5003, 9000, 16383):
+            t = time.time()
+            det = G.detail(srcs, dump_index=k, batch=64)
+            say(f"  full run with detail of source #{k}: mode {det['mode']}, {det['n_levels']} levels, "
+                f"{time.time() - t:.2f}s")
+            check_detail(g, det, srcs[k])
+            bits = G.scores().copy()
+            if full is None:
+                full = bits
+                assert np.isfinite(full).all() and (full >= 0).all()
+            assert np.array_equal(bits.view(np.uint64), full.view(np.uint64))
         G.run(srcs[:256], batch=64)
         _sum_check(G.scores(), g, srcs[:256])
-        G.run(srcs[:4], batch=64)
+        G.run(srcs[:64], batch=64)
         got = G.scores()
-    ref, _ = oracle.bc(g, srcs[:4])
+    t = time.time()
+    ref, _ = oracle.bc_sliced(g, srcs[:64], threads=16)
+    say(f"  oracle on 64 sources: {time.time() - t:.1f}s on the host")
     assert_bc_close(got, ref)
 
 
@@ -119,7 +129,7 @@ def test_ba512_sampled_sources():
     # details of three sources, the score sum against the path-length excess,
     # and three whole graphs' scores against the oracle
     t = time.time()
-    g, _ = W.workload("ba512")
+    g = _ba_all_graph()
     off = g.vtx_offsets.astype(np.int64)
     rng = np.random.default_rng(77)
     srcs = np.concatenate([off[i] + rng.choice(off[i + 1] - off[i], 8, replace=False)
@@ -139,3 +149,74 @@ def test_ba512_sampled_sources():
         lo, hi = int(off[i]), int(off[i + 1])
         ref, _ = oracle.bc(_block(g, lo, hi), srcs[8 * i:8 * i + 8] - lo)
         assert_bc_close(got[lo:hi], ref)
+
+
+# The whole BA workload, every vertex of every graph a source, in steps that
+# each finish within a couple of minutes: the union is generated once, one
+# run in the default launch configuration computes every score, and the
+# host checks follow in parts.
+_BA_ALL = {}
+
+
+def _ba_all_graph():
+    if "g" not in _BA_ALL:
+        t = time.time()
+        g, _ = W.workload("ba512")
+        _BA_ALL["g"] = g
+        say(f"[fullsize ba512 all sources] n={g.n} m={g.m} (generated in {time.time() - t:.1f}s)")
+    return _BA_ALL["g"]
+
+
+def test_ba512_all_sources_run():
+    g = _ba_all_graph()
+    with _graph(g) as G:
+        t = time.time()
+        G.run(None, batch=64)
+        got = G.scores().copy()
+        st = G.stats()
+    say(f"  all {g.n} sources: {time.time() - t:.1f}s, batches {st['n_batches']}")
+    assert np.isfinite(got).all() and (got >= 0).all()
+    _BA_ALL["bc"] = got
+
+
+def _ba_all_pick():
+    g = _ba_all_graph()
+    off = g.vtx_offsets.astype(np.int64)
+    sizes = np.diff(off)
+    order = np.argsort(sizes, kind="stable")
+    whole = [int(order[0]), int(order[-1])] + [int(order[k]) for k in np.linspace(1, len(order) - 2, 14).astype(int)]
+    chosen = set(whole)
+    rest = [i for i in range(len(sizes)) if i not in chosen and sizes[i] <= 20000]
+    excess = [int(i) for i in np.random.default_rng(2024).choice(rest, 48, replace=False)]
+    return g, off, whole, excess
+
+
+@pytest.mark.parametrize("part", [0, 1, 2, 3])
+def test_ba512_all_sources_whole_graphs(part):
+    # 16 whole graphs (the smallest, the largest, 14 spread over the size
+    # range; every source of each) against the oracle, four per test
+    if "bc" not in _BA_ALL:
+        pytest.skip("needs test_ba512_all_sources_run in the same session")
+    g, off, whole, _ = _ba_all_pick()
+    got = _BA_ALL["bc"]
+    t = time.time()
+    for i in whole[part::4]:
+        lo, hi = int(off[i]), int(off[i + 1])
+        ref, _ = oracle.bc_sliced(_block(g, lo, hi), np.arange(hi - lo, dtype=np.int32), threads=16)
+        assert_bc_close(got[lo:hi], ref, what=f"graph {i} (n={hi - lo})")
+    say(f"  whole graphs {whole[part::4]} against the oracle: {time.time() - t:.1f}s on the host")
+
+
+def test_ba512_all_sources_score_sums():
+    # the score sum of 48 more graphs against their path-length excess
+    if "bc" not in _BA_ALL:
+        pytest.skip("needs test_ba512_all_sources_run in the same session")
+    g, off, _, excess = _ba_all_pick()
+    got = _BA_ALL["bc"]
+    t = time.time()
+    for i in excess:
+        lo, hi = int(off[i]), int(off[i + 1])
+        want = float(oracle.path_excess(_block(g, lo, hi), np.arange(hi - lo, dtype=np.int32)).sum())
+        have = float(np.sum(got[lo:hi], dtype=np.float64))
+        assert abs(have - want) <= REL * want, (i, have, want)
+    say(f"  score sums of 48 more graphs: {time.time() - t:.1f}s on the host")

@@ -121,17 +121,19 @@ def test_learned_policy_same_bits_and_its_gain():
         G.run(srcs, batch=64, policy=b.BC_POLICY_MLP)
         m_bits = G.scores().copy()
         assert np.array_equal(h_bits.view(np.uint64), m_bits.view(np.uint64))
-        times = {}
-        for pol in (b.BC_POLICY_HEURISTIC, b.BC_POLICY_MLP, b.BC_POLICY_FORCE_PUSH_TPV, b.BC_POLICY_FORCE_PULL):
-            best = 1e30
-            for _ in range(3):
+        # best of 7 runs each, the policies taken in turn so that drift of
+        # the device clock or of other load hits them alike
+        pols = (b.BC_POLICY_HEURISTIC, b.BC_POLICY_MLP, b.BC_POLICY_FORCE_PUSH_TPV, b.BC_POLICY_FORCE_PULL)
+        times = {p: 1e30 for p in pols}
+        for _ in range(7):
+            for pol in pols:
                 t = time.perf_counter()
                 G.run(srcs, batch=64, policy=pol)
-                best = min(best, time.perf_counter() - t)
-            times[pol] = best
+                times[pol] = min(times[pol], time.perf_counter() - t)
         gain = times[b.BC_POLICY_HEURISTIC] / times[b.BC_POLICY_MLP]
-        say(f"  heuristic {times[1]*1e3:.1f} ms, mlp {times[2]*1e3:.1f} ms (gain x{gain:.3f}), "
-            f"tpv {times[3]*1e3:.1f} ms, pull {times[5]*1e3:.1f} ms")
-        # speed is the only thing the network may change; it must not be a
-        # regression beyond timing noise against the rule it replaces
-        assert gain > 0.8
+        say(f"  heuristic {times[1]*1e3:.2f} ms, mlp {times[2]*1e3:.2f} ms (gain x{gain:.3f}), "
+            f"tpv {times[3]*1e3:.2f} ms, pull {times[5]*1e3:.2f} ms")
+        # speed is the only thing the network may change: on a graph it was
+        # not trained on it must be at least as fast as the rule it replaces,
+        # up to 2 % of timing noise
+        assert gain >= 0.98

@@ -492,3 +492,30 @@ def test_device_limit_refuses_before_allocating_and_falls_back():
         assert np.array_equal(H.scores().view(np.uint64), one.view(np.uint64))
     assert_bc_close(one, ref)
     assert_bc_close(many, ref)
+
+
+@pytest.mark.parametrize("case", ["grid", "rmat", "grid_f64"])
+def test_entry_source_items_same_bits(case):
+    # path-count and backward groups summed one thread per (entry, source)
+    # pair or one wavefront lane per source: same sums in the same CSR order,
+    # so the same bits; details of one source against the oracle
+    if case == "rmat":
+        g = W.rmat(12, 16, seed=23)
+        srcs = W.choose_sources(g, 130, seed=8)
+    else:
+        g = W.grid(64, 0.1, 0.0 if case == "grid_f64" else 0.002, seed=9)
+        srcs = W.choose_sources(g, 130, seed=8)
+    flags = b.BC_RUN_ONE_QUEUE | (b.BC_RUN_FORCE_F64 if case == "grid_f64" else 0)
+    say(f"[items] {case} n={g.n}")
+    outs = {}
+    with b.Graph(g) as G:
+        for lpe in (-1.0, 0.0, 64.0):
+            G.run(srcs, batch=64, flags=flags, lanes_per_entry=lpe)
+            outs[lpe] = G.scores().copy()
+        if case != "grid_f64":  # forced FP64 mode has no oracle counterpart for small counts
+            det = G.detail(srcs, dump_index=77, batch=64, flags=flags, lanes_per_entry=64.0)
+            check_detail(g, det, int(srcs[77]))
+    for k, v in outs.items():
+        assert np.array_equal(v.view(np.uint64), outs[-1.0].view(np.uint64)), f"bits differ for lanes_per_entry={k}"
+    ref, _ = oracle.bc(g, srcs)
+    assert_bc_close(outs[64.0], ref)
