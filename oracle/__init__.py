@@ -6,7 +6,8 @@ and shares no code with it.
 
 ``bc_oracle.c`` is a plain single-threaded C implementation of Eq. 1-2 of
 the paper's Section "Background", written out from their definitions:
-breadth-first distances, the path-count recurrence over predecessors, and
+breadth-first distances (Dijkstra's method for graphs with positive integer
+arc weights, ``g.weights``), the path-count recurrence over predecessors, and
 Eq. 2 as a sum over each vertex's successors.  This module compiles it with
 gcc and wraps it with ctypes.  ``tests/brute.py`` holds definition-level
 checkers (path enumeration, walk counting) used to pin the oracle.
@@ -49,6 +50,10 @@ def _load():
     lib.oracle_source_dir.argtypes = [ctypes.c_int32, P, P, P, P, P, P, ctypes.c_int32, P, P, P, P, P]
     lib.oracle_path_excess.restype = ctypes.c_int
     lib.oracle_path_excess.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.c_int64, P]
+    lib.oracle_bc_w.restype = ctypes.c_int
+    lib.oracle_bc_w.argtypes = [ctypes.c_int32, P, P, P, P, P, P, P, P, P, ctypes.c_int64, P, P]
+    lib.oracle_source_w.restype = ctypes.c_int
+    lib.oracle_source_w.argtypes = [ctypes.c_int32, P, P, P, P, P, P, P, P, ctypes.c_int32, P, P, P, P]
     lib.oracle_sizeof_long_double.restype = ctypes.c_int
     if lib.oracle_sizeof_long_double() != np.dtype(np.longdouble).itemsize:
         raise RuntimeError("long double size mismatch between gcc and numpy")
@@ -80,6 +85,26 @@ def _in_arcs(g):
     return irp32, irp64, np.ascontiguousarray(g.in_col_idx, dtype=np.int32)
 
 
+def _weights(g):
+    """(wt, in_wt) int32 arrays of a weighted graph (in_wt None when
+    undirected), or (None, None)."""
+    w = getattr(g, "weights", None)
+    if w is None:
+        return None, None
+    iw = getattr(g, "in_weights", None)
+    return (np.ascontiguousarray(w, dtype=np.int32),
+            None if iw is None else np.ascontiguousarray(iw, dtype=np.int32))
+
+
+def _bc_call(lib, g, rp32, rp64, col, irp32, irp64, icol, src, ns, out, modes):
+    wt, iwt = _weights(g)
+    if wt is None:
+        return lib.oracle_bc_dir(g.n, _ptr(rp32), _ptr(rp64), _ptr(col), _ptr(irp32), _ptr(irp64), _ptr(icol),
+                                 _ptr(src), ns, _ptr(out), _ptr(modes))
+    return lib.oracle_bc_w(g.n, _ptr(rp32), _ptr(rp64), _ptr(col), _ptr(wt), _ptr(irp32), _ptr(irp64), _ptr(icol),
+                           _ptr(iwt), _ptr(src), ns, _ptr(out), _ptr(modes))
+
+
 def bc(g, sources=None):
     """Raw ordered-pair BC sums over ``sources`` (None = all vertices).  A
     graph with ``in_row_ptr`` / ``in_col_idx`` is directed (paths follow
@@ -100,8 +125,7 @@ def bc(g, sources=None):
         ns = src.size
     modes = np.zeros(ns, dtype=np.int32)
     irp32, irp64, icol = _in_arcs(g)
-    rc = lib.oracle_bc_dir(g.n, _ptr(rp32), _ptr(rp64), _ptr(col), _ptr(irp32), _ptr(irp64), _ptr(icol),
-                           _ptr(src), ns, _ptr(out), _ptr(modes))
+    rc = _bc_call(lib, g, rp32, rp64, col, irp32, irp64, icol, src, ns, out, modes)
     if rc != 0:
         raise ValueError(f"oracle_bc failed with code {rc}")
     return out, modes
@@ -131,8 +155,7 @@ def bc_sliced(g, sources, threads: int = 0):
             return 0
         s = src[lo:hi]
         m = modes[lo:hi]
-        return lib.oracle_bc_dir(g.n, _ptr(rp32), _ptr(rp64), _ptr(col), _ptr(irp32), _ptr(irp64), _ptr(icol),
-                                 _ptr(s), hi - lo, _ptr(parts[i]), _ptr(m))
+        return _bc_call(lib, g, rp32, rp64, col, irp32, irp64, icol, s, hi - lo, parts[i], m)
 
     with ThreadPoolExecutor(nt) as ex:
         rcs = list(ex.map(work, range(nt)))
@@ -161,8 +184,16 @@ def source(g, s: int) -> SourceDetail:
     r.delta = np.empty(n, np.float64)
     nl = np.zeros(1, np.int32)
     irp32, irp64, icol = _in_arcs(g)
-    mode = lib.oracle_source_dir(n, _ptr(rp32), _ptr(rp64), _ptr(col), _ptr(irp32), _ptr(irp64), _ptr(icol),
-                                 int(s), _ptr(r.d), _ptr(r.sigma_u64), _ptr(r.sigma_ld), _ptr(r.delta), _ptr(nl))
+    wt, iwt = _weights(g)
+    if wt is None:
+        mode = lib.oracle_source_dir(n, _ptr(rp32), _ptr(rp64), _ptr(col), _ptr(irp32), _ptr(irp64), _ptr(icol),
+                                     int(s), _ptr(r.d), _ptr(r.sigma_u64), _ptr(r.sigma_ld), _ptr(r.delta), _ptr(nl))
+    else:  # weighted: int64 distances; n_levels = number of distinct distances
+        r.d = np.empty(n, np.int64)
+        mode = lib.oracle_source_w(n, _ptr(rp32), _ptr(rp64), _ptr(col), _ptr(wt), _ptr(irp32), _ptr(irp64),
+                                   _ptr(icol), _ptr(iwt), int(s), _ptr(r.d), _ptr(r.sigma_u64), _ptr(r.sigma_ld),
+                                   _ptr(r.delta))
+        nl[0] = len(np.unique(r.d[r.d >= 0])) if mode >= 0 else 0
     if mode < 0:
         raise ValueError(f"oracle_source failed with code {mode}")
     r.mode = int(mode)
@@ -179,6 +210,8 @@ def path_excess(g, sources, threads: int = 0) -> np.ndarray:
     cores, at most 16), each call owning its buffers.
     """
     from concurrent.futures import ThreadPoolExecutor
+    if getattr(g, "weights", None) is not None:
+        raise ValueError("path_excess counts hops: it does not apply to weighted graphs")
     lib = _load()
     rp32, rp64 = _rp(g)
     col = np.ascontiguousarray(g.col_idx, dtype=np.int32)

@@ -42,6 +42,10 @@ class CSR:
     # whose symmetric adjacency is both.
     in_row_ptr: np.ndarray | None = None
     in_col_idx: np.ndarray | None = None
+    # Weighted graphs: positive int32 arc weights aligned with col_idx (and
+    # with in_col_idx for directed graphs); symmetric for undirected graphs.
+    weights: np.ndarray | None = None
+    in_weights: np.ndarray | None = None
 
     @property
     def directed(self) -> bool:
@@ -134,6 +138,35 @@ def rmat_directed(scale: int, edgefactor: int = 16, a: float = 0.57, b: float = 
     g = digraph_from_arcs(1 << scale, u, v, name=f"rmatdir{scale}_ef{edgefactor}_s{seed}")
     g.meta.update(family="rmat_directed", scale=scale, edgefactor=edgefactor, seed=seed)
     return g
+
+
+def with_weights(g: CSR, lo: int = 1, hi: int = 16, seed: int = 1) -> CSR:
+    """The same graph with integer arc weights drawn uniformly from [lo, hi]:
+    one weight per undirected edge (both arcs carry it), or one per arc of a
+    directed graph (the in-arcs carry the weight of the same arc)."""
+    rng = np.random.default_rng(seed)
+    n = g.n
+    rp = g.row_ptr.astype(np.int64)
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    dst = g.col_idx.astype(np.int64)
+    if g.directed:
+        w = rng.integers(lo, hi + 1, size=g.nnz).astype(np.int32)
+        key = src * n + dst  # ascending: out-rows are sorted
+        irp = g.in_row_ptr.astype(np.int64)
+        isrc = np.repeat(np.arange(n, dtype=np.int64), np.diff(irp))  # head of the in-arc
+        ikey = g.in_col_idx.astype(np.int64) * n + isrc  # the same arc, tail * n + head
+        iw = w[np.searchsorted(key, ikey)]
+    else:
+        a, b = np.minimum(src, dst), np.maximum(src, dst)
+        ekey = a * n + b
+        uniq, inv = np.unique(ekey, return_inverse=True)
+        wu = rng.integers(lo, hi + 1, size=uniq.size).astype(np.int32)
+        w = wu[inv]
+        iw = None
+    h = CSR(g.row_ptr, g.col_idx, name=g.name + f"_w{lo}-{hi}", vtx_offsets=g.vtx_offsets, meta=dict(g.meta),
+            in_row_ptr=g.in_row_ptr, in_col_idx=g.in_col_idx, weights=w, in_weights=iw)
+    h.meta.update(weights=(lo, hi, seed))
+    return h
 
 
 def csr_from_networkx(G) -> CSR:
