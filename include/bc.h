@@ -355,6 +355,29 @@ bc_status bc_mlp_loss_grad(const float *weights, const float *X, const float *Y,
                            int64_t n, float *loss, float *grad, void *stream);
 bc_status bc_mlp_train(float *weights, const float *X, const float *Y, const uint8_t *mask, int64_t n,
                        int32_t steps, float lr, float *final_loss, void *stream);
+
+/*
+ * Allocation-free variant of bc_mlp_loss_grad, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight training loops,
+ * harnesses that forbid hipMalloc.  Same kernels, same result bits.
+ *   weights, X, Y, mask   DEVICE pointers, layouts as above; read only.
+ *   n                     1 <= n <= 16384 samples, else BC_ERR_INVALID_ARG
+ *                         (the intermediates live in a fixed 8.7 MB array of
+ *                         the library, one per GPU, kept for the process).
+ *   loss, grad            DEVICE pointers to float[1] and float[BC_MLP_PARAMS].
+ * The work is enqueued on `stream` and the call returns without waiting:
+ * outputs are valid once that stream reaches this point.  Inputs are not
+ * checked on the host (that would need a copy): a mask with no measured
+ * target gives loss 0 and a zero gradient; non-finite inputs give non-finite
+ * outputs.  Every call on one GPU uses the same array, so calls whose work
+ * can overlap on one GPU (different streams without ordering) race; calls on
+ * one stream are ordered.  Nothing is allocated or freed, on the device or
+ * the host.  Errors: BC_ERR_INVALID_ARG (NULL pointer, n out of range),
+ * BC_ERR_DEVICE (the array's address could not be obtained, a launch failed).
+ */
+bc_status bc_mlp_loss_grad_noalloc(const float *weights, const float *X, const float *Y,
+                                   const uint8_t *mask, int64_t n, float *loss, float *grad,
+                                   void *stream);
 bc_status bc_mlp_predict(const float *weights, const float *X, int64_t n, float *Y, void *stream);
 
 /*

@@ -46,7 +46,7 @@ BC_MLP_PARAMS = 32 * 5 + 32 + 32 * 32 + 32 + 3 * 32 + 3
 EXPORTS = ["bc_status_string", "bc_last_error", "bc_graph_create", "bc_graph_create_multi", "bc_destroy",
            "bc_graph_info", "bc_run_options_init", "bc_run", "bc_scores", "bc_run_detail", "bc_run_stats",
            "bc_load_policy", "bc_mlp_loss_grad", "bc_mlp_train", "bc_mlp_predict", "bc_collect_level_times",
-           "bc_autotune", "bc_set_device_limit", "bc_run_level_stats"]
+           "bc_autotune", "bc_set_device_limit", "bc_run_level_stats", "bc_mlp_loss_grad_noalloc"]
 
 
 class LibraryMissing(RuntimeError):
@@ -140,6 +140,8 @@ def lib():
     L.bc_load_policy.argtypes = [P, P, I64]
     L.bc_mlp_loss_grad.restype = ctypes.c_int
     L.bc_mlp_loss_grad.argtypes = [P, P, P, P, I64, P, P, P]
+    L.bc_mlp_loss_grad_noalloc.restype = ctypes.c_int
+    L.bc_mlp_loss_grad_noalloc.argtypes = [P, P, P, P, I64, P, P, P]
     L.bc_mlp_train.restype = ctypes.c_int
     L.bc_mlp_train.argtypes = [P, P, P, P, I64, I32, ctypes.c_float, P, P]
     L.bc_mlp_predict.restype = ctypes.c_int
@@ -349,6 +351,22 @@ def bc_mlp_loss_grad(weights, X, Y, mask):
     grad = np.zeros(BC_MLP_PARAMS, np.float32)
     _check(lib().bc_mlp_loss_grad(_p(w), _p(x), _p(y), _p(m), n, ctypes.byref(loss), _p(grad), None))
     return float(loss.value), grad
+
+
+def bc_mlp_loss_grad_noalloc(weights, X, Y, mask, loss, grad, stream=None):
+    """Allocation-free loss and gradient: every argument is a contiguous
+    torch cuda tensor (weights float32[BC_MLP_PARAMS], X float32[n][5],
+    Y float32[n][3], mask uint8[n][3], loss float32[1], grad
+    float32[BC_MLP_PARAMS]).  Enqueued on ``stream``; the outputs are valid
+    once that stream's work is done."""
+    import torch
+    n = int(X.shape[0])
+    for name, t, dt in (("weights", weights, torch.float32), ("X", X, torch.float32), ("Y", Y, torch.float32),
+                        ("mask", mask, torch.uint8), ("loss", loss, torch.float32), ("grad", grad, torch.float32)):
+        if not (_is_torch(t) and t.is_cuda and t.is_contiguous() and t.dtype == dt):
+            raise TypeError(f"{name} must be a contiguous cuda tensor of {dt}")
+    P = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    _check(lib().bc_mlp_loss_grad_noalloc(P(weights), P(X), P(Y), P(mask), n, P(loss), P(grad), _stream(stream)))
 
 
 def bc_mlp_train(weights, X, Y, mask, steps: int, lr: float):

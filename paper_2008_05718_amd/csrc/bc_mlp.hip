@@ -10,6 +10,7 @@
 // parameter, so they do not depend on the launch shape.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -28,13 +29,14 @@ static_assert(kP == kMlpParams, "parameter layout");
 // need, plus the sample's squared error (pre-scaled).
 __global__ __launch_bounds__(256) void mlp_rows(const float *__restrict__ w, const float *__restrict__ X,
                                                 const float *__restrict__ Y, const uint8_t *__restrict__ mask,
-                                                int64_t n, float inv_cnt, float *__restrict__ H1,
+                                                int64_t n, const float *__restrict__ inv_p, float *__restrict__ H1,
                                                 float *__restrict__ H2, float *__restrict__ D1,
                                                 float *__restrict__ D2, float *__restrict__ D3,
                                                 float *__restrict__ sq) {
     __shared__ float sw[kP];
     for (int i = threadIdx.x; i < kP; i += blockDim.x) sw[i] = w[i];
     __syncthreads();
+    const float inv_cnt = *inv_p;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
         float x[kIn], h1[kH], h2[kH], y[kOut], d3[kOut], d2[kH];
         for (int i = 0; i < kIn; ++i) x[i] = X[r * kIn + i];
@@ -74,6 +76,23 @@ __global__ __launch_bounds__(256) void mlp_rows(const float *__restrict__ w, con
         for (int k = 0; k < kOut; ++k) D3[r * kOut + k] = d3[k];
         sq[r] = 0.5f * e * inv_cnt;
     }
+}
+
+// 1 / (number of measured targets), or 0 when there are none (the loss and
+// gradient are then 0).  One workgroup; integer count, so the order of the
+// additions does not matter.
+__global__ __launch_bounds__(256) void mlp_mask_count(const uint8_t *__restrict__ mask, int64_t n,
+                                                      float *__restrict__ inv) {
+    __shared__ unsigned long long part[256];
+    unsigned long long c = 0;
+    for (int64_t i = threadIdx.x; i < n * kOut; i += blockDim.x) c += mask[i] ? 1u : 0u;
+    part[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *inv = part[0] ? 1.0f / (float)part[0] : 0.0f;
 }
 
 // One thread per parameter: gradient = sum over samples, in sample order.
@@ -163,10 +182,13 @@ namespace {
 // Device buffers for one training / gradient call.
 struct MlpBufs {
     float *w = nullptr, *X = nullptr, *Y = nullptr, *H1 = nullptr, *H2 = nullptr, *D1 = nullptr, *D2 = nullptr,
-          *D3 = nullptr, *sq = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr, *loss = nullptr;
+          *D3 = nullptr, *sq = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr, *loss = nullptr,
+          *inv = nullptr;
     uint8_t *mask = nullptr;
+    bool owned = true;  // false: views into the static scratch (nothing to free)
     ~MlpBufs() {
-        void *ps[] = {w, X, Y, H1, H2, D1, D2, D3, sq, grad, m1, m2, loss, mask};
+        if (!owned) return;
+        void *ps[] = {w, X, Y, H1, H2, D1, D2, D3, sq, grad, m1, m2, loss, inv, mask};
         for (void *p : ps)
             if (p) (void)hipFree(p);
     }
@@ -202,6 +224,7 @@ static bc_status mlp_upload(MlpBufs &b, const float *weights, const float *X, co
     MLP_TRY(hipMalloc((void **)&b.m1, kP * sizeof(float)));
     MLP_TRY(hipMalloc((void **)&b.m2, kP * sizeof(float)));
     MLP_TRY(hipMalloc((void **)&b.loss, sizeof(float)));
+    MLP_TRY(hipMalloc((void **)&b.inv, sizeof(float)));
     MLP_TRY(hipMemcpyAsync(b.w, weights, kP * sizeof(float), hipMemcpyHostToDevice, st));
     if (n > 0) {
         MLP_TRY(hipMemcpyAsync(b.X, X, (size_t)n * kIn * sizeof(float), hipMemcpyHostToDevice, st));
@@ -223,15 +246,13 @@ static bc_status mlp_check(const float *weights, const float *X, const float *Y,
     return BC_OK;
 }
 
-static float inv_count(const uint8_t *mask, int64_t n) {
-    int64_t cnt = 0;
-    for (int64_t i = 0; i < n * kOut; ++i) cnt += mask[i] ? 1 : 0;
-    return 1.0f / (float)cnt;
+static void mlp_count(MlpBufs &b, int64_t n, hipStream_t st) {
+    mlp_mask_count<<<1, 256, 0, st>>>(b.mask, n, b.inv);
 }
 
-static void mlp_step_grad(MlpBufs &b, int64_t n, float inv, hipStream_t st) {
+static void mlp_step_grad(MlpBufs &b, int64_t n, hipStream_t st) {
     const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
-    mlp_rows<<<blocks, 256, 0, st>>>(b.w, b.X, b.Y, b.mask, n, inv, b.H1, b.H2, b.D1, b.D2, b.D3, b.sq);
+    mlp_rows<<<blocks, 256, 0, st>>>(b.w, b.X, b.Y, b.mask, n, b.inv, b.H1, b.H2, b.D1, b.D2, b.D3, b.sq);
     mlp_grad<<<(kP + 1 + 255) / 256, 256, 0, st>>>(b.X, b.H1, b.H2, b.D1, b.D2, b.D3, b.sq, n, b.grad, b.loss);
 }
 
@@ -243,7 +264,8 @@ extern "C" bc_status bc_mlp_loss_grad(const float *weights, const float *X, cons
     MlpBufs b;
     s = mlp_upload(b, weights, X, Y, mask, n, st);
     if (s != BC_OK) return s;
-    mlp_step_grad(b, n, inv_count(mask, n), st);
+    mlp_count(b, n, st);
+    mlp_step_grad(b, n, st);
     MLP_TRY(hipGetLastError());
     float l = 0.0f;
     std::vector<float> g(kP);
@@ -252,6 +274,73 @@ extern "C" bc_status bc_mlp_loss_grad(const float *weights, const float *X, cons
     MLP_TRY(hipStreamSynchronize(st));
     if (loss) *loss = l;
     if (grad) std::memcpy(grad, g.data(), kP * sizeof(float));
+    return BC_OK;
+}
+
+// ------------------------------------------------ allocation-free variant
+// bc_mlp_loss_grad_noalloc keeps every intermediate of the loss and gradient
+// (hidden activations, back-propagated errors, per-sample squared errors and
+// the target count) in this fixed array: no device memory is allocated per
+// call.  Each GPU holds its own copy for the life of the process.  Host code
+// must not pass the array's name to a kernel (on the host it only stands for
+// the symbol): the device address comes from hipGetSymbolAddress, taken once
+// per device on the first call there.
+constexpr int64_t kNoAllocMaxSamples = 16384;
+constexpr size_t kNoAllocFloats = (size_t)kNoAllocMaxSamples * (4 * kH + kOut + 1) + 64;
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static bc_status scratch_address(float **out) {
+    int dev = -1;
+    MLP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return bc_set_error(BC_ERR_NOT_SUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        MLP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return bc_set_error(BC_ERR_DEVICE, "hipGetSymbolAddress returned NULL for the scratch array");
+        g_scratch_ptr[dev] = (float *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return BC_OK;
+}
+
+extern "C" bc_status bc_mlp_loss_grad_noalloc(const float *weights, const float *X, const float *Y,
+                                              const uint8_t *mask, int64_t n, float *loss, float *grad,
+                                              void *stream) {
+    if (!weights || !X || !Y || !mask || !loss || !grad) return bc_set_error(BC_ERR_INVALID_ARG, "NULL argument");
+    if (n < 1 || n > kNoAllocMaxSamples)
+        return bc_set_error(BC_ERR_INVALID_ARG, ("n must be in [1, " + std::to_string(kNoAllocMaxSamples) +
+                                                 "] for the allocation-free call").c_str());
+    float *sc = nullptr;
+    bc_status s = scratch_address(&sc);
+    if (s != BC_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    MlpBufs b;
+    b.owned = false;
+    b.w = const_cast<float *>(weights);
+    b.X = const_cast<float *>(X);
+    b.Y = const_cast<float *>(Y);
+    b.mask = const_cast<uint8_t *>(mask);
+    b.grad = grad;
+    b.loss = loss;
+    // scratch layout: H1, H2, D1, D2 [n][kH] each, D3 [n][kOut], sq [n], inv [1]
+    const size_t N = (size_t)n;
+    b.H1 = sc;
+    b.H2 = b.H1 + N * kH;
+    b.D1 = b.H2 + N * kH;
+    b.D2 = b.D1 + N * kH;
+    b.D3 = b.D2 + N * kH;
+    b.sq = b.D3 + N * kOut;
+    b.inv = b.sq + N;
+    mlp_count(b, n, st);
+    mlp_step_grad(b, n, st);
+    MLP_TRY(hipGetLastError());
     return BC_OK;
 }
 
@@ -268,12 +357,12 @@ extern "C" bc_status bc_mlp_train(float *weights, const float *X, const float *Y
     if (s != BC_OK) return s;
     MLP_TRY(hipMemsetAsync(b.m1, 0, kP * sizeof(float), st));
     MLP_TRY(hipMemsetAsync(b.m2, 0, kP * sizeof(float), st));
-    const float inv = inv_count(mask, n);
+    mlp_count(b, n, st);
     for (int t = 1; t <= steps; ++t) {
-        mlp_step_grad(b, n, inv, st);
+        mlp_step_grad(b, n, st);
         mlp_adam<<<(kP + 255) / 256, 256, 0, st>>>(b.w, b.grad, b.m1, b.m2, t, lr, 0.9f, 0.999f, 1e-8f);
     }
-    mlp_step_grad(b, n, inv, st);  // loss of the final weights
+    mlp_step_grad(b, n, st);  // loss of the final weights
     MLP_TRY(hipGetLastError());
     std::vector<float> w(kP);
     float l = 0.0f;
