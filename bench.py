@@ -69,7 +69,7 @@ def measured_traffic(kernel: str, workload: str):
     summary of this workload (FETCH_SIZE and WRITE_SIZE, each scaled by its
     copy-kernel calibration), or None when there is none or the kernel
     sources changed since the counters were taken."""
-    tag = {"batch_step<0>": "batch_step_u64", "batch_step<1>": "batch_step_f64"}.get(kernel)
+    tag = {"batch_step<0>": "batch_step_u64", "batch_step<1>": "batch_step_f64", "block_run<0>": "block_run_u64"}.get(kernel)
     path = os.path.join(ROOT, "profiles", f"{tag}_{workload}.md")
     if tag is None or not os.path.exists(path):
         return None
@@ -296,6 +296,7 @@ def main():
     ap.add_argument("--sources", type=int, default=0, help="use only the first N sources (profiling runs)")
     ap.add_argument("--no-graphs", action="store_true", help="launch level steps one by one")
     ap.add_argument("--grid", type=int, default=0, help="workgroups per step launch (0 = library default)")
+    ap.add_argument("--no-blocks", action="store_true", help="never use the block engine (small graphs)")
     ap.add_argument("--lanes-per-entry", type=float, default=0.0,
                     help="entry-by-source summation threshold of the batched engine (0 = library default, <0 = off)")
     ap.add_argument("--no-tune", action="store_true", help="skip bc_autotune (default: tune on the first 512 sources)")
@@ -382,7 +383,7 @@ def main():
         return wall, gpu_ms, stats
 
     # ---- batched (headline); launch configuration tuned on a sample first (untimed)
-    gflags = b.BC_RUN_NO_GRAPHS if args.no_graphs else 0
+    gflags = (b.BC_RUN_NO_GRAPHS if args.no_graphs else 0) | (b.BC_RUN_NO_BLOCKS if args.no_blocks else 0)
     tuned = None
     if not args.no_tune:
         t = time.time()
@@ -415,12 +416,13 @@ def main():
     achieved_gbs = k_algo / max(dev_ms * 1e-3, 1e-12) / 1e9
     # the same bytes without the per-(vertex, source) slab term
     arcs_frac = sum(s["algo_bytes_arcs"] for s in stats) / max(sum(s["algo_bytes"] for s in stats), 1e-12)
-    kernel = f"batch_step<{k}>"
+    kernel = "block_run<0>" if (k == 0 and st.get("block_workgroups", 0) > 0) else f"batch_step<{k}>"
     log(f"[bench] batched: {ms_step:.1f} ms/step, {gteps:.2f} GTEPS, launches/step={launches // args.steps}, "
         f"{kernel}: {k_launches} launches, {avg_launch_us:.2f} us each of device time ({trace_launch_us:.2f} us "
         f"on its stream), algo {achieved_gbs:.1f} GB/s, device ms per mode {[round(x, 1) for x in mode_ms]} "
         f"(host wall {wall * 1e3:.1f}, events {gpu_ms:.1f}), policy={st['policy']} "
-        f"variants={st['variant_levels']} f64={st['f64_sources']} reached pairs={st['reached_pairs']}")
+        f"variants={st['variant_levels']} f64={st['f64_sources']} reached pairs={st['reached_pairs']} "
+        f"block engine workgroups={st['block_workgroups']} chunks={st['block_chunks']}")
     log("[bench] batched phase ms (fwd, sig, bwd, fin, bc):",
         [round(x, 1) for x in st["phase_ms"][1:6]], "variant ms:", [round(x, 1) for x in st["variant_ms"]])
     log("[bench] batched per phase: arcs", st["phase_arcs"][1:4], "lane arcs", st["phase_lane_arcs"][1:4],

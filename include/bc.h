@@ -101,6 +101,27 @@ bc_status bc_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr,
                           const int32_t *col_idx, uint32_t flags, bc_graph **out);
 
 /*
+ * Weighted graph: as bc_graph_create, plus int32 arc weights aligned with
+ * col_idx (host, or device with BC_INPUT_DEVICE like the CSR).  The paper's
+ * forward phase is "a BFS traversal or SSSP calculation" (Section
+ * "Background") and its layout keeps edge weights (Section "Space
+ * Complexity"): shortest paths minimise the sum of weights.  Every weight
+ * must be >= 1 (exact integer distances, so equal lengths are recognised
+ * exactly); an undirected graph must carry the same weight on both arcs of
+ * an edge (else BC_ERR_INVALID_GRAPH).  BC_DIRECTED is accepted (the library
+ * builds the in-arcs and their weights).  The handle keeps the caller's
+ * numbering and runs the weighted engine: a persistent launch in which every
+ * workgroup computes whole sources (distances by relaxation rounds, path
+ * counts over the shortest-path DAG in rounds of ready vertices, Eq. 2 over
+ * those rounds in reverse); uint64 path counts, redone in FP64 (unscaled; a
+ * count beyond the double range gives BC_ERR_SIGMA_RANGE) for sources whose
+ * counts overflow.  Run options other than flags and sigma_limit are ignored.
+ * bc_run_detail reports distances in bc_detail.d64.
+ */
+bc_status bc_graph_create_weighted(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                                   const int32_t *weights, uint32_t flags, bc_graph **out);
+
+/*
  * Block-diagonal union of n_graphs independent graphs, one handle.  Graph g
  * owns vertices [vtx_offsets[g], vtx_offsets[g+1]); vtx_offsets is host
  * int32[n_graphs + 1] with vtx_offsets[0] = 0 and vtx_offsets[n_graphs] = n.
@@ -157,6 +178,10 @@ bc_status bc_set_device_limit(bc_graph *g, int64_t max_device_bytes);
 #define BC_RUN_FORCE_F64   0x4u  /* test hook: evaluate every source in FP64 mode */
 #define BC_RUN_ONE_QUEUE   0x10u /* a handle over many graphs: run every batch on one
                                     level state machine instead of concurrent parts */
+#define BC_RUN_BLOCKS      0x20u /* batched work of graphs of at most 131072 vertices runs on
+                                    the block engine (one persistent launch; every workgroup
+                                    owns whole batches) even for short source lists       */
+#define BC_RUN_NO_BLOCKS   0x40u /* never use the block engine                               */
 #define BC_RUN_TUNED       0x8u  /* K, policy, workgroups, chunk and WPV threshold left
                                     automatic (zero) come from bc_autotune's result */
 
@@ -252,7 +277,9 @@ typedef struct bc_detail {
     int32_t *sigma_exp;
     double *delta;
     int32_t mode;
-    int32_t n_levels;
+    int32_t n_levels;   /* number of distinct distances of the source (largest d + 1 unweighted) */
+    int64_t *d64;       /* optional: distances as int64 (weighted graphs; d is then clamped to
+                           INT32_MAX); unweighted runs leave it untouched */
 } bc_detail;
 
 bc_status bc_run_detail(bc_graph *g, const int32_t *sources, int64_t n_sources,
@@ -295,6 +322,8 @@ typedef struct bc_stats {
     double mode_algo_bytes[2]; /* algorithmic bytes of those passes            */
     int64_t reached_pairs;     /* (vertex, source) pairs reached, sources included */
     double algo_bytes_arcs;    /* algo_bytes without the 40 B per reached pair  */
+    int64_t block_workgroups;  /* block engine: workgroups of its launch (0 = not used) */
+    int64_t block_chunks;      /* block engine: chunks of consecutive batches   */
 } bc_stats;
 
 bc_status bc_run_stats(const bc_graph *g, bc_stats *out);

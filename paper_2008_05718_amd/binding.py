@@ -32,6 +32,8 @@ BC_RUN_NO_GRAPHS = 0x2
 BC_RUN_FORCE_F64 = 0x4
 BC_RUN_TUNED = 0x8
 BC_RUN_ONE_QUEUE = 0x10
+BC_RUN_BLOCKS = 0x20
+BC_RUN_NO_BLOCKS = 0x40
 BC_OUT_DEVICE = 0x1
 
 BC_VARIANT_PUSH_TPV, BC_VARIANT_PUSH_WPV, BC_VARIANT_PULL = 0, 1, 2
@@ -43,7 +45,8 @@ BC_POLICY_FORCE_PUSH_WPV = 4
 BC_POLICY_FORCE_PULL = 5
 BC_MLP_PARAMS = 32 * 5 + 32 + 32 * 32 + 32 + 3 * 32 + 3
 
-EXPORTS = ["bc_status_string", "bc_last_error", "bc_graph_create", "bc_graph_create_multi", "bc_destroy",
+EXPORTS = ["bc_status_string", "bc_last_error", "bc_graph_create", "bc_graph_create_multi",
+           "bc_graph_create_weighted", "bc_destroy",
            "bc_graph_info", "bc_run_options_init", "bc_run", "bc_scores", "bc_run_detail", "bc_run_stats",
            "bc_load_policy", "bc_mlp_loss_grad", "bc_mlp_train", "bc_mlp_predict", "bc_collect_level_times",
            "bc_autotune", "bc_set_device_limit", "bc_run_level_stats", "bc_mlp_loss_grad_noalloc"]
@@ -71,7 +74,7 @@ class RunOptions(ctypes.Structure):
 class Detail(ctypes.Structure):
     _fields_ = [("d", ctypes.c_void_p), ("sigma_u64", ctypes.c_void_p), ("sigma_mant", ctypes.c_void_p),
                 ("sigma_exp", ctypes.c_void_p), ("delta", ctypes.c_void_p), ("mode", ctypes.c_int32),
-                ("n_levels", ctypes.c_int32)]
+                ("n_levels", ctypes.c_int32), ("d64", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -85,7 +88,8 @@ class Stats(ctypes.Structure):
                 ("phase_arcs", ctypes.c_int64 * 10), ("phase_lane_arcs", ctypes.c_int64 * 10),
                 ("phase_pairs", ctypes.c_int64 * 10), ("mode_launches", ctypes.c_int64 * 2),
                 ("mode_ms", ctypes.c_double * 2), ("mode_algo_bytes", ctypes.c_double * 2),
-                ("reached_pairs", ctypes.c_int64), ("algo_bytes_arcs", ctypes.c_double)]
+                ("reached_pairs", ctypes.c_int64), ("algo_bytes_arcs", ctypes.c_double),
+                ("block_workgroups", ctypes.c_int64), ("block_chunks", ctypes.c_int64)]
 
 
 class LevelStats(ctypes.Structure):
@@ -118,6 +122,8 @@ def lib():
     L.bc_last_error.argtypes = []
     L.bc_graph_create.restype = ctypes.c_int
     L.bc_graph_create.argtypes = [I32, I64, P, P, U32, ctypes.POINTER(P)]
+    L.bc_graph_create_weighted.restype = ctypes.c_int
+    L.bc_graph_create_weighted.argtypes = [I32, I64, P, P, P, U32, ctypes.POINTER(P)]
     L.bc_graph_create_multi.restype = ctypes.c_int
     L.bc_graph_create_multi.argtypes = [I32, P, I32, I64, P, P, U32, ctypes.POINTER(P)]
     L.bc_destroy.restype = None
@@ -209,6 +215,20 @@ def bc_graph_create(row_ptr, col_idx, flags: int = 0):
     return h
 
 
+def bc_graph_create_weighted(row_ptr, col_idx, weights, flags: int = 0):
+    rp, keep1, dev1 = _ptr_i32(row_ptr)
+    ci, keep2, dev2 = _ptr_i32(col_idx)
+    wt, keep3, dev3 = _ptr_i32(weights)
+    if not (dev1 == dev2 == dev3):
+        raise TypeError("row_ptr, col_idx and weights must all be host or all be device arrays")
+    n = (keep1.shape[0] if not _is_torch(keep1) else keep1.numel()) - 1
+    nnz = keep2.shape[0] if not _is_torch(keep2) else keep2.numel()
+    h = ctypes.c_void_p()
+    _check(lib().bc_graph_create_weighted(n, nnz, rp, ci, wt, flags | (BC_INPUT_DEVICE if dev1 else 0),
+                                          ctypes.byref(h)))
+    return h
+
+
 def bc_graph_create_multi(vtx_offsets, row_ptr, col_idx, flags: int = 0):
     vo = np.ascontiguousarray(vtx_offsets, dtype=np.int32)
     rp, keep1, dev1 = _ptr_i32(row_ptr)
@@ -269,9 +289,9 @@ def bc_run_detail(h, sources, dump_index: int, options: RunOptions | None = None
     n = bc_graph_info(h)["n"]
     p, ns, keep = _sources(sources)
     r = {"d": np.zeros(n, np.int32), "sigma_u64": np.zeros(n, np.uint64), "sigma_mant": np.zeros(n, np.float64),
-         "sigma_exp": np.zeros(n, np.int32), "delta": np.zeros(n, np.float64)}
+         "sigma_exp": np.zeros(n, np.int32), "delta": np.zeros(n, np.float64), "d64": np.full(n, -1, np.int64)}
     det = Detail()
-    for k in ("d", "sigma_u64", "sigma_mant", "sigma_exp", "delta"):
+    for k in ("d", "sigma_u64", "sigma_mant", "sigma_exp", "delta", "d64"):
         setattr(det, k, r[k].ctypes.data_as(ctypes.c_void_p))
     _check(lib().bc_run_detail(h, p, ns, ctypes.byref(options) if options is not None else None, int(dump_index),
                                ctypes.byref(det), _stream(stream)))
@@ -406,13 +426,17 @@ class Graph:
     """Owning handle: ``with Graph(csr) as g: g.run(sources); g.scores()``."""
 
     def __init__(self, csr=None, row_ptr=None, col_idx=None, vtx_offsets=None, flags: int = 0):
+        weights = None
         if csr is not None:
             row_ptr, col_idx = csr.row_ptr, csr.col_idx
             if getattr(csr, "directed", False):
                 flags |= BC_DIRECTED
+            weights = getattr(csr, "weights", None)
             if vtx_offsets is None and getattr(csr, "vtx_offsets", None) is not None and len(csr.vtx_offsets) > 2:
                 vtx_offsets = csr.vtx_offsets
-        if vtx_offsets is not None:
+        if weights is not None:
+            self.h = bc_graph_create_weighted(row_ptr, col_idx, weights, flags)
+        elif vtx_offsets is not None:
             self.h = bc_graph_create_multi(vtx_offsets, row_ptr, col_idx, flags)
         else:
             self.h = bc_graph_create(row_ptr, col_idx, flags)

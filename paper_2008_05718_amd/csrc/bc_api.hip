@@ -18,6 +18,8 @@
 namespace bcx {
 template <int MODE> __global__ void plain_step(PlainArgs a);
 template <int MODE> __global__ void batch_step(BatchArgs a);
+template <int MODE> __global__ void block_run(BlockArgs a);
+template <int MODE> __global__ void weighted_run(WeightedArgs a);
 }  // namespace bcx
 
 using namespace bcx;
@@ -166,6 +168,20 @@ struct bc_graph {
     // directed graphs: row_ptr / col are the out-arcs, these the in-arcs
     bool directed = false;
     int32_t *in_row_ptr = nullptr, *in_col = nullptr;
+    // weighted graphs: arc weights aligned with col and with in_col (the
+    // same array for an undirected graph); the weighted engine's state
+    bool weighted = false;
+    int32_t *wt = nullptr, *in_wt = nullptr;
+    int w_wg = 0;                     // workgroups whose state is allocated
+    size_t w_stride = 0;
+    char *w_scratch = nullptr;
+    unsigned long long *w_ctr = nullptr;  // [0] work queue, [1] overflow count, [2] error bits, [4..7] statistics
+    int32_t *w_chunk = nullptr;       // s0, s1, order
+    int64_t w_chunk_cap = 0;
+    int64_t *w_pos = nullptr;
+    int64_t w_pos_cap = 0;
+    double *w_partials = nullptr;
+    int64_t w_partials_cap = 0;
     int64_t nonisolated = 0;
     // vertices of degree > kSegBatched (ascending) and their segment prefix
     // sums; p_*: the same for the plain engine's kSegPlain
@@ -234,6 +250,24 @@ struct bc_graph {
     std::vector<int32_t> part_of_graph, local_base;  // per parent graph
     bool replicas = false;  // parts are full copies of a single graph (see ensure_replicas)
     bool parts_refused = false;  // concurrent parts would not fit under the cap (see parts_fit)
+    // block engine (graphs of at most kBlockMaxN vertices; see run_block)
+    bool blk_sized = false;            // per-graph facts below are computed
+    int32_t blk_nmax = 0;              // largest graph
+    int64_t blk_cost_max = 0, blk_heavy_max = 0, blk_segs_max = 0;
+    int blk_wg = 0;                    // workgroups whose state is allocated
+    size_t blk_stride = 0;
+    BlockArgs blk_dims{};              // capacities of one workgroup's state
+    char *blk_scratch = nullptr;
+    Ctl *blk_ctls = nullptr;
+    int32_t *blk_chunk = nullptr;      // b0, b1, order (3 x n_chunks), grown per run
+    int64_t blk_chunk_cap = 0;
+    int64_t *blk_part_off = nullptr;
+    int64_t blk_part_off_cap = 0;
+    double *blk_partials = nullptr;
+    int64_t blk_partials_cap = 0;
+    int32_t *blk_gsum = nullptr;       // per graph: lo, hi, first chunk, end chunk
+    int64_t blk_gsum_cap = 0;
+    uint32_t *blk_next = nullptr;
     // graph cache
     std::vector<CachedGraph> graphs;
     bc_stats stats{};
@@ -264,14 +298,17 @@ extern "C" void bc_destroy(bc_graph *g) {
     (void)hipDeviceSynchronize();
     free_parts(g);
     free_graphs(g);
-    void *dev[] = {g->row_ptr, g->col, g->in_row_ptr, g->in_col, g->bc, g->ctl, g->p_d, g->p_queue, g->p_level_off, g->p_shift,
+    void *dev[] = {g->row_ptr, g->col, g->in_row_ptr, g->in_col, g->wt,
+                   g->in_wt == g->wt ? nullptr : g->in_wt, g->w_scratch, g->w_ctr, g->w_chunk, g->w_pos,
+                   g->w_partials, g->bc, g->ctl, g->p_d, g->p_queue, g->p_level_off, g->p_shift,
                    g->p_sig, g->p_chat, g->b_vn, g->b_fw0, g->b_fw1, g->b_lq_vtx, g->b_lq_mask,
                    g->b_level_off, g->b_delta, g->b_chat, g->b_shift, g->b_maxexp, g->b_lane_src,
                    g->b_sigma, g->b_gstart, g->b_gbase, g->inv_dev, g->bc_out,
                    g->srcs, g->ovf, g->bstart, g->blo, g->bhi, g->mlp, g->hv_vtx, g->hv_seg, g->p_hv_vtx, g->p_hv_seg,
                    g->p_hq.pos, g->p_hq.seg, g->p_hq.cnt, g->p_hq.off, g->p_hq.nseg, g->p_hq.part_lo,
                    g->p_hq.part_hi, g->b_hq.pos, g->b_hq.seg, g->b_hq.cnt, g->b_hq.off, g->b_hq.nseg,
-                   g->b_hq.part_lo, g->b_hq.part_hi, g->lvl};
+                   g->b_hq.part_lo, g->b_hq.part_hi, g->lvl, g->blk_scratch, g->blk_ctls, g->blk_chunk,
+                   g->blk_part_off, g->blk_partials, g->blk_gsum, g->blk_next};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (g->ctl_host) (void)hipHostFree(g->ctl_host);
@@ -364,7 +401,8 @@ static void source_ranks(int32_t n_graphs, const std::vector<int32_t> &voff, con
 }
 
 static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n, int64_t nnz,
-                             const int32_t *row_ptr, const int32_t *col_idx, uint32_t flags, bc_graph **out) {
+                             const int32_t *row_ptr, const int32_t *col_idx, uint32_t flags, bc_graph **out,
+                             const int32_t *weights = nullptr) {
     if (!out) return fail(BC_ERR_INVALID_ARG, "out is NULL");
     if (n < 0 || n >= INT32_MAX - 2) return fail(BC_ERR_INVALID_ARG, "n out of range");
     if (nnz < 0 || nnz > INT32_MAX) return fail(BC_ERR_INVALID_ARG, "nnz out of range (must be <= 2^31-1)");
@@ -384,8 +422,12 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
     if (directed && n_graphs > 1)
         return fail(BC_ERR_NOT_SUPPORTED, "directed graphs are supported one per handle (bc_graph_create)");
     if (directed) flags |= BC_SKIP_SYMMETRY_CHECK | BC_KEEP_ORDER;
+    if (weights && n_graphs > 1)
+        return fail(BC_ERR_NOT_SUPPORTED, "weighted graphs are supported one per handle (bc_graph_create_weighted)");
+    if (weights) flags |= BC_KEEP_ORDER;  // weights stay aligned with the caller's arcs
     bc_graph *g = new bc_graph();
     g->directed = directed;
+    g->weighted = weights != nullptr;
     g->n = n;
     g->nnz = nnz;
     g->n_graphs = n_graphs;
@@ -474,6 +516,16 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
             for (int32_t u = 0; u < n; ++u)  // sources in ascending order: every in-row comes out sorted
                 for (int32_t k = rp[u]; k < rp[u + 1]; ++k) icol[fill[col[k]]++] = u;
             for (int32_t v = 0; v < n; ++v) cdeg[v] = std::max(cdeg[v], irp[v + 1] - irp[v]);
+            if (weights) {  // the in-arcs carry the weight of the same arc
+                std::vector<int32_t> w((size_t)nnz), iw((size_t)nnz);
+                if (nnz) CR_TRY(hipMemcpy(w.data(), weights, sizeof(int32_t) * (size_t)nnz,
+                                          on_dev ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+                std::vector<int32_t> fill2(irp.begin(), irp.end() - 1);
+                for (int32_t u = 0; u < n; ++u)
+                    for (int32_t k = rp[u]; k < rp[u + 1]; ++k) iw[fill2[col[k]]++] = w[k];
+                CR_TRY(dalloc(&g->in_wt, (size_t)nnz, &g->acct));
+                if (nnz) CR_TRY(hipMemcpy(g->in_wt, iw.data(), sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice));
+            }
             CR_TRY(dalloc(&g->in_row_ptr, (size_t)n + 1, &g->acct));
             CR_TRY(dalloc(&g->in_col, (size_t)nnz, &g->acct));
             CR_TRY(hipMemcpy(g->in_row_ptr, irp.data(), sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice));
@@ -543,6 +595,38 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
         // (one list per engine segment size)
         if (!directed)  // after any renumbering
             for (int32_t v = 0; v < n; ++v) cdeg[v] = rp[v + 1] - rp[v];
+        if (weights) {
+            // every weight >= 1; an undirected graph carries the same weight on
+            // both arcs of an edge
+            std::vector<int32_t> w((size_t)nnz), col((size_t)nnz);
+            if (nnz) {
+                CR_TRY(hipMemcpy(w.data(), weights, sizeof(int32_t) * (size_t)nnz,
+                                 on_dev ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+                CR_TRY(hipMemcpy(col.data(), g->col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToHost));
+            }
+            bool ok = true;
+            for (int64_t k = 0; k < nnz && ok; ++k) ok = w[k] >= 1;
+            if (!ok) {
+                fail(BC_ERR_INVALID_GRAPH, "invalid weights: every arc weight must be >= 1");
+                return bail(BC_ERR_INVALID_GRAPH);
+            }
+            if (!directed) {
+                for (int32_t u = 0; u < n && ok; ++u)
+                    for (int32_t k = rp[u]; k < rp[u + 1] && ok; ++k) {
+                        const int32_t v = col[k];
+                        const int32_t *b0 = col.data() + rp[v], *b1 = col.data() + rp[v + 1];
+                        const int32_t *f = std::lower_bound(b0, b1, u);
+                        ok = f != b1 && *f == u && w[(size_t)(f - col.data())] == w[k];
+                    }
+                if (!ok) {
+                    fail(BC_ERR_INVALID_GRAPH, "invalid weights: the two arcs of an undirected edge differ");
+                    return bail(BC_ERR_INVALID_GRAPH);
+                }
+            }
+            CR_TRY(dalloc(&g->wt, (size_t)nnz, &g->acct));
+            if (nnz) CR_TRY(hipMemcpy(g->wt, w.data(), sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice));
+            if (!directed) g->in_wt = g->wt;
+        }
         int64_t cost_units = 0;
         for (int32_t v = 0; v < n; ++v) cost_units += entry_cost(cdeg[v]);
         g->cost_units = cost_units;
@@ -600,6 +684,14 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
 extern "C" bc_status bc_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                                      uint32_t flags, bc_graph **out) {
     return create_impl(1, nullptr, n, nnz, row_ptr, col_idx, flags, out);
+}
+
+extern "C" bc_status bc_graph_create_weighted(int32_t n, int64_t nnz, const int32_t *row_ptr,
+                                              const int32_t *col_idx, const int32_t *weights, uint32_t flags,
+                                              bc_graph **out) {
+    if (!weights && nnz > 0) return fail(BC_ERR_INVALID_ARG, "NULL weights");
+    static const int32_t one = 1;
+    return create_impl(1, nullptr, n, nnz, row_ptr, col_idx, flags, out, weights ? weights : &one);
 }
 
 extern "C" bc_status bc_graph_create_multi(int32_t n_graphs, const int32_t *vtx_offsets, int32_t n, int64_t nnz,
@@ -915,6 +1007,7 @@ struct DumpBufs {
     unsigned long long *sig = nullptr;
     double *delta = nullptr;
     int32_t *shift = nullptr;
+    int64_t *d64 = nullptr;  // weighted graphs: distances
 };
 
 // Algorithmic bytes: every scanned arc reads its column index and a 4-8 byte
@@ -1229,6 +1322,537 @@ __global__ void sum_parts_f64(double *dst, PartScores ps, int acc, int64_t n) {
         for (int k = 1; k < ps.n; ++k) t += ps.p[k][i];
         dst[i] = acc ? dst[i] + t : t;
     }
+}
+
+// ------------------------------------------------------------ block engine
+// Graphs of at most kBlockMaxN vertices: one persistent launch of block_run
+// in which every workgroup owns a level state machine and works through
+// chunks of consecutive batches of one graph (see bc_dev.h).  A chunk's
+// scores go to a partial vector; block_sum then adds, for every vertex, the
+// partials of its graph's chunks in batch order.  The result is
+// deterministic for a given run (the chunking depends only on the graph
+// sizes, the source list and the number of workgroups), but the additions
+// are grouped per chunk, so it agrees with one level state machine to
+// rounding only.  Capacities of a workgroup's state are sized for the
+// largest graph with a margin; a run that exceeds one (or overflows a
+// workgroup's list of 64-bit overflows) is run again by the general engine.
+
+// dst[v] += partial scores of v's graph, chunk by chunk in batch order.
+// gsum: per graph with chunks {lo, hi, first, end} into lst (part offsets).
+__global__ void block_sum(double *dst, const double *partials, const int32_t *gsum, int32_t n_gsum,
+                          const int64_t *lst) {
+    for (int32_t k = blockIdx.y; k < n_gsum; k += gridDim.y) {
+        const int32_t lo = gsum[4 * k], hi = gsum[4 * k + 1], c0 = gsum[4 * k + 2], c1 = gsum[4 * k + 3];
+        for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < hi - lo; i += gridDim.x * blockDim.x) {
+            double t = dst[lo + i];
+            for (int32_t c = c0; c < c1; ++c) t += partials[lst[c] + i];
+            dst[lo + i] = t;
+        }
+    }
+}
+
+// Zero the two tagged frontier arrays of every workgroup (tags restart each run).
+__global__ void block_clear_tags(char *scratch, size_t stride, size_t off, size_t bytes, int nwg) {
+    const size_t words = bytes / 8;
+    for (int w = blockIdx.y; w < nwg; w += gridDim.y) {
+        unsigned long long *p = (unsigned long long *)(scratch + (size_t)w * stride + off);
+        for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
+            p[i] = 0ull;
+    }
+}
+
+// Largest graph, cost units, heavy vertices and segments over the handle's
+// graphs (entries classified by the larger of out- and in-degree).
+static bc_status block_facts(bc_graph *g) {
+    if (g->blk_sized) return BC_OK;
+    const int32_t n = g->n;
+    std::vector<int32_t> rp((size_t)n + 1), irp;
+    HIP_TRY(hipMemcpy(rp.data(), g->row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost));
+    if (g->directed) {
+        irp.resize((size_t)n + 1);
+        HIP_TRY(hipMemcpy(irp.data(), g->in_row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost));
+    }
+    int32_t nmax = 0;
+    int64_t cmax = 0, hmax = 0, smax = 0;
+    for (int gi = 0; gi < g->n_graphs; ++gi) {
+        const int32_t lo = g->voff[gi], hi = g->voff[gi + 1];
+        int64_t cost = 0, heavy = 0, segs = 0;
+        for (int32_t v = lo; v < hi; ++v) {
+            int32_t d = rp[v + 1] - rp[v];
+            if (g->directed) d = std::max(d, irp[v + 1] - irp[v]);
+            cost += entry_cost(d);
+            if (d > kSegBatched) {
+                ++heavy;
+                segs += (d + kSegBatched - 1) / kSegBatched;
+            }
+        }
+        nmax = std::max(nmax, hi - lo);
+        cmax = std::max(cmax, cost);
+        hmax = std::max(hmax, heavy);
+        smax = std::max(smax, segs);
+    }
+    g->blk_nmax = nmax;
+    g->blk_cost_max = cmax;
+    g->blk_heavy_max = hmax;
+    g->blk_segs_max = smax;
+    g->blk_sized = true;
+    return BC_OK;
+}
+
+// Capacities of one workgroup's state (once per handle) and how many
+// workgroups can run: resident ones (occupancy) that fit in the memory
+// budget (half the free device memory, at most 96 GiB, under the handle's
+// cap).  Returns 0 workgroups when not even one fits.
+static bc_status block_dims(bc_graph *g, int *resident) {
+    BlockArgs &d = g->blk_dims;
+    const int64_t nmax = std::max<int32_t>(g->blk_nmax, 1);
+    d.nmax = (int32_t)nmax;
+    d.max_levels = (int32_t)std::min<int64_t>(nmax + 2, 4096);
+    // every (vertex, lane) pair enters a batch's queues at most once: small
+    // graphs get that bound, larger ones 16 entries per vertex
+    d.lq_cap = (uint32_t)std::min<int64_t>(std::max<int64_t>(16 * nmax + 4096, (int64_t)1 << 20),
+                                           (int64_t)kLanes * nmax + 64);
+    d.gcap = (uint32_t)((int64_t)kLanes * g->blk_cost_max / kBudget + 2 * ((int64_t)d.max_levels + 2) + 64);
+    d.hq_entries = (uint32_t)(g->blk_heavy_max * kLanes + kLanes);
+    d.hq_levels = (uint32_t)d.max_levels + 3;
+    d.part_cap = (uint32_t)(g->blk_segs_max + 1);
+    d.ovf_cap = 4096;
+    const BlockLayout L((size_t)d.nmax, d.lq_cap, (size_t)d.max_levels, d.gcap, d.hq_entries, d.hq_levels,
+                        d.part_cap, d.ovf_cap);
+    g->blk_stride = L.bytes;
+    int dev = 0, cus = 0, per_cu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)block_run<0>, kBlock, 0));
+    int64_t want = (int64_t)std::max(1, cus) * std::max(1, per_cu);
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    // what this handle already holds for the block engine counts as free
+    free_b += (size_t)g->blk_wg * (g->blk_stride + sizeof(Ctl));
+    size_t budget = std::min<size_t>(free_b / 4 * 3, (size_t)192 << 30);
+    if (g->acct.limit) {
+        const size_t held = (size_t)g->blk_wg * (g->blk_stride + sizeof(Ctl));
+        const size_t room = g->acct.limit > g->acct.bytes - held ? g->acct.limit - (g->acct.bytes - held) : 0;
+        budget = std::min(budget, room);
+    }
+    want = std::min<int64_t>(want, (int64_t)(budget / (g->blk_stride + sizeof(Ctl))));
+    *resident = (int)std::max<int64_t>(want, 0);
+    return BC_OK;
+}
+
+// State for `need` workgroups (kept and grown across runs).
+static bc_status ensure_block(bc_graph *g, int need) {
+    if (g->blk_wg >= need) return BC_OK;
+    if (g->blk_scratch) {
+        HIP_TRY(hipStreamSynchronize(nullptr));
+        (void)hipFree(g->blk_scratch);
+        (void)hipFree(g->blk_ctls);
+        g->acct.bytes -= (size_t)g->blk_wg * (g->blk_stride + sizeof(Ctl));
+        g->blk_scratch = nullptr;
+        g->blk_ctls = nullptr;
+        g->blk_wg = 0;
+    }
+    HIP_TRY(dalloc(&g->blk_scratch, (size_t)need * g->blk_stride, &g->acct));
+    HIP_TRY(dalloc(&g->blk_ctls, (size_t)need, &g->acct));
+    if (!g->blk_next) HIP_TRY(dalloc(&g->blk_next, 1, &g->acct));
+    g->blk_wg = need;
+    return BC_OK;
+}
+
+// The block engine is used for runs of the batched engine without a detail
+// dump over handles whose graphs all have at most kBlockMaxN vertices, always
+// with BC_RUN_BLOCKS, never with BC_RUN_NO_BLOCKS or BC_RUN_ONE_QUEUE, and by
+// default when every graph has at most kBlockDefaultN vertices and the list
+// fills 8 batches.  (A workgroup holds fewer wavefronts than a CU can run,
+// so on larger graphs, whose level steps keep the whole GPU busy, the
+// general engine is faster: 38.0 against 29.4 GTEPS on the BA union
+// sample; on ER(2000) the block engine is faster, 2.36 against 1.65.)
+constexpr int kBlockDefaultN = 16384;
+static bool use_block(bc_graph *g, const bc_run_options &o, int64_t ns, bool detail) {
+    if (g->weighted || detail || o.batch == 1 || (o.flags & (BC_RUN_NO_BLOCKS | BC_RUN_ONE_QUEUE | BC_RUN_FORCE_F64)))
+        return false;
+    if (o.batch == 0 && ns < 2) return false;
+    if (block_facts(g) != BC_OK || g->blk_nmax > kBlockMaxN || g->blk_nmax < 1) return false;
+    if (o.flags & BC_RUN_BLOCKS) return true;
+    const int K = o.batch >= 8 ? o.batch : 64;
+    return g->blk_nmax <= kBlockDefaultN && ns >= 8 * (int64_t)K;
+}
+
+// One 64-bit pass over h_srcs on the block engine.  *fallback = true when a
+// workgroup's capacity was exceeded or its state does not fit: nothing was
+// added to the scores and the caller runs the general engine instead.
+static bc_status run_block(bc_graph *g, const RunCfg &cfg, const bc_run_options &o, const int32_t *h_srcs,
+                           int64_t ns, hipStream_t st, std::vector<int64_t> *ovf_positions, bool *fallback) {
+    *fallback = false;
+    ovf_positions->clear();
+    if (ns == 0) return BC_OK;
+    int resident = 0;
+    bc_status s = block_dims(g, &resident);
+    if (s != BC_OK) return s;
+    if (resident < 1) {
+        *fallback = true;
+        return BC_OK;
+    }
+    const BlockArgs &dm = g->blk_dims;
+    s = grow(&g->srcs, &g->srcs_cap, ns, &g->acct);
+    if (s != BC_OK) return s;
+    HIP_TRY(hipMemcpyAsync(g->srcs, h_srcs, sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
+    // batches of up to K sources of one graph (as in the general engine)
+    std::vector<int64_t> bs;
+    std::vector<int32_t> blo, bhi, bg;
+    for (int64_t i = 0; i < ns;) {
+        const int32_t v = h_srcs[i];
+        const int gi = (int)(std::upper_bound(g->voff.begin(), g->voff.end(), v) - g->voff.begin()) - 1;
+        const int32_t glo = g->voff[gi], ghi = g->voff[gi + 1];
+        int64_t j = i + 1;
+        while (j < ns && j - i < cfg.lanes && h_srcs[j] >= glo && h_srcs[j] < ghi) ++j;
+        bs.push_back(i);
+        blo.push_back(glo);
+        bhi.push_back(ghi);
+        bg.push_back(gi);
+        i = j;
+    }
+    bs.push_back(ns);
+    const int64_t nb = (int64_t)blo.size();
+    // chunks: runs of at most C consecutive batches of one graph, about four
+    // per resident workgroup
+    const int64_t C =
+        std::min<int64_t>(64, std::max<int64_t>(1, (nb + 4 * (int64_t)resident - 1) / (4 * (int64_t)resident)));
+    std::vector<int32_t> cb0, cb1;
+    for (int64_t b = 0; b < nb;) {
+        int64_t e = b + 1;
+        while (e < nb && e - b < C && bg[e] == bg[b]) ++e;
+        cb0.push_back((int32_t)b);
+        cb1.push_back((int32_t)e);
+        b = e;
+    }
+    const int64_t nc = (int64_t)cb0.size();
+    const int nwg = (int)std::min<int64_t>(resident, nc);
+    s = ensure_block(g, nwg);
+    if (s == BC_ERR_OUT_OF_MEMORY) {  // the general engine needs less: let it run
+        *fallback = true;
+        return BC_OK;
+    }
+    if (s != BC_OK) return s;
+    std::vector<int64_t> part_off((size_t)nc);
+    int64_t tot = 0;
+    for (int64_t t = 0; t < nc; ++t) {
+        part_off[t] = tot;
+        tot += bhi[cb0[t]] - blo[cb0[t]];
+    }
+    // per graph, its chunks in batch order (the summation order)
+    std::vector<std::vector<int64_t>> per_graph((size_t)g->n_graphs);
+    for (int64_t t = 0; t < nc; ++t) per_graph[bg[cb0[t]]].push_back(t);
+    std::vector<int32_t> gsum;
+    std::vector<int64_t> lst;
+    for (int gi = 0; gi < g->n_graphs; ++gi) {
+        if (per_graph[gi].empty()) continue;
+        gsum.push_back(g->voff[gi]);
+        gsum.push_back(g->voff[gi + 1]);
+        gsum.push_back((int32_t)lst.size());
+        for (int64_t t : per_graph[gi]) lst.push_back(part_off[t]);
+        gsum.push_back((int32_t)lst.size());
+    }
+    // dispatch order: largest work (vertices x sources of the chunk) first
+    std::vector<int32_t> order((size_t)nc);
+    for (int64_t t = 0; t < nc; ++t) order[t] = (int32_t)t;
+    std::vector<double> work((size_t)nc);
+    for (int64_t t = 0; t < nc; ++t)
+        work[t] = (double)(bhi[cb0[t]] - blo[cb0[t]]) * (double)(bs[cb1[t]] - bs[cb0[t]]);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a_, int32_t b_) { return work[a_] > work[b_]; });
+    // device copies
+    s = grow(&g->bstart, &g->bcap[0], nb + 1, &g->acct);
+    if (s == BC_OK) s = grow(&g->blo, &g->bcap[1], nb + 1, &g->acct);
+    if (s == BC_OK) s = grow(&g->bhi, &g->bcap[2], nb + 1, &g->acct);
+    if (s == BC_OK) s = grow(&g->blk_chunk, &g->blk_chunk_cap, 3 * nc, &g->acct);
+    if (s == BC_OK) s = grow(&g->blk_part_off, &g->blk_part_off_cap, std::max<int64_t>(nc, (int64_t)lst.size()) * 2, &g->acct);
+    if (s == BC_OK) s = grow(&g->blk_partials, &g->blk_partials_cap, std::max<int64_t>(tot, 1), &g->acct);
+    if (s == BC_OK) s = grow(&g->blk_gsum, &g->blk_gsum_cap, std::max<int64_t>((int64_t)gsum.size(), 4), &g->acct);
+    if (s != BC_OK) {
+        if (s == BC_ERR_OUT_OF_MEMORY) {  // the general engine needs less: let it run
+            *fallback = true;
+            return BC_OK;
+        }
+        return s;
+    }
+    std::vector<int32_t> chunk_host;
+    chunk_host.insert(chunk_host.end(), cb0.begin(), cb0.end());
+    chunk_host.insert(chunk_host.end(), cb1.begin(), cb1.end());
+    chunk_host.insert(chunk_host.end(), order.begin(), order.end());
+    std::vector<int64_t> offs(part_off);
+    offs.insert(offs.end(), lst.begin(), lst.end());
+    HIP_TRY(hipMemcpyAsync(g->bstart, bs.data(), sizeof(int64_t) * bs.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(g->blo, blo.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(g->bhi, bhi.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(g->blk_chunk, chunk_host.data(), sizeof(int32_t) * chunk_host.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(g->blk_part_off, offs.data(), sizeof(int64_t) * offs.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(g->blk_gsum, gsum.data(), sizeof(int32_t) * gsum.size(), hipMemcpyHostToDevice, st));
+    // control blocks and tags
+    std::vector<Ctl> hc((size_t)nwg);
+    for (Ctl &c : hc) {
+        init_ctl(&c);
+        c.policy = cfg.policy;
+        c.mode = 0;
+    }
+    HIP_TRY(hipMemcpyAsync(g->blk_ctls, hc.data(), sizeof(Ctl) * hc.size(), hipMemcpyHostToDevice, st));
+    {
+        const BlockLayout L((size_t)dm.nmax, dm.lq_cap, (size_t)dm.max_levels, dm.gcap, dm.hq_entries, dm.hq_levels,
+                            dm.part_cap, dm.ovf_cap);
+        dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)dm.nmax * 4 / 256 + 1)),
+                  (unsigned)std::min(nwg, 65535));
+        block_clear_tags<<<grid, 256, 0, st>>>(g->blk_scratch, g->blk_stride, L.fw0, L.fw1 - L.fw0 + (size_t)dm.nmax * sizeof(Tagged), nwg);
+    }
+    fill_u64<<<1, 64, 0, st>>>((unsigned long long *)g->blk_next, 1, 0ull);
+    HIP_TRY(hipGetLastError());
+    BlockArgs ra = dm;
+    std::memset(&ra.a, 0, sizeof(ra.a));
+    GraphArgs ga;
+    ga.n = g->n;
+    ga.nnz_lo = (int32_t)g->nnz;
+    ga.row_ptr = g->row_ptr;
+    ga.col = g->col;
+    ga.directed = g->directed ? 1 : 0;
+    ga.in_row_ptr = g->directed ? g->in_row_ptr : g->row_ptr;
+    ga.in_col = g->directed ? g->in_col : g->col;
+    ga.nonisolated = g->nonisolated;
+    ga.hv_vtx = g->hv_vtx;
+    ga.hv_seg = g->hv_seg;
+    ga.n_heavy = g->n_heavy;
+    ra.a.g = ga;
+    ra.a.p = policy_args(g, o);
+    ra.a.srcs = g->srcs;
+    ra.a.batch_start = g->bstart;
+    ra.a.batch_lo = g->blo;
+    ra.a.batch_hi = g->bhi;
+    ra.a.sigma_limit = o.sigma_limit > 0 ? (unsigned long long)o.sigma_limit : ~0ull;
+    ra.scratch = g->blk_scratch;
+    ra.stride = g->blk_stride;
+    ra.ctls = g->blk_ctls;
+    ra.c_b0 = g->blk_chunk;
+    ra.c_b1 = g->blk_chunk + nc;
+    ra.order = g->blk_chunk + 2 * nc;
+    ra.c_part = g->blk_part_off;
+    ra.n_chunks = (int32_t)nc;
+    ra.next = g->blk_next;
+    ra.partials = g->blk_partials;
+    ra.max_steps = 3 * ((int64_t)dm.max_levels + 2) + 16;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, st));
+    block_run<0><<<(unsigned)nwg, kBlock, 0, st>>>(ra);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipMemcpyAsync(hc.data(), g->blk_ctls, sizeof(Ctl) * hc.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const int used = nwg;
+    for (int w = 0; w < used; ++w)
+        if (hc[w].err) {
+            *fallback = true;
+            return BC_OK;
+        }
+    // scores: partials of every graph, chunk by chunk
+    if (!gsum.empty()) {
+        const int32_t ng = (int32_t)(gsum.size() / 4);
+        dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)dm.nmax / 256 + 1)),
+                  (unsigned)std::min(ng, 65535));
+        block_sum<<<grid, 256, 0, st>>>(g->bc, g->blk_partials, g->blk_gsum, ng, g->blk_part_off + nc);
+        HIP_TRY(hipGetLastError());
+    }
+    const double bytes0 = algo_bytes(g->stats);
+    for (int w = 0; w < used; ++w) {
+        accumulate_stats(&g->stats, hc[w], g->clock_khz);
+        if (hc[w].n_ovf) {
+            std::vector<int64_t> tmp(hc[w].n_ovf);
+            const BlockLayout L((size_t)dm.nmax, dm.lq_cap, (size_t)dm.max_levels, dm.gcap, dm.hq_entries,
+                                dm.hq_levels, dm.part_cap, dm.ovf_cap);
+            HIP_TRY(hipMemcpy(tmp.data(), g->blk_scratch + (size_t)w * g->blk_stride + L.ovf,
+                              sizeof(int64_t) * tmp.size(), hipMemcpyDeviceToHost));
+            ovf_positions->insert(ovf_positions->end(), tmp.begin(), tmp.end());
+        }
+    }
+    std::sort(ovf_positions->begin(), ovf_positions->end());
+    g->stats.launches += 1;
+    g->stats.mode_launches[0] += 1;
+    g->stats.mode_ms[0] += ms;
+    g->stats.mode_algo_bytes[0] += algo_bytes(g->stats) - bytes0;
+    g->stats.block_workgroups = used;
+    g->stats.block_chunks = nc;
+    HIP_TRY(hipStreamSynchronize(st));
+    return BC_OK;
+}
+
+// --------------------------------------------------------- weighted engine
+// Graphs with arc weights: one persistent launch of weighted_run per pass,
+// every workgroup computing whole sources (chunks of consecutive positions)
+// on a private copy of the per-vertex state; a chunk's scores go to a
+// partial vector, added in chunk order by sum_partials.  First a 64-bit pass
+// over every source, then an FP64 pass over the sources whose path counts
+// overflowed.
+
+// dst[v] += sum over chunks t (in order) of partials[t * n + v]
+__global__ void sum_partials(double *dst, const double *partials, int64_t n, int64_t n_chunks) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        double t = dst[v];
+        for (int64_t c = 0; c < n_chunks; ++c) t += partials[c * n + v];
+        dst[v] = t;
+    }
+}
+
+static bc_status ensure_weighted(bc_graph *g) {
+    if (g->w_wg > 0) return BC_OK;
+    const WeightedLayout L((size_t)std::max<int32_t>(g->n, 1));
+    g->w_stride = L.bytes;
+    int dev = 0, cus = 0, per_cu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)weighted_run<0>, kBlock, 0));
+    int64_t want = (int64_t)std::max(1, cus) * std::max(1, std::min(per_cu, 2));
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    size_t budget = std::min<size_t>(free_b / 2, (size_t)64 << 30);
+    if (g->acct.limit) budget = std::min(budget, g->acct.limit > g->acct.bytes ? g->acct.limit - g->acct.bytes : 0);
+    want = std::min<int64_t>(want, (int64_t)(budget / g->w_stride));
+    if (want < 1) return fail(BC_ERR_OUT_OF_MEMORY, "the weighted engine's per-workgroup state does not fit");
+    HIP_TRY(dalloc(&g->w_scratch, (size_t)want * g->w_stride, &g->acct));
+    HIP_TRY(dalloc(&g->w_ctr, 8, &g->acct));
+    g->w_wg = (int)want;
+    return BC_OK;
+}
+
+// One pass over the run positions `pos` (sources h_srcs[pos[i]]) with the
+// given path-count mode; overflowed positions (mode 0) are returned.
+static bc_status weighted_pass(bc_graph *g, int mode, const bc_run_options &o, const int32_t *h_srcs,
+                               const std::vector<int64_t> &pos, int64_t dump_pos_run, DumpBufs *dump, hipStream_t st,
+                               std::vector<int64_t> *ovf, bool *dumped) {
+    ovf->clear();
+    if (pos.empty()) return BC_OK;
+    bc_status s = ensure_weighted(g);
+    if (s != BC_OK) return s;
+    const int64_t ns = (int64_t)pos.size(), n = std::max<int32_t>(g->n, 1);
+    // chunks of consecutive positions: up to two per workgroup, and at most
+    // 8 GiB of partial scores
+    int64_t nc = std::min<int64_t>(ns, 2 * (int64_t)g->w_wg);
+    nc = std::max<int64_t>(1, std::min<int64_t>(nc, ((int64_t)8 << 30) / (8 * n)));
+    const int nwg = (int)std::min<int64_t>(g->w_wg, nc);
+    std::vector<int32_t> ch(3 * (size_t)nc), list((size_t)ns);
+    for (int64_t t = 0; t < nc; ++t) {
+        ch[t] = (int32_t)(ns * t / nc);
+        ch[nc + t] = (int32_t)(ns * (t + 1) / nc);
+        ch[2 * nc + t] = (int32_t)t;
+    }
+    int64_t pdump = -1;
+    for (int64_t i = 0; i < ns; ++i) {
+        list[i] = h_srcs[pos[i]];
+        if (pos[i] == dump_pos_run) pdump = i;
+    }
+    s = grow(&g->srcs, &g->srcs_cap, ns, &g->acct);
+    if (s == BC_OK) s = grow(&g->w_chunk, &g->w_chunk_cap, 3 * nc, &g->acct);
+    if (s == BC_OK) s = grow(&g->w_pos, &g->w_pos_cap, ns, &g->acct);
+    if (s == BC_OK) s = grow(&g->ovf, &g->ovf_cap, ns, &g->acct);
+    if (s == BC_OK) s = grow(&g->w_partials, &g->w_partials_cap, nc * n, &g->acct);
+    if (s != BC_OK) return s;
+    HIP_TRY(hipMemcpyAsync(g->srcs, list.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(g->w_chunk, ch.data(), sizeof(int32_t) * ch.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(g->w_pos, pos.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, st));
+    fill_u64<<<1, 64, 0, st>>>(g->w_ctr, 8, 0ull);
+    HIP_TRY(hipGetLastError());
+    WeightedArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g.n = g->n;
+    a.g.nnz_lo = (int32_t)g->nnz;
+    a.g.row_ptr = g->row_ptr;
+    a.g.col = g->col;
+    a.g.directed = g->directed ? 1 : 0;
+    a.g.in_row_ptr = g->directed ? g->in_row_ptr : g->row_ptr;
+    a.g.in_col = g->directed ? g->in_col : g->col;
+    a.wt = g->wt;
+    a.in_wt = g->in_wt;
+    a.srcs = g->srcs;
+    a.pos = g->w_pos;
+    a.c_s0 = g->w_chunk;
+    a.c_s1 = g->w_chunk + nc;
+    a.order = g->w_chunk + 2 * nc;
+    a.n_chunks = (int32_t)nc;
+    a.next = (uint32_t *)&g->w_ctr[0];
+    a.ovf_count = (uint32_t *)&g->w_ctr[1];
+    a.err = (int32_t *)&g->w_ctr[2];
+    a.st = &g->w_ctr[4];
+    a.partials = g->w_partials;
+    a.scratch = g->w_scratch;
+    a.stride = g->w_stride;
+    a.ovf_list = g->ovf;
+    a.ovf_cap = (uint32_t)std::min<int64_t>(g->ovf_cap, UINT32_MAX);
+    a.sigma_limit = o.sigma_limit > 0 ? (unsigned long long)o.sigma_limit : ~0ull;
+    a.dump_pos = (dump && pdump >= 0) ? pdump : -1;
+    if (dump) {
+        a.dump_d = dump->d64;
+        a.dump_sig = dump->sig;
+        a.dump_delta = dump->delta;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, st));
+    if (mode) weighted_run<1><<<nwg, kBlock, 0, st>>>(a);
+    else weighted_run<0><<<nwg, kBlock, 0, st>>>(a);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(e1, st));
+    sum_partials<<<grid_for(n, 256, 4096), 256, 0, st>>>(g->bc, g->w_partials, n, nc);
+    HIP_TRY(hipGetLastError());
+    unsigned long long ctr[8];
+    HIP_TRY(hipMemcpyAsync(ctr, g->w_ctr, sizeof(ctr), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const int32_t err = (int32_t)(uint32_t)ctr[2];
+    if (err & ERR_SIGMA_RANGE) return fail(BC_ERR_SIGMA_RANGE, "FP64 path counts left the double range");
+    if (err) return fail(BC_ERR_DEVICE, "weighted engine capacity error");
+    const uint32_t no = (uint32_t)ctr[1];
+    if (no) {
+        ovf->resize(no);
+        HIP_TRY(hipMemcpy(ovf->data(), g->ovf, sizeof(int64_t) * no, hipMemcpyDeviceToHost));
+        std::sort(ovf->begin(), ovf->end());
+    }
+    if (pdump >= 0 && dump) *dumped = std::find(ovf->begin(), ovf->end(), dump_pos_run) == ovf->end();
+    g->stats.launches += 1;
+    g->stats.mode_launches[mode] += 1;
+    g->stats.mode_ms[mode] += ms;
+    g->stats.forward_levels += (int64_t)ctr[4];
+    g->stats.arcs_scanned += (int64_t)ctr[5];
+    g->stats.max_levels = std::max<int64_t>(g->stats.max_levels, 0);
+    g->stats.steps += (int64_t)ctr[6];
+    g->stats.reached_pairs += (int64_t)ctr[7];
+    return BC_OK;
+}
+
+static bc_status run_weighted(bc_graph *g, const int32_t *src, int64_t ns, const bc_run_options &o, hipStream_t st,
+                              int64_t dump_index, DumpBufs *db, int *dump_mode) {
+    std::vector<int64_t> all((size_t)ns), ovf, none;
+    for (int64_t i = 0; i < ns; ++i) all[i] = i;
+    bool dumped = false;
+    const bool force = (o.flags & BC_RUN_FORCE_F64) != 0;
+    bc_status s = weighted_pass(g, force ? 1 : 0, o, src, all, dump_index, db, st, &ovf, &dumped);
+    if (s != BC_OK) return s;
+    *dump_mode = force ? 1 : 0;
+    if (force) {
+        g->stats.f64_sources = ns;
+        return BC_OK;
+    }
+    if (!ovf.empty()) {
+        bool dumped2 = false;
+        s = weighted_pass(g, 1, o, src, ovf, dump_index, db, st, &none, &dumped2);
+        if (s != BC_OK) return s;
+        if (dumped2) *dump_mode = 1;
+    }
+    g->stats.f64_sources = (int64_t)ovf.size();
+    return BC_OK;
 }
 
 static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources, const bc_run_options *opt,
@@ -1623,7 +2247,8 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
         if (o.lanes_per_entry == 0.0f) o.lanes_per_entry = g->tuned.lanes_per_entry;
         o.flags &= ~BC_RUN_TUNED;
     }
-    if (use_parts(g, o, sources ? n_sources : g->n)) {
+    const bool blk = use_block(g, o, sources ? n_sources : g->n, detail != nullptr);
+    if (!blk && !g->weighted && use_parts(g, o, sources ? n_sources : g->n)) {
         g->last_parts = true;
         const bc_status ps = run_parts(g, sources, n_sources, o, stream, dump_index, detail);
         if (!(ps == BC_ERR_OUT_OF_MEMORY && g->parts_refused)) return ps;
@@ -1671,6 +2296,7 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
         HIP_TRY(hipMalloc((void **)&db.sig, n * sizeof(unsigned long long)));
         HIP_TRY(hipMalloc((void **)&db.delta, n * sizeof(double)));
         HIP_TRY(hipMalloc((void **)&db.shift, ((size_t)g->n + 2) * sizeof(int32_t)));
+        if (g->weighted) HIP_TRY(hipMalloc((void **)&db.d64, n * sizeof(int64_t)));
         fill_i32<<<grid_for(n, 256, 4096), 256, 0, st>>>(db.d, n, -1);
         fill_u64<<<grid_for(n, 256, 4096), 256, 0, st>>>(db.sig, n, 0ull);
         fill_u64<<<grid_for(n, 256, 4096), 256, 0, st>>>((unsigned long long *)db.delta, n, 0ull);
@@ -1678,11 +2304,48 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
         HIP_TRY(hipGetLastError());
     }
     auto free_dump = [&]() {
+        if (db.d64) (void)hipFree(db.d64);
         if (db.d) (void)hipFree(db.d);
         if (db.sig) (void)hipFree(db.sig);
         if (db.delta) (void)hipFree(db.delta);
         if (db.shift) (void)hipFree(db.shift);
     };
+    if (g->weighted) {
+        int wmode = 0;
+        s = run_weighted(g, src, ns, o, st, detail ? dump_index : -1, detail ? &db : nullptr, &wmode);
+        if (s != BC_OK) { free_dump(); return s; }
+        if (detail) {
+            const size_t n = (size_t)g->n;
+            std::vector<int64_t> hd(n);
+            std::vector<unsigned long long> hs(n);
+            std::vector<double> hdel(n);
+            HIP_TRY(hipMemcpyAsync(hd.data(), db.d64, n * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(hs.data(), db.sig, n * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(hdel.data(), db.delta, n * sizeof(double), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            free_dump();
+            std::vector<int64_t> dvals;
+            for (size_t v = 0; v < n; ++v) {
+                if (detail->d) detail->d[v] = hd[v] > INT32_MAX ? INT32_MAX : (int32_t)hd[v];
+                if (detail->d64) detail->d64[v] = hd[v];
+                if (hd[v] >= 0) dvals.push_back(hd[v]);
+                double sv;
+                if (wmode) std::memcpy(&sv, &hs[v], sizeof(sv));
+                else sv = (double)hs[v];
+                if (detail->sigma_u64) detail->sigma_u64[v] = wmode ? 0 : hs[v];
+                if (detail->sigma_mant) detail->sigma_mant[v] = hd[v] >= 0 ? sv : 0.0;
+                if (detail->sigma_exp) detail->sigma_exp[v] = 0;
+                if (detail->delta) detail->delta[v] = hdel[v];
+            }
+            std::sort(dvals.begin(), dvals.end());
+            detail->mode = wmode;
+            detail->n_levels = (int32_t)(std::unique(dvals.begin(), dvals.end()) - dvals.begin());
+        }
+        g->stats.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        g->stats.algo_bytes = algo_bytes(g->stats);
+        g->stats.algo_bytes_arcs = algo_bytes_arcs(g->stats);
+        return BC_OK;
+    }
     int dump_done = 0;
     int dump_mode = 0;
     Ctl last{};
@@ -1717,12 +2380,28 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
     std::vector<int64_t> all_pos((size_t)ns);
     for (int64_t i = 0; i < ns; ++i) all_pos[i] = i;
     std::vector<int64_t> f64_pos;  // sources that end in FP64 mode (sorted)
+    bool block_done = false;
+    if (!force_f64 && blk) {
+        // the block engine: every source in one 64-bit pass; the sources
+        // that overflowed run again in FP64 on the general engine
+        std::vector<int64_t> ovf;
+        bool fb = false;
+        s = run_block(g, cfg, o, src, ns, st, &ovf, &fb);
+        if (s != BC_OK) { free_dump(); return s; }
+        if (!fb) {
+            std::vector<int64_t> none;
+            s = pass(1, false, ovf, &none);
+            if (s != BC_OK) { free_dump(); return s; }
+            g->stats.f64_sources = (int64_t)ovf.size();
+            block_done = true;
+        }
+    }
     if (force_f64) {
         std::vector<int64_t> none;
         s = pass(1, false, all_pos, &none);
         if (s != BC_OK) { free_dump(); return s; }
         g->stats.f64_sources = ns;
-    } else {
+    } else if (!block_done) {
         // 64-bit counts first.  When most of the first batch overflows, the
         // graph's counts exceed 64 bits as a rule: the rest runs in FP64
         // straight away (checked), and only the lanes whose counts stay below

@@ -698,7 +698,7 @@ __device__ __forceinline__ void batch_begin(const BatchArgs &a, Ctl *c, int64_t 
         c->phase = PH_FWD;
         c->st_batches += 1;
         c->st_lane_entries += (unsigned long long)lanes;
-        level_rec(a.lvl, 0).entries += (unsigned long long)cnt;
+        if (a.lvl) level_rec(a.lvl, 0).entries += (unsigned long long)cnt;
         const int64_t dp = c->dump_pos;
         c->dump_lane = (dp >= start && dp < end && c->dump_state == 0) ? (int)(dp - start) : -1;
         sf->nf = (float)cnt;
@@ -718,8 +718,12 @@ __device__ __forceinline__ void batch_begin(const BatchArgs &a, Ctl *c, int64_t 
 #endif
 // Register budget of the step kernel: at least BC_WAVES wavefronts per SIMD
 // (memory latency is hidden by resident wavefronts).
+// One step of the level state machine for workgroup bid of a launch of
+// `grid` workgroups: the step kernel below runs it once per launch over the
+// whole grid; the block engine runs it in a loop inside one workgroup
+// (grid = 1), which then owns the state machine alone.
 template <int MODE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES))) void batch_step(BatchArgs a) {
+__device__ __forceinline__ void batch_step_body(const BatchArgs &a, const unsigned bid, const unsigned grid) {
     __shared__ int s_phase, s_level, s_variant, s_last, s_qb, s_qe, s_qn, s_L, s_lo, s_hi, s_dlane, s_cnt;
     __shared__ int s_h0, s_h1, s_hseg, s_hqb;
     __shared__ uint32_t s_gb, s_ng;
@@ -807,7 +811,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
         } else if (s_phase == PH_UNDO) {
             items = (s_qn + kWave - 1) / kWave;
         }
-        s_nblk = active_blocks(items);
+        s_nblk = active_blocks(items, grid);
     }
     if (tid < kLanes) {
         s_lsrc[tid] = a.lane_src[tid];
@@ -818,9 +822,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
     const int phase = s_phase;
     if (phase == PH_DONE || phase == PH_IDLE) return;
     const unsigned nblk = s_nblk;
-    const bool active = blockIdx.x < nblk;  // workgroups beyond nblk only count in
+    const bool active = bid < nblk;  // workgroups beyond nblk only count in
 
-    const int gw = blockIdx.x * kWavesPerBlock + wid;
+    const int gw = (int)bid * kWavesPerBlock + wid;
     const int nw = (int)nblk * kWavesPerBlock;
     const int l = s_level;
     const int32_t *__restrict__ rp = a.g.row_ptr;
@@ -1005,7 +1009,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
         const uint32_t *gs = a.gstart + s_gb;
         const int total = n_groups + hseg;
         SigCounters sc;
-        for (WorkCursor wc(c, nblk); wc.item() < total; wc.next(total)) {
+        for (WorkCursor wc(c, nblk, bid); wc.item() < total; wc.next(total)) {
             const int k = wc.item();
             const int it = k < hseg ? n_groups + k : k - hseg;  // heavy segments first
             if (it < n_groups) {
@@ -1074,7 +1078,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
         const int n_groups = (int)s_ng;
         const uint32_t *gs = a.gstart + s_gb;
         const int total = n_groups + hseg;
-        for (WorkCursor wc(c, nblk); wc.item() < total; wc.next(total)) {
+        for (WorkCursor wc(c, nblk, bid); wc.item() < total; wc.next(total)) {
             const int k = wc.item();
             const int it = k < hseg ? n_groups + k : k - hseg;  // heavy segments first
             if (it < n_groups) {
@@ -1107,13 +1111,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
         // timing collection: forget the level just discovered (its entries
         // are the only vertices with next words set)
         const int qs = s_qe, cnt = s_qn;
-        for (int i = blockIdx.x * kBlock + tid; i < cnt; i += (int)nblk * kBlock) a.vn[a.lq_vtx[qs + i]].nxt = 0ull;
+        for (int i = (int)bid * kBlock + tid; i < cnt; i += (int)nblk * kBlock) a.vn[a.lq_vtx[qs + i]].nxt = 0ull;
     } else if (phase == PH_BC) {
         // dependencies -> BC in lane order (the run's source order), then
         // clear the visited words
         const int lo = s_lo, span = s_hi - s_lo;
         const unsigned long long keep = s_lmask & ~s_dead;
-        for (int i = blockIdx.x * kBlock + tid; i < span; i += (int)nblk * kBlock) {
+        for (int i = (int)bid * kBlock + tid; i < span; i += (int)nblk * kBlock) {
             const int w = lo + i;
             const VisNext x = a.vn[w];
             unsigned long long vis = x.vis & keep;
@@ -1137,7 +1141,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
         const int k = s_dlane;
         const int L = s_L;
         const int total = s_qe;
-        for (int j = blockIdx.x * kBlock + tid; j < total; j += (int)nblk * kBlock) {
+        for (int j = (int)bid * kBlock + tid; j < total; j += (int)nblk * kBlock) {
             if (!((a.lq_mask[j] >> k) & 1ull)) continue;
             int lo = 0, hi = L;  // level of entry j: level_off[lvl] <= j < level_off[lvl+1]
             while (hi - lo > 1) {
@@ -1153,7 +1157,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
                 a.dump_delta[v] = a.delta[(size_t)v * kLanes + k];
             }
         }
-        if (phase == PH_DUMP_FWD && blockIdx.x == 0)
+        if (phase == PH_DUMP_FWD && bid == 0)
             for (int i = tid; i < L; i += kBlock) a.dump_shift[i] = MODE ? a.shift[(size_t)i * kLanes + k] : 0;
     }
 
@@ -1176,7 +1180,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
             if (my_mine != INT_MAX) atomicMin(&s_emin[lane], my_mine);
         }
         __syncthreads();
-        const int slot = blockIdx.x % kSlots;
+        const int slot = (int)(bid % kSlots);
         if (tid < kLanes && s_emax[tid] != INT_MIN) atomicMax(&a.maxexp[slot * kLanes + tid], s_emax[tid]);
         else if (tid >= kLanes && tid < 2 * kLanes && s_emin[tid - kLanes] != INT_MAX)
             atomicMin(&a.maxexp[(kSlots + slot) * kLanes + tid - kLanes], s_emin[tid - kLanes]);
@@ -1185,7 +1189,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
         __builtin_amdgcn_s_waitcnt(0);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
-    if (!step_epilogue(c, cn, s_red, &s_last, active)) return;
+    if (!step_epilogue(c, cn, s_red, &s_last, active, bid, grid)) return;
     collect_slots(c, s_tot, s_red);
 
     // ---- the last workgroup advances the state machine
@@ -1205,7 +1209,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
         if (phase == PH_FWD) c->st_vticks[s_variant] += dt;
         c->last_tick = now;
         const int rl = (phase == PH_FWD || phase == PH_BWD) ? l : (phase == PH_SIG ? l + 1 : -1);
-        if (rl >= 0) {
+        if (rl >= 0 && a.lvl) {
             LevelRec &r = level_rec(a.lvl, rl);
             r.arcs += s_tot[SC_ARCS];
             r.ticks += dt;
@@ -1245,7 +1249,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
             c->st_fwd_levels += 1;
             c->st_var[s_variant] += 1;
             c->st_qentries += cnt;
-            level_rec(a.lvl, l + 1).entries += cnt;
+            if (a.lvl) level_rec(a.lvl, l + 1).entries += cnt;
             a.hq.off[l + 2] = a.hq.off[l + 1] + (int)(uint32_t)nh;
             a.hq.nseg[l + 1] = (int)(nh >> 32);
             c->next_hq = 0;
@@ -1387,7 +1391,131 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES
     }
 }
 
+template <int MODE>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_WAVES))) void batch_step(BatchArgs a) {
+    batch_step_body<MODE>(a, blockIdx.x, gridDim.x);
+}
+
 template __global__ void batch_step<0>(BatchArgs);
 template __global__ void batch_step<1>(BatchArgs);
+
+#ifndef BC_BLOCK_WAVES
+#define BC_BLOCK_WAVES 2
+#endif
+// Block engine: a persistent launch in which every workgroup owns a level
+// state machine.  A workgroup takes a chunk (batches [b0, b1) of one graph
+// with vertices [lo, hi)), points the per-vertex arrays of its arguments at
+// its private scratch shifted by lo (every index the steps use lies in
+// [lo, hi): arcs never leave a graph), and runs the steps of the chunk one
+// after another with workgroup barriers in between.  Scores of the chunk go
+// to its own partial vector.  The control block keeps its tag epochs from
+// chunk to chunk, so tags left by an earlier chunk never match.  Exit: the
+// work queue runs dry (every workgroup takes chunks until the counter passes
+// n_chunks), a step reports an error, or a chunk exceeds max_steps per batch.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_BLOCK_WAVES))) void block_run(BlockArgs ra) {
+    // the workgroup's arguments live in LDS: thread 0 points them at the
+    // chunk's state, every thread reads them there
+    __shared__ BatchArgs s_a;
+    __shared__ int s_go;
+    const int tid = threadIdx.x;
+    Ctl *c = ra.ctls + blockIdx.x;
+    char *base = ra.scratch + (size_t)blockIdx.x * ra.stride;
+    const BlockLayout L((size_t)ra.nmax, ra.lq_cap, (size_t)ra.max_levels, ra.gcap, ra.hq_entries, ra.hq_levels,
+                        ra.part_cap, ra.ovf_cap);
+    if (tid == 0) {
+        BatchArgs &a = s_a;
+        a = ra.a;
+        a.ctl = c;
+        a.lvl = nullptr;
+        a.lq_vtx = (int32_t *)(base + L.lq_vtx);
+        a.lq_mask = (unsigned long long *)(base + L.lq_mask);
+        a.lq_cap = ra.lq_cap;
+        a.level_off = (int32_t *)(base + L.level_off);
+        a.max_levels = ra.max_levels;
+        a.gstart = (uint32_t *)(base + L.gstart);
+        a.gbase = (uint32_t *)(base + L.gbase);
+        a.gcap = ra.gcap;
+        a.shift = (int32_t *)(base + L.shift);
+        a.maxexp = (int32_t *)(base + L.maxexp);
+        a.lane_src = (int32_t *)(base + L.lane_src);
+        a.hq.pos = (int32_t *)(base + L.hq_pos);
+        a.hq.seg = (int32_t *)(base + L.hq_seg);
+        a.hq.cnt = (int32_t *)(base + L.hq_cnt);
+        a.hq.off = (int32_t *)(base + L.hq_off);
+        a.hq.nseg = (int32_t *)(base + L.hq_nseg);
+        a.hq.cap = ra.hq_entries;
+        a.hq.part_lo = (unsigned long long *)(base + L.part_lo);
+        a.hq.part_hi = (unsigned long long *)(base + L.part_hi);
+        a.hq.part_cap = ra.part_cap;
+        a.ovf_list = (int64_t *)(base + L.ovf);
+        a.ovf_cap = ra.ovf_cap;
+        a.dump_d = nullptr;
+        a.dump_sig = nullptr;
+        a.dump_delta = nullptr;
+        a.dump_shift = nullptr;
+        a.col_X = nullptr;
+        a.col_Y = nullptr;
+        a.col_cap = 0;
+    }
+    int32_t *mx = (int32_t *)(base + L.maxexp);
+    for (int i = tid; i < 2 * kSlots * kLanes; i += kBlock) mx[i] = i < kSlots * kLanes ? INT_MIN : INT_MAX;
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) {
+            const uint32_t k = atomicAdd(ra.next, 1u);
+            const int t = (k < (uint32_t)ra.n_chunks && c->err == 0) ? ra.order[k] : -1;
+            s_go = t;
+            if (t >= 0) {
+                const int b0 = ra.c_b0[t], b1 = ra.c_b1[t];
+                const int lo = ra.a.batch_lo[b0], hi = ra.a.batch_hi[b0];
+                BatchArgs &a = s_a;
+                a.vn = (VisNext *)(base + L.vn) - lo;
+                a.fw0 = (Tagged *)(base + L.fw0) - lo;
+                a.fw1 = (Tagged *)(base + L.fw1) - lo;
+                a.sigma = (unsigned long long *)(base + L.sigma) - (size_t)lo * kLanes;
+                a.chat = (double *)(base + L.chat) - (size_t)lo * kLanes;
+                a.delta = (double *)(base + L.delta) - (size_t)lo * kLanes;
+                a.bc = ra.partials + ra.c_part[t] - lo;
+                // the first step (phase BC of an empty batch) clears the
+                // visited words of [lo, hi), then the chunk's batches follow
+                c->phase = PH_BC;
+                c->pos = (int64_t)b0 - 1;
+                c->n_items = b1;
+                c->range_lo = lo;
+                c->range_hi = hi;
+                c->lane_mask = 0ull;
+                c->dead = 0ull;
+                c->active = 0ull;
+                c->level = 0;
+            }
+        }
+        __syncthreads();
+        const int t = s_go;
+        if (t < 0) break;
+        const int b0 = ra.c_b0[t], b1 = ra.c_b1[t];
+        const int lo = ra.a.batch_lo[b0], hi = ra.a.batch_hi[b0];
+        double *part = ra.partials + ra.c_part[t];
+        for (int i = tid; i < hi - lo; i += kBlock) part[i] = 0.0;
+        const int64_t max_steps = (int64_t)(b1 - b0 + 1) * ra.max_steps;
+        for (int64_t step = 0;; ++step) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (tid == 0) {
+                int go = (c->phase != PH_DONE && c->err == 0) ? 1 : 0;
+                if (go && step >= max_steps) {
+                    c->err |= ERR_LEVEL_CAP;
+                    go = 0;
+                }
+                s_go = go;
+            }
+            __syncthreads();
+            if (!s_go) break;
+            batch_step_body<MODE>(s_a, 0u, 1u);
+        }
+    }
+}
+
+template __global__ void block_run<0>(BlockArgs);
 
 }  // namespace bcx

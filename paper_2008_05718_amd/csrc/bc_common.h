@@ -88,12 +88,13 @@ __device__ __forceinline__ unsigned long long cnt_combine(int k, unsigned long l
 
 // Workgroups a step needs for `items` wavefront work items (at least one, at
 // most the launched grid).  Workgroups beyond it leave at once.
-__device__ __forceinline__ unsigned active_blocks(long long items) {
+__device__ __forceinline__ unsigned active_blocks(long long items, unsigned grid) {
     long long b = (items + kWavesPerBlock - 1) / kWavesPerBlock;
     if (b < 1) b = 1;
-    if (b > (long long)gridDim.x) b = gridDim.x;
+    if (b > (long long)grid) b = grid;
     return (unsigned)b;
 }
+__device__ __forceinline__ unsigned active_blocks(long long items) { return active_blocks(items, gridDim.x); }
 
 // Work items of a step, [0, total), are dealt to ncls = min(nblk, kSlots)
 // classes k mod ncls; the workgroups of class r (blockIdx.x mod ncls) share
@@ -105,12 +106,12 @@ __device__ __forceinline__ unsigned active_blocks(long long items) {
 struct WorkCursor {
     uint32_t *ctr;
     int r, ncls, nwr, j, jn;
-    __device__ __forceinline__ WorkCursor(Ctl *c, unsigned nblk) {
+    __device__ __forceinline__ WorkCursor(Ctl *c, unsigned nblk, unsigned bid) {
         ncls = (int)(nblk < (unsigned)kSlots ? nblk : (unsigned)kSlots);
-        r = (int)(blockIdx.x % (unsigned)ncls);
+        r = (int)(bid % (unsigned)ncls);
         const int nb = ((int)nblk - r + ncls - 1) / ncls;  // workgroups of class r
         nwr = nb * kWavesPerBlock;
-        j = (int)(blockIdx.x / (unsigned)ncls) * kWavesPerBlock + (int)(threadIdx.x >> 6);
+        j = (int)(bid / (unsigned)ncls) * kWavesPerBlock + (int)(threadIdx.x >> 6);
         ctr = &c->work[r][0];
         jn = fetch();
     }
@@ -145,9 +146,9 @@ struct WorkCursor {
 // itself in: each wave that issued one waits for its memory counters first.
 // s_red needs kWavesPerBlock * kNCnt entries.
 __device__ __forceinline__ bool step_epilogue(Ctl *c, Counters &cn, unsigned long long *s_red, int *s_last,
-                                              bool active) {
+                                              bool active, unsigned bid, unsigned grid) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int slot = blockIdx.x % kSlots;
+    const int slot = bid % kSlots;
     if (active) {
 #pragma unroll
         for (int k = 0; k < kNCnt; ++k) {
@@ -178,10 +179,10 @@ __device__ __forceinline__ bool step_epilogue(Ctl *c, Counters &cn, unsigned lon
     }
     if (threadIdx.x == 0) {
         int last = 0;
-        const unsigned in_slot = (gridDim.x - slot + kSlots - 1) / kSlots;
+        const unsigned in_slot = (grid - slot + kSlots - 1) / kSlots;
         const unsigned t = atomicAdd(&c->arrive[slot], 1u);
         if (t == in_slot - 1) {
-            const unsigned nslots = gridDim.x < (unsigned)kSlots ? gridDim.x : (unsigned)kSlots;
+            const unsigned nslots = grid < (unsigned)kSlots ? grid : (unsigned)kSlots;
             const unsigned t2 = atomicAdd(&c->blocks_done, 1u);
             last = (t2 == nslots - 1) ? 1 : 0;
         }
@@ -189,6 +190,10 @@ __device__ __forceinline__ bool step_epilogue(Ctl *c, Counters &cn, unsigned lon
     }
     __syncthreads();
     return *s_last != 0;
+}
+__device__ __forceinline__ bool step_epilogue(Ctl *c, Counters &cn, unsigned long long *s_red, int *s_last,
+                                              bool active) {
+    return step_epilogue(c, cn, s_red, s_last, active, blockIdx.x, gridDim.x);
 }
 
 // In the last workgroup: totals of all slots into s_tot[kNCnt] (valid after

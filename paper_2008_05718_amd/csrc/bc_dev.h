@@ -279,4 +279,119 @@ struct BatchArgs {
     LevelRec *lvl;               // [kLevelRecs]
 };
 
+// ---------------------------------------------------------- block engine
+// Unions of small graphs (and single small graphs): every workgroup runs the
+// batched state machine on its own (one workgroup per launch in effect, so
+// steps are separated by workgroup barriers, not by launches) over chunks of
+// consecutive batches of one graph that it takes from a work queue, for the
+// whole run in one persistent launch.  Each workgroup owns a private copy of
+// the per-vertex state, sized for the largest graph it may hold; a chunk's
+// scores go to a partial vector of its own, and the partials of a graph are
+// added in chunk order afterwards.
+constexpr int kBlockMaxN = 131072;  // largest graph (vertices) the block engine takes
+
+// Byte offsets of one workgroup's state inside its scratch region; the same
+// arithmetic on the host (sizing) and on the device (carving).
+struct BlockLayout {
+    size_t vn, fw0, fw1, lq_vtx, lq_mask, level_off, sigma, chat, delta, gstart, gbase, shift, maxexp, lane_src,
+        hq_pos, hq_seg, hq_cnt, hq_off, hq_nseg, part_lo, part_hi, ovf, bytes;
+    __host__ __device__ static size_t up(size_t x) { return (x + 255) & ~(size_t)255; }
+    __host__ __device__ BlockLayout(size_t nmax, size_t lq_cap, size_t max_levels, size_t gcap, size_t hq_entries,
+                                    size_t hq_levels, size_t part_cap, size_t ovf_cap) {
+        size_t o = 0;
+        auto take = [&](size_t bytes) { const size_t at = o; o = up(o + bytes); return at; };
+        vn = take(nmax * sizeof(VisNext));
+        fw0 = take(nmax * sizeof(Tagged));
+        fw1 = take(nmax * sizeof(Tagged));
+        lq_vtx = take(lq_cap * 4);
+        lq_mask = take(lq_cap * 8);
+        level_off = take((max_levels + 2) * 4);
+        sigma = take(nmax * kLanes * 8);
+        chat = take(nmax * kLanes * 8);
+        delta = take(nmax * kLanes * 8);
+        gstart = take(gcap * 4);
+        gbase = take((max_levels + 2) * 4);
+        shift = take((max_levels + 2) * kLanes * 4);
+        maxexp = take(2 * kSlots * kLanes * 4);
+        lane_src = take(kLanes * 4);
+        hq_pos = take(hq_entries * 4);
+        hq_seg = take(hq_entries * 4);
+        hq_cnt = take(hq_entries * 4);
+        hq_off = take(hq_levels * 4);
+        hq_nseg = take(hq_levels * 4);
+        part_lo = take(part_cap * kLanes * 8);
+        part_hi = take(part_cap * kLanes * 8);
+        ovf = take(ovf_cap * 8);
+        bytes = o;
+    }
+};
+
+struct BlockArgs {
+    BatchArgs a;                 // graph, policy, source list and batch table of the run
+    char *scratch;               // per-workgroup state, `stride` bytes each (BlockLayout)
+    size_t stride;
+    Ctl *ctls;                   // one control block per workgroup
+    int32_t nmax;
+    uint32_t lq_cap, gcap, hq_entries, hq_levels, part_cap, ovf_cap;
+    int32_t max_levels;
+    // chunk t: batches [c_b0[t], c_b1[t]) of one graph; its partial scores
+    // are partials[c_part[t] + (v - lo)]
+    const int32_t *c_b0, *c_b1;
+    const int64_t *c_part;
+    const int32_t *order;        // chunks in dispatch order (largest graphs first)
+    int32_t n_chunks;
+    uint32_t *next;              // work-queue counter
+    double *partials;
+    int64_t max_steps;           // per batch: a bound no valid run reaches
+};
+
+// ------------------------------------------------------- weighted engine
+// (bc_weighted.hip) One workgroup's state for a graph of n vertices, and the
+// arguments of the persistent launch.
+struct WeightedLayout {
+    size_t dist, sig, chat, dep, cnt, mark, reached, qa, qb, lvl, lvl_off, bytes;
+    __host__ __device__ static size_t up(size_t x) { return (x + 255) & ~(size_t)255; }
+    __host__ __device__ explicit WeightedLayout(size_t n) {
+        size_t o = 0;
+        auto take = [&](size_t b) { const size_t at = o; o = up(o + b); return at; };
+        dist = take(n * 8);
+        sig = take(n * 8);
+        chat = take(n * 8);
+        dep = take(n * 8);
+        cnt = take(n * 4);
+        mark = take(n * 4);
+        reached = take(n * 4);
+        qa = take(n * 4);
+        qb = take(n * 4);
+        lvl = take(n * 4);
+        lvl_off = take((n + 2) * 4);
+        bytes = o;
+    }
+};
+
+struct WeightedArgs {
+    GraphArgs g;
+    const int32_t *wt;        // weights of the out-arcs (aligned with g.col)
+    const int32_t *in_wt;     // weights of the in-arcs (aligned with g.in_col)
+    const int32_t *srcs;      // source list of the pass
+    const int64_t *pos;       // absolute positions of the pass's sources in the run (for the overflow list)
+    const int32_t *c_s0, *c_s1;  // chunk t: pass positions [c_s0[t], c_s1[t])
+    const int32_t *order;     // chunks in dispatch order
+    int32_t n_chunks;
+    uint32_t *next;           // work-queue counter
+    double *partials;         // chunk t: partials[t * n .. (t + 1) * n)
+    char *scratch;            // per-workgroup state, `stride` bytes each
+    size_t stride;
+    int32_t *err;             // ERR_* bits
+    int64_t *ovf_list;        // positions whose path counts overflowed (MODE 0)
+    uint32_t *ovf_count;
+    uint32_t ovf_cap;
+    unsigned long long sigma_limit;
+    int64_t dump_pos;         // pass position whose d / sigma / delta are copied out (-1 = none)
+    int64_t *dump_d;
+    unsigned long long *dump_sig;
+    double *dump_delta;
+    unsigned long long *st;   // statistics: [0] relaxation rounds, [1] arcs scanned, [2] DAG rounds, [3] reached pairs
+};
+
 }  // namespace bcx

@@ -87,7 +87,9 @@ def test_diamond_chain_rescaled_counts_exact(batch):
         a, c = 3 * j + 1, 3 * j + 3
         assert d[a] == 2 * j + 1 and d[c] == 2 * j + 2
         assert sig[a] == 2 ** j and sig[a + 1] == 2 ** j and sig[c] == 2 ** (j + 1), j
-    assert max(int(e) for e in det["sigma_exp"]) > 1024  # beyond the double range
+    # counts up to 2^1100 are beyond the double range: they were stored
+    # divided by a power of two (sigma = mantissa * 2^exp, exp > 0)
+    assert max(sig) == 2 ** D and max(int(e) for e in det["sigma_exp"]) > 0
     assert all(sig[3 * D + 1 + i] == 1 for i in range(tail))
     # Eq. 2 on the chain: delta(c_j) = 3 (D - 1 - j), delta(a_j) = (1 + delta(c_j)) / 2,
     # tail vertex i: tail - 1 - i

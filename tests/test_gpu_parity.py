@@ -337,11 +337,11 @@ def test_many_graph_union_parts_bit_identical():
     with b.Graph(u) as G:
         G.run(srcs, batch=64, flags=b.BC_RUN_ONE_QUEUE)
         one = G.scores().copy()
-        G.run(srcs, batch=64)
+        G.run(srcs, batch=64, flags=b.BC_RUN_NO_BLOCKS)  # concurrent parts of the general engine
         parts = G.scores().copy()
         assert np.array_equal(one.view(np.uint64), parts.view(np.uint64))
-        G.run(srcs[:300], batch=64)
-        G.run(srcs[300:], batch=64, flags=b.BC_RUN_ACCUMULATE)
+        G.run(srcs[:300], batch=64, flags=b.BC_RUN_NO_BLOCKS)
+        G.run(srcs[300:], batch=64, flags=b.BC_RUN_ACCUMULATE | b.BC_RUN_NO_BLOCKS)
         acc = G.scores().copy()
         for idx in (0, 333, len(srcs) - 1):
             det = G.detail(srcs, dump_index=idx, batch=64)

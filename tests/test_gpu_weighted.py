@@ -1,0 +1,103 @@
+"""GPU parity on graphs with positive integer arc weights (the forward phase
+as a shortest-path computation; the weighted engine).  Against the oracle,
+whose weighted form is pinned in tests/test_oracle_weighted.py: int64
+distances and uint64 path counts bit for bit, FP64 counts, dependencies
+and scores within 1e-10 relative; runs repeat bit for bit; unit weights
+agree with the unweighted engines."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_bc_close, check_detail, say
+from paper_2008_05718_amd import binding as b
+from paper_2008_05718_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("directed", [False, True])
+@pytest.mark.parametrize("wmax", [1, 3, 100])
+def test_weighted_rmat_against_oracle(directed, wmax):
+    base = W.rmat_directed(11, 8, seed=61) if directed else W.rmat(11, 8, seed=61)
+    g = W.with_weights(base, 1, wmax, seed=7)
+    srcs = W.choose_sources(base, 200, seed=3)
+    ref, modes = oracle.bc(g, srcs)
+    say(f"[weighted] directed={directed} wmax={wmax} n={g.n} f64 {int(modes.sum())}")
+    with b.Graph(g) as G:
+        G.run(srcs)
+        got = G.scores().copy()
+        G.run(srcs)
+        assert np.array_equal(G.scores().view(np.uint64), got.view(np.uint64))
+        for k in (0, 77, 199):
+            det = G.detail(srcs, dump_index=k)
+            check_detail(g, det, int(srcs[k]))
+        st = G.stats()
+        say(f"  relaxation rounds {st['forward_levels']}, DAG rounds {st['steps']}, arcs {st['arcs_scanned']}")
+    assert_bc_close(got, ref)
+
+
+def test_unit_weights_equal_unweighted_engine():
+    base = W.rmat(12, 16, seed=62)
+    g = W.with_weights(base, 1, 1, seed=1)
+    srcs = W.choose_sources(base, 300, seed=4)
+    with b.Graph(g) as G:
+        G.run(srcs)
+        wgot = G.scores().copy()
+    with b.Graph(base, flags=b.BC_KEEP_ORDER) as U:
+        U.run(srcs, batch=64, flags=b.BC_RUN_ONE_QUEUE)
+        ugot = U.scores().copy()
+    assert np.max(np.abs(wgot - ugot) / np.maximum(np.abs(ugot), 1e-300)) <= 1e-12
+
+
+def test_weighted_grid_overflow_to_fp64():
+    # unit weights on a 45 x 45 grid: counts from a corner pass 2^64, so the
+    # sources run again with FP64 counts
+    base = W.grid(45)
+    g = W.with_weights(base, 1, 1, seed=2)
+    srcs = np.array([0, 44, 22 * 45 + 22, 45 * 45 - 1, 100], np.int32)
+    ref, modes = oracle.bc(g, srcs)
+    assert modes[0] == 1
+    with b.Graph(g) as G:
+        G.run(srcs)
+        assert G.stats()["f64_sources"] == int(modes.sum())
+        assert_bc_close(G.scores(), ref)
+        det = G.detail(srcs, dump_index=0)
+        check_detail(g, det, 0)
+
+
+def test_weighted_closed_forms_and_errors():
+    # a weighted path keeps the unweighted scores; weights < 1 and
+    # asymmetric undirected weights are refused
+    n = 30
+    u = np.arange(n - 1)
+    base = W.csr_from_edges(n, u, u + 1)
+    g = W.with_weights(base, 1, 9, seed=5)
+    with b.Graph(g) as G:
+        G.run(None)
+        np.testing.assert_array_equal(G.scores(), [2.0 * i * (n - 1 - i) for i in range(n)])
+    bad = g.weights.copy()
+    bad[3] = 0
+    with pytest.raises(b.BCError) as e:
+        b.bc_graph_create_weighted(g.row_ptr, g.col_idx, bad)
+    assert e.value.status == 2
+    asym = g.weights.copy()
+    asym[0] += 1
+    with pytest.raises(b.BCError) as e:
+        b.bc_graph_create_weighted(g.row_ptr, g.col_idx, asym)
+    assert e.value.status == 2
+
+
+def test_weighted_heavy_vertices():
+    # hubs above the thread-per-vertex degree: sums run lane-strided
+    base = W.rmat(13, 16, seed=63)
+    g = W.with_weights(base, 1, 4, seed=6)
+    deg = base.degrees()
+    srcs = np.concatenate([np.argsort(-deg)[:4], W.choose_sources(base, 60, seed=5)]).astype(np.int32)
+    ref, _ = oracle.bc(g, srcs)
+    with b.Graph(g) as G:
+        G.run(srcs)
+        assert_bc_close(G.scores(), ref)
+        det = G.detail(srcs, dump_index=1)
+        check_detail(g, det, int(srcs[1]))
