@@ -69,7 +69,8 @@ def measured_traffic(kernel: str, workload: str):
     summary of this workload (FETCH_SIZE and WRITE_SIZE, each scaled by its
     copy-kernel calibration), or None when there is none or the kernel
     sources changed since the counters were taken."""
-    tag = {"batch_step<0>": "batch_step_u64", "batch_step<1>": "batch_step_f64", "block_run<0>": "block_run_u64"}.get(kernel)
+    tag = {"batch_step<0>": "batch_step_u64", "batch_step<1>": "batch_step_f64", "block_run<0>": "block_run_u64",
+           "weighted_run<0>": "weighted_run_u64", "weighted_run<1>": "weighted_run_f64"}.get(kernel)
     path = os.path.join(ROOT, "profiles", f"{tag}_{workload}.md")
     if tag is None or not os.path.exists(path):
         return None
@@ -382,6 +383,13 @@ def main():
         gpu_ms = ev0.elapsed_time(ev1)
         return wall, gpu_ms, stats
 
+    # graphs with arc weights run on the weighted engine (one workgroup per
+    # source; no batch width, level policy or launch shape to tune, and no
+    # per-source or heuristic leg)
+    weighted = getattr(g, "weights", None) is not None
+    if weighted:
+        args.no_tune, args.no_plain, args.heuristic_steps = True, True, 0
+
     # ---- batched (headline); launch configuration tuned on a sample first (untimed)
     gflags = (b.BC_RUN_NO_GRAPHS if args.no_graphs else 0) | (b.BC_RUN_NO_BLOCKS if args.no_blocks else 0)
     tuned = None
@@ -416,7 +424,12 @@ def main():
     achieved_gbs = k_algo / max(dev_ms * 1e-3, 1e-12) / 1e9
     # the same bytes without the per-(vertex, source) slab term
     arcs_frac = sum(s["algo_bytes_arcs"] for s in stats) / max(sum(s["algo_bytes"] for s in stats), 1e-12)
-    kernel = "block_run<0>" if (k == 0 and st.get("block_workgroups", 0) > 0) else f"batch_step<{k}>"
+    if weighted:
+        kernel = f"weighted_run<{k}>"
+    elif k == 0 and st.get("block_workgroups", 0) > 0:
+        kernel = "block_run<0>"
+    else:
+        kernel = f"batch_step<{k}>"
     log(f"[bench] batched: {ms_step:.1f} ms/step, {gteps:.2f} GTEPS, launches/step={launches // args.steps}, "
         f"{kernel}: {k_launches} launches, {avg_launch_us:.2f} us each of device time ({trace_launch_us:.2f} us "
         f"on its stream), algo {achieved_gbs:.1f} GB/s, device ms per mode {[round(x, 1) for x in mode_ms]} "
@@ -477,7 +490,11 @@ def main():
         "vs_baseline": None,
         "dtype": "u64 path counts, f64 dependencies",
         "data": "synthetic (seeded generator, no dataset)",
-        "config": {"workload": args.workload, "n": g.n, "m": g.m, "sources": int(len(srcs)), "batch": 64,
+        "config": {"workload": args.workload, "n": g.n, "m": g.m, "sources": int(len(srcs)),
+                   "directed": bool(getattr(g, "directed", False)),
+                   "arc_weights": (f"integers in [{int(g.weights.min())}, {int(g.weights.max())}]"
+                                   if weighted else None),
+                   "batch": 1 if weighted else 64,
                    "policy": {1: "heuristic", 2: "mlp", 3: "tpv", 4: "wpv", 5: "pull"}.get(st["policy"]),
                    "mlp_weights_loaded": weights_loaded, "graph_chunk_steps": st["chunk_steps"],
                    "grid_blocks": st["grid_blocks"], "tuned": tuned},

@@ -230,7 +230,9 @@ bc_status bc_run(bc_graph *g, const int32_t *sources, int64_t n_sources,
  * Runs bc_run over the host source list sample[0 .. n_sample) (a few
  * batches' worth of the workload's sources) for every candidate, one
  * dimension at a time starting from base (NULL = defaults): batch K in
- * {64, 32, 16}, policy {heuristic, learned when weights are loaded},
+ * {64, 32, 16, 8, 1} (K = 1, the per-source engine, is timed on the first
+ * 32 sources of the sample and scaled to the whole sample, since it runs
+ * sources one after another), policy {heuristic, learned when weights are loaded},
  * workgroups per step {default, 1/2, 1/4}, level steps per captured chunk
  * {8, 16, 32}, push WPV degree threshold {12, 24, 48}, sources per entry
  * below which groups are summed by (entry, source) pairs {never, 2, 4, 12}.
@@ -244,10 +246,41 @@ bc_status bc_run(bc_graph *g, const int32_t *sources, int64_t n_sources,
  * concurrent replicas differently (agreement to rounding; see
  * BC_RUN_ONE_QUEUE), so the tuner changes speed only.  Scores are reset
  * afterwards.
- * Errors: BC_ERR_INVALID_ARG for NULL g / best or an empty or invalid sample.
+ * Tune cache: every result is also kept for the rest of the process under
+ * (device architecture and CU count, the graph's fingerprint -- sizes,
+ * flags, block offsets and degree sequence --, the sample, the resolved base
+ * options).  A later call with the same key returns the kept result without
+ * timing anything, unless base->flags has BC_TUNE_FRESH, which tunes again
+ * and replaces it.  bc_tune_cache_save / _load keep the results in a JSON
+ * file across processes.  Graphs with arc weights have nothing to tune: the
+ * resolved base options are returned.
+ * Errors: BC_ERR_INVALID_ARG for NULL g / best or an empty or invalid
+ * sample, or a cached result of the learned policy on a handle without
+ * weights.
  */
 bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_sample, const bc_run_options *base,
                       bc_run_options *best, void *stream);
+
+#define BC_TUNE_FRESH 0x80u /* bc_autotune only: ignore and replace a cached result */
+
+/*
+ * The tune cache (see bc_autotune) as a file:
+ *   {"format": "bc-autotune-cache", "version": 1, "entries": [
+ *     {"device": "gfx950:256", "graph": "<16 hex digits>", "sample": "<16 hex>",
+ *      "base": "<16 hex>", "batch": 64, "policy": 2, "grid_blocks": 384,
+ *      "chunk_steps": 16, "wpv_degree": 24, "lanes_per_entry": 4, "flags": 0}, ...]}
+ * bc_tune_cache_save writes every entry of this process to path (replacing
+ * the file); bc_tune_cache_load adds the file's entries (an entry with the
+ * same key replaces the one held).  Neither touches the GPU.
+ * Errors: BC_ERR_INVALID_ARG for a NULL path, a file that cannot be opened,
+ * read or written, or a file that is not in this format (nothing is added
+ * then).  bc_tune_cache_clear drops every entry; bc_tune_cache_size counts
+ * them.  Safe to call from several threads.
+ */
+bc_status bc_tune_cache_save(const char *path);
+bc_status bc_tune_cache_load(const char *path);
+void bc_tune_cache_clear(void);
+int64_t bc_tune_cache_size(void);
 
 /* bc_scores flags */
 #define BC_OUT_DEVICE 0x1u
@@ -322,6 +355,14 @@ typedef struct bc_stats {
     double mode_algo_bytes[2]; /* algorithmic bytes of those passes            */
     int64_t reached_pairs;     /* (vertex, source) pairs reached, sources included */
     double algo_bytes_arcs;    /* algo_bytes without the 40 B per reached pair  */
+    /* Graphs with arc weights (bc_graph_create_weighted) fill the fields
+       above as follows: forward_levels = relaxation rounds, steps = rounds
+       of the shortest-path DAG, arcs_scanned = arcs relaxed, lane_arcs = arcs
+       read by the four passes over the reached vertices (DAG in-arc counts,
+       path counts, release of successors, dependencies), launches and
+       mode_* = the engine's launches; algo_bytes = 16 per arc read in any of
+       them + 64 per reached (vertex, source) pair, algo_bytes_arcs = the
+       arc term alone. */
     int64_t block_workgroups;  /* block engine: workgroups of its launch (0 = not used) */
     int64_t block_chunks;      /* block engine: chunks of consecutive batches   */
 } bc_stats;
@@ -352,15 +393,31 @@ bc_status bc_run_level_stats(const bc_graph *g, bc_level_stats *out, int64_t cap
 /* ---------------------------------------------------------- learned policy */
 
 /*
- * Policy network: 5 features -> 32 -> 32 -> 3, ReLU hidden layers, FP32,
- * predicting log2 of the time of each BC_VARIANT_*; the level takes the
- * argmin.  Weights are packed row-major as W1[32][5], b1[32], W2[32][32],
- * b2[32], W3[3][32], b3[3]: BC_MLP_PARAMS floats.
+ * Policy network: 5 features -> 32 -> 32 -> 9, ReLU hidden layers, FP32,
+ * predicting log2 of step times at a level; each group of three outputs is
+ * a choice taken by its argmin:
+ *   0-2  the discover variant of the level (BC_VARIANT_*: the direction
+ *        switch);
+ *   3-5  the path-count step of the entries the level discovers, and
+ *   6-8  the backward step of the level's own entries, each under the
+ *        summation options (the load-balance switch) BC_LB_PACKED, BC_LB_RULE,
+ *        BC_LB_ITEMS.
+ * The summation options change speed only, never a sum or its order.
+ * Weights are packed row-major as W1[32][5], b1[32], W2[32][32], b2[32],
+ * W3[9][32], b3[9]: BC_MLP_PARAMS floats.
  * Features of a level, in order: log2(1+n_f)/log2(1+n), log2(1+m_f)/log2(1+nnz),
  * log2(1+n_u)/log2(1+n), log2(1+m_u)/log2(1+nnz), level/64, where n_f/m_f
  * are the frontier's vertices/arcs and n_u/m_u the unvisited ones.
  */
-#define BC_MLP_PARAMS (32 * 5 + 32 + 32 * 32 + 32 + 3 * 32 + 3)
+#define BC_MLP_IN 5
+#define BC_MLP_OUT 9
+#define BC_MLP_PARAMS (32 * 5 + 32 + 32 * 32 + 32 + 9 * 32 + 9)
+/* summation options of path-count and backward groups: one wavefront lane
+ * per source; the sources-per-entry rule of bc_run_options.lanes_per_entry;
+ * one thread per (entry, source) pair */
+#define BC_LB_PACKED 0
+#define BC_LB_RULE   1
+#define BC_LB_ITEMS  2
 
 /* Load weights (host float[len], len == BC_MLP_PARAMS); weights == NULL
  * unloads them.  A wrong length or non-finite weights -> BC_ERR_INVALID_ARG
@@ -369,14 +426,15 @@ bc_status bc_load_policy(bc_graph *g, const float *weights, int64_t len);
 
 /*
  * Training support for the policy network (no graph handle needed).
- * Samples: X float[n][5] (normalised features as above), Y float[n][3]
- * (log2 of the measured time of each variant, microseconds), mask uint8[n][3]
- * (1 = Y entry measured).  Loss L = sum mask * (f(x) - y)^2 / (2 * sum mask).
+ * Samples: X float[n][BC_MLP_IN] (normalised features as above), Y
+ * float[n][BC_MLP_OUT] (log2 of the measured time of each choice,
+ * microseconds), mask uint8[n][BC_MLP_OUT] (1 = Y entry measured).
+ * Loss L = sum mask * (f(x) - y)^2 / (2 * sum mask).
  * All pointers are host memory; weights are BC_MLP_PARAMS floats.
  *   bc_mlp_loss_grad  L and dL/dweights (float[BC_MLP_PARAMS]) at weights.
  *   bc_mlp_train      `steps` full-batch Adam steps (beta1 0.9, beta2 0.999,
  *                     eps 1e-8) from *weights, updated in place; final loss.
- *   bc_mlp_predict    f(X) into Y float[n][3].
+ *   bc_mlp_predict    f(X) into Y float[n][BC_MLP_OUT].
  * Errors: BC_ERR_INVALID_ARG for NULL pointers, n < 1, an all-zero mask or
  * non-finite inputs; weights are left unchanged on any error.
  */
@@ -391,7 +449,7 @@ bc_status bc_mlp_train(float *weights, const float *X, const float *Y, const uin
  * harnesses that forbid hipMalloc.  Same kernels, same result bits.
  *   weights, X, Y, mask   DEVICE pointers, layouts as above; read only.
  *   n                     1 <= n <= 16384 samples, else BC_ERR_INVALID_ARG
- *                         (the intermediates live in a fixed 8.7 MB array of
+ *                         (the intermediates live in a fixed 9.0 MB array of
  *                         the library, one per GPU, kept for the process).
  *   loss, grad            DEVICE pointers to float[1] and float[BC_MLP_PARAMS].
  * The work is enqueued on `stream` and the call returns without waiting:
@@ -413,9 +471,13 @@ bc_status bc_mlp_predict(const float *weights, const float *X, int64_t n, float 
  * Training data from real runs: runs the batched engine over the sources
  * like bc_run (scores included) but executes every forward level with each
  * of the three variants in turn from the same state (undoing the first two),
- * timing each one on the device clock.  One sample per forward level:
- * X float[cap][5] features, Y float[cap][3] log2 microseconds.  *count gets
- * the number of samples written (at most cap).
+ * every path-count step with each of the three summation options (restoring
+ * the level's visited and next words in between) and every backward step
+ * with each option (it overwrites what it writes), timing each one on the
+ * device clock.  One sample per timed step: X float[cap][BC_MLP_IN] features
+ * of the level that takes the choice, Y float[cap][BC_MLP_OUT] log2
+ * microseconds at the three outputs of that choice and NaN elsewhere.
+ * *count gets the number of samples written (at most cap).
  */
 bc_status bc_collect_level_times(bc_graph *g, const int32_t *sources, int64_t n_sources,
                                  const bc_run_options *opt, float *X, float *Y, int64_t cap,

@@ -1,9 +1,10 @@
 """Float64 CPU reference of the level-policy network -- TEST INFRASTRUCTURE ONLY.
 
 Only tests may import it.  The network maps 5 level features through two
-32-unit ReLU layers to 3 outputs (predicted log2 time of each variant).
-Parameters are packed as W1[32][5], b1[32], W2[32][32], b2[32], W3[3][32],
-b3[3].  Loss over samples (x, y, mask):
+32-unit ReLU layers to 9 outputs (predicted log2 times: three discover
+variants, three summation options of the path-count step, three of the
+backward step).  Parameters are packed as W1[32][5], b1[32], W2[32][32],
+b2[32], W3[9][32], b3[9].  Loss over samples (x, y, mask):
 
     L = sum mask * (f(x) - y)^2 / (2 * sum mask)
 
@@ -14,7 +15,7 @@ from __future__ import annotations
 
 import numpy as np
 
-H, I, O = 32, 5, 3
+H, I, O = 32, 5, 9
 N_PARAMS = H * I + H + H * H + H + O * H + O
 
 

@@ -34,6 +34,7 @@ BC_RUN_TUNED = 0x8
 BC_RUN_ONE_QUEUE = 0x10
 BC_RUN_BLOCKS = 0x20
 BC_RUN_NO_BLOCKS = 0x40
+BC_TUNE_FRESH = 0x80
 BC_OUT_DEVICE = 0x1
 
 BC_VARIANT_PUSH_TPV, BC_VARIANT_PUSH_WPV, BC_VARIANT_PULL = 0, 1, 2
@@ -43,13 +44,17 @@ BC_POLICY_MLP = 2
 BC_POLICY_FORCE_PUSH_TPV = 3
 BC_POLICY_FORCE_PUSH_WPV = 4
 BC_POLICY_FORCE_PULL = 5
-BC_MLP_PARAMS = 32 * 5 + 32 + 32 * 32 + 32 + 3 * 32 + 3
+BC_MLP_IN = 5
+BC_MLP_OUT = 9
+BC_MLP_PARAMS = 32 * 5 + 32 + 32 * 32 + 32 + 9 * 32 + 9
+BC_LB_PACKED, BC_LB_RULE, BC_LB_ITEMS = 0, 1, 2
 
 EXPORTS = ["bc_status_string", "bc_last_error", "bc_graph_create", "bc_graph_create_multi",
            "bc_graph_create_weighted", "bc_destroy",
            "bc_graph_info", "bc_run_options_init", "bc_run", "bc_scores", "bc_run_detail", "bc_run_stats",
            "bc_load_policy", "bc_mlp_loss_grad", "bc_mlp_train", "bc_mlp_predict", "bc_collect_level_times",
-           "bc_autotune", "bc_set_device_limit", "bc_run_level_stats", "bc_mlp_loss_grad_noalloc"]
+           "bc_autotune", "bc_set_device_limit", "bc_run_level_stats", "bc_mlp_loss_grad_noalloc",
+           "bc_tune_cache_save", "bc_tune_cache_load", "bc_tune_cache_clear", "bc_tune_cache_size"]
 
 
 class LibraryMissing(RuntimeError):
@@ -142,6 +147,14 @@ def lib():
     L.bc_run_stats.argtypes = [P, ctypes.POINTER(Stats)]
     L.bc_autotune.restype = ctypes.c_int
     L.bc_autotune.argtypes = [P, P, I64, ctypes.POINTER(RunOptions), ctypes.POINTER(RunOptions), P]
+    L.bc_tune_cache_save.restype = ctypes.c_int
+    L.bc_tune_cache_save.argtypes = [ctypes.c_char_p]
+    L.bc_tune_cache_load.restype = ctypes.c_int
+    L.bc_tune_cache_load.argtypes = [ctypes.c_char_p]
+    L.bc_tune_cache_clear.restype = None
+    L.bc_tune_cache_clear.argtypes = []
+    L.bc_tune_cache_size.restype = I64
+    L.bc_tune_cache_size.argtypes = []
     L.bc_load_policy.restype = ctypes.c_int
     L.bc_load_policy.argtypes = [P, P, I64]
     L.bc_mlp_loss_grad.restype = ctypes.c_int
@@ -341,6 +354,22 @@ def bc_autotune(h, sample, options: RunOptions | None = None, stream=None) -> di
             "lanes_per_entry": best.lanes_per_entry}
 
 
+def bc_tune_cache_save(path: str):
+    _check(lib().bc_tune_cache_save(os.fsencode(path)))
+
+
+def bc_tune_cache_load(path: str):
+    _check(lib().bc_tune_cache_load(os.fsencode(path)))
+
+
+def bc_tune_cache_clear():
+    lib().bc_tune_cache_clear()
+
+
+def bc_tune_cache_size() -> int:
+    return int(lib().bc_tune_cache_size())
+
+
 def bc_load_policy(h, weights):
     if weights is None:
         _check(lib().bc_load_policy(h, None, 0))
@@ -364,9 +393,9 @@ def bc_mlp_loss_grad(weights, X, Y, mask):
     """(loss, grad float32[BC_MLP_PARAMS]) of the policy-network loss."""
     n = int(np.asarray(X).shape[0])
     w = _f32(weights, (BC_MLP_PARAMS,))
-    x = _f32(X, (n, 5))
-    y = _f32(Y, (n, 3))
-    m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(n, 3)
+    x = _f32(X, (n, BC_MLP_IN))
+    y = _f32(Y, (n, BC_MLP_OUT))
+    m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(n, BC_MLP_OUT)
     loss = ctypes.c_float()
     grad = np.zeros(BC_MLP_PARAMS, np.float32)
     _check(lib().bc_mlp_loss_grad(_p(w), _p(x), _p(y), _p(m), n, ctypes.byref(loss), _p(grad), None))
@@ -375,8 +404,8 @@ def bc_mlp_loss_grad(weights, X, Y, mask):
 
 def bc_mlp_loss_grad_noalloc(weights, X, Y, mask, loss, grad, stream=None):
     """Allocation-free loss and gradient: every argument is a contiguous
-    torch cuda tensor (weights float32[BC_MLP_PARAMS], X float32[n][5],
-    Y float32[n][3], mask uint8[n][3], loss float32[1], grad
+    torch cuda tensor (weights float32[BC_MLP_PARAMS], X float32[n][BC_MLP_IN],
+    Y float32[n][BC_MLP_OUT], mask uint8[n][BC_MLP_OUT], loss float32[1], grad
     float32[BC_MLP_PARAMS]).  Enqueued on ``stream``; the outputs are valid
     once that stream's work is done."""
     import torch
@@ -393,9 +422,9 @@ def bc_mlp_train(weights, X, Y, mask, steps: int, lr: float):
     """Adam training; returns (new weights, final loss)."""
     n = int(np.asarray(X).shape[0])
     w = _f32(weights, (BC_MLP_PARAMS,)).copy()
-    x = _f32(X, (n, 5))
-    y = _f32(Y, (n, 3))
-    m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(n, 3)
+    x = _f32(X, (n, BC_MLP_IN))
+    y = _f32(Y, (n, BC_MLP_OUT))
+    m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(n, BC_MLP_OUT)
     loss = ctypes.c_float()
     _check(lib().bc_mlp_train(_p(w), _p(x), _p(y), _p(m), n, int(steps), float(lr), ctypes.byref(loss), None))
     return w, float(loss.value)
@@ -404,17 +433,18 @@ def bc_mlp_train(weights, X, Y, mask, steps: int, lr: float):
 def bc_mlp_predict(weights, X):
     n = int(np.asarray(X).shape[0])
     w = _f32(weights, (BC_MLP_PARAMS,))
-    x = _f32(X, (n, 5))
-    y = np.zeros((n, 3), np.float32)
+    x = _f32(X, (n, BC_MLP_IN))
+    y = np.zeros((n, BC_MLP_OUT), np.float32)
     _check(lib().bc_mlp_predict(_p(w), _p(x), n, _p(y), None))
     return y
 
 
 def bc_collect_level_times(h, sources, cap: int = 100000, options: RunOptions | None = None, stream=None):
-    """Per-level (features, log2 microseconds of each variant) from a real run."""
+    """Timed steps of a real run: (features, log2 microseconds of each
+    choice; NaN where a sample's choice is another one)."""
     s = np.ascontiguousarray(sources, dtype=np.int32)
-    X = np.zeros((cap, 5), np.float32)
-    Y = np.zeros((cap, 3), np.float32)
+    X = np.zeros((cap, BC_MLP_IN), np.float32)
+    Y = np.zeros((cap, BC_MLP_OUT), np.float32)
     cnt = ctypes.c_int64()
     _check(lib().bc_collect_level_times(h, _p(s), s.size, ctypes.byref(options) if options is not None else None,
                                         _p(X), _p(Y), cap, ctypes.byref(cnt), _stream(stream)))

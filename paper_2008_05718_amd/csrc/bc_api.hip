@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <type_traits>
@@ -26,6 +27,18 @@ using namespace bcx;
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_last_error;
+
+// 64-bit FNV-1a over bytes (keys of the tune cache; not a security hash).
+struct Fnv64 {
+    uint64_t v = 0xcbf29ce484222325ull;
+    void add(const void *p, size_t bytes) {
+        const unsigned char *c = (const unsigned char *)p;
+        for (size_t i = 0; i < bytes; ++i) {
+            v ^= c[i];
+            v *= 0x100000001b3ull;
+        }
+    }
+};
 
 static bc_status fail(bc_status st, const std::string &msg) {
     g_last_error = msg;
@@ -245,6 +258,9 @@ struct bc_graph {
     // autotuner result (bc_autotune), used by bc_run with BC_RUN_TUNED
     bool has_tuned = false;
     bc_run_options tuned{};
+    // sizes, flags, block offsets and degree sequence (caller's order) of the
+    // graph: the key of its autotuner results in the tune cache
+    uint64_t fingerprint = 0;
     // unions of many graphs: sub-unions run concurrently (see run_parts)
     std::vector<struct SubPart> parts;
     std::vector<int32_t> part_of_graph, local_base;  // per parent graph
@@ -503,6 +519,14 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
     {
         std::vector<int32_t> rp((size_t)n + 1);
         CR_TRY(hipMemcpy(rp.data(), g->row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost));
+        {
+            Fnv64 h;
+            const int64_t head[5] = {n, nnz, n_graphs, directed ? 1 : 0, weights ? 1 : 0};
+            h.add(head, sizeof(head));
+            h.add(voff.data(), sizeof(int32_t) * voff.size());
+            h.add(rp.data(), sizeof(int32_t) * rp.size());
+            g->fingerprint = h.v;
+        }
         // directed: the in-arcs (transpose), rows ascending; a vertex is
         // classified by the larger of its out- and in-degree
         std::vector<int32_t> cdeg((size_t)n);
@@ -801,7 +825,7 @@ static BatchedSizes batched_sizes(int64_t n, int64_t cost_units, int64_t n_heavy
     z.hq_levels = z.max_levels + 3;
     const size_t nn = (size_t)std::max<int64_t>(n, 1);
     z.bytes = nn * (sizeof(VisNext) + 2 * sizeof(Tagged)) + (size_t)z.lq_cap * (sizeof(int32_t) + 8) +
-              (size_t)(z.max_levels + 2) * sizeof(int32_t) * 2 + nn * kLanes * 3 * 8 + (size_t)z.gcap * 4 +
+              (size_t)(z.max_levels + 2) * sizeof(int32_t) * 3 + nn * kLanes * 3 * 8 + (size_t)z.gcap * 4 +
               (size_t)(z.max_levels + 2) * kLanes * 4 + (size_t)2 * kSlots * kLanes * 4 + kLanes * 4 +
               (size_t)z.hq_entries * 12 + (size_t)z.hq_levels * 8 + (size_t)(heavy_segs + 1) * kLanes * 16;
     return z;
@@ -831,7 +855,8 @@ static bc_status ensure_batched(bc_graph *g) {
     HIP_TRY(dalloc(&g->b_delta, (size_t)n * kLanes, &g->acct));
     g->b_gcap = (uint32_t)z.gcap;
     HIP_TRY(dalloc(&g->b_gstart, (size_t)z.gcap, &g->acct));
-    HIP_TRY(dalloc(&g->b_gbase, (size_t)g->b_max_levels + 2, &g->acct));
+    // group bases, then the summation options chosen at each level
+    HIP_TRY(dalloc(&g->b_gbase, 2 * ((size_t)g->b_max_levels + 2), &g->acct));
     HIP_TRY(dalloc(&g->b_shift, ((size_t)g->b_max_levels + 2) * kLanes, &g->acct));
     HIP_TRY(dalloc(&g->b_maxexp, (size_t)2 * kSlots * kLanes, &g->acct));
     HIP_TRY(dalloc(&g->b_lane_src, (size_t)kLanes, &g->acct));
@@ -1021,6 +1046,15 @@ static double algo_bytes_arcs(const bc_stats &s) {
     return 16.0 * (double)s.arcs_scanned + 8.0 * (double)s.lane_arcs + 32.0 * (double)s.queue_entries;
 }
 static double algo_bytes(const bc_stats &s) { return algo_bytes_arcs(s) + 40.0 * (double)s.reached_pairs; }
+// Weighted engine: 16 B per arc visit (target or source id, weight, the
+// other end's 64-bit distance) in the relaxation rounds and in the four
+// passes over the reached vertices' arcs (DAG in-arc counts, path counts,
+// release of successors, dependencies); 64 B per reached (vertex, source)
+// pair (distance set and reset, path count, c and delta written, delta read
+// into the partial scores, the partial's read-modify-write).
+static double algo_bytes_weighted(double relax_bytes, double dag_arcs, double reached) {
+    return relax_bytes + 16.0 * dag_arcs + 64.0 * reached;
+}
 
 static void accumulate_stats(bc_stats *s, const Ctl &c, double clock_khz) {
     for (int i = 0; i < kPhases; ++i) s->phase_ms[i] += (double)c.st_ticks[i] / clock_khz;
@@ -1053,6 +1087,7 @@ static bc_status ctl_error(const Ctl &c) {
 // positions (mode 0) are returned in *ovf_positions.
 struct CollectBufs {
     float *X = nullptr, *Y = nullptr;  // device
+    float *F = nullptr;                // device: per-level features of the current batch
     uint32_t cap = 0;
 };
 
@@ -1194,6 +1229,7 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
         a.chat = g->b_chat;
         a.gstart = g->b_gstart;
         a.gbase = g->b_gbase;
+        a.lbsel = (int32_t *)(g->b_gbase + g->b_max_levels + 2);
         a.gcap = g->b_gcap;
         a.shift = g->b_shift;
         a.maxexp = g->b_maxexp;
@@ -1208,6 +1244,7 @@ static bc_status run_pass(bc_graph *g, const RunCfg &cfg, const bc_run_options &
         if (col) {
             a.col_X = col->X;
             a.col_Y = col->Y;
+            a.col_F = col->F;
             a.col_cap = col->cap;
         }
         a.ovf_list = g->ovf;
@@ -1719,7 +1756,7 @@ static bc_status ensure_weighted(bc_graph *g) {
     want = std::min<int64_t>(want, (int64_t)(budget / g->w_stride));
     if (want < 1) return fail(BC_ERR_OUT_OF_MEMORY, "the weighted engine's per-workgroup state does not fit");
     HIP_TRY(dalloc(&g->w_scratch, (size_t)want * g->w_stride, &g->acct));
-    HIP_TRY(dalloc(&g->w_ctr, 8, &g->acct));
+    HIP_TRY(dalloc(&g->w_ctr, 16, &g->acct));
     g->w_wg = (int)want;
     return BC_OK;
 }
@@ -1759,7 +1796,7 @@ static bc_status weighted_pass(bc_graph *g, int mode, const bc_run_options &o, c
     HIP_TRY(hipMemcpyAsync(g->srcs, list.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(g->w_chunk, ch.data(), sizeof(int32_t) * ch.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(g->w_pos, pos.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, st));
-    fill_u64<<<1, 64, 0, st>>>(g->w_ctr, 8, 0ull);
+    fill_u64<<<1, 64, 0, st>>>(g->w_ctr, 16, 0ull);
     HIP_TRY(hipGetLastError());
     WeightedArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -1804,7 +1841,7 @@ static bc_status weighted_pass(bc_graph *g, int mode, const bc_run_options &o, c
     HIP_TRY(hipEventRecord(e1, st));
     sum_partials<<<grid_for(n, 256, 4096), 256, 0, st>>>(g->bc, g->w_partials, n, nc);
     HIP_TRY(hipGetLastError());
-    unsigned long long ctr[8];
+    unsigned long long ctr[16];
     HIP_TRY(hipMemcpyAsync(ctr, g->w_ctr, sizeof(ctr), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     float ms = 0.0f;
@@ -1829,6 +1866,8 @@ static bc_status weighted_pass(bc_graph *g, int mode, const bc_run_options &o, c
     g->stats.max_levels = std::max<int64_t>(g->stats.max_levels, 0);
     g->stats.steps += (int64_t)ctr[6];
     g->stats.reached_pairs += (int64_t)ctr[7];
+    g->stats.lane_arcs += (int64_t)ctr[8];
+    g->stats.mode_algo_bytes[mode] += algo_bytes_weighted(16.0 * (double)ctr[5], (double)ctr[8], (double)ctr[7]);
     return BC_OK;
 }
 
@@ -2342,8 +2381,8 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
             detail->n_levels = (int32_t)(std::unique(dvals.begin(), dvals.end()) - dvals.begin());
         }
         g->stats.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        g->stats.algo_bytes = algo_bytes(g->stats);
-        g->stats.algo_bytes_arcs = algo_bytes_arcs(g->stats);
+        g->stats.algo_bytes = g->stats.mode_algo_bytes[0] + g->stats.mode_algo_bytes[1];
+        g->stats.algo_bytes_arcs = 16.0 * (double)(g->stats.arcs_scanned + g->stats.lane_arcs);
         return BC_OK;
     }
     int dump_done = 0;
@@ -2571,14 +2610,19 @@ extern "C" bc_status bc_collect_level_times(bc_graph *g, const int32_t *sources,
     if (s != BC_OK) return s;
     cfg.mode = (o.flags & BC_RUN_FORCE_F64) ? 1 : 0;
     hipStream_t st = (hipStream_t)stream;
+    s = ensure_batched(g);
+    if (s != BC_OK) return s;
     CollectBufs cb;
     cb.cap = (uint32_t)std::min<int64_t>(cap, UINT32_MAX);
-    if (over_cap(&g->acct, (size_t)cb.cap * (kMlpIn + 3) * sizeof(float)))
+    const size_t nf = ((size_t)g->b_max_levels + 2) * kMlpIn;
+    if (over_cap(&g->acct, ((size_t)cb.cap * (kMlpIn + kMlpOut) + nf) * sizeof(float)))
         return fail(BC_ERR_OUT_OF_MEMORY, "collection buffers are over the handle's max_device_bytes");
     HIP_TRY(hipMalloc((void **)&cb.X, (size_t)cb.cap * kMlpIn * sizeof(float)));
-    hipError_t e = hipMalloc((void **)&cb.Y, (size_t)cb.cap * 3 * sizeof(float));
+    hipError_t e = hipMalloc((void **)&cb.Y, (size_t)cb.cap * kMlpOut * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&cb.F, nf * sizeof(float));
     if (e != hipSuccess) {
         (void)hipFree(cb.X);
+        if (cb.Y) (void)hipFree(cb.Y);
         return fail(BC_ERR_OUT_OF_MEMORY, "collection buffers");
     }
     std::memset(&g->stats, 0, sizeof(g->stats));
@@ -2604,7 +2648,8 @@ extern "C" bc_status bc_collect_level_times(bc_graph *g, const int32_t *sources,
         c1.mode = 1;
         CollectBufs cb1;
         cb1.X = cb.X + (size_t)n_samples * kMlpIn;
-        cb1.Y = cb.Y + (size_t)n_samples * 3;
+        cb1.Y = cb.Y + (size_t)n_samples * kMlpOut;
+        cb1.F = cb.F;
         cb1.cap = cb.cap - (uint32_t)n_samples;
         s = run_pass(g, c1, o, redo.data(), (int64_t)redo.size(), -1, nullptr, st, nullptr, nullptr, &last,
                      cb1.cap ? &cb1 : nullptr);
@@ -2613,22 +2658,23 @@ extern "C" bc_status bc_collect_level_times(bc_graph *g, const int32_t *sources,
     }
     if (s == BC_OK) {
         const int64_t k = n_samples;
-        std::vector<float> hy((size_t)k * 3);
+        std::vector<float> hy((size_t)k * kMlpOut);
         hipError_t e1 = hipMemcpy(X, cb.X, (size_t)k * kMlpIn * sizeof(float), hipMemcpyDeviceToHost);
-        hipError_t e2 = hipMemcpy(hy.data(), cb.Y, (size_t)k * 3 * sizeof(float), hipMemcpyDeviceToHost);
+        hipError_t e2 = hipMemcpy(hy.data(), cb.Y, (size_t)k * kMlpOut * sizeof(float), hipMemcpyDeviceToHost);
         if (e1 != hipSuccess || e2 != hipSuccess) {
             s = fail(BC_ERR_DEVICE, "copying collected samples");
         } else {
-            // device ticks -> log2 microseconds
+            // device ticks -> log2 microseconds; NaN where not timed
             for (size_t i = 0; i < hy.size(); ++i) {
                 const double us = (double)hy[i] / g->clock_khz * 1000.0;
-                Y[i] = (float)std::log2(std::max(us, 0.01));
+                Y[i] = hy[i] < 0.0f ? std::nanf("") : (float)std::log2(std::max(us, 0.01));
             }
             *count = k;
         }
     }
     (void)hipFree(cb.X);
     (void)hipFree(cb.Y);
+    (void)hipFree(cb.F);
     return s;
 }
 
@@ -2719,15 +2765,251 @@ extern "C" bc_status bc_load_policy(bc_graph *g, const float *weights, int64_t l
     return BC_OK;
 }
 
+// ---------------------------------------------------------------- tune cache
+// Autotuner results of this process, keyed by device (architecture and CU
+// count), graph fingerprint, sample and resolved base options; saved to and
+// loaded from a JSON file by bc_tune_cache_save / bc_tune_cache_load.
+namespace {
+struct TuneEntry {
+    std::string device;
+    uint64_t graph = 0, sample = 0, base = 0;
+    bc_run_options best{};
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+void tune_put(const TuneEntry &e) {  // caller holds g_tune_mu
+    for (TuneEntry &x : g_tune)
+        if (x.device == e.device && x.graph == e.graph && x.sample == e.sample && x.base == e.base) {
+            x.best = e.best;
+            return;
+        }
+    g_tune.push_back(e);
+}
+
+std::string hex64(uint64_t v) {
+    char b[17];
+    std::snprintf(b, sizeof(b), "%016llx", (unsigned long long)v);
+    return b;
+}
+
+// A small reader for the cache file: one object with an "entries" array of
+// flat objects whose values are strings or numbers.
+struct JsonIn {
+    const char *p, *end;
+    std::string err;
+    void ws() {
+        while (p < end && (*p == ' ' || *p == '\n' || *p == '\t' || *p == '\r')) ++p;
+    }
+    bool eat(char c) {
+        ws();
+        if (p < end && *p == c) {
+            ++p;
+            return true;
+        }
+        return false;
+    }
+    bool str(std::string *out) {
+        ws();
+        if (p >= end || *p != '"') return false;
+        ++p;
+        out->clear();
+        while (p < end && *p != '"') {
+            if (*p == '\\' && p + 1 < end) ++p;
+            out->push_back(*p++);
+        }
+        if (p >= end) return false;
+        ++p;
+        return true;
+    }
+    bool num(double *out) {
+        ws();
+        char *q = nullptr;
+        const double v = std::strtod(p, &q);
+        if (q == p || q > end) return false;
+        p = q;
+        *out = v;
+        return true;
+    }
+    // a scalar or a nested value we do not use
+    bool skip() {
+        ws();
+        if (p >= end) return false;
+        if (*p == '"') {
+            std::string t;
+            return str(&t);
+        }
+        if (*p == '{' || *p == '[') {
+            const char open = *p, close = open == '{' ? '}' : ']';
+            int depth = 0;
+            bool in_str = false;
+            for (; p < end; ++p) {
+                if (in_str) {
+                    if (*p == '\\') ++p;
+                    else if (*p == '"') in_str = false;
+                } else if (*p == '"') in_str = true;
+                else if (*p == open) ++depth;
+                else if (*p == close && --depth == 0) {
+                    ++p;
+                    return true;
+                }
+            }
+            return false;
+        }
+        while (p < end && *p != ',' && *p != '}' && *p != ']') ++p;
+        return true;
+    }
+};
+
+bool parse_entry(JsonIn &in, TuneEntry *e) {
+    bc_run_options_init(&e->best);
+    if (!in.eat('{')) return false;
+    bool have[4] = {false, false, false, false};
+    if (in.eat('}')) return false;
+    do {
+        std::string key, sv;
+        double x = 0.0;
+        if (!in.str(&key) || !in.eat(':')) return false;
+        if (key == "device" || key == "graph" || key == "sample" || key == "base") {
+            if (!in.str(&sv)) return false;
+            if (key == "device") {
+                e->device = sv;
+                have[0] = true;
+            } else {
+                char *q = nullptr;
+                const uint64_t v = std::strtoull(sv.c_str(), &q, 16);
+                if (sv.empty() || *q) return false;
+                (key == "graph" ? e->graph : key == "sample" ? e->sample : e->base) = v;
+                have[key == "graph" ? 1 : key == "sample" ? 2 : 3] = true;
+            }
+        } else if (key == "batch" || key == "policy" || key == "grid_blocks" || key == "chunk_steps" ||
+                   key == "wpv_degree" || key == "lanes_per_entry" || key == "flags") {
+            if (!in.num(&x)) return false;
+            if (key == "batch") e->best.batch = (int32_t)x;
+            else if (key == "policy") e->best.policy = (int32_t)x;
+            else if (key == "grid_blocks") e->best.grid_blocks = (int32_t)x;
+            else if (key == "chunk_steps") e->best.chunk_steps = (int32_t)x;
+            else if (key == "wpv_degree") e->best.wpv_degree = (float)x;
+            else if (key == "lanes_per_entry") e->best.lanes_per_entry = (float)x;
+            else e->best.flags = (uint32_t)x;
+        } else if (!in.skip()) {
+            return false;
+        }
+    } while (in.eat(','));
+    if (!in.eat('}')) return false;
+    return have[0] && have[1] && have[2] && have[3];
+}
+}  // namespace
+
+static std::string device_tag() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "";
+    return std::string(prop.gcnArchName) + ":" + std::to_string(prop.multiProcessorCount);
+}
+
+extern "C" bc_status bc_tune_cache_save(const char *path) {
+    if (!path) return fail(BC_ERR_INVALID_ARG, "path is NULL");
+    std::string out = "{\"format\": \"bc-autotune-cache\", \"version\": 1, \"entries\": [";
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (size_t i = 0; i < g_tune.size(); ++i) {
+            const TuneEntry &e = g_tune[i];
+            char buf[512];
+            std::snprintf(buf, sizeof(buf),
+                          "%s\n  {\"device\": \"%s\", \"graph\": \"%s\", \"sample\": \"%s\", \"base\": \"%s\", "
+                          "\"batch\": %d, \"policy\": %d, \"grid_blocks\": %d, \"chunk_steps\": %d, "
+                          "\"wpv_degree\": %.9g, \"lanes_per_entry\": %.9g, \"flags\": %u}",
+                          i ? "," : "", e.device.c_str(), hex64(e.graph).c_str(), hex64(e.sample).c_str(),
+                          hex64(e.base).c_str(), e.best.batch, e.best.policy, e.best.grid_blocks, e.best.chunk_steps,
+                          (double)e.best.wpv_degree, (double)e.best.lanes_per_entry, e.best.flags);
+            out += buf;
+        }
+    }
+    out += "\n]}\n";
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(BC_ERR_INVALID_ARG, std::string("cannot open ") + path + " for writing");
+    const bool ok = std::fwrite(out.data(), 1, out.size(), f) == out.size();
+    if (std::fclose(f) != 0 || !ok) return fail(BC_ERR_INVALID_ARG, std::string("cannot write ") + path);
+    return BC_OK;
+}
+
+extern "C" bc_status bc_tune_cache_load(const char *path) {
+    if (!path) return fail(BC_ERR_INVALID_ARG, "path is NULL");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(BC_ERR_INVALID_ARG, std::string("cannot open ") + path);
+    std::string text;
+    char buf[65536];
+    size_t k;
+    while ((k = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, k);
+    std::fclose(f);
+    JsonIn in{text.data(), text.data() + text.size(), ""};
+    std::vector<TuneEntry> got;
+    bool ok = in.eat('{');
+    bool seen = false;
+    if (ok && !in.eat('}')) {
+        do {
+            std::string key;
+            if (!in.str(&key) || !in.eat(':')) {
+                ok = false;
+                break;
+            }
+            if (key == "entries") {
+                seen = true;
+                if (!in.eat('[')) {
+                    ok = false;
+                    break;
+                }
+                if (!in.eat(']')) {
+                    do {
+                        TuneEntry e;
+                        if (!parse_entry(in, &e)) {
+                            ok = false;
+                            break;
+                        }
+                        got.push_back(e);
+                    } while (in.eat(','));
+                    if (!ok || !in.eat(']')) {
+                        ok = false;
+                        break;
+                    }
+                }
+            } else if (!in.skip()) {
+                ok = false;
+                break;
+            }
+        } while (in.eat(','));
+        ok = ok && in.eat('}');
+    }
+    if (!ok || !seen) return fail(BC_ERR_INVALID_ARG, std::string("not a tune cache file: ") + path);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const TuneEntry &e : got) tune_put(e);
+    return BC_OK;
+}
+
+extern "C" void bc_tune_cache_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+}
+
+extern "C" int64_t bc_tune_cache_size(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return (int64_t)g_tune.size();
+}
+
 extern "C" bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_sample, const bc_run_options *base,
                                  bc_run_options *best, void *stream) {
     if (!g || !best || !sample || n_sample < 1) return fail(BC_ERR_INVALID_ARG, "NULL argument or empty sample");
+    Fnv64 hs;
+    hs.add(&n_sample, sizeof(n_sample));
+    hs.add(sample, sizeof(int32_t) * (size_t)n_sample);
     std::vector<int32_t> sbuf;
     sample = to_internal(g, sample, &n_sample, &sbuf);
     bc_run_options cur;
     bc_run_options_init(&cur);
     if (base) cur = *base;
-    cur.flags &= ~(BC_RUN_ACCUMULATE | BC_RUN_TUNED);
+    const bool fresh = (cur.flags & BC_TUNE_FRESH) != 0;
+    cur.flags &= ~(BC_RUN_ACCUMULATE | BC_RUN_TUNED | BC_TUNE_FRESH);
     // resolve the automatic fields so every candidate is explicit
     RunCfg c0;
     bc_status s = resolve_cfg(g, cur, n_sample, &c0);
@@ -2739,17 +3021,70 @@ extern "C" bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_s
     if (cur.wpv_degree <= 0.0f) cur.wpv_degree = 24.0f;
     if (cur.lanes_per_entry == 0.0f) cur.lanes_per_entry = 4.0f;
     hipStream_t st = (hipStream_t)stream;
-    // a warm-up run (builds the captured graphs), then the best of two timed runs
+    auto reset_scores = [&]() -> bc_status {
+        if (g->n > 0) {
+            fill_u64<<<grid_for(g->n, 256, 4096), 256, 0, st>>>((unsigned long long *)g->bc, g->n, 0ull);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+        return BC_OK;
+    };
+    // the cache: same device, graph, sample and resolved base options
+    TuneEntry key;
+    key.device = device_tag();
+    key.graph = g->fingerprint;
+    key.sample = hs.v;
+    {
+        Fnv64 hb;
+        const int64_t f[6] = {cur.flags, cur.batch, cur.policy, cur.grid_blocks, cur.chunk_steps,
+                              (int64_t)cur.sigma_limit};
+        const float x[4] = {cur.alpha, cur.beta, cur.wpv_degree, cur.lanes_per_entry};
+        hb.add(f, sizeof(f));
+        hb.add(x, sizeof(x));
+        hb.add(&g->has_mlp, sizeof(g->has_mlp));
+        key.base = hb.v;
+    }
+    if (!fresh) {
+        bool hit = false;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            for (const TuneEntry &e : g_tune)
+                if (e.device == key.device && e.graph == key.graph && e.sample == key.sample && e.base == key.base) {
+                    cur = e.best;
+                    hit = true;
+                    break;
+                }
+        }
+        if (hit && (cur.policy != BC_POLICY_MLP || g->has_mlp)) {
+            g->tuned = cur;
+            g->has_tuned = true;
+            *best = cur;
+            return reset_scores();
+        }
+        if (hit) return fail(BC_ERR_INVALID_ARG, "cached tuning uses the learned policy; load its weights first");
+    }
+    // Weighted graphs run on their own engine, which has none of these knobs.
+    if (g->weighted) {
+        g->tuned = cur;
+        g->has_tuned = true;
+        *best = cur;
+        return reset_scores();
+    }
+    // a warm-up run (builds the captured graphs), then the best of two timed
+    // runs; the per-source engine (K = 1) runs its sources one after another,
+    // so it is timed on a prefix of the sample and scaled to the whole
     auto time_one = [&](const bc_run_options &o, double *ms) -> bc_status {
-        bc_status r = run_impl(g, sample, n_sample, &o, st, -1, nullptr);
+        const int64_t m = o.batch == 1 ? std::min<int64_t>(n_sample, 32) : n_sample;
+        bc_status r = run_impl(g, sample, m, &o, st, -1, nullptr);
         if (r != BC_OK) return r;
         *ms = 1e300;
         for (int rep = 0; rep < 2; ++rep) {
             const auto t0 = std::chrono::steady_clock::now();
-            r = run_impl(g, sample, n_sample, &o, st, -1, nullptr);
+            r = run_impl(g, sample, m, &o, st, -1, nullptr);
             if (r != BC_OK) return r;
             *ms = std::min(*ms, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
         }
+        *ms *= (double)n_sample / (double)m;
         return BC_OK;
     };
     const double kGain = 0.98;  // a candidate must be 2 % faster to replace the current choice
@@ -2757,12 +3092,13 @@ extern "C" bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_s
     s = time_one(cur, &best_ms);
     if (s != BC_OK) return s;
     const int dflt_grid = cur.grid_blocks;
+    const bool asked_plain = cur.batch == 1;
     for (int dim = 0; dim < 6; ++dim) {
         std::vector<bc_run_options> cand;
         bc_run_options c = cur;
         if (dim == 0) {
-            if (cur.batch == 1) continue;  // the per-source engine was asked for
-            for (int k : {64, 32, 16}) { c.batch = k; cand.push_back(c); }
+            if (asked_plain) continue;  // the per-source engine was asked for
+            for (int k : {64, 32, 16, 8, 1}) { c.batch = k; cand.push_back(c); }
         } else if (dim == 1) {
             if (!g->has_mlp) continue;
             for (int p : {BC_POLICY_HEURISTIC, BC_POLICY_MLP}) { c.policy = p; cand.push_back(c); }
@@ -2790,10 +3126,10 @@ extern "C" bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_s
     g->tuned = cur;
     g->has_tuned = true;
     *best = cur;
-    if (g->n > 0) {
-        fill_u64<<<grid_for(g->n, 256, 4096), 256, 0, st>>>((unsigned long long *)g->bc, g->n, 0ull);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipStreamSynchronize(st));
+    key.best = cur;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_put(key);
     }
-    return BC_OK;
+    return reset_scores();
 }

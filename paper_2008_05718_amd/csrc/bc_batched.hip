@@ -310,7 +310,7 @@ constexpr int kPack = BC_PACK;    // entries of degree <= kPack share 64-arc sca
 template <int MODE>
 __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__restrict__ fw_cur, Tagged *fw_nxt,
                                           uint32_t T, int qs, int i0, int i1, int sh, unsigned long long lmask,
-                                          SigCounters &sc, int l, int *s_emax, int *s_emin) {
+                                          SigCounters &sc, int l, int *s_emax, int *s_emin, float il) {
     // predecessors: the in-arcs (the adjacency itself for undirected graphs)
     const int32_t *__restrict__ rp = a.g.in_row_ptr;
     const int32_t *__restrict__ col = a.g.in_col;
@@ -336,7 +336,7 @@ __device__ __forceinline__ void sig_group(const BatchArgs &a, const Tagged *__re
     int iincl = 0;
     const int n_items = group_items(light ? __popcll(nxt) : 0, iincl);
     const int n_light = __popcll(__ballot(light));
-    if (n_light > 0 && (float)n_items <= a.p.item_lanes * (float)n_light) {
+    if (n_light > 0 && (float)n_items <= il * (float)n_light) {
         for (int base = 0; base < n_items; base += kWave) {
             const int it = base + lane;
             const int o = packed_owner(iincl, min(it, n_items - 1));
@@ -466,7 +466,7 @@ template <int MODE>
 __device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__restrict__ fb_nxt, Tagged *fb_cur,
                                           uint32_t TB, int qb, int i0, int i1, unsigned long long dead, int sh,
                                           int shn, unsigned long long &my_larcs, unsigned long long &my_arcs,
-                                          unsigned long long &my_pairs, int l, bool has_next) {
+                                          unsigned long long &my_pairs, int l, bool has_next, float il) {
     const int32_t *__restrict__ rp = a.g.row_ptr;
     const int32_t *__restrict__ col = a.g.col;
     const int lane = lane_id();
@@ -486,7 +486,7 @@ __device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__re
     int iincl = 0;
     const int n_items = group_items(light ? __popcll(M) : 0, iincl);
     const int n_light = __popcll(__ballot(light));
-    if (n_light > 0 && (float)n_items <= a.p.item_lanes * (float)n_light) {
+    if (n_light > 0 && (float)n_items <= il * (float)n_light) {
         for (int base = 0; base < n_items; base += kWave) {
             const int it = base + lane;
             const int o = packed_owner(iincl, min(it, n_items - 1));
@@ -588,13 +588,18 @@ __device__ __forceinline__ void bwd_group(const BatchArgs &a, const Tagged *__re
     }
 }
 
-// The variant of the next level; when collecting timings, every level starts
-// with variant 0 and its normalised features are kept for the sample.
-__device__ __forceinline__ void set_level_variant(Ctl *c, int v, const LevelFeatures &f, float n, float nnz) {
+// The variant of the next level and the summation options chosen with it
+// (lbo, see choose_variant); when collecting timings, every level starts
+// with variant 0 and its normalised features are kept for the samples.
+__device__ __forceinline__ void set_level_variant(const BatchArgs &a, Ctl *c, int v, int lbo, const LevelFeatures &f,
+                                                  float n, float nnz) {
+    if (f.level < a.max_levels + 2) a.lbsel[f.level] = lbo;
     if (c->collect) {
         float x[kMlpIn];
         mlp_inputs(f, n, nnz, x);
         for (int i = 0; i < kMlpIn; ++i) c->feat[i] = x[i];
+        if (a.col_F && f.level < a.max_levels + 2)
+            for (int i = 0; i < kMlpIn; ++i) a.col_F[(size_t)f.level * kMlpIn + i] = x[i];
         c->cvar = 0;
         c->variant = 0;
     } else {
@@ -708,14 +713,16 @@ __device__ __forceinline__ void batch_begin(const BatchArgs &a, Ctl *c, int64_t 
         sf->level = 0;
     }
     __syncthreads();
+    int lbo;
     const int v = choose_variant(a.p, c->policy, V_PUSH_TPV, *sf, (float)(c->range_hi - c->range_lo),
-                                 (float)c->range_arcs, lds);
-    if (t == 0) set_level_variant(c, v, *sf, (float)(c->range_hi - c->range_lo), (float)c->range_arcs);
+                                 (float)c->range_arcs, lds, &lbo);
+    if (t == 0) set_level_variant(a, c, v, lbo, *sf, (float)(c->range_hi - c->range_lo), (float)c->range_arcs);
 }
 
 #ifndef BC_WAVES
 #define BC_WAVES 6
 #endif
+constexpr int kBcBatch = 8;  // dependencies loaded together by the BC accumulation
 // Register budget of the step kernel: at least BC_WAVES wavefronts per SIMD
 // (memory latency is hidden by resident wavefronts).
 // One step of the level state machine for workgroup bid of a launch of
@@ -736,8 +743,10 @@ __device__ __forceinline__ void batch_step_body(const BatchArgs &a, const unsign
     __shared__ int s_lsrc[kLanes];
     __shared__ int s_lead[kLanes];
     __shared__ Stage s_stage[kWavesPerBlock];
-    __shared__ float s_lds[2 * kMlpH + 4];
+    __shared__ float s_lds[2 * kMlpH + kMlpOut + 4];
     __shared__ LevelFeatures s_feat;
+    __shared__ float s_il;  // sources-per-entry threshold of this path-count / backward step
+    __shared__ int s_usig;  // an undo step restores a path-count step (timing collection)
     __shared__ int s_emax[kLanes], s_emin[kLanes];
     Ctl *c = a.ctl;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -758,6 +767,13 @@ __device__ __forceinline__ void batch_step_body(const BatchArgs &a, const unsign
         s_h0 = s_h1 = s_hseg = s_hqb = 0;
         s_gb = s_ng = 0;
         const int l = s_level;
+        s_il = a.p.item_lanes;
+        if (s_phase == PH_SIG || s_phase == PH_BWD) {
+            // the option timed (collection), else the one chosen with level l
+            const int sel = (l < a.max_levels + 2) ? a.lbsel[l] : kLbDefault;
+            const int opt = c->collect ? c->clb : (s_phase == PH_SIG ? (sel & 3) : ((sel >> 2) & 3));
+            s_il = lb_item_lanes(a.p, opt);
+        }
         if (s_phase == PH_FWD || s_phase == PH_SIG || s_phase == PH_BWD) {
             s_qb = a.level_off[l];
             s_qe = a.level_off[l + 1];
@@ -768,6 +784,7 @@ __device__ __forceinline__ void batch_step_body(const BatchArgs &a, const unsign
             s_qe = a.level_off[l + 1];
             s_qn = (int)(uint32_t)c->next_qc;
         }
+        s_usig = c->undo_sig;
         if (s_phase == PH_FWD) {
             if (s_variant == V_PULL) {  // static heavy vertices of the batch's range
                 const int i0 = lower_bound_i32(a.g.hv_vtx, a.g.n_heavy, s_lo);
@@ -1008,13 +1025,14 @@ __device__ __forceinline__ void batch_step_body(const BatchArgs &a, const unsign
         const int n_groups = (int)s_ng;
         const uint32_t *gs = a.gstart + s_gb;
         const int total = n_groups + hseg;
+        const float il = s_il;
         SigCounters sc;
         for (WorkCursor wc(c, nblk, bid); wc.item() < total; wc.next(total)) {
             const int k = wc.item();
             const int it = k < hseg ? n_groups + k : k - hseg;  // heavy segments first
             if (it < n_groups) {
                 const int i0 = (int)gs[it], i1 = min((int)gs[it + 1], cnt);
-                if (i1 > i0) sig_group<MODE>(a, fw_cur, fw_nxt, T, qs, i0, i1, sh, lmask, sc, l, s_emax, s_emin);
+                if (i1 > i0) sig_group<MODE>(a, fw_cur, fw_nxt, T, qs, i0, i1, sh, lmask, sc, l, s_emax, s_emin, il);
                 continue;
             }
             // a segment of a heavy new vertex
@@ -1085,7 +1103,7 @@ __device__ __forceinline__ void batch_step_body(const BatchArgs &a, const unsign
                 const int i0 = (int)gs[it], i1 = min((int)gs[it + 1], cnt);
                 if (i1 > i0)
                     bwd_group<MODE>(a, fb_nxt, fb_cur, TB, qb, i0, i1, dead, sh, shn, my_larcs, my_arcs, my_pairs, l,
-                                    l + 1 < s_L);
+                                    l + 1 < s_L, s_il);
                 continue;
             }
             const int t = it - n_groups;
@@ -1108,10 +1126,24 @@ __device__ __forceinline__ void batch_step_body(const BatchArgs &a, const unsign
             bwd_finalize<MODE>(a, fb_cur, TB, v, Mf, M, acc, sh, shn);
         }
     } else if (phase == PH_UNDO) {
-        // timing collection: forget the level just discovered (its entries
-        // are the only vertices with next words set)
         const int qs = s_qe, cnt = s_qn;
-        for (int i = (int)bid * kBlock + tid; i < cnt; i += (int)nblk * kBlock) a.vn[a.lq_vtx[qs + i]].nxt = 0ull;
+        if (s_usig) {
+            // timing collection: the entries of level l+1 get back the words
+            // they had before their path-count step (that step set the lanes
+            // of their queue masks visited and cleared their next words)
+            for (int i = (int)bid * kBlock + tid; i < cnt; i += (int)nblk * kBlock) {
+                const int w = a.lq_vtx[qs + i];
+                const unsigned long long m = a.lq_mask[qs + i];
+                VisNext x = a.vn[w];
+                x.vis &= ~m;
+                x.nxt = m;
+                a.vn[w] = x;
+            }
+        } else {
+            // timing collection: forget the level just discovered (its
+            // entries are the only vertices with next words set)
+            for (int i = (int)bid * kBlock + tid; i < cnt; i += (int)nblk * kBlock) a.vn[a.lq_vtx[qs + i]].nxt = 0ull;
+        }
     } else if (phase == PH_BC) {
         // dependencies -> BC in lane order (the run's source order), then
         // clear the visited words
@@ -1123,10 +1155,23 @@ __device__ __forceinline__ void batch_step_body(const BatchArgs &a, const unsign
             unsigned long long vis = x.vis & keep;
             if (vis) {
                 double b = a.bc[w];
+                const double *dw = a.delta + (size_t)w * kLanes;
+                // the lanes' dependencies in lane order, loaded kBcBatch at a
+                // time before they are added (a source's own lane adds +0.0,
+                // which leaves the non-negative sum's bits unchanged)
                 while (vis) {
-                    const int k = __ffsll(vis) - 1;
-                    vis &= vis - 1;
-                    if (s_lsrc[k] != w) b += a.delta[(size_t)w * kLanes + k];
+                    double d[kBcBatch];
+#pragma unroll
+                    for (int j = 0; j < kBcBatch; ++j) {
+                        d[j] = 0.0;
+                        if (vis) {
+                            const int k = __ffsll(vis) - 1;
+                            vis &= vis - 1;
+                            if (s_lsrc[k] != w) d[j] = dw[k];
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < kBcBatch; ++j) b += d[j];
                 }
                 a.bc[w] = b;
             }
@@ -1219,22 +1264,56 @@ __device__ __forceinline__ void batch_step_body(const BatchArgs &a, const unsign
             }
         }
         bool timed_again = false;
+        // one training sample: features x, device ticks t[0..2] at outputs k0..k0+2
+        auto put_sample = [&](const float *x, const unsigned long long *t, int k0) {
+            const uint32_t k = c->n_samples;
+            if (k < a.col_cap) {
+                for (int i = 0; i < kMlpIn; ++i) a.col_X[(size_t)k * kMlpIn + i] = x[i];
+                for (int j = 0; j < kMlpOut; ++j)
+                    a.col_Y[(size_t)k * kMlpOut + j] = (j >= k0 && j < k0 + 3) ? (float)t[j - k0] : -1.0f;
+            }
+            c->n_samples = k + 1;
+        };
         if (phase == PH_FWD && c->collect) {
             c->ct[c->cvar] = c->last_tick ? now - prev_tick : 0ull;
             if (c->cvar < 2) {
                 timed_again = true;  // undo, then run the level with the next variant
                 c->phase = PH_UNDO;
+                c->undo_sig = 0;
             } else {
-                const uint32_t k = c->n_samples;
-                if (k < a.col_cap) {
-                    for (int i = 0; i < kMlpIn; ++i) a.col_X[(size_t)k * kMlpIn + i] = c->feat[i];
-                    for (int v = 0; v < 3; ++v) a.col_Y[(size_t)k * 3 + v] = (float)c->ct[v];
-                }
-                c->n_samples = k + 1;
+                put_sample(c->feat, c->ct, kOutFwd);
                 c->cvar = 0;
             }
         }
-        if (phase == PH_UNDO) {
+        if (phase == PH_SIG && c->collect) {
+            // the path counts of level l+1 under each summation option (the
+            // features are those of level l, which chose the option)
+            c->ct_lb[c->clb] = dt;
+            if (c->clb < 2) {
+                timed_again = true;  // restore the level's words, then sum again
+                c->phase = PH_UNDO;
+                c->undo_sig = 1;
+            } else {
+                if (a.col_F && l < a.max_levels + 2) put_sample(a.col_F + (size_t)l * kMlpIn, c->ct_lb, kOutSig);
+                c->clb = 0;
+            }
+        }
+        if (phase == PH_BWD && c->collect) {
+            // the backward step overwrites what it writes: run it again as is
+            c->ct_lb[c->clb] = dt;
+            if (c->clb < 2) {
+                timed_again = true;
+                c->clb += 1;
+            } else {
+                if (a.col_F && l < a.max_levels + 2) put_sample(a.col_F + (size_t)l * kMlpIn, c->ct_lb, kOutBwd);
+                c->clb = 0;
+            }
+        }
+        if (phase == PH_UNDO && c->undo_sig) {
+            c->undo_sig = 0;
+            c->clb += 1;
+            c->phase = PH_SIG;
+        } else if (phase == PH_UNDO) {
             c->next_qc = 0ull;
             c->next_hq = 0;
             c->cvar += 1;
@@ -1385,9 +1464,11 @@ __device__ __forceinline__ void batch_step_body(const BatchArgs &a, const unsign
             c->phase = PH_FWD;
         }
         __syncthreads();
+        int lbo;
         const int v = choose_variant(a.p, c->policy, c->prev_variant, s_feat, (float)(c->range_hi - c->range_lo),
-                                     (float)c->range_arcs, s_lds);
-        if (tid == 0) set_level_variant(c, v, s_feat, (float)(c->range_hi - c->range_lo), (float)c->range_arcs);
+                                     (float)c->range_arcs, s_lds, &lbo);
+        if (tid == 0)
+            set_level_variant(a, c, v, lbo, s_feat, (float)(c->range_hi - c->range_lo), (float)c->range_arcs);
     }
 }
 
@@ -1435,6 +1516,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BC_BLOCK
         a.max_levels = ra.max_levels;
         a.gstart = (uint32_t *)(base + L.gstart);
         a.gbase = (uint32_t *)(base + L.gbase);
+        a.lbsel = (int32_t *)(a.gbase + ra.max_levels + 2);
         a.gcap = ra.gcap;
         a.shift = (int32_t *)(base + L.shift);
         a.maxexp = (int32_t *)(base + L.maxexp);

@@ -433,11 +433,25 @@ __device__ __forceinline__ int heuristic_variant(const PolicyArgs &p, int prev, 
     return (f.nf > 0.0f && f.mf / f.nf > p.wpv_degree) ? V_PUSH_WPV : V_PUSH_TPV;
 }
 
-// Choose the variant of the next level.  Called by every thread of one
-// workgroup (the MLP spreads its hidden units over threads); the result is
-// returned to every thread.  lds needs 2 * kMlpH + 4 floats.
+// argmin of y[k0 .. k0 + 2] (the first on ties)
+__device__ __forceinline__ int argmin3(const float *y, int k0) {
+    int best = 0;
+    float bv = y[k0];
+    if (y[k0 + 1] < bv) { best = 1; bv = y[k0 + 1]; }
+    if (y[k0 + 2] < bv) best = 2;
+    return best;
+}
+
+// Choose the variant of the next level, and (in *lbo) the summation options
+// of the path-count step that sums the entries it discovers and of the
+// backward step over the level's own entries (option | option << 2).  Called
+// by every thread of one workgroup (the MLP spreads its hidden units over
+// threads); the result is returned to every thread.  lds needs
+// 2 * kMlpH + kMlpOut floats.  Only the learned policy changes the summation
+// options; every other policy keeps the sources-per-entry rule.
 __device__ __forceinline__ int choose_variant(const PolicyArgs &p, int policy, int prev, const LevelFeatures &f, float n,
-                              float nnz, float *lds) {
+                              float nnz, float *lds, int *lbo) {
+    *lbo = kLbDefault;
     if (policy == POL_FORCE_TPV) return V_PUSH_TPV;
     if (policy == POL_FORCE_WPV) return V_PUSH_WPV;
     if (policy == POL_FORCE_PULL) return V_PULL;
@@ -470,18 +484,27 @@ __device__ __forceinline__ int choose_variant(const PolicyArgs &p, int policy, i
             y[t] = s;
         }
         __syncthreads();
-        const float y0 = y[0], y1 = y[1], y2 = y[2];
-        __syncthreads();
-        if (isfinite(y0) && isfinite(y1) && isfinite(y2)) {
-            int best = 0;
-            float bv = y0;
-            if (y1 < bv) { best = 1; bv = y1; }
-            if (y2 < bv) { best = 2; }
-            return best;
+        float yy[kMlpOut];
+        bool finite = true;
+        for (int k = 0; k < kMlpOut; ++k) {
+            yy[k] = y[k];
+            finite = finite && isfinite(yy[k]);
         }
-        // non-finite prediction: fall back to the rule
+        __syncthreads();
+        if (finite) {
+            *lbo = argmin3(yy, kOutSig) | (argmin3(yy, kOutBwd) << 2);
+            return argmin3(yy, kOutFwd);
+        }
+        // non-finite prediction: fall back to the rules
     }
     return heuristic_variant(p, prev, f, n);
+}
+
+// Sources-per-entry threshold of a summation option: groups whose light
+// entries carry at most this many sources on average are summed by (entry,
+// source) pairs.
+__device__ __forceinline__ float lb_item_lanes(const PolicyArgs &p, int opt) {
+    return opt == LB_PACKED ? -1.0f : (opt == LB_ITEMS ? 65.0f : p.item_lanes);
 }
 
 // Partial sums exchanged between the wavefronts of one launch (segments of

@@ -72,7 +72,17 @@ enum : int32_t {
 enum : int32_t { V_PUSH_TPV = 0, V_PUSH_WPV = 1, V_PULL = 2 };
 enum : int32_t { POL_HEUR = 1, POL_MLP = 2, POL_FORCE_TPV = 3, POL_FORCE_WPV = 4, POL_FORCE_PULL = 5 };
 
-constexpr int kMlpIn = 5, kMlpH = 32, kMlpOut = 3;
+// Policy network: kMlpIn level features -> 32 -> 32 -> kMlpOut predicted
+// log2 times.  Outputs 0-2: the discover variants (V_*); 3-5: the path-count
+// step of the entries discovered next, 6-8: the backward step of the
+// level's entries, each under the three summation options (LB_*).
+constexpr int kMlpIn = 5, kMlpH = 32, kMlpOut = 9;
+constexpr int kOutFwd = 0, kOutSig = 3, kOutBwd = 6;
+// How path-count and backward groups sum their light entries: one wavefront
+// lane per source always (packed), by the run's sources-per-entry rule, or
+// one thread per (entry, source) pair always.  Same bits every way.
+enum : int32_t { LB_PACKED = 0, LB_RULE = 1, LB_ITEMS = 2 };
+constexpr int32_t kLbDefault = LB_RULE | (LB_RULE << 2);  // sig option | bwd option << 2
 constexpr int kMlpParams = kMlpH * kMlpIn + kMlpH + kMlpH * kMlpH + kMlpH + kMlpOut * kMlpH + kMlpOut;
 
 // Control block in device memory.  Written by the host before a run, then
@@ -113,9 +123,13 @@ struct Ctl {
     unsigned long long f_nf, f_mf, visited_n, visited_m, full_n, full_m;
     unsigned long long range_nodeg, range_arcs;  // non-isolated vertices / arcs of the range
     // --- timing collection (policy training data)
-    int32_t collect;      // 1 = run every forward level with each variant
+    int32_t collect;      // 1 = run every forward level with each variant, every path-count
+                          // and backward step with each summation option
     int32_t cvar;         // variant being timed
+    int32_t clb;          // summation option being timed (path-count and backward steps)
+    int32_t undo_sig;     // the pending undo step restores a path-count step, not a discover step
     unsigned long long ct[3];
+    unsigned long long ct_lb[3];
     float feat[kMlpIn];   // normalised features of the level being timed
     uint32_t n_samples;
     // --- detail dump
@@ -270,11 +284,14 @@ struct BatchArgs {
     double *dump_delta;
     int32_t *dump_shift;         // [max_levels + 2]
     HeavyQ hq;
-    float *col_X;                // collected features [cap][5]
-    float *col_Y;                // collected device ticks per variant [cap][3]
+    float *col_X;                // collected features [cap][kMlpIn]
+    float *col_Y;                // collected device ticks [cap][kMlpOut], -1 = not timed
+    float *col_F;                // features of every level of the batch [max_levels + 2][kMlpIn]
     uint32_t col_cap;
     uint32_t *gstart;            // group starts of every level of the batch (see GroupArgs)
     uint32_t *gbase;             // [max_levels + 2]: first gstart slot of each level
+    int32_t *lbsel;              // [max_levels + 2]: summation options chosen at each level
+                                 // (path-count option | backward option << 2)
     uint32_t gcap;
     LevelRec *lvl;               // [kLevelRecs]
 };
@@ -310,7 +327,7 @@ struct BlockLayout {
         chat = take(nmax * kLanes * 8);
         delta = take(nmax * kLanes * 8);
         gstart = take(gcap * 4);
-        gbase = take((max_levels + 2) * 4);
+        gbase = take((max_levels + 2) * 4 * 2);  // group bases, then the level's summation options
         shift = take((max_levels + 2) * kLanes * 4);
         maxexp = take(2 * kSlots * kLanes * 4);
         lane_src = take(kLanes * 4);

@@ -142,7 +142,8 @@ __device__ __forceinline__ void plain_begin_source(const PlainArgs &a, Ctl *c, i
         sf->level = 0;
     }
     __syncthreads();
-    const int v = choose_variant(a.p, c->policy, V_PUSH_TPV, *sf, (float)a.g.n, (float)a.g.nnz_lo, lds);
+    int lbo;  // one source per entry: no summation options here
+    const int v = choose_variant(a.p, c->policy, V_PUSH_TPV, *sf, (float)a.g.n, (float)a.g.nnz_lo, lds, &lbo);
     if (threadIdx.x == 0) c->variant = v;
 }
 
@@ -164,7 +165,8 @@ __device__ __forceinline__ void plain_advance_level(const PlainArgs &a, Ctl *c, 
         c->phase = PH_FWD;
     }
     __syncthreads();
-    const int v = choose_variant(a.p, c->policy, c->prev_variant, *sf, (float)a.g.n, (float)a.g.nnz_lo, lds);
+    int lbo;
+    const int v = choose_variant(a.p, c->policy, c->prev_variant, *sf, (float)a.g.n, (float)a.g.nnz_lo, lds, &lbo);
     if (threadIdx.x == 0) c->variant = v;
 }
 
@@ -190,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void plain_step(PlainArgs a) {
     __shared__ unsigned long long s_red[kSlots * kNCnt];
     __shared__ unsigned long long s_tot[kNCnt];
     __shared__ Stage s_stage[kWavesPerBlock];
-    __shared__ float s_lds[2 * kMlpH + 4];
+    __shared__ float s_lds[2 * kMlpH + kMlpOut + 4];
     __shared__ LevelFeatures s_feat;
     Ctl *c = a.ctl;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;

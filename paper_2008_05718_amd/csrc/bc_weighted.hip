@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void weighted_run(WeightedArgs a) {
     int32_t *qb = (int32_t *)(base + L.qb);
     int32_t *lvl = (int32_t *)(base + L.lvl);
     int32_t *lvl_off = (int32_t *)(base + L.lvl_off);
-    unsigned long long st_rounds = 0, st_arcs = 0, st_dag = 0, st_reached = 0;
+    unsigned long long st_rounds = 0, st_arcs = 0, st_dag = 0, st_reached = 0, st_darcs = 0;
     // the state of a fresh workgroup: every distance unknown, no marks, no counts
     for (int i = tid; i < n; i += kBlock) {
         dist[i] = kInf;
@@ -174,6 +174,7 @@ __global__ __launch_bounds__(kBlock) void weighted_run(WeightedArgs a) {
                 const int v = reached[i];
                 if (irp[v + 1] - irp[v] > kLightDeg) continue;
                 const unsigned long long dv = ld_dist(&dist[v]);
+                st_darcs += (unsigned)(irp[v + 1] - irp[v]);
                 int c = 0;
                 for (int e = irp[v]; e < irp[v + 1]; ++e) {
                     const unsigned long long du = ld_dist(&dist[icol[e]]);
@@ -185,6 +186,7 @@ __global__ __launch_bounds__(kBlock) void weighted_run(WeightedArgs a) {
                 const int v = reached[i];
                 if (irp[v + 1] - irp[v] <= kLightDeg) continue;
                 const unsigned long long dv = ld_dist(&dist[v]);
+                if (lane == 0) st_darcs += (unsigned)(irp[v + 1] - irp[v]);
                 int c = 0;
                 for (int e = irp[v] + lane; e < irp[v + 1]; e += kWave) {
                     const unsigned long long du = ld_dist(&dist[icol[e]]);
@@ -220,6 +222,7 @@ __global__ __launch_bounds__(kBlock) void weighted_run(WeightedArgs a) {
                         continue;
                     }
                     const unsigned long long dv = ld_dist(&dist[v]);
+                    st_darcs += (unsigned)(e1 - e0);
                     unsigned long long lo = 0, hi = 0;
                     double accd = 0.0;
                     for (int e = e0; e < e1; ++e) {
@@ -245,6 +248,7 @@ __global__ __launch_bounds__(kBlock) void weighted_run(WeightedArgs a) {
                     const int e0 = irp[v], e1 = irp[v + 1];
                     if (v == s || e1 - e0 <= kLightDeg) continue;
                     const unsigned long long dv = ld_dist(&dist[v]);
+                    if (lane == 0) st_darcs += (unsigned)(e1 - e0);
                     unsigned long long lo = 0, hi = 0;
                     double accd = 0.0;
                     for (int e = e0 + lane; e < e1; e += kWave) {
@@ -282,6 +286,7 @@ __global__ __launch_bounds__(kBlock) void weighted_run(WeightedArgs a) {
                     const int v = cur[i];
                     if (rp[v + 1] - rp[v] > kLightDeg) continue;
                     const unsigned long long dv = ld_dist(&dist[v]);
+                    st_darcs += (unsigned)(rp[v + 1] - rp[v]);
                     for (int e = rp[v]; e < rp[v + 1]; ++e) {
                         const int x = col[e];
                         if (dv + (unsigned long long)wt[e] == ld_dist(&dist[x]) && atomicSub(&cnt[x], 1) == 1)
@@ -292,6 +297,7 @@ __global__ __launch_bounds__(kBlock) void weighted_run(WeightedArgs a) {
                     const int v = cur[i];
                     if (rp[v + 1] - rp[v] <= kLightDeg) continue;
                     const unsigned long long dv = ld_dist(&dist[v]);
+                    if (lane == 0) st_darcs += (unsigned)(rp[v + 1] - rp[v]);
                     for (int e = rp[v] + lane; e < rp[v + 1]; e += kWave) {
                         const int x = col[e];
                         if (dv + (unsigned long long)wt[e] == ld_dist(&dist[x]) && atomicSub(&cnt[x], 1) == 1)
@@ -321,6 +327,7 @@ __global__ __launch_bounds__(kBlock) void weighted_run(WeightedArgs a) {
                         const int e0 = rp[v], e1 = rp[v + 1];
                         if (e1 - e0 > kLightDeg) continue;
                         const unsigned long long dv = ld_dist(&dist[v]);
+                        st_darcs += (unsigned)(e1 - e0);
                         double acc = 0.0;
                         for (int e = e0; e < e1; ++e) {
                             const int u = col[e];
@@ -336,6 +343,7 @@ __global__ __launch_bounds__(kBlock) void weighted_run(WeightedArgs a) {
                         const int e0 = rp[v], e1 = rp[v + 1];
                         if (e1 - e0 <= kLightDeg) continue;
                         const unsigned long long dv = ld_dist(&dist[v]);
+                        if (lane == 0) st_darcs += (unsigned)(e1 - e0);
                         double acc = 0.0;
                         for (int e = e0 + lane; e < e1; e += kWave) {
                             const int u = col[e];
@@ -383,12 +391,14 @@ __global__ __launch_bounds__(kBlock) void weighted_run(WeightedArgs a) {
         }
     }
     // statistics
-    const unsigned long long vals[4] = {st_rounds, st_arcs, st_dag, st_reached};
+    // (rounds, DAG rounds and reached pairs are the same in every thread;
+    // arc counts are per thread)
+    const unsigned long long vals[5] = {st_rounds, st_arcs, st_dag, st_reached, st_darcs};
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        unsigned long long x = wave_sum_u64(vals[k]);
-        if (k != 1) x = vals[k];  // rounds, DAG rounds and reached pairs are the same in every thread
-        if (lane == 0 && (k == 1 || tid == 0) && x) atomicAdd(&a.st[k], x);
+    for (int k = 0; k < 5; ++k) {
+        const bool per_thread = k == 1 || k == 4;
+        unsigned long long x = per_thread ? wave_sum_u64(vals[k]) : vals[k];
+        if (lane == 0 && (per_thread || tid == 0) && x) atomicAdd(&a.st[k], x);
     }
 }
 

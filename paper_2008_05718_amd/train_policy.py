@@ -6,9 +6,11 @@ Training graphs (seeds >= 100, disjoint from every benchmark input): R-MAT
 scales 16-20 and 256^2 - 1024^2 damaged grids with and without shortcuts.
 For each graph the batched engine runs 64-source batches in timing
 mode (bc_collect_level_times): every forward level is executed with each of
-the three variants from the same state and timed on the device clock.  The
-samples train the 5 -> 32 -> 32 -> 3 network with the library's own HIP
-kernels (bc_mlp_train); the weights are written as float32[BC_MLP_PARAMS].
+the three variants from the same state, every path-count and backward step
+with each of the three summation options, each timed on the device clock.
+The samples (each with the three outputs of its own choice measured) train
+the 5 -> 32 -> 32 -> 9 network with the library's own HIP kernels
+(bc_mlp_train); the weights are written as float32[BC_MLP_PARAMS].
 """
 from __future__ import annotations
 
@@ -29,17 +31,39 @@ from paper_2008_05718_amd import workloads as W  # noqa: E402
 
 def he_init(seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
-    H, I, O = 32, 5, 3
+    H, I, O = 32, b.BC_MLP_IN, b.BC_MLP_OUT
     parts = [rng.normal(0, np.sqrt(2.0 / I), H * I), np.zeros(H), rng.normal(0, np.sqrt(2.0 / H), H * H),
              np.zeros(H), rng.normal(0, np.sqrt(1.0 / H), O * H), np.full(O, 6.0)]
     return np.concatenate(parts).astype(np.float32)
+
+
+GROUPS = {"discover": 0, "path_counts": 3, "backward": 6}
+
+
+def group_report(Y, pred):
+    """Per choice group: samples, how often the argmin of the prediction is
+    the measured best, and the summed time of the choices (and of each fixed
+    choice) over the summed best time."""
+    out = {}
+    for name, k0 in GROUPS.items():
+        rows = np.isfinite(Y[:, k0])
+        if not rows.any():
+            continue
+        y = Y[rows, k0:k0 + 3]
+        ch = np.argmin(pred[rows, k0:k0 + 3], axis=1)
+        tb = np.exp2(y.min(axis=1)).sum()
+        out[name] = {"samples": int(rows.sum()),
+                     "argmin_accuracy": float((ch == np.argmin(y, axis=1)).mean()),
+                     "time_of_choices_over_best": float(np.exp2(y[np.arange(len(y)), ch]).sum() / tb),
+                     "time_of_fixed_choice_over_best": [float(np.exp2(y[:, v]).sum() / tb) for v in range(3)]}
+    return out
 
 
 def training_graphs(quick: bool):
     specs = []
     scales = [16, 17] if quick else [16, 17, 18, 19, 20]
     for i, sc in enumerate(scales):
-        specs.append((f"rmat{sc}", lambda sc=sc, i=i: W.rmat(sc, 16, seed=100 + i), 256 if quick else 1024))
+        specs.append((f"rmat{sc}", lambda sc=sc, i=i: W.rmat(sc, 16, seed=100 + i), 256 if quick else 2048))
     grids = [256] if quick else [256, 512, 1024]
     for j, L in enumerate(grids):
         specs.append((f"grid{L}_sc", lambda L=L, j=j: W.grid(L, 0.10, 0.001, seed=110 + j), 64))
@@ -65,10 +89,13 @@ def main():
             X, Y = G.collect_level_times(srcs)
         Xs.append(X)
         Ys.append(Y)
-        best = np.bincount(np.argmin(Y, axis=1), minlength=3).tolist()
+        best = {}
+        for gname, k0 in GROUPS.items():
+            rows = np.isfinite(Y[:, k0])
+            best[gname] = np.bincount(np.argmin(Y[rows, k0:k0 + 3], axis=1), minlength=3).tolist()
         meta.append({"graph": name, "n": g.n, "m": g.m, "sources": int(nsrc), "samples": int(len(X)),
-                     "best_variant_counts": best, "seconds": round(time.time() - t0, 1)})
-        print(f"[train] {name}: {len(X)} samples, best variant counts {best}", flush=True)
+                     "best_choice_counts": best, "seconds": round(time.time() - t0, 1)})
+        print(f"[train] {name}: {len(X)} samples, best choice counts {best}", flush=True)
     # every graph weighs about the same in the loss: a deep grid yields
     # thousands of levels, a power-law graph a handful per batch
     top = max(len(x) for x in Xs)
@@ -76,29 +103,19 @@ def main():
     for m, r in zip(meta, reps):
         m["replicated"] = r
     X = np.concatenate([np.repeat(x, r, axis=0) for x, r in zip(Xs, reps)]).astype(np.float32)
-    Y = np.concatenate([np.repeat(y, r, axis=0) for y, r in zip(Ys, reps)]).astype(np.float32)
-    M = np.ones_like(Y, dtype=np.uint8)
+    Yr = np.concatenate([np.repeat(y, r, axis=0) for y, r in zip(Ys, reps)]).astype(np.float32)
+    M = np.isfinite(Yr).astype(np.uint8)  # each sample measured one choice group
+    Y = np.nan_to_num(Yr)
     w0 = he_init(0)
     loss0, _ = b.bc_mlp_loss_grad(w0, X, Y, M)
     w, loss = b.bc_mlp_train(w0, X, Y, M, args.steps, args.lr)
-    pred = b.bc_mlp_predict(w, X)
-    choice = np.argmin(pred, axis=1)
-    best = np.argmin(Y, axis=1)
-    t_choice = np.exp2(Y[np.arange(len(Y)), choice]).sum()
-    t_best = np.exp2(Y.min(axis=1)).sum()
     wp = b.bc_mlp_predict(w, np.concatenate(Xs).astype(np.float32))
     o = 0
     for m, y in zip(meta, Ys):
-        ch = np.argmin(wp[o:o + len(y)], axis=1)
+        m["choices"] = group_report(y, wp[o:o + len(y)])
         o += len(y)
-        tb = np.exp2(y.min(axis=1)).sum()
-        m["time_of_choices_over_best"] = float(np.exp2(y[np.arange(len(y)), ch]).sum() / tb)
-        m["time_of_fixed_variant_over_best"] = [float(np.exp2(y[:, v]).sum() / tb) for v in range(3)]
     report = {"samples": int(len(X)), "loss_initial": loss0, "loss_final": loss, "steps": args.steps,
-              "lr": args.lr, "argmin_accuracy": float((choice == best).mean()),
-              "time_of_choices_over_best": float(t_choice / t_best),
-              "time_of_fixed_variant_over_best": [float(np.exp2(Y[:, v]).sum() / t_best) for v in range(3)],
-              "graphs": meta}
+              "lr": args.lr, "choices": group_report(Yr, b.bc_mlp_predict(w, X)), "graphs": meta}
     print(json.dumps(report, indent=1), flush=True)
     np.save(args.out, w)
     if args.report:

@@ -382,6 +382,10 @@ def workload(name: str, small: bool = False):
     ba512      : 512 BA graphs, n log-uniform [1e3, 1e5], all sources (seed 4)
     ba512_frac64 : the same union, every 64th vertex of every graph as a source
     rmat22     : R-MAT scale 22, ef 16, 16384 sources              (seed 5, src 1004)
+    rmat18_directed : R-MAT scale 18 arcs kept directed, 8192 sources of out-degree >= 1
+                      (seed 2, src 1001)
+    rmat18_weighted : rmat18 with edge weights uniform in [1, 100], 4096 sources
+                      (weight seed 6, src 1001)
     """
     if name == "er2000":
         g = erdos_renyi(2000, 8.0, seed=1)
@@ -410,4 +414,11 @@ def workload(name: str, small: bool = False):
     if name == "rmat22":
         g = rmat(22, 16, seed=5)
         return g, choose_sources(g, 16384, seed=1004)
+    if name == "rmat18_directed":
+        g = rmat_directed(18, 16, seed=2)
+        return g, choose_sources(g, 8192, seed=1001)
+    if name == "rmat18_weighted":
+        g = rmat(18, 16, seed=2)
+        srcs = choose_sources(g, 4096, seed=1001)
+        return with_weights(g, 1, 100, seed=6), srcs
     raise KeyError(name)

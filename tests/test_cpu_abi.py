@@ -68,7 +68,11 @@ def test_struct_layouts_match_header(cname, pyt):
 def test_mlp_param_count_matches_header():
     txt = open(HEADER).read()
     m = re.search(r"#define BC_MLP_PARAMS \((.*?)\)\n", txt)
-    assert eval(m.group(1)) == b.BC_MLP_PARAMS == 1347
+    assert eval(m.group(1)) == b.BC_MLP_PARAMS == 1545
+    for name in ("BC_MLP_IN", "BC_MLP_OUT", "BC_LB_PACKED", "BC_LB_RULE", "BC_LB_ITEMS"):
+        v = re.search(rf"#define {name} +(\d+)", txt)
+        assert v and int(v.group(1)) == getattr(b, name), name
+    assert b.BC_MLP_PARAMS == 32 * b.BC_MLP_IN + 32 + 32 * 32 + 32 + b.BC_MLP_OUT * 32 + b.BC_MLP_OUT
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

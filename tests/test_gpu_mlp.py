@@ -23,9 +23,10 @@ WEIGHTS = os.path.join(os.path.dirname(HERE), "paper_2008_05718_amd", "policy_we
 
 def _data(n, seed):
     rng = np.random.default_rng(seed)
-    X = rng.uniform(0, 1, (n, 5)).astype(np.float32)
-    Y = (3 + 4 * X[:, [0, 1, 2]] - 2 * X[:, [3, 4, 0]] + rng.normal(0, 0.1, (n, 3))).astype(np.float32)
-    M = (rng.uniform(0, 1, (n, 3)) < 0.9).astype(np.uint8)
+    X = rng.uniform(0, 1, (n, b.BC_MLP_IN)).astype(np.float32)
+    Y = (3 + 4 * X[:, [0, 1, 2, 3, 4, 0, 1, 2, 3]] - 2 * X[:, [3, 4, 0, 1, 2, 2, 4, 0, 1]]
+         + rng.normal(0, 0.1, (n, b.BC_MLP_OUT))).astype(np.float32)
+    M = (rng.uniform(0, 1, (n, b.BC_MLP_OUT)) < 0.9).astype(np.uint8)
     M[0] = 1
     return X, Y, M
 
@@ -81,10 +82,21 @@ def test_collect_level_times_keeps_results():
     say("[collect] rmat12")
     with b.Graph(g) as G:
         X, Y = G.collect_level_times(srcs)
-        assert len(X) >= 3 and np.isfinite(X).all() and np.isfinite(Y).all()
+        assert len(X) >= 9 and np.isfinite(X).all()
         assert (X >= 0).all() and (X[:, :4] <= 1.0 + 1e-6).all()
+        _check_samples(Y)
         ref, _ = oracle.bc(g, srcs)
-        assert_bc_close(G.scores(), ref)  # three variants per level, one result
+        assert_bc_close(G.scores(), ref)  # three variants / options per step, one result
+
+
+def _check_samples(Y):
+    # every sample times one choice: three finite outputs of one group
+    fin = np.isfinite(Y)
+    groups = fin.reshape(len(Y), 3, 3)
+    assert (fin.sum(axis=1) == 3).all()
+    assert (groups.all(axis=2).sum(axis=1) == 1).all()
+    per = groups.all(axis=2).sum(axis=0)
+    assert (per > 0).all(), per  # discover, path-count and backward samples
 
 
 def test_collect_level_times_deep_grid():
@@ -94,7 +106,8 @@ def test_collect_level_times_deep_grid():
     say("[collect] grid48")
     with b.Graph(g) as G:
         X, Y = G.collect_level_times(srcs)
-        assert len(X) > 100 and np.isfinite(Y).all()
+        assert len(X) > 300
+        _check_samples(Y)
         ref, _ = oracle.bc(g, srcs)
         assert_bc_close(G.scores(), ref)
 
@@ -104,8 +117,47 @@ def _weights_or_train(g):
         return np.load(WEIGHTS)
     with b.Graph(g) as G:
         X, Y = G.collect_level_times(W.choose_sources(g, 128, seed=11))
-    w, _ = b.bc_mlp_train(mlp_ref.init(0), X, Y, np.ones_like(Y, dtype=np.uint8), 1500, 3e-3)
+    M = np.isfinite(Y).astype(np.uint8)
+    w, _ = b.bc_mlp_train(mlp_ref.init(0), X, np.nan_to_num(Y), M, 1500, 3e-3)
     return w
+
+
+def _constant_policy(fwd, sig, bwd):
+    # zero layers, output biases only: the network predicts b3 at every level
+    w = np.zeros(b.BC_MLP_PARAMS, np.float32)
+    b3 = np.ones(b.BC_MLP_OUT, np.float32)
+    b3[fwd] = b3[3 + sig] = b3[6 + bwd] = 0.0
+    w[-b.BC_MLP_OUT:] = b3
+    return w
+
+
+@pytest.mark.parametrize("flags", [0, b.BC_RUN_NO_BLOCKS])
+def test_learned_summation_options_take_effect(flags):
+    # the network's path-count / backward choices replace the run's rule:
+    # arc counts of those phases follow the option (the (entry, source)
+    # summation scans an entry's arcs once per source), scores keep their bits
+    g = W.rmat(12, 16, seed=21)
+    srcs = W.choose_sources(g, 640, seed=4)
+    say(f"[learned summation] rmat12 flags={flags}")
+    with b.Graph(g) as G:
+        def run(**kw):
+            G.run(srcs, batch=64, flags=flags, **kw)
+            st = G.stats()
+            return G.scores().copy(), st["phase_arcs"][2:4]
+        bits_p, arcs_p = run(policy=b.BC_POLICY_HEURISTIC, lanes_per_entry=-1.0)
+        bits_i, arcs_i = run(policy=b.BC_POLICY_HEURISTIC, lanes_per_entry=65.0)
+        assert np.array_equal(bits_p.view(np.uint64), bits_i.view(np.uint64))
+        assert arcs_p != arcs_i
+        G.load_policy(_constant_policy(b.BC_VARIANT_PUSH_TPV, b.BC_LB_ITEMS, b.BC_LB_ITEMS))
+        bits, arcs = run(policy=b.BC_POLICY_MLP, lanes_per_entry=-1.0)
+        assert arcs == arcs_i and np.array_equal(bits.view(np.uint64), bits_p.view(np.uint64))
+        G.load_policy(_constant_policy(b.BC_VARIANT_PULL, b.BC_LB_PACKED, b.BC_LB_PACKED))
+        bits, arcs = run(policy=b.BC_POLICY_MLP, lanes_per_entry=65.0)
+        assert arcs == arcs_p and np.array_equal(bits.view(np.uint64), bits_p.view(np.uint64))
+        G.load_policy(_constant_policy(b.BC_VARIANT_PULL, b.BC_LB_ITEMS, b.BC_LB_PACKED))
+        bits, arcs = run(policy=b.BC_POLICY_MLP)
+        assert arcs[0] == arcs_i[0] and arcs[1] == arcs_p[1]
+        assert np.array_equal(bits.view(np.uint64), bits_p.view(np.uint64))
 
 
 def test_learned_policy_same_bits_and_its_gain():

@@ -10,9 +10,9 @@ from oracle import mlp_ref
 
 def _data(n=40, seed=3):
     rng = np.random.default_rng(seed)
-    X = rng.uniform(0, 1, (n, 5))
-    Y = rng.normal(5, 2, (n, 3))
-    M = (rng.uniform(0, 1, (n, 3)) < 0.8).astype(np.uint8)
+    X = rng.uniform(0, 1, (n, mlp_ref.I))
+    Y = rng.normal(5, 2, (n, mlp_ref.O))
+    M = (rng.uniform(0, 1, (n, mlp_ref.O)) < 0.8).astype(np.uint8)
     M[0] = 1
     return X, Y, M
 
@@ -44,8 +44,9 @@ def test_gradient_matches_torch_autograd():
         nonlocal o
         t = wt[o:o + k]; o += k
         return t
-    W1 = take(160).reshape(32, 5); b1 = take(32); W2 = take(1024).reshape(32, 32); b2 = take(32)
-    W3 = take(96).reshape(3, 32); b3 = take(3)
+    W1 = take(32 * 5).reshape(32, 5); b1 = take(32); W2 = take(1024).reshape(32, 32); b2 = take(32)
+    W3 = take(9 * 32).reshape(9, 32); b3 = take(9)
+    assert o == w.size
     x = torch.tensor(X); y = torch.tensor(Y); m = torch.tensor(M, dtype=torch.float64)
     h1 = torch.relu(x @ W1.T + b1)
     h2 = torch.relu(h1 @ W2.T + b2)
@@ -66,4 +67,4 @@ def test_planted_gradient_mistake_is_caught():
     d3 = M * (y - Y) / M.sum()
     d2 = (d3 @ W3) * (z2 > 0)
     wrong_gW1 = ((d2 @ W2)).T @ Xf  # mask omitted
-    assert not np.allclose(wrong_gW1.ravel(), g[:160], rtol=1e-6, atol=1e-9)
+    assert not np.allclose(wrong_gW1.ravel(), g[:32 * 5], rtol=1e-6, atol=1e-9)

@@ -15,9 +15,9 @@ pytestmark = pytest.mark.gpu
 
 def _samples(n, seed):
     rng = np.random.default_rng(seed)
-    X = rng.random((n, 5), dtype=np.float32)
-    Y = (rng.standard_normal((n, 3)) * 3).astype(np.float32)
-    mask = (rng.random((n, 3)) < 0.8).astype(np.uint8)
+    X = rng.random((n, b.BC_MLP_IN), dtype=np.float32)
+    Y = (rng.standard_normal((n, b.BC_MLP_OUT)) * 3).astype(np.float32)
+    mask = (rng.random((n, b.BC_MLP_OUT)) < 0.8).astype(np.uint8)
     mask[0] = 1
     return X, Y, mask
 
