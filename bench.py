@@ -35,7 +35,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-TUNE_SOURCES = 512  # autotuner sample: the first sources of the list (untimed)
+TUNE_SOURCES = 2048  # autotuner sample: the first sources of the list (untimed)
+# autotuner results for the benchmark workloads on this GPU model, written by
+# `bench.py --tune-cache-out` on an MI355X; a hit skips the timing runs
+TUNE_CACHE = os.path.join(ROOT, "paper_2008_05718_amd", "tune_cache.json")
 KERNEL_SOURCES = ["paper_2008_05718_amd/csrc/bc_batched.hip", "paper_2008_05718_amd/csrc/bc_common.h",
                   "paper_2008_05718_amd/csrc/bc_api.hip",
                   "paper_2008_05718_amd/csrc/bc_dev.h", "paper_2008_05718_amd/build.py"]
@@ -300,7 +303,13 @@ def main():
     ap.add_argument("--no-blocks", action="store_true", help="never use the block engine (small graphs)")
     ap.add_argument("--lanes-per-entry", type=float, default=0.0,
                     help="entry-by-source summation threshold of the batched engine (0 = library default, <0 = off)")
-    ap.add_argument("--no-tune", action="store_true", help="skip bc_autotune (default: tune on the first 512 sources)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help=f"skip bc_autotune (default: tune on the first {TUNE_SOURCES} sources)")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE, help="tune cache file to load (if it exists)")
+    ap.add_argument("--tune-cache-out", help="write the process's tune cache here after tuning")
+    ap.add_argument("--retune", action="store_true", help="tune even when the cache holds a result")
+    ap.add_argument("--policy-margin", type=float, default=0.0,
+                    help="learned policy: log2 gain needed to override the rule (0 = library default, <0 = none)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes 3 times (counter calibration)")
     ap.add_argument("--summarize-profile", action="store_true",
@@ -393,14 +402,24 @@ def main():
     # ---- batched (headline); launch configuration tuned on a sample first (untimed)
     gflags = (b.BC_RUN_NO_GRAPHS if args.no_graphs else 0) | (b.BC_RUN_NO_BLOCKS if args.no_blocks else 0)
     tuned = None
+    tune_cached = False
     if not args.no_tune:
+        if args.tune_cache and os.path.exists(args.tune_cache):
+            b.bc_tune_cache_load(args.tune_cache)
         t = time.time()
-        tuned = G.autotune(srcs[:TUNE_SOURCES], batch=64, policy=pol, grid_blocks=args.grid, flags=gflags,
-                           lanes_per_entry=args.lanes_per_entry)
+        n0 = b.bc_tune_cache_size()
+        tuned = G.autotune(srcs[:TUNE_SOURCES], batch=64, policy=pol, grid_blocks=args.grid,
+                           flags=gflags | (b.BC_TUNE_FRESH if args.retune else 0),
+                           lanes_per_entry=args.lanes_per_entry, policy_margin=args.policy_margin)
+        tune_cached = b.bc_tune_cache_size() == n0 and not args.retune  # a miss adds an entry
         gflags |= b.BC_RUN_TUNED
-        log(f"[bench] autotuned on {min(TUNE_SOURCES, len(srcs))} sources in {time.time() - t:.1f}s: {tuned}")
+        log(f"[bench] autotuned on {min(TUNE_SOURCES, len(srcs))} sources in {time.time() - t:.1f}s"
+            f"{' (tune cache hit)' if tune_cached else ''}: {tuned}")
+        if args.tune_cache_out:
+            b.bc_tune_cache_save(args.tune_cache_out)
     wall, gpu_ms, stats = timed(srcs, args.steps, args.warmup, batch=64, policy=pol, flags=gflags,
-                                grid_blocks=args.grid, lanes_per_entry=args.lanes_per_entry)
+                                grid_blocks=args.grid, lanes_per_entry=args.lanes_per_entry,
+                                policy_margin=args.policy_margin)
     st = stats[-1]
     headline_bits = G.scores().copy()
     ms_step = wall * 1e3 / args.steps
@@ -445,7 +464,8 @@ def main():
     heur = None
     if args.heuristic_steps > 0 and pol == b.BC_POLICY_MLP:
         hw, _, hst = timed(srcs, args.heuristic_steps, 1, batch=64, policy=b.BC_POLICY_HEURISTIC, flags=gflags,
-                           grid_blocks=args.grid, lanes_per_entry=args.lanes_per_entry)
+                           grid_blocks=args.grid, lanes_per_entry=args.lanes_per_entry,
+                           policy_margin=args.policy_margin)
         same = bool(np.array_equal(G.scores().view(np.uint64), headline_bits.view(np.uint64)))
         hg = work * args.heuristic_steps / hw / 1e9
         heur = {"value": round(hg, 4), "unit": "GTEPS", "steps": args.heuristic_steps,
@@ -497,7 +517,8 @@ def main():
                    "batch": 1 if weighted else 64,
                    "policy": {1: "heuristic", 2: "mlp", 3: "tpv", 4: "wpv", 5: "pull"}.get(st["policy"]),
                    "mlp_weights_loaded": weights_loaded, "graph_chunk_steps": st["chunk_steps"],
-                   "grid_blocks": st["grid_blocks"], "tuned": tuned},
+                   "grid_blocks": st["grid_blocks"], "tuned": tuned, "tune_cache_hit": tune_cached,
+                   "policy_margin": args.policy_margin},
         "create_s": round(create_s, 3),
         "heuristic": heur,
         "plain": plain,

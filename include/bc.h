@@ -203,7 +203,13 @@ typedef struct bc_run_options {
                              pair instead of one wavefront lane per source
                              (0 = default 4; negative = never).  Same results bit
                              for bit either way; speed only.                */
-    int32_t reserved[7];
+    float policy_margin;  /* learned policy: a level keeps the rule's choice (the
+                             direction-optimising variant, the sources-per-entry
+                             summation) unless the network predicts the other
+                             choice faster by at least this many log2 units
+                             (0 = default 0.07, about 5 %; negative = no margin:
+                             the network's argmin).  Speed only.            */
+    int32_t reserved[6];
 } bc_run_options;
 
 /* Fill *opt with defaults (all zero fields, i.e. autotuned/automatic). */
@@ -268,7 +274,8 @@ bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_sample, cons
  *   {"format": "bc-autotune-cache", "version": 1, "entries": [
  *     {"device": "gfx950:256", "graph": "<16 hex digits>", "sample": "<16 hex>",
  *      "base": "<16 hex>", "batch": 64, "policy": 2, "grid_blocks": 384,
- *      "chunk_steps": 16, "wpv_degree": 24, "lanes_per_entry": 4, "flags": 0}, ...]}
+ *      "chunk_steps": 16, "wpv_degree": 24, "lanes_per_entry": 4,
+ *      "policy_margin": 0, "flags": 0}, ...]}
  * bc_tune_cache_save writes every entry of this process to path (replacing
  * the file); bc_tune_cache_load adds the file's entries (an entry with the
  * same key replaces the one held).  Neither touches the GPU.

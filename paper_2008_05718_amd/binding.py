@@ -73,7 +73,7 @@ class RunOptions(ctypes.Structure):
                 ("alpha", ctypes.c_float), ("beta", ctypes.c_float), ("wpv_degree", ctypes.c_float),
                 ("grid_blocks", ctypes.c_int32), ("chunk_steps", ctypes.c_int32),
                 ("sigma_limit", ctypes.c_int64), ("lanes_per_entry", ctypes.c_float),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("policy_margin", ctypes.c_float), ("reserved", ctypes.c_int32 * 6)]
 
 
 class Detail(ctypes.Structure):
@@ -205,13 +205,15 @@ def _stream(stream):
 
 
 def make_options(batch=0, policy=BC_POLICY_AUTO, flags=0, alpha=0.0, beta=0.0, wpv_degree=0.0,
-                 grid_blocks=0, chunk_steps=0, sigma_limit=0, lanes_per_entry=0.0) -> RunOptions:
+                 grid_blocks=0, chunk_steps=0, sigma_limit=0, lanes_per_entry=0.0,
+                 policy_margin=0.0) -> RunOptions:
     o = RunOptions()
     lib().bc_run_options_init(ctypes.byref(o))
     o.flags, o.batch, o.policy = flags, batch, policy
     o.alpha, o.beta, o.wpv_degree = alpha, beta, wpv_degree
     o.grid_blocks, o.chunk_steps, o.sigma_limit = grid_blocks, chunk_steps, sigma_limit
     o.lanes_per_entry = lanes_per_entry
+    o.policy_margin = policy_margin
     return o
 
 

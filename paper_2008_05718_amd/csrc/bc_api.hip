@@ -1022,6 +1022,7 @@ static PolicyArgs policy_args(const bc_graph *g, const bc_run_options &o) {
     p.beta = o.beta > 0 ? o.beta : 24.0f;
     p.wpv_degree = o.wpv_degree > 0 ? o.wpv_degree : 24.0f;
     p.item_lanes = o.lanes_per_entry > 0 ? o.lanes_per_entry : (o.lanes_per_entry < 0 ? -1.0f : 4.0f);
+    p.margin = o.policy_margin > 0 ? o.policy_margin : (o.policy_margin < 0 ? 0.0f : kPolicyMargin);
     p.has_mlp = g->has_mlp ? 1 : 0;
     p.mlp = g->mlp;
     return p;
@@ -2883,7 +2884,7 @@ bool parse_entry(JsonIn &in, TuneEntry *e) {
                 have[key == "graph" ? 1 : key == "sample" ? 2 : 3] = true;
             }
         } else if (key == "batch" || key == "policy" || key == "grid_blocks" || key == "chunk_steps" ||
-                   key == "wpv_degree" || key == "lanes_per_entry" || key == "flags") {
+                   key == "wpv_degree" || key == "lanes_per_entry" || key == "policy_margin" || key == "flags") {
             if (!in.num(&x)) return false;
             if (key == "batch") e->best.batch = (int32_t)x;
             else if (key == "policy") e->best.policy = (int32_t)x;
@@ -2891,6 +2892,7 @@ bool parse_entry(JsonIn &in, TuneEntry *e) {
             else if (key == "chunk_steps") e->best.chunk_steps = (int32_t)x;
             else if (key == "wpv_degree") e->best.wpv_degree = (float)x;
             else if (key == "lanes_per_entry") e->best.lanes_per_entry = (float)x;
+            else if (key == "policy_margin") e->best.policy_margin = (float)x;
             else e->best.flags = (uint32_t)x;
         } else if (!in.skip()) {
             return false;
@@ -2919,10 +2921,12 @@ extern "C" bc_status bc_tune_cache_save(const char *path) {
             std::snprintf(buf, sizeof(buf),
                           "%s\n  {\"device\": \"%s\", \"graph\": \"%s\", \"sample\": \"%s\", \"base\": \"%s\", "
                           "\"batch\": %d, \"policy\": %d, \"grid_blocks\": %d, \"chunk_steps\": %d, "
-                          "\"wpv_degree\": %.9g, \"lanes_per_entry\": %.9g, \"flags\": %u}",
+                          "\"wpv_degree\": %.9g, \"lanes_per_entry\": %.9g, \"policy_margin\": %.9g, "
+                          "\"flags\": %u}",
                           i ? "," : "", e.device.c_str(), hex64(e.graph).c_str(), hex64(e.sample).c_str(),
                           hex64(e.base).c_str(), e.best.batch, e.best.policy, e.best.grid_blocks, e.best.chunk_steps,
-                          (double)e.best.wpv_degree, (double)e.best.lanes_per_entry, e.best.flags);
+                          (double)e.best.wpv_degree, (double)e.best.lanes_per_entry,
+                          (double)e.best.policy_margin, e.best.flags);
             out += buf;
         }
     }
@@ -3038,7 +3042,7 @@ extern "C" bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_s
         Fnv64 hb;
         const int64_t f[6] = {cur.flags, cur.batch, cur.policy, cur.grid_blocks, cur.chunk_steps,
                               (int64_t)cur.sigma_limit};
-        const float x[4] = {cur.alpha, cur.beta, cur.wpv_degree, cur.lanes_per_entry};
+        const float x[5] = {cur.alpha, cur.beta, cur.wpv_degree, cur.lanes_per_entry, cur.policy_margin};
         hb.add(f, sizeof(f));
         hb.add(x, sizeof(x));
         hb.add(&g->has_mlp, sizeof(g->has_mlp));

@@ -492,8 +492,16 @@ __device__ __forceinline__ int choose_variant(const PolicyArgs &p, int policy, i
         }
         __syncthreads();
         if (finite) {
-            *lbo = argmin3(yy, kOutSig) | (argmin3(yy, kOutBwd) << 2);
-            return argmin3(yy, kOutFwd);
+            // the rule's choice stands unless the network predicts a gain of
+            // at least p.margin (log2 units) for another one
+            const float m = p.margin;
+            int v = argmin3(yy, kOutFwd), so = argmin3(yy, kOutSig), bo = argmin3(yy, kOutBwd);
+            const int h = heuristic_variant(p, prev, f, n);
+            if (yy[kOutFwd + h] - yy[kOutFwd + v] < m) v = h;
+            if (yy[kOutSig + LB_RULE] - yy[kOutSig + so] < m) so = LB_RULE;
+            if (yy[kOutBwd + LB_RULE] - yy[kOutBwd + bo] < m) bo = LB_RULE;
+            *lbo = so | (bo << 2);
+            return v;
         }
         // non-finite prediction: fall back to the rules
     }

@@ -83,6 +83,7 @@ constexpr int kOutFwd = 0, kOutSig = 3, kOutBwd = 6;
 // one thread per (entry, source) pair always.  Same bits every way.
 enum : int32_t { LB_PACKED = 0, LB_RULE = 1, LB_ITEMS = 2 };
 constexpr int32_t kLbDefault = LB_RULE | (LB_RULE << 2);  // sig option | bwd option << 2
+constexpr float kPolicyMargin = 0.07f;  // default override margin of the learned policy (log2 units)
 constexpr int kMlpParams = kMlpH * kMlpIn + kMlpH + kMlpH * kMlpH + kMlpH + kMlpOut * kMlpH + kMlpOut;
 
 // Control block in device memory.  Written by the host before a run, then
@@ -212,6 +213,7 @@ struct PolicyArgs {
     float alpha, beta, wpv_degree;
     float item_lanes;       // path-count / backward groups whose light entries carry at most this many
                             // sources on average run one thread per (entry, source) pair
+    float margin;           // learned policy: predicted log2 gain needed to override the rule (0 = none)
     int32_t has_mlp;
     const float *mlp;       // kMlpParams floats (device), or nullptr
 };
