@@ -207,7 +207,7 @@ typedef struct bc_run_options {
                              direction-optimising variant, the sources-per-entry
                              summation) unless the network predicts the other
                              choice faster by at least this many log2 units
-                             (0 = default 0.07, about 5 %; negative = no margin:
+                             (0 = default 0.15, about 11 %; negative = no margin:
                              the network's argmin).  Speed only.            */
     int32_t reserved[6];
 } bc_run_options;
