@@ -39,9 +39,16 @@ TUNE_SOURCES = 2048  # autotuner sample: the first sources of the list (untimed)
 # autotuner results for the benchmark workloads on this GPU model, written by
 # `bench.py --tune-cache-out` on an MI355X; a hit skips the timing runs
 TUNE_CACHE = os.path.join(ROOT, "paper_2008_05718_amd", "tune_cache.json")
-KERNEL_SOURCES = ["paper_2008_05718_amd/csrc/bc_batched.hip", "paper_2008_05718_amd/csrc/bc_common.h",
-                  "paper_2008_05718_amd/csrc/bc_api.hip",
-                  "paper_2008_05718_amd/csrc/bc_dev.h", "paper_2008_05718_amd/build.py"]
+_COMMON_SOURCES = ["paper_2008_05718_amd/csrc/bc_common.h", "paper_2008_05718_amd/csrc/bc_dev.h",
+                   "paper_2008_05718_amd/build.py"]
+# the sources each step kernel is compiled from (its counters per launch
+# depend on these and on the workload, not on the host driver)
+KERNEL_FILES = {
+    "batch_step": ["paper_2008_05718_amd/csrc/bc_batched.hip"] + _COMMON_SOURCES,
+    "block_run": ["paper_2008_05718_amd/csrc/bc_batched.hip"] + _COMMON_SOURCES,
+    "weighted_run": ["paper_2008_05718_amd/csrc/bc_weighted.hip"] + _COMMON_SOURCES,
+}
+KERNEL_SOURCES = sorted({f for v in KERNEL_FILES.values() for f in v})
 
 
 def _code_only(text: str) -> str:
@@ -52,13 +59,14 @@ def _code_only(text: str) -> str:
     return " ".join(text.split())
 
 
-def kernel_sources_sha256() -> str:
-    """Hash of the sources the step kernel is built from; comments and
-    whitespace of the HIP sources are ignored, so an edit of comments only
-    keeps the recorded counters valid."""
+def kernel_sources_sha256(kernel: str = "batch_step<0>") -> str:
+    """Hash of the sources a step kernel is built from (``kernel`` as in the
+    bench line, e.g. "batch_step<0>"); comments and whitespace of the HIP
+    sources are ignored, so an edit of comments only keeps the recorded
+    counters valid."""
     import hashlib
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in KERNEL_FILES[kernel.split("<")[0]]:
         with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
             text = f.read()
         if rel.endswith((".hip", ".h")):
@@ -84,7 +92,7 @@ def measured_traffic(kernel: str, workload: str):
                 key, _, val = line[2:].partition(":")
                 vals[key.strip()] = val.strip().strip("`")
     try:
-        if vals.get("kernel_sources_sha256") != kernel_sources_sha256():
+        if vals.get("kernel_sources_sha256") != kernel_sources_sha256(kernel):
             return None
         return float(vals["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -211,7 +219,7 @@ def profile_summary(args) -> str:
         lines += [f"- avg_launch_us_trace: {avg_us:.3f}", f"- launches_in_flight: {inflight:.3f}"]
     if traffic is not None:
         lines.append(f"- traffic_bytes_per_launch: {traffic:.0f}")
-    lines.append(f"- kernel_sources_sha256: {kernel_sources_sha256()}")
+    lines.append(f"- kernel_sources_sha256: {kernel_sources_sha256(kernel)}")
     return "\n".join(lines) + "\n"
 
 
@@ -455,6 +463,11 @@ def main():
         f"(host wall {wall * 1e3:.1f}, events {gpu_ms:.1f}), policy={st['policy']} "
         f"variants={st['variant_levels']} f64={st['f64_sources']} reached pairs={st['reached_pairs']} "
         f"block engine workgroups={st['block_workgroups']} chunks={st['block_chunks']}")
+    if weighted:
+        ns_run = max(st["n_sources"], 1)
+        log(f"[bench] weighted: per source {st['forward_levels'] / ns_run:.1f} relaxation rounds, "
+            f"{st['arcs_scanned'] / ns_run / max(g.nnz, 1):.2f} x nnz arcs relaxed, "
+            f"{st['steps'] / ns_run:.1f} DAG rounds, {st['lane_arcs'] / ns_run / max(g.nnz, 1):.2f} x nnz DAG-pass arcs")
     log("[bench] batched phase ms (fwd, sig, bwd, fin, bc):",
         [round(x, 1) for x in st["phase_ms"][1:6]], "variant ms:", [round(x, 1) for x in st["variant_ms"]])
     log("[bench] batched per phase: arcs", st["phase_arcs"][1:4], "lane arcs", st["phase_lane_arcs"][1:4],

@@ -1750,7 +1750,10 @@ static bc_status ensure_weighted(bc_graph *g) {
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)weighted_run<0>, kBlock, 0));
-    int64_t want = (int64_t)std::max(1, cus) * std::max(1, std::min(per_cu, 2));
+    // as many workgroups as the CUs hold (each works through its sources
+    // alone, so resident workgroups are what hides memory latency), within
+    // the memory budget
+    int64_t want = (int64_t)std::max(1, cus) * std::max(1, std::min(per_cu, 8));
     size_t free_b = 0, total_b = 0;
     HIP_TRY(hipMemGetInfo(&free_b, &total_b));
     size_t budget = std::min<size_t>(free_b / 2, (size_t)64 << 30);

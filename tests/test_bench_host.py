@@ -16,11 +16,11 @@ def _copy_sources(tmp_path):
         shutil.copy(os.path.join(bench.ROOT, rel), dst)
 
 
-def _hash_at(root):
+def _hash_at(root, kernel="batch_step<0>"):
     old = bench.ROOT
     try:
         bench.ROOT = str(root)
-        return bench.kernel_sources_sha256()
+        return bench.kernel_sources_sha256(kernel)
     finally:
         bench.ROOT = old
 
@@ -28,29 +28,38 @@ def _hash_at(root):
 def test_hash_ignores_comments_but_not_code(tmp_path):
     _copy_sources(tmp_path)
     h0 = _hash_at(tmp_path)
+    w0 = _hash_at(tmp_path, "weighted_run<0>")
+    assert w0 != h0
     hip = tmp_path / "paper_2008_05718_amd/csrc/bc_batched.hip"
     text = hip.read_text()
     hip.write_text("// a new comment line\n" + text.replace("\n", "\n  ", 3) + "\n/* trailing\n block */\n")
     assert _hash_at(tmp_path) == h0
     hip.write_text(text.replace("constexpr int kUnroll = BC_UNROLL;", "constexpr int kUnroll = BC_UNROLL + 0;"))
     assert _hash_at(tmp_path) != h0
+    # a kernel's hash covers its own sources only
+    assert _hash_at(tmp_path, "weighted_run<0>") == w0
+    dev = tmp_path / "paper_2008_05718_amd/csrc/bc_dev.h"
+    dev.write_text(dev.read_text() + "\nconstexpr int kUnusedHere = 1;\n")
+    assert _hash_at(tmp_path, "weighted_run<1>") != w0
 
 
 def test_summaries_are_read_only_for_their_sources():
     # a summary's traffic is used while its recorded hash is the current one
     # and ignored (null in the bench line) once the kernel sources change
     import re
-    cur = bench.kernel_sources_sha256()
-    tags = {"batch_step_u64": "batch_step<0>", "batch_step_f64": "batch_step<1>"}
+    tags = {"batch_step_u64": "batch_step<0>", "batch_step_f64": "batch_step<1>", "block_run_u64": "block_run<0>",
+            "weighted_run_u64": "weighted_run<0>", "weighted_run_f64": "weighted_run<1>"}
     found = 0
     for name in os.listdir(os.path.join(bench.ROOT, "profiles")):
-        m = re.match(r"(batch_step_[uf]64)_(\w+)\.md$", name)
+        m = re.match(r"((?:batch_step|block_run|weighted_run)_[uf]64)_(\w+)\.md$", name)
         if not m:
             continue
         found += 1
+        kernel = tags[m.group(1)]
         text = open(os.path.join(bench.ROOT, "profiles", name)).read()
         rec = re.search(r"- kernel_sources_sha256: (\w+)", text).group(1)
-        t = bench.measured_traffic(tags[m.group(1)], m.group(2))
+        t = bench.measured_traffic(kernel, m.group(2))
+        cur = bench.kernel_sources_sha256(kernel)
         assert (t is not None and t > 0) if rec == cur else t is None, name
     assert found >= 1
     assert bench.measured_traffic("batch_step<0>", "no_such_workload") is None
@@ -99,7 +108,7 @@ def test_profile_summary_reduces_rocprof_csvs(tmp_path):
     assert f"- traffic_bytes_per_launch: {want:.0f}" in text
     assert "- avg_launch_us_trace: 1.000" in text
     assert "- launches_in_flight: 2.000" in text
-    assert "cmd a" in text and f"- kernel_sources_sha256: {bench.kernel_sources_sha256()}" in text
+    assert "cmd a" in text and f"- kernel_sources_sha256: {bench.kernel_sources_sha256('batch_step<0>')}" in text
     # read back the way the bench line reads it
     prof = tmp_path / "profiles"
     prof.mkdir()
