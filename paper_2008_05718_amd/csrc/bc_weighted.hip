@@ -23,10 +23,13 @@
 //      factored out), then the source's delta is added to the workgroup's
 //      partial scores.
 //
-// Sums over a vertex's arcs are taken by one thread in CSR order (degree <=
-// kLightDeg) or by one wavefront, lane-strided then a fixed butterfly, so
-// every result is fixed by the vertex alone and runs are bitwise
-// reproducible.  Path counts are uint64 (MODE 0) with exact overflow
+// Arcs of up to 64 list entries (one per lane) are packed into rounds of 64
+// arcs, one per lane, so the loads of a round are issued together; a sum over
+// a vertex's arcs is then taken by its own lane in CSR order from the
+// round's values (readlane, ascending lane = ascending arc).  Vertices of
+// degree above kWHeavy are taken by one wavefront, lane-strided then a fixed
+// butterfly.  Every result is fixed by the vertex alone and runs are
+// bitwise reproducible.  Path counts are uint64 (MODE 0) with exact overflow
 // detection; a source that overflows is handed back and computed again with
 // FP64 counts (MODE 1).  Chunks of consecutive sources go to one partial
 // vector, and the partials are added in chunk order afterwards (host).
@@ -42,6 +45,47 @@ __device__ __forceinline__ unsigned long long ld_dist(const unsigned long long *
 
 // Wavefront-wide sum of v over lanes (fixed butterfly; every lane gets it).
 __device__ __forceinline__ double wsum_f64(double v) { return wave_sum_f64(v); }
+
+constexpr int kWHeavy = 4096;  // vertices with more arcs go to one wavefront each
+
+__device__ __forceinline__ unsigned long long lane_u64(unsigned long long x, int j) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, j);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), j);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Lane holding packed arc a: the first lane whose inclusive degree prefix
+// exceeds a (binary search over the wavefront).
+__device__ __forceinline__ int arc_lane(int incl, int a) {
+    int o = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        if (__shfl(incl, o + step - 1) <= a) o += step;
+    }
+    return o;
+}
+
+// The arcs [rp[v], rp[v+1]) of this lane's entry v (v < 0: none; degree above
+// kWHeavy: skipped), all lanes' arcs in lane order, handed out 64 per round:
+// body(ok, o, e) runs on every lane of every round, with arc e of the entry
+// of lane o when ok.  The wavefront must be converged.
+template <class Body>
+__device__ __forceinline__ void packed_arcs(const int32_t *__restrict__ rp, int v, Body body) {
+    const int lane = lane_id();
+    const int e0 = v >= 0 ? rp[v] : 0;
+    int deg = v >= 0 ? rp[v + 1] - e0 : 0;
+    if (deg > kWHeavy) deg = 0;
+    const int incl = wave_incl_scan(deg);
+    const int total = __shfl(incl, kWave - 1);
+    const int excl = incl - deg;
+    for (int ab = 0; ab < total; ab += kWave) {
+        const int a = ab + lane;
+        const bool ok = a < total;
+        const int o = arc_lane(incl, ok ? a : total - 1);
+        const int e = __shfl(e0, o) + (a - __shfl(excl, o));
+        body(ok, o, e);
+    }
+}
 
 // Workgroup barrier after which every global store and atomic issued before
 // it has completed: distances are read with device-scope loads that go to
@@ -119,16 +163,17 @@ __global__ __launch_bounds__(kBlock) void weighted_run(WeightedArgs a) {
                     if (tid == 0) atomicOr(a.err, ERR_LEVEL_CAP);
                     break;
                 }
-                // light vertices one per thread, heavy ones one per wavefront
-                for (uint32_t i = tid; i < nc; i += kBlock) {
-                    const int v = cur[i];
-                    const int e0 = rp[v], e1 = rp[v + 1];
-                    if (e1 - e0 > kLightDeg) continue;
-                    const unsigned long long dv = ld_dist(&dist[v]);
-                    st_arcs += (unsigned)(e1 - e0);
-                    for (int e = e0; e < e1; ++e) {
+                // packed rounds of 64 arcs per wavefront, heavy vertices one per wavefront
+                for (uint32_t cb = (uint32_t)wid * kWave; cb < nc; cb += kBlock) {
+                    const uint32_t i = cb + lane;
+                    const int v = i < nc ? cur[i] : -1;
+                    const unsigned long long dv = v >= 0 ? ld_dist(&dist[v]) : 0ull;
+                    if (v >= 0 && rp[v + 1] - rp[v] <= kWHeavy) st_arcs += (unsigned)(rp[v + 1] - rp[v]);
+                    packed_arcs(rp, v, [&](bool ok, int o, int e) {
+                        const unsigned long long dvo = shfl_u64(dv, o);
+                        if (!ok) return;
                         const int x = col[e];
-                        const unsigned long long nd = dv + (unsigned long long)wt[e];
+                        const unsigned long long nd = dvo + (unsigned long long)wt[e];
                         if (nd < ld_dist(&dist[x])) {
                             const unsigned long long old = atomicMin(&dist[x], nd);
                             if (nd < old) {
@@ -136,12 +181,12 @@ __global__ __launch_bounds__(kBlock) void weighted_run(WeightedArgs a) {
                                 if (atomicExch(&mark[x], round) != round) nxt[atomicAdd(&s_n1, 1u)] = x;
                             }
                         }
-                    }
+                    });
                 }
                 for (uint32_t i = wid; i < nc; i += kWavesPerBlock) {
                     const int v = cur[i];
                     const int e0 = rp[v], e1 = rp[v + 1];
-                    if (e1 - e0 <= kLightDeg) continue;
+                    if (e1 - e0 <= kWHeavy) continue;
                     const unsigned long long dv = ld_dist(&dist[v]);
                     if (lane == 0) st_arcs += (unsigned)(e1 - e0);
                     for (int e = e0 + lane; e < e1; e += kWave) {
@@ -170,21 +215,31 @@ __global__ __launch_bounds__(kBlock) void weighted_run(WeightedArgs a) {
             const uint32_t nr = s_nr;
             st_reached += nr;
             // ---------------- B: DAG in-arc counts, then rounds of ready vertices
-            for (uint32_t i = tid; i < nr; i += kBlock) {
-                const int v = reached[i];
-                if (irp[v + 1] - irp[v] > kLightDeg) continue;
-                const unsigned long long dv = ld_dist(&dist[v]);
-                st_darcs += (unsigned)(irp[v + 1] - irp[v]);
+            for (uint32_t cb = (uint32_t)wid * kWave; cb < nr; cb += kBlock) {
+                const uint32_t i = cb + lane;
+                const int v = i < nr ? reached[i] : -1;
+                const bool light = v >= 0 && irp[v + 1] - irp[v] <= kWHeavy;
+                const unsigned long long dv = v >= 0 ? ld_dist(&dist[v]) : 0ull;
+                if (light) st_darcs += (unsigned)(irp[v + 1] - irp[v]);
                 int c = 0;
-                for (int e = irp[v]; e < irp[v + 1]; ++e) {
-                    const unsigned long long du = ld_dist(&dist[icol[e]]);
-                    if (du != kInf && du + (unsigned long long)iwt[e] == dv) ++c;
-                }
-                cnt[v] = c;
+                packed_arcs(irp, v, [&](bool ok, int o, int e) {
+                    const unsigned long long dvo = shfl_u64(dv, o);
+                    bool dag = false;
+                    if (ok) {
+                        const unsigned long long du = ld_dist(&dist[icol[e]]);
+                        dag = du != kInf && du + (unsigned long long)iwt[e] == dvo;
+                    }
+                    // each lane counts the DAG in-arcs that belong to its entry
+                    for (unsigned long long bal = __ballot(dag); bal; bal &= bal - 1) {
+                        const int j = __ffsll(bal) - 1;
+                        if (__builtin_amdgcn_readlane(o, j) == lane) ++c;
+                    }
+                });
+                if (light) cnt[v] = c;
             }
             for (uint32_t i = wid; i < nr; i += kWavesPerBlock) {
                 const int v = reached[i];
-                if (irp[v + 1] - irp[v] <= kLightDeg) continue;
+                if (irp[v + 1] - irp[v] <= kWHeavy) continue;
                 const unsigned long long dv = ld_dist(&dist[v]);
                 if (lane == 0) st_darcs += (unsigned)(irp[v + 1] - irp[v]);
                 int c = 0;
@@ -212,41 +267,55 @@ __global__ __launch_bounds__(kBlock) void weighted_run(WeightedArgs a) {
                 if (nc == 0) break;
                 const int off = lvl_off[nl];
                 // path counts of the ready vertices (their predecessors are final)
-                for (uint32_t i = tid; i < nc; i += kBlock) {
-                    const int v = cur[i];
-                    lvl[off + i] = v;
-                    const int e0 = irp[v], e1 = irp[v + 1];
-                    if (v != s && e1 - e0 > kLightDeg) continue;
-                    if (v == s) {
-                        sig[v] = MODE ? as_u64(1.0) : 1ull;
-                        continue;
-                    }
-                    const unsigned long long dv = ld_dist(&dist[v]);
-                    st_darcs += (unsigned)(e1 - e0);
+                for (uint32_t i = tid; i < nc; i += kBlock) lvl[off + i] = cur[i];
+                for (uint32_t cb = (uint32_t)wid * kWave; cb < nc; cb += kBlock) {
+                    const uint32_t i = cb + lane;
+                    const int v0 = i < nc ? cur[i] : -1;
+                    const int v = v0 == s ? -1 : v0;  // the source has no predecessors
+                    const bool light = v >= 0 && irp[v + 1] - irp[v] <= kWHeavy;
+                    const unsigned long long dv = v >= 0 ? ld_dist(&dist[v]) : 0ull;
+                    if (light) st_darcs += (unsigned)(irp[v + 1] - irp[v]);
                     unsigned long long lo = 0, hi = 0;
                     double accd = 0.0;
-                    for (int e = e0; e < e1; ++e) {
-                        const int u = icol[e];
-                        const unsigned long long du = ld_dist(&dist[u]);
-                        if (du == kInf || du + (unsigned long long)iwt[e] != dv) continue;
-                        if (MODE == 0) {
-                            lo += sig[u];
-                            hi += (lo < sig[u]) ? 1ull : 0ull;
-                        } else {
-                            accd += as_f64(sig[u]);
+                    packed_arcs(irp, v, [&](bool ok, int o, int e) {
+                        const unsigned long long dvo = shfl_u64(dv, o);
+                        unsigned long long x = 0;
+                        bool dag = false;
+                        if (ok) {
+                            const int u = icol[e];
+                            const unsigned long long du = ld_dist(&dist[u]);
+                            dag = du != kInf && du + (unsigned long long)iwt[e] == dvo;
+                            if (dag) x = sig[u];
                         }
-                    }
-                    if (MODE == 0) {
-                        sig[v] = lo;
-                        if (hi != 0 || lo > a.sigma_limit) s_ovf = 1;
-                    } else {
-                        sig[v] = as_u64(accd);
+                        // each lane adds its entry's terms in arc order
+                        for (unsigned long long bal = __ballot(dag); bal; bal &= bal - 1) {
+                            const int j = __ffsll(bal) - 1;
+                            const unsigned long long xj = lane_u64(x, j);
+                            if (__builtin_amdgcn_readlane(o, j) == lane) {
+                                if (MODE == 0) {
+                                    lo += xj;
+                                    hi += (lo < xj) ? 1ull : 0ull;
+                                } else {
+                                    accd += as_f64(xj);
+                                }
+                            }
+                        }
+                    });
+                    if (v0 == s) {
+                        sig[s] = MODE ? as_u64(1.0) : 1ull;
+                    } else if (light) {
+                        if (MODE == 0) {
+                            sig[v] = lo;
+                            if (hi != 0 || lo > a.sigma_limit) s_ovf = 1;
+                        } else {
+                            sig[v] = as_u64(accd);
+                        }
                     }
                 }
                 for (uint32_t i = wid; i < nc; i += kWavesPerBlock) {
                     const int v = cur[i];
                     const int e0 = irp[v], e1 = irp[v + 1];
-                    if (v == s || e1 - e0 <= kLightDeg) continue;
+                    if (v == s || e1 - e0 <= kWHeavy) continue;
                     const unsigned long long dv = ld_dist(&dist[v]);
                     if (lane == 0) st_darcs += (unsigned)(e1 - e0);
                     unsigned long long lo = 0, hi = 0;
@@ -282,20 +351,22 @@ __global__ __launch_bounds__(kBlock) void weighted_run(WeightedArgs a) {
                 }
                 wg_sync();
                 // release the DAG successors
-                for (uint32_t i = tid; i < nc; i += kBlock) {
-                    const int v = cur[i];
-                    if (rp[v + 1] - rp[v] > kLightDeg) continue;
-                    const unsigned long long dv = ld_dist(&dist[v]);
-                    st_darcs += (unsigned)(rp[v + 1] - rp[v]);
-                    for (int e = rp[v]; e < rp[v + 1]; ++e) {
+                for (uint32_t cb = (uint32_t)wid * kWave; cb < nc; cb += kBlock) {
+                    const uint32_t i = cb + lane;
+                    const int v = i < nc ? cur[i] : -1;
+                    const unsigned long long dv = v >= 0 ? ld_dist(&dist[v]) : 0ull;
+                    if (v >= 0 && rp[v + 1] - rp[v] <= kWHeavy) st_darcs += (unsigned)(rp[v + 1] - rp[v]);
+                    packed_arcs(rp, v, [&](bool ok, int o, int e) {
+                        const unsigned long long dvo = shfl_u64(dv, o);
+                        if (!ok) return;
                         const int x = col[e];
-                        if (dv + (unsigned long long)wt[e] == ld_dist(&dist[x]) && atomicSub(&cnt[x], 1) == 1)
+                        if (dvo + (unsigned long long)wt[e] == ld_dist(&dist[x]) && atomicSub(&cnt[x], 1) == 1)
                             nxt[atomicAdd(&s_n1, 1u)] = x;
-                    }
+                    });
                 }
                 for (uint32_t i = wid; i < nc; i += kWavesPerBlock) {
                     const int v = cur[i];
-                    if (rp[v + 1] - rp[v] <= kLightDeg) continue;
+                    if (rp[v + 1] - rp[v] <= kWHeavy) continue;
                     const unsigned long long dv = ld_dist(&dist[v]);
                     if (lane == 0) st_darcs += (unsigned)(rp[v + 1] - rp[v]);
                     for (int e = rp[v] + lane; e < rp[v + 1]; e += kWave) {
@@ -322,26 +393,40 @@ __global__ __launch_bounds__(kBlock) void weighted_run(WeightedArgs a) {
             if (!ovf) {
                 for (int l = nl - 1; l >= 0; --l) {
                     const int b0 = lvl_off[l], b1 = lvl_off[l + 1];
-                    for (int i = b0 + tid; i < b1; i += kBlock) {
-                        const int v = lvl[i];
-                        const int e0 = rp[v], e1 = rp[v + 1];
-                        if (e1 - e0 > kLightDeg) continue;
-                        const unsigned long long dv = ld_dist(&dist[v]);
-                        st_darcs += (unsigned)(e1 - e0);
+                    for (int cb = b0 + wid * kWave; cb < b1; cb += kBlock) {
+                        const int i = cb + lane;
+                        const int v = i < b1 ? lvl[i] : -1;
+                        const bool light = v >= 0 && rp[v + 1] - rp[v] <= kWHeavy;
+                        const unsigned long long dv = v >= 0 ? ld_dist(&dist[v]) : 0ull;
+                        if (light) st_darcs += (unsigned)(rp[v + 1] - rp[v]);
                         double acc = 0.0;
-                        for (int e = e0; e < e1; ++e) {
-                            const int u = col[e];
-                            if (dv + (unsigned long long)wt[e] == ld_dist(&dist[u])) acc += chat[u];
+                        packed_arcs(rp, v, [&](bool ok, int o, int e) {
+                            const unsigned long long dvo = shfl_u64(dv, o);
+                            double x = 0.0;
+                            bool dag = false;
+                            if (ok) {
+                                const int u = col[e];
+                                dag = dvo + (unsigned long long)wt[e] == ld_dist(&dist[u]);
+                                if (dag) x = chat[u];
+                            }
+                            // each lane adds its entry's terms in arc order
+                            for (unsigned long long bal = __ballot(dag); bal; bal &= bal - 1) {
+                                const int j = __ffsll(bal) - 1;
+                                const double xj = as_f64(lane_u64(as_u64(x), j));
+                                if (__builtin_amdgcn_readlane(o, j) == lane) acc += xj;
+                            }
+                        });
+                        if (light) {
+                            const double sv = MODE ? as_f64(sig[v]) : (double)sig[v];
+                            const double delta = sv * acc;
+                            chat[v] = (1.0 + delta) / sv;
+                            dep[v] = delta;
                         }
-                        const double sv = MODE ? as_f64(sig[v]) : (double)sig[v];
-                        const double delta = sv * acc;
-                        chat[v] = (1.0 + delta) / sv;
-                        dep[v] = delta;
                     }
                     for (int i = b0 + wid; i < b1; i += kWavesPerBlock) {
                         const int v = lvl[i];
                         const int e0 = rp[v], e1 = rp[v + 1];
-                        if (e1 - e0 <= kLightDeg) continue;
+                        if (e1 - e0 <= kWHeavy) continue;
                         const unsigned long long dv = ld_dist(&dist[v]);
                         if (lane == 0) st_darcs += (unsigned)(e1 - e0);
                         double acc = 0.0;
