@@ -209,7 +209,14 @@ typedef struct bc_run_options {
                              choice faster by at least this many log2 units
                              (0 = default 0.15, about 11 %; negative = no margin:
                              the network's argmin).  Speed only.            */
-    int32_t reserved[6];
+    int32_t replicas;     /* single graphs, batched engine: level state machines run
+                             concurrently, each with its own per-vertex state and
+                             batches dealt to them in turn (0 = by size: 8 up to
+                             2^19 vertices, 4 above; 1 = one; at most 16; autotuned).
+                             Scores agree to rounding across values; a given value
+                             repeats bit for bit (BC_RUN_ONE_QUEUE: one, whatever
+                             this says). */
+    int32_t reserved[5];
 } bc_run_options;
 
 /* Fill *opt with defaults (all zero fields, i.e. autotuned/automatic). */
@@ -241,7 +248,8 @@ bc_status bc_run(bc_graph *g, const int32_t *sources, int64_t n_sources,
  * sources one after another), policy {heuristic, learned when weights are loaded},
  * workgroups per step {default, 1/2, 1/4}, level steps per captured chunk
  * {8, 16, 32}, push WPV degree threshold {12, 24, 48}, sources per entry
- * below which groups are summed by (entry, source) pairs {never, 2, 4, 12}.
+ * below which groups are summed by (entry, source) pairs {never, 2, 4, 12},
+ * concurrent replicas of a single graph {half, default, twice}.
  * Each candidate is
  * timed (host clock around a synchronised run, best of two) after one
  * untimed run that builds its captured graphs; a value replaces the current
@@ -275,7 +283,7 @@ bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_sample, cons
  *     {"device": "gfx950:256", "graph": "<16 hex digits>", "sample": "<16 hex>",
  *      "base": "<16 hex>", "batch": 64, "policy": 2, "grid_blocks": 384,
  *      "chunk_steps": 16, "wpv_degree": 24, "lanes_per_entry": 4,
- *      "policy_margin": 0, "flags": 0}, ...]}
+ *      "policy_margin": 0, "replicas": 4, "flags": 0}, ...]}
  * bc_tune_cache_save writes every entry of this process to path (replacing
  * the file); bc_tune_cache_load adds the file's entries (an entry with the
  * same key replaces the one held).  Neither touches the GPU.

@@ -73,7 +73,8 @@ class RunOptions(ctypes.Structure):
                 ("alpha", ctypes.c_float), ("beta", ctypes.c_float), ("wpv_degree", ctypes.c_float),
                 ("grid_blocks", ctypes.c_int32), ("chunk_steps", ctypes.c_int32),
                 ("sigma_limit", ctypes.c_int64), ("lanes_per_entry", ctypes.c_float),
-                ("policy_margin", ctypes.c_float), ("reserved", ctypes.c_int32 * 6)]
+                ("policy_margin", ctypes.c_float), ("replicas", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class Detail(ctypes.Structure):
@@ -206,7 +207,7 @@ def _stream(stream):
 
 def make_options(batch=0, policy=BC_POLICY_AUTO, flags=0, alpha=0.0, beta=0.0, wpv_degree=0.0,
                  grid_blocks=0, chunk_steps=0, sigma_limit=0, lanes_per_entry=0.0,
-                 policy_margin=0.0) -> RunOptions:
+                 policy_margin=0.0, replicas=0) -> RunOptions:
     o = RunOptions()
     lib().bc_run_options_init(ctypes.byref(o))
     o.flags, o.batch, o.policy = flags, batch, policy
@@ -214,6 +215,7 @@ def make_options(batch=0, policy=BC_POLICY_AUTO, flags=0, alpha=0.0, beta=0.0, w
     o.grid_blocks, o.chunk_steps, o.sigma_limit = grid_blocks, chunk_steps, sigma_limit
     o.lanes_per_entry = lanes_per_entry
     o.policy_margin = policy_margin
+    o.replicas = replicas
     return o
 
 
@@ -353,7 +355,7 @@ def bc_autotune(h, sample, options: RunOptions | None = None, stream=None) -> di
                              ctypes.byref(best), _stream(stream)))
     return {"batch": best.batch, "policy": best.policy, "grid_blocks": best.grid_blocks,
             "chunk_steps": best.chunk_steps, "wpv_degree": best.wpv_degree,
-            "lanes_per_entry": best.lanes_per_entry}
+            "lanes_per_entry": best.lanes_per_entry, "replicas": best.replicas}
 
 
 def bc_tune_cache_save(path: str):

@@ -1911,16 +1911,20 @@ static void free_parts(bc_graph *g) {
     g->parts.clear();
 }
 
-// Replicas of a single graph: 8 while one batch's steps are small (up to
-// 2^19 vertices), 4 above, where fewer, larger state machines measured
-// faster (R-MAT 18: 8 replicas +3 % over 4; R-MAT 22: -3 %).  BC_REPLICAS
-// overrides (1 .. 16).
-static int n_replicas(const bc_graph *g) {
+// Replicas of a single graph: the run option, else 8 while one batch's steps
+// are small (up to 2^19 vertices), 4 above, where fewer, larger state
+// machines measured faster (R-MAT 18: 8 replicas +3 % over 4; R-MAT 22:
+// -3 %; the damaged 1024^2 grid, whose levels are many and thin: 8 replicas
+// 5.83 GTEPS against 5.42 for 4 and 5.41 for 16, which the autotuner finds).
+// BC_REPLICAS overrides both (1 .. 16).
+constexpr int kMaxReplicas = 16;
+static int n_replicas(const bc_graph *g, const bc_run_options &o) {
     static const int env = [] {
         const char *e = std::getenv("BC_REPLICAS");
-        return e ? std::min(16, std::max(1, std::atoi(e))) : 0;
+        return e ? std::min(kMaxReplicas, std::max(1, std::atoi(e))) : 0;
     }();
     if (env) return env;
+    if (o.replicas > 0) return std::min(kMaxReplicas, o.replicas);
     return g->n <= (1 << 19) ? 8 : 4;
 }
 
@@ -1930,7 +1934,7 @@ static bool use_parts(const bc_graph *g, const bc_run_options &o, int64_t ns) {
     if (o.batch == 0 && ns < 2) return false;  // the per-source engine would be chosen
     if (g->n_graphs >= 4) return true;
     const int K = o.batch >= 8 ? o.batch : 64;
-    return n_replicas(g) >= 2 && ns >= 2 * (int64_t)K;
+    return n_replicas(g, o) >= 2 && ns >= 2 * (int64_t)K;
 }
 
 // Single graph: parts are full copies of the graph (own per-vertex state);
@@ -1952,9 +1956,13 @@ static bool parts_fit(bc_graph *g, size_t need) {
 // list, batch bounds.
 static size_t run_buffer_bytes(int64_t ns) { return (size_t)(ns + 16) * 12 + (size_t)(ns + 17) * 16; }
 
-static bc_status ensure_replicas(bc_graph *g) {
-    if (!g->parts.empty()) return BC_OK;
-    const int R = n_replicas(g);
+static bc_status ensure_replicas(bc_graph *g, int R) {
+    if (!g->parts.empty() && (int)g->parts.size() == R) return BC_OK;
+    if (!g->parts.empty()) {  // another count was asked for: make them again
+        (void)hipDeviceSynchronize();
+        free_parts(g);
+        g->replicas = false;
+    }
     {
         // a replica holds the graph (created with the parent's internal
         // numbering) and its own batched engine state
@@ -2100,7 +2108,7 @@ static bc_status ensure_parts(bc_graph *g) {
 
 static bc_status run_parts(bc_graph *g, const int32_t *sources, int64_t n_sources, const bc_run_options &o,
                            void *stream, int64_t dump_index, bc_detail *detail) {
-    bc_status s = g->n_graphs >= 4 ? ensure_parts(g) : ensure_replicas(g);
+    bc_status s = g->n_graphs >= 4 ? ensure_parts(g) : ensure_replicas(g, n_replicas(g, o));
     if (s != BC_OK) return s;
     const bool repl = g->replicas;
     const int64_t K = o.batch >= 8 ? o.batch : 64;
@@ -2289,6 +2297,7 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
         if (o.chunk_steps == 0) o.chunk_steps = g->tuned.chunk_steps;
         if (o.wpv_degree <= 0.0f) o.wpv_degree = g->tuned.wpv_degree;
         if (o.lanes_per_entry == 0.0f) o.lanes_per_entry = g->tuned.lanes_per_entry;
+        if (o.replicas == 0) o.replicas = g->tuned.replicas;
         o.flags &= ~BC_RUN_TUNED;
     }
     const bool blk = use_block(g, o, sources ? n_sources : g->n, detail != nullptr);
@@ -2888,7 +2897,8 @@ bool parse_entry(JsonIn &in, TuneEntry *e) {
                 have[key == "graph" ? 1 : key == "sample" ? 2 : 3] = true;
             }
         } else if (key == "batch" || key == "policy" || key == "grid_blocks" || key == "chunk_steps" ||
-                   key == "wpv_degree" || key == "lanes_per_entry" || key == "policy_margin" || key == "flags") {
+                   key == "wpv_degree" || key == "lanes_per_entry" || key == "policy_margin" || key == "replicas" ||
+                   key == "flags") {
             if (!in.num(&x)) return false;
             if (key == "batch") e->best.batch = (int32_t)x;
             else if (key == "policy") e->best.policy = (int32_t)x;
@@ -2897,6 +2907,7 @@ bool parse_entry(JsonIn &in, TuneEntry *e) {
             else if (key == "wpv_degree") e->best.wpv_degree = (float)x;
             else if (key == "lanes_per_entry") e->best.lanes_per_entry = (float)x;
             else if (key == "policy_margin") e->best.policy_margin = (float)x;
+            else if (key == "replicas") e->best.replicas = (int32_t)x;
             else e->best.flags = (uint32_t)x;
         } else if (!in.skip()) {
             return false;
@@ -2926,11 +2937,11 @@ extern "C" bc_status bc_tune_cache_save(const char *path) {
                           "%s\n  {\"device\": \"%s\", \"graph\": \"%s\", \"sample\": \"%s\", \"base\": \"%s\", "
                           "\"batch\": %d, \"policy\": %d, \"grid_blocks\": %d, \"chunk_steps\": %d, "
                           "\"wpv_degree\": %.9g, \"lanes_per_entry\": %.9g, \"policy_margin\": %.9g, "
-                          "\"flags\": %u}",
+                          "\"replicas\": %d, \"flags\": %u}",
                           i ? "," : "", e.device.c_str(), hex64(e.graph).c_str(), hex64(e.sample).c_str(),
                           hex64(e.base).c_str(), e.best.batch, e.best.policy, e.best.grid_blocks, e.best.chunk_steps,
                           (double)e.best.wpv_degree, (double)e.best.lanes_per_entry,
-                          (double)e.best.policy_margin, e.best.flags);
+                          (double)e.best.policy_margin, e.best.replicas, e.best.flags);
             out += buf;
         }
     }
@@ -3028,6 +3039,8 @@ extern "C" bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_s
     if (cur.chunk_steps == 0) cur.chunk_steps = c0.chunk;
     if (cur.wpv_degree <= 0.0f) cur.wpv_degree = 24.0f;
     if (cur.lanes_per_entry == 0.0f) cur.lanes_per_entry = 4.0f;
+    const bool single = g->n_graphs < 4 && !g->weighted;  // replicas apply to single graphs
+    if (cur.replicas == 0 && single) cur.replicas = n_replicas(g, cur);
     hipStream_t st = (hipStream_t)stream;
     auto reset_scores = [&]() -> bc_status {
         if (g->n > 0) {
@@ -3044,8 +3057,8 @@ extern "C" bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_s
     key.sample = hs.v;
     {
         Fnv64 hb;
-        const int64_t f[6] = {cur.flags, cur.batch, cur.policy, cur.grid_blocks, cur.chunk_steps,
-                              (int64_t)cur.sigma_limit};
+        const int64_t f[7] = {cur.flags, cur.batch, cur.policy, cur.grid_blocks, cur.chunk_steps,
+                              (int64_t)cur.sigma_limit, cur.replicas};
         const float x[5] = {cur.alpha, cur.beta, cur.wpv_degree, cur.lanes_per_entry, cur.policy_margin};
         hb.add(f, sizeof(f));
         hb.add(x, sizeof(x));
@@ -3101,7 +3114,8 @@ extern "C" bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_s
     if (s != BC_OK) return s;
     const int dflt_grid = cur.grid_blocks;
     const bool asked_plain = cur.batch == 1;
-    for (int dim = 0; dim < 6; ++dim) {
+    const int dflt_repl = cur.replicas;
+    for (int dim = 0; dim < 7; ++dim) {
         std::vector<bc_run_options> cand;
         bc_run_options c = cur;
         if (dim == 0) {
@@ -3116,9 +3130,15 @@ extern "C" bc_status bc_autotune(bc_graph *g, const int32_t *sample, int64_t n_s
             for (int k : {8, 16, 32}) { c.chunk_steps = k; cand.push_back(c); }
         } else if (dim == 4) {
             for (float w : {12.0f, 24.0f, 48.0f}) { c.wpv_degree = w; cand.push_back(c); }
-        } else {
+        } else if (dim == 5) {
             if (cur.batch == 1) continue;
             for (float x : {-1.0f, 2.0f, 4.0f, 12.0f}) { c.lanes_per_entry = x; cand.push_back(c); }
+        } else {
+            if (cur.batch == 1 || !single) continue;
+            for (int r : {dflt_repl / 2, dflt_repl, 2 * dflt_repl}) {
+                c.replicas = std::max(1, std::min(kMaxReplicas, r));
+                cand.push_back(c);
+            }
         }
         for (const bc_run_options &x : cand) {
             if (std::memcmp(&x, &cur, sizeof(x)) == 0) continue;

@@ -12,7 +12,7 @@ from paper_2008_05718_amd import binding as b
 
 ENTRY = {"device": "gfx950:256", "graph": "00000000000000ab", "sample": "0123456789abcdef",
          "base": "fedcba9876543210", "batch": 32, "policy": 1, "grid_blocks": 192, "chunk_steps": 8,
-         "wpv_degree": 12.0, "lanes_per_entry": -1.0, "policy_margin": 0.25, "flags": 0}
+         "wpv_degree": 12.0, "lanes_per_entry": -1.0, "policy_margin": 0.25, "replicas": 8, "flags": 0}
 
 
 def _write(path, obj):

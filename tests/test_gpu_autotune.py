@@ -33,6 +33,7 @@ def test_autotune_candidates_and_same_bits():
         assert best["chunk_steps"] in (8, 16, 32)
         assert best["wpv_degree"] in (12.0, 24.0, 48.0)
         assert best["grid_blocks"] >= 1
+        assert best["replicas"] in (4, 8, 16)  # half, default (2^14 vertices: 8) or twice
         assert not G.scores().any()
         G.run(srcs, batch=best["batch"])  # same width, default policy and launch shape
         ref_bits = G.scores().copy()
@@ -84,3 +85,20 @@ def test_tune_cache_hit_save_load_and_fresh(tmp_path):
         H.autotune(srcs[:64], flags=b.BC_TUNE_FRESH)  # tuned again, replaces its entry
         assert b.bc_tune_cache_size() == 2
     b.bc_tune_cache_clear()
+
+
+def test_replicas_option_repeats_and_agrees():
+    # the number of concurrent state machines of a single graph changes only
+    # how batch results are grouped: each count repeats bit for bit, all agree
+    # with the oracle
+    g = W.rmat(13, 16, seed=31)
+    srcs = W.choose_sources(g, 640, seed=7)
+    ref, _ = oracle.bc(g, srcs)
+    say("[replicas] rmat13")
+    with b.Graph(g) as G:
+        for r in (1, 2, 5, 16, 2):
+            G.run(srcs, batch=64, replicas=r)
+            got = G.scores().copy()
+            G.run(srcs, batch=64, replicas=r)
+            assert np.array_equal(G.scores().view(np.uint64), got.view(np.uint64)), r
+            assert_bc_close(got, ref)

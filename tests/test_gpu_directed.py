@@ -147,3 +147,31 @@ def test_directed_multi_graph_refused():
     with pytest.raises(b.BCError) as ei:
         b.bc_graph_create_multi(np.array([0, 2, 4], np.int32), g.row_ptr, g.col_idx, flags=b.BC_DIRECTED)
     assert ei.value.status == 6
+
+
+def test_directed_degenerate_inputs_and_accumulate():
+    # no arcs at all, sinks and sources, an empty list, duplicates, accumulation
+    empty = _dg(5, [])
+    for K in (1, 64):
+        assert (_run(empty, None, batch=K) == 0).all()
+    g = _dg(6, [(0, 1), (1, 2), (3, 1)])  # 2 is a sink, 4 and 5 isolated
+    ref, _ = oracle.bc(g)
+    for K in (1, 8, 64):
+        assert_bc_close(_run(g, None, batch=K), ref)
+    with b.Graph(g) as G:
+        G.run([2, 2, 4], batch=64)
+        assert (G.scores() == 0).all()
+        G.run([], batch=64)
+        assert (G.scores() == 0).all()
+    dg = W.rmat_directed(11, 6, seed=72)
+    s1 = W.choose_sources(dg, 90, seed=1)
+    s2 = W.choose_sources(dg, 40, seed=2)
+    with b.Graph(dg) as G:
+        for K in (1, 64):
+            G.run(s1, batch=K)
+            G.run(s2, batch=K, flags=b.BC_RUN_ACCUMULATE)
+            ref, _ = oracle.bc(dg, np.concatenate([s1, s2]))
+            assert_bc_close(G.scores(), ref)
+            G.run(np.concatenate([s1[:5], s1[:5]]), batch=K)
+            r1, _ = oracle.bc(dg, s1[:5])
+            assert_bc_close(G.scores(), 2 * r1)

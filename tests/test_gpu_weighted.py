@@ -101,3 +101,36 @@ def test_weighted_heavy_vertices():
         assert_bc_close(G.scores(), ref)
         det = G.detail(srcs, dump_index=1)
         check_detail(g, det, int(srcs[1]))
+
+
+def test_weighted_degenerate_inputs_accumulate_and_duplicates():
+    # one vertex, isolated vertices, a source that reaches nothing, an empty
+    # source list, duplicates counted twice, accumulation across runs
+    one = W.with_weights(W.CSR(np.array([0, 0], np.int32), np.zeros(0, np.int32)), 1, 5, seed=1)
+    with b.Graph(one) as G:
+        G.run([0, 0])
+        assert G.scores().tolist() == [0.0]
+    u = np.array([0, 1, 4])
+    base = W.csr_from_edges(7, u, u + 1)  # 3 and 6 isolated
+    g = W.with_weights(base, 1, 7, seed=3)
+    ref, _ = oracle.bc(g)
+    with b.Graph(g) as G:
+        G.run(None)
+        assert_bc_close(G.scores(), ref)
+        G.run([])
+        assert (G.scores() == 0).all()
+        G.run([3, 3, 6])
+        assert (G.scores() == 0).all()
+        det = G.detail([3], dump_index=0)
+        assert det["d64"].tolist() == [-1, -1, -1, 0, -1, -1, -1]
+    dg = W.with_weights(W.rmat_directed(10, 6, seed=71), 1, 20, seed=4)
+    s1 = W.choose_sources(dg, 50, seed=1)
+    s2 = W.choose_sources(dg, 30, seed=2)
+    with b.Graph(dg) as G:
+        G.run(s1)
+        G.run(s2, flags=b.BC_RUN_ACCUMULATE)
+        ref, _ = oracle.bc(dg, np.concatenate([s1, s2]))
+        assert_bc_close(G.scores(), ref)
+        G.run(np.concatenate([s1[:5], s1[:5]]))
+        r1, _ = oracle.bc(dg, s1[:5])
+        assert_bc_close(G.scores(), 2 * r1)
