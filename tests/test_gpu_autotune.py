@@ -1,7 +1,8 @@
 """GPU tests of the launch-configuration autotuner: it returns one of its
 candidates, leaves the scores reset, and a tuned run gives the same bits as
-a default run of the same batch width (policy, workgroups, chunk length and
-WPV threshold never change a sum or its order) and matches the oracle.  The
+a default run of the same batch width and replica count (policy,
+workgroups, chunk length, WPV threshold and summation never change a sum or
+its order) and matches the oracle.  The
 tune cache returns a kept result without timing, also to a new handle of the
 same graph after a save and load, and BC_TUNE_FRESH tunes again."""
 from __future__ import annotations
@@ -35,7 +36,8 @@ def test_autotune_candidates_and_same_bits():
         assert best["grid_blocks"] >= 1
         assert best["replicas"] in (4, 8, 16)  # half, default (2^14 vertices: 8) or twice
         assert not G.scores().any()
-        G.run(srcs, batch=best["batch"])  # same width, default policy and launch shape
+        # same width and replica count, default policy and launch shape
+        G.run(srcs, batch=best["batch"], replicas=best["replicas"])
         ref_bits = G.scores().copy()
         G.run(srcs, flags=b.BC_RUN_TUNED)
         got = G.scores()
@@ -78,7 +80,7 @@ def test_tune_cache_hit_save_load_and_fresh(tmp_path):
         assert time.perf_counter() - t < t_tune / 5
         H.run(srcs, flags=b.BC_RUN_TUNED)
         got = H.scores().copy()
-        H.run(srcs, batch=best["batch"])
+        H.run(srcs, batch=best["batch"], replicas=best["replicas"])
         assert np.array_equal(got.view(np.uint64), H.scores().view(np.uint64))
         H.autotune(srcs[:64])  # another sample: tuned and kept beside the first
         assert b.bc_tune_cache_size() == 2
