@@ -220,3 +220,35 @@ def test_ba512_all_sources_score_sums():
         have = float(np.sum(got[lo:hi], dtype=np.float64))
         assert abs(have - want) <= REL * want, (i, have, want)
     say(f"  score sums of 48 more graphs: {time.time() - t:.1f}s on the host")
+
+
+def test_rmat18_directed_8192_sources():
+    # the directed benchmark workload at full size: dumps, the score sum
+    # (hop-count excess over out-arcs) and an oracle prefix
+    _full_case("rmat18_directed", dump_at=[0, 4097, 8191], prefix=96)
+
+
+def test_rmat18_weighted_4096_sources():
+    # the weighted benchmark workload at full size: repeatable bits, dumps
+    # from the full run (int64 distances and uint64 counts bit-exact), and a
+    # 48-source prefix against the oracle on 16 host threads
+    t = time.time()
+    g, srcs = W.workload("rmat18_weighted")
+    say(f"[fullsize rmat18_weighted] n={g.n} m={g.m} sources={len(srcs)} (generated in {time.time() - t:.1f}s)")
+    with _graph(g) as G:
+        t = time.time()
+        G.run(srcs)
+        full = G.scores().copy()
+        st = G.stats()
+        say(f"  full run {time.time() - t:.2f}s, f64 sources {st['f64_sources']}, relaxation rounds "
+            f"{st['forward_levels']}")
+        for k in (0, 2049, 4095):
+            det = G.detail(srcs, dump_index=k)
+            check_detail(g, det, srcs[k])
+            assert np.array_equal(G.scores().view(np.uint64), full.view(np.uint64))
+        G.run(srcs[:48])
+        got = G.scores()
+    t = time.time()
+    ref, _ = oracle.bc_sliced(g, srcs[:48], threads=16)
+    say(f"  oracle on 48 sources: {time.time() - t:.1f}s on the host")
+    assert_bc_close(got, ref)
