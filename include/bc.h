@@ -110,12 +110,17 @@ bc_status bc_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr,
  * exactly); an undirected graph must carry the same weight on both arcs of
  * an edge (else BC_ERR_INVALID_GRAPH).  BC_DIRECTED is accepted (the library
  * builds the in-arcs and their weights).  The handle keeps the caller's
- * numbering and runs the weighted engine: a persistent launch in which every
- * workgroup computes whole sources (distances by relaxation rounds, path
+ * numbering; unless BC_KEEP_ORDER is given it still takes the sources of a
+ * run in the ranked order described for bc_graph_create (by hop distance
+ * from the vertex of largest degree, ...).  It runs the weighted engine: a
+ * persistent launch in which every
+ * workgroup computes whole batches of 16 sources, or single sources
+ * (bc_run_options.weighted_lanes), (distances by relaxation rounds, path
  * counts over the shortest-path DAG in rounds of ready vertices, Eq. 2 over
  * those rounds in reverse); uint64 path counts, redone in FP64 (unscaled; a
  * count beyond the double range gives BC_ERR_SIGMA_RANGE) for sources whose
- * counts overflow.  Run options other than flags and sigma_limit are ignored.
+ * counts overflow.  Run options other than flags, sigma_limit and weighted_lanes
+ * are ignored.
  * bc_run_detail reports distances in bc_detail.d64.
  */
 bc_status bc_graph_create_weighted(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
@@ -216,7 +221,11 @@ typedef struct bc_run_options {
                              Scores agree to rounding across values; a given value
                              repeats bit for bit (BC_RUN_ONE_QUEUE: one, whatever
                              this says). */
-    int32_t reserved[5];
+    int32_t weighted_lanes;/* graphs with arc weights: sources one workgroup runs
+                             together (0 = default 16; 1 = one source per
+                             workgroup; 16).  Scores agree to rounding across
+                             values; a given value repeats bit for bit.     */
+    int32_t reserved[4];
 } bc_run_options;
 
 /* Fill *opt with defaults (all zero fields, i.e. autotuned/automatic). */
@@ -375,9 +384,14 @@ typedef struct bc_stats {
        of the shortest-path DAG, arcs_scanned = arcs relaxed, lane_arcs = arcs
        read by the four passes over the reached vertices (DAG in-arc counts,
        path counts, release of successors, dependencies), launches and
-       mode_* = the engine's launches; algo_bytes = 16 per arc read in any of
-       them + 64 per reached (vertex, source) pair, algo_bytes_arcs = the
-       arc term alone. */
+       mode_* = the engine's launches; algo_bytes_arcs = algo_bytes without
+       64 B per reached (vertex, source) pair.  One source per workgroup
+       (weighted_lanes 1): algo_bytes = 16 per arc read + 64 per reached pair.
+       Lane batches (weighted_lanes 16; arcs counted once per round entry,
+       for all of its sources): phase_lane_arcs[1] and [2] = (arc, source)
+       pairs of the relaxation rounds and of the four passes; algo_bytes = 8
+       per arc read (far end and weight) + 8 per (arc, source) pair (that
+       source's value at the far end) + 64 per reached pair. */
     int64_t block_workgroups;  /* block engine: workgroups of its launch (0 = not used) */
     int64_t block_chunks;      /* block engine: chunks of consecutive batches   */
 } bc_stats;

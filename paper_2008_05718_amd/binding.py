@@ -74,7 +74,7 @@ class RunOptions(ctypes.Structure):
                 ("grid_blocks", ctypes.c_int32), ("chunk_steps", ctypes.c_int32),
                 ("sigma_limit", ctypes.c_int64), ("lanes_per_entry", ctypes.c_float),
                 ("policy_margin", ctypes.c_float), ("replicas", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("weighted_lanes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class Detail(ctypes.Structure):
@@ -207,7 +207,7 @@ def _stream(stream):
 
 def make_options(batch=0, policy=BC_POLICY_AUTO, flags=0, alpha=0.0, beta=0.0, wpv_degree=0.0,
                  grid_blocks=0, chunk_steps=0, sigma_limit=0, lanes_per_entry=0.0,
-                 policy_margin=0.0, replicas=0) -> RunOptions:
+                 policy_margin=0.0, replicas=0, weighted_lanes=0) -> RunOptions:
     o = RunOptions()
     lib().bc_run_options_init(ctypes.byref(o))
     o.flags, o.batch, o.policy = flags, batch, policy
@@ -216,6 +216,7 @@ def make_options(batch=0, policy=BC_POLICY_AUTO, flags=0, alpha=0.0, beta=0.0, w
     o.lanes_per_entry = lanes_per_entry
     o.policy_margin = policy_margin
     o.replicas = replicas
+    o.weighted_lanes = weighted_lanes
     return o
 
 

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbc.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["bc_api.hip", "bc_plain.hip", "bc_batched.hip", "bc_mlp.hip", "bc_weighted.hip"]
+SOURCES = ["bc_api.hip", "bc_plain.hip", "bc_batched.hip", "bc_mlp.hip", "bc_weighted.hip", "bc_wbatch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

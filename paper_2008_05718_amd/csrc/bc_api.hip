@@ -21,6 +21,7 @@ template <int MODE> __global__ void plain_step(PlainArgs a);
 template <int MODE> __global__ void batch_step(BatchArgs a);
 template <int MODE> __global__ void block_run(BlockArgs a);
 template <int MODE> __global__ void weighted_run(WeightedArgs a);
+template <int MODE> __global__ void wbatch_run(WeightedArgs a);
 }  // namespace bcx
 
 using namespace bcx;
@@ -185,6 +186,7 @@ struct bc_graph {
     // same array for an undirected graph); the weighted engine's state
     bool weighted = false;
     int32_t *wt = nullptr, *in_wt = nullptr;
+    int w_lanes = 0;                  // sources per workgroup of the allocated state (1 or kWL)
     int w_wg = 0;                     // workgroups whose state is allocated
     size_t w_stride = 0;
     char *w_scratch = nullptr;
@@ -440,6 +442,7 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
     if (directed) flags |= BC_SKIP_SYMMETRY_CHECK | BC_KEEP_ORDER;
     if (weights && n_graphs > 1)
         return fail(BC_ERR_NOT_SUPPORTED, "weighted graphs are supported one per handle (bc_graph_create_weighted)");
+    const bool keep_sources = flags & BC_KEEP_ORDER;  // the caller's own request
     if (weights) flags |= BC_KEEP_ORDER;  // weights stay aligned with the caller's arcs
     bc_graph *g = new bc_graph();
     g->directed = directed;
@@ -614,6 +617,13 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
                 CR_TRY(hipMemcpy(col.data(), g->col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToHost));
                 source_ranks(n_graphs, voff, rp, col, &g->srank);
             }
+        }
+        if (weights && !keep_sources && n > 0 && nnz > 0) {
+            // the vertex numbering stays, the sources are still ranked: a lane
+            // batch of the weighted engine then holds sources near each other
+            std::vector<int32_t> col((size_t)nnz);
+            CR_TRY(hipMemcpy(col.data(), g->col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToHost));
+            source_ranks(n_graphs, voff, rp, col, &g->srank);
         }
         // vertices heavier than one segment, for the split load balancing
         // (one list per engine segment size)
@@ -1055,6 +1065,14 @@ static double algo_bytes(const bc_stats &s) { return algo_bytes_arcs(s) + 40.0 *
 // into the partial scores, the partial's read-modify-write).
 static double algo_bytes_weighted(double relax_bytes, double dag_arcs, double reached) {
     return relax_bytes + 16.0 * dag_arcs + 64.0 * reached;
+}
+
+// Lane-batched weighted engine: 8 B per arc read by a round's entry (far end
+// and weight, once for all sources of the entry), 8 B per (arc, source) pair
+// (the far end's 64-bit distance, path count or c of that source), 64 B per
+// reached (vertex, source) pair as above.
+static double algo_bytes_wbatch(double entry_arcs, double lane_arcs, double reached) {
+    return 8.0 * entry_arcs + 8.0 * lane_arcs + 64.0 * reached;
 }
 
 static void accumulate_stats(bc_stats *s, const Ctl &c, double clock_khz) {
@@ -1742,14 +1760,27 @@ __global__ void sum_partials(double *dst, const double *partials, int64_t n, int
     }
 }
 
-static bc_status ensure_weighted(bc_graph *g) {
-    if (g->w_wg > 0) return BC_OK;
-    const WeightedLayout L((size_t)std::max<int32_t>(g->n, 1));
-    g->w_stride = L.bytes;
+// Sources one workgroup runs together on a weighted graph: the run option,
+// else kWL.
+static int weighted_lanes(const bc_run_options &o) { return o.weighted_lanes == 1 ? 1 : kWL; }
+
+static bc_status ensure_weighted(bc_graph *g, int lanes) {
+    if (g->w_wg > 0 && g->w_lanes == lanes) return BC_OK;
+    if (g->w_scratch) {  // the other engine's state
+        (void)hipFree(g->w_scratch);
+        g->acct.bytes -= std::min(g->acct.bytes, (size_t)g->w_wg * g->w_stride);
+        g->w_scratch = nullptr;
+        g->w_wg = 0;
+    }
+    const size_t n = (size_t)std::max<int32_t>(g->n, 1);
+    g->w_stride = lanes == 1 ? WeightedLayout(n).bytes : WBLayout(n).bytes;
     int dev = 0, cus = 0, per_cu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)weighted_run<0>, kBlock, 0));
+    if (lanes == 1)
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)weighted_run<0>, kBlock, 0));
+    else
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)wbatch_run<0>, kWBatchBlock, 0));
     // as many workgroups as the CUs hold (each works through its sources
     // alone, so resident workgroups are what hides memory latency), within
     // the memory budget
@@ -1761,8 +1792,9 @@ static bc_status ensure_weighted(bc_graph *g) {
     want = std::min<int64_t>(want, (int64_t)(budget / g->w_stride));
     if (want < 1) return fail(BC_ERR_OUT_OF_MEMORY, "the weighted engine's per-workgroup state does not fit");
     HIP_TRY(dalloc(&g->w_scratch, (size_t)want * g->w_stride, &g->acct));
-    HIP_TRY(dalloc(&g->w_ctr, 16, &g->acct));
+    if (!g->w_ctr) HIP_TRY(dalloc(&g->w_ctr, 16, &g->acct));
     g->w_wg = (int)want;
+    g->w_lanes = lanes;
     return BC_OK;
 }
 
@@ -1773,18 +1805,20 @@ static bc_status weighted_pass(bc_graph *g, int mode, const bc_run_options &o, c
                                std::vector<int64_t> *ovf, bool *dumped) {
     ovf->clear();
     if (pos.empty()) return BC_OK;
-    bc_status s = ensure_weighted(g);
+    const int lanes = weighted_lanes(o);
+    bc_status s = ensure_weighted(g, lanes);
     if (s != BC_OK) return s;
     const int64_t ns = (int64_t)pos.size(), n = std::max<int32_t>(g->n, 1);
-    // chunks of consecutive positions: up to two per workgroup, and at most
-    // 8 GiB of partial scores
-    int64_t nc = std::min<int64_t>(ns, 2 * (int64_t)g->w_wg);
+    // chunks of consecutive positions, whole batches of `lanes` sources: up
+    // to two per workgroup, and at most 8 GiB of partial scores
+    const int64_t nbatch = (ns + lanes - 1) / lanes;
+    int64_t nc = std::min<int64_t>(nbatch, 2 * (int64_t)g->w_wg);
     nc = std::max<int64_t>(1, std::min<int64_t>(nc, ((int64_t)8 << 30) / (8 * n)));
     const int nwg = (int)std::min<int64_t>(g->w_wg, nc);
     std::vector<int32_t> ch(3 * (size_t)nc), list((size_t)ns);
     for (int64_t t = 0; t < nc; ++t) {
-        ch[t] = (int32_t)(ns * t / nc);
-        ch[nc + t] = (int32_t)(ns * (t + 1) / nc);
+        ch[t] = (int32_t)std::min<int64_t>(ns, lanes * (nbatch * t / nc));
+        ch[nc + t] = (int32_t)std::min<int64_t>(ns, lanes * (nbatch * (t + 1) / nc));
         ch[2 * nc + t] = (int32_t)t;
     }
     int64_t pdump = -1;
@@ -1840,8 +1874,13 @@ static bc_status weighted_pass(bc_graph *g, int mode, const bc_run_options &o, c
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, st));
-    if (mode) weighted_run<1><<<nwg, kBlock, 0, st>>>(a);
-    else weighted_run<0><<<nwg, kBlock, 0, st>>>(a);
+    if (lanes == 1) {
+        if (mode) weighted_run<1><<<nwg, kBlock, 0, st>>>(a);
+        else weighted_run<0><<<nwg, kBlock, 0, st>>>(a);
+    } else {
+        if (mode) wbatch_run<1><<<nwg, kWBatchBlock, 0, st>>>(a);
+        else wbatch_run<0><<<nwg, kWBatchBlock, 0, st>>>(a);
+    }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(e1, st));
     sum_partials<<<grid_for(n, 256, 4096), 256, 0, st>>>(g->bc, g->w_partials, n, nc);
@@ -1871,8 +1910,16 @@ static bc_status weighted_pass(bc_graph *g, int mode, const bc_run_options &o, c
     g->stats.max_levels = std::max<int64_t>(g->stats.max_levels, 0);
     g->stats.steps += (int64_t)ctr[6];
     g->stats.reached_pairs += (int64_t)ctr[7];
-    g->stats.lane_arcs += (int64_t)ctr[8];
-    g->stats.mode_algo_bytes[mode] += algo_bytes_weighted(16.0 * (double)ctr[5], (double)ctr[8], (double)ctr[7]);
+    if (lanes == 1) {
+        g->stats.lane_arcs += (int64_t)ctr[8];
+        g->stats.mode_algo_bytes[mode] += algo_bytes_weighted(16.0 * (double)ctr[5], (double)ctr[8], (double)ctr[7]);
+    } else {
+        g->stats.lane_arcs += (int64_t)ctr[8];
+        g->stats.phase_lane_arcs[1] += (int64_t)ctr[9];
+        g->stats.phase_lane_arcs[2] += (int64_t)ctr[10];
+        g->stats.mode_algo_bytes[mode] +=
+            algo_bytes_wbatch((double)(ctr[5] + ctr[8]), (double)(ctr[9] + ctr[10]), (double)ctr[7]);
+    }
     return BC_OK;
 }
 
@@ -2300,6 +2347,8 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
         if (o.replicas == 0) o.replicas = g->tuned.replicas;
         o.flags &= ~BC_RUN_TUNED;
     }
+    if (o.weighted_lanes != 0 && o.weighted_lanes != 1 && o.weighted_lanes != kWL)
+        return fail(BC_ERR_INVALID_ARG, "weighted_lanes must be 0, 1 or 16");
     const bool blk = use_block(g, o, sources ? n_sources : g->n, detail != nullptr);
     if (!blk && !g->weighted && use_parts(g, o, sources ? n_sources : g->n)) {
         g->last_parts = true;
@@ -2396,7 +2445,7 @@ static bc_status run_impl(bc_graph *g, const int32_t *sources, int64_t n_sources
         }
         g->stats.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         g->stats.algo_bytes = g->stats.mode_algo_bytes[0] + g->stats.mode_algo_bytes[1];
-        g->stats.algo_bytes_arcs = 16.0 * (double)(g->stats.arcs_scanned + g->stats.lane_arcs);
+        g->stats.algo_bytes_arcs = g->stats.algo_bytes - 64.0 * (double)g->stats.reached_pairs;
         return BC_OK;
     }
     int dump_done = 0;
@@ -2545,7 +2594,9 @@ static const int32_t *to_internal(const bc_graph *g, const int32_t *sources, int
         buf->resize((size_t)g->n);
         for (int32_t v = 0; v < g->n; ++v) (*buf)[v] = map ? g->inv[v] : v;
     } else {
-        if (*n_sources < 0) return sources;
+        // an empty list stays as given (an empty vector's data() may be NULL,
+        // which would mean "every vertex")
+        if (*n_sources <= 0) return sources;
         buf->resize((size_t)*n_sources);
         for (int64_t i = 0; i < *n_sources; ++i) {
             const int32_t v = sources[i];

@@ -401,6 +401,14 @@ def test_degenerate_inputs():
         assert (G.scores() == 0).all()
         G.run([3, 3, 6], batch=64)
         assert (G.scores() == 0).all()
+    # a handle with hubs ranks its sources: an empty list is still no source
+    hub = W.rmat(10, 8, seed=5)
+    with b.Graph(hub) as G:
+        G.run(W.choose_sources(hub, 10, seed=1), batch=64)
+        assert (G.scores() > 0).any()
+        for K in (1, 64):
+            G.run([], batch=K)
+            assert (G.scores() == 0).all()
 
 
 def test_accumulate_and_duplicates():

@@ -1,5 +1,6 @@
 """GPU parity on graphs with positive integer arc weights (the forward phase
-as a shortest-path computation; the weighted engine).  Against the oracle,
+as a shortest-path computation; the weighted engines: 16 sources per
+workgroup in lane batches, the default, and one source per workgroup).  Against the oracle,
 whose weighted form is pinned in tests/test_oracle_weighted.py: int64
 distances and uint64 path counts bit for bit, FP64 counts, dependencies
 and scores within 1e-10 relative; runs repeat bit for bit; unit weights
@@ -17,21 +18,25 @@ from paper_2008_05718_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
+LANES = [16, 1]
+
+
+@pytest.mark.parametrize("lanes", LANES)
 @pytest.mark.parametrize("directed", [False, True])
 @pytest.mark.parametrize("wmax", [1, 3, 100])
-def test_weighted_rmat_against_oracle(directed, wmax):
+def test_weighted_rmat_against_oracle(directed, wmax, lanes):
     base = W.rmat_directed(11, 8, seed=61) if directed else W.rmat(11, 8, seed=61)
     g = W.with_weights(base, 1, wmax, seed=7)
     srcs = W.choose_sources(base, 200, seed=3)
     ref, modes = oracle.bc(g, srcs)
-    say(f"[weighted] directed={directed} wmax={wmax} n={g.n} f64 {int(modes.sum())}")
+    say(f"[weighted] directed={directed} wmax={wmax} lanes={lanes} n={g.n} f64 {int(modes.sum())}")
     with b.Graph(g) as G:
-        G.run(srcs)
+        G.run(srcs, weighted_lanes=lanes)
         got = G.scores().copy()
-        G.run(srcs)
+        G.run(srcs, weighted_lanes=lanes)
         assert np.array_equal(G.scores().view(np.uint64), got.view(np.uint64))
         for k in (0, 77, 199):
-            det = G.detail(srcs, dump_index=k)
+            det = G.detail(srcs, dump_index=k, weighted_lanes=lanes)
             check_detail(g, det, int(srcs[k]))
         st = G.stats()
         say(f"  relaxation rounds {st['forward_levels']}, DAG rounds {st['steps']}, arcs {st['arcs_scanned']}")
@@ -51,7 +56,8 @@ def test_unit_weights_equal_unweighted_engine():
     assert np.max(np.abs(wgot - ugot) / np.maximum(np.abs(ugot), 1e-300)) <= 1e-12
 
 
-def test_weighted_grid_overflow_to_fp64():
+@pytest.mark.parametrize("lanes", LANES)
+def test_weighted_grid_overflow_to_fp64(lanes):
     # unit weights on a 45 x 45 grid: counts from a corner pass 2^64, so the
     # sources run again with FP64 counts
     base = W.grid(45)
@@ -60,11 +66,49 @@ def test_weighted_grid_overflow_to_fp64():
     ref, modes = oracle.bc(g, srcs)
     assert modes[0] == 1
     with b.Graph(g) as G:
-        G.run(srcs)
+        G.run(srcs, weighted_lanes=lanes)
         assert G.stats()["f64_sources"] == int(modes.sum())
         assert_bc_close(G.scores(), ref)
-        det = G.detail(srcs, dump_index=0)
+        det = G.detail(srcs, dump_index=0, weighted_lanes=lanes)
         check_detail(g, det, 0)
+
+
+def test_weighted_lane_batches_path_count_limit():
+    # a path-count limit hands the sources whose counts pass it to the FP64
+    # pass; within a lane batch the other sources keep their uint64 results.
+    # Both engines, and both against the oracle.
+    base = W.rmat(11, 8, seed=64)
+    g = W.with_weights(base, 1, 2, seed=8)
+    srcs = W.choose_sources(base, 120, seed=9)
+    ref, _ = oracle.bc(g, srcs)
+    lim = 119  # about half of the sources have a count above it
+    over = []
+    for s in srcs:  # sources with a path count above the limit
+        o = oracle.source(g, int(s))
+        over.append(o.mode == 1 or bool((o.sigma_u64[o.d >= 0] > lim).any()))
+    want = sum(over)
+    assert 0 < want < len(srcs)
+    k_under, k_over = over.index(False), over.index(True)
+    got = {}
+    for lanes in LANES:
+        with b.Graph(g) as G:
+            G.run(srcs, weighted_lanes=lanes, sigma_limit=lim)
+            assert G.stats()["f64_sources"] == want
+            got[lanes] = G.scores().copy()
+            det = G.detail(srcs, dump_index=k_under, weighted_lanes=lanes, sigma_limit=lim)
+            check_detail(g, det, int(srcs[k_under]))
+            # a source over the limit is dumped from the FP64 pass
+            det = G.detail(srcs, dump_index=k_over, weighted_lanes=lanes, sigma_limit=lim)
+            o = oracle.source(g, int(srcs[k_over]))
+            assert det["mode"] == 1
+            np.testing.assert_array_equal(det["d64"], o.d)
+            r = o.d >= 0
+            sig = np.ldexp(det["sigma_mant"][r].astype(np.longdouble), det["sigma_exp"][r].astype(np.int64))
+            np.testing.assert_array_equal(sig, o.sigma_u64[r].astype(np.longdouble))
+            inner = o.d >= 1
+            assert_bc_close(det["delta"][inner], o.delta[inner])
+        assert_bc_close(got[lanes], ref)
+    assert_bc_close(got[16], got[1])
 
 
 def test_weighted_closed_forms_and_errors():
@@ -89,18 +133,24 @@ def test_weighted_closed_forms_and_errors():
     assert e.value.status == 2
 
 
-def test_weighted_heavy_vertices():
-    # hubs above the thread-per-vertex degree: sums run lane-strided
+@pytest.mark.parametrize("lanes", LANES)
+def test_weighted_heavy_vertices(lanes):
+    # hubs above the lane-batched engine's light-entry degree (256): their
+    # arcs are walked by a whole wavefront (sums as partials added in a
+    # fixed order)
     base = W.rmat(13, 16, seed=63)
     g = W.with_weights(base, 1, 4, seed=6)
     deg = base.degrees()
+    assert (deg > 256).sum() >= 4
     srcs = np.concatenate([np.argsort(-deg)[:4], W.choose_sources(base, 60, seed=5)]).astype(np.int32)
     ref, _ = oracle.bc(g, srcs)
     with b.Graph(g) as G:
-        G.run(srcs)
-        assert_bc_close(G.scores(), ref)
-        det = G.detail(srcs, dump_index=1)
+        G.run(srcs, weighted_lanes=lanes)
+        got = G.scores().copy()
+        assert_bc_close(got, ref)
+        det = G.detail(srcs, dump_index=1, weighted_lanes=lanes)
         check_detail(g, det, int(srcs[1]))
+        assert np.array_equal(G.scores().view(np.uint64), got.view(np.uint64))
 
 
 def test_weighted_degenerate_inputs_accumulate_and_duplicates():
@@ -134,3 +184,10 @@ def test_weighted_degenerate_inputs_accumulate_and_duplicates():
         G.run(np.concatenate([s1[:5], s1[:5]]))
         r1, _ = oracle.bc(dg, s1[:5])
         assert_bc_close(G.scores(), 2 * r1)
+        # a source listed 16 times fills one lane batch with the same vertex
+        G.run(np.repeat(s1[:1], 16))
+        r0, _ = oracle.bc(dg, s1[:1])
+        assert_bc_close(G.scores(), 16 * r0)
+        with pytest.raises(b.BCError) as e:
+            G.run(s1, weighted_lanes=8)
+        assert e.value.status == 1
