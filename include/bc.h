@@ -391,7 +391,10 @@ typedef struct bc_stats {
        for all of its sources): phase_lane_arcs[1] and [2] = (arc, source)
        pairs of the relaxation rounds and of the four passes; algo_bytes = 8
        per arc read (far end and weight) + 8 per (arc, source) pair (that
-       source's value at the far end) + 64 per reached pair. */
+       source's value at the far end) + 64 per reached pair; phase_ms[1],
+       [2], [3] = device time of the relaxation rounds, of the DAG rounds
+       (in-arc counts included) and of the dependencies (score accumulation
+       included), summed over the batches; phase_ms[4] = the longest batch. */
     int64_t block_workgroups;  /* block engine: workgroups of its launch (0 = not used) */
     int64_t block_chunks;      /* block engine: chunks of consecutive batches   */
 } bc_stats;

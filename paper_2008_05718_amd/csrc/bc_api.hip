@@ -190,7 +190,7 @@ struct bc_graph {
     int w_wg = 0;                     // workgroups whose state is allocated
     size_t w_stride = 0;
     char *w_scratch = nullptr;
-    unsigned long long *w_ctr = nullptr;  // [0] work queue, [1] overflow count, [2] error bits, [4..7] statistics
+    unsigned long long *w_ctr = nullptr;  // [0] work queue, [1] overflow count, [2] error bits, [4..14] statistics
     int32_t *w_chunk = nullptr;       // s0, s1, order
     int64_t w_chunk_cap = 0;
     int64_t *w_pos = nullptr;
@@ -1917,6 +1917,8 @@ static bc_status weighted_pass(bc_graph *g, int mode, const bc_run_options &o, c
         g->stats.lane_arcs += (int64_t)ctr[8];
         g->stats.phase_lane_arcs[1] += (int64_t)ctr[9];
         g->stats.phase_lane_arcs[2] += (int64_t)ctr[10];
+        for (int i = 0; i < 3; ++i) g->stats.phase_ms[1 + i] += (double)ctr[11 + i] / g->clock_khz;
+        g->stats.phase_ms[4] = std::max(g->stats.phase_ms[4], (double)ctr[14] / g->clock_khz);
         g->stats.mode_algo_bytes[mode] +=
             algo_bytes_wbatch((double)(ctr[5] + ctr[8]), (double)(ctr[9] + ctr[10]), (double)ctr[7]);
     }

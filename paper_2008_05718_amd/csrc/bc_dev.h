@@ -447,7 +447,8 @@ struct WeightedArgs {
     double *dump_delta;
     unsigned long long *st;   // statistics: [0] relaxation rounds, [1] arcs scanned, [2] DAG rounds,
                               // [3] reached pairs, [4] DAG-pass arcs, [5] relaxation (arc, source)
-                              // pairs, [6] DAG-pass (arc, source) pairs (the last two: lane batches)
+                              // pairs, [6] DAG-pass (arc, source) pairs, [7..9] clock ticks of the
+                              // three phases, [10] longest batch (the last six: lane batches)
 };
 
 }  // namespace bcx

@@ -36,8 +36,17 @@ constexpr unsigned long long kWInf = ~0ull;
 constexpr int kWGrp = kWave / kWL;  // groups per wavefront
 constexpr int kWBBlock = kWBatchBlock;
 constexpr int kWBWaves = kWBBlock / kWave;
-constexpr int kWBLight = 256;  // entries with more arcs are walked by a whole wavefront
-constexpr int kWU = 4;         // arcs whose loads a group issues together
+// (A/B on R-MAT 18 with weights, 4096 sources: 8 arcs per load round 1.88 s
+// against 2.04 s for 4 and 2.79 s for 2; light entries up to 32 arcs within
+// 2 % of 8 and 16, 64 arcs 1.95 s, 256 arcs 2.17 s)
+#ifndef BC_WB_LIGHT
+#define BC_WB_LIGHT 32
+#endif
+#ifndef BC_WB_UNROLL
+#define BC_WB_UNROLL 8
+#endif
+constexpr int kWBLight = BC_WB_LIGHT;  // entries with more arcs are walked by a whole wavefront
+constexpr int kWU = BC_WB_UNROLL;      // arcs whose loads a group issues together (divides kWL)
 
 // Values that other threads of the workgroup change (by atomics, or by stores
 // from other wavefronts) are read and written at device scope, in the L2,
@@ -192,6 +201,8 @@ __global__ __launch_bounds__(kWBBlock) void wbatch_run(WeightedArgs a) {
     uint32_t *lvlm = (uint32_t *)(base + L.lvlm);
     int32_t *lvl_off = (int32_t *)(base + L.lvl_off);
     unsigned long long st_rounds = 0, st_arcs = 0, st_dag = 0, st_pairs = 0, st_darcs = 0, st_rl = 0, st_dl = 0;
+    // device clock per phase (thread 0): relaxation, DAG rounds, dependencies; longest batch
+    unsigned long long tk_a = 0, tk_b = 0, tk_c = 0, tk_max = 0, tk0 = 0, tk1 = 0;
     const size_t nk = (size_t)n * kWL;
     for (size_t i = tid; i < nk; i += kWBBlock) {
         dist[i] = kWInf;
@@ -218,6 +229,20 @@ __global__ __launch_bounds__(kWBBlock) void wbatch_run(WeightedArgs a) {
         }
         __builtin_amdgcn_wave_barrier();
     };
+    // appends every vertex whose mask word is non-zero to list (count in
+    // *cnt, LDS), one wavefront-wide reservation per 64 vertices
+    auto gather = [&](const uint32_t *mask, int32_t *list, uint32_t *cnt) {
+        for (int b0 = wid * kWave; b0 < n; b0 += kWBBlock) {
+            const int v = b0 + lane;
+            const bool on = v < n && wb_ld32(&mask[v]) != 0u;
+            const unsigned long long bal = __ballot(on);
+            if (!bal) continue;
+            uint32_t at = 0;
+            if (lane == 0) at = atomicAdd(cnt, (uint32_t)__popcll(bal));
+            at = __shfl(at, 0);
+            if (on) list[at + __popcll(bal & ((1ull << lane) - 1ull))] = v;
+        }
+    };
     for (;;) {
         wb_sync();
         if (tid == 0) {
@@ -233,6 +258,7 @@ __global__ __launch_bounds__(kWBBlock) void wbatch_run(WeightedArgs a) {
             const int nb = min(kWL, a.c_s1[t] - p0);
             // ---------------- A: distances, relaxation rounds over lane masks
             wb_sync();
+            if (tid == 0) tk0 = tk1 = wall_clock64();
             if (tid < kWL) s_src[tid] = tid < nb ? a.srcs[p0 + tid] : -1;
             if (tid == 0) {
                 s_n0 = 0;
@@ -245,7 +271,7 @@ __global__ __launch_bounds__(kWBBlock) void wbatch_run(WeightedArgs a) {
                 const int s = s_src[tid];
                 __hip_atomic_store(&dist[row(s) + tid], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (atomicOr(&fm0[s], 1u << tid) == 0u) qa[atomicAdd(&s_n0, 1u)] = s;
-                if (atomicOr(&rm[s], 1u << tid) == 0u) reached[atomicAdd(&s_nr, 1u)] = s;
+                (void)atomicOr(&rm[s], 1u << tid);
             }
             wb_sync();
             uint32_t *fc = fm0, *fn = fm1;
@@ -262,21 +288,26 @@ __global__ __launch_bounds__(kWBBlock) void wbatch_run(WeightedArgs a) {
                 }
 #pragma unroll
                 for (int q = 0; q < kWU; ++q) {
+                    // No atomic here waits for its result: a lane whose tentative
+                    // distance was above the candidate is marked for the next
+                    // round even if another arc lowered it further meanwhile
+                    // (one relaxation more, never a wrong distance), and the
+                    // next round's queue is gathered from the marks afterwards.
                     bool dropped = false, first = false;
                     if (act[q]) {
                         ++st_rl;
                         const unsigned long long nd = dv[q] + (unsigned long long)r[q].w;
                         if (nd < dx[q]) {
-                            const unsigned long long old = atomicMin(&dist[row(r[q].x) + k], nd);
-                            dropped = nd < old;
-                            first = old == kWInf;
+                            (void)atomicMin(&dist[row(r[q].x) + k], nd);
+                            dropped = true;
+                            first = dx[q] == kWInf;
                         }
                     }
                     const uint32_t gd = (uint32_t)(__ballot(dropped) >> gb) & ((1u << kWL) - 1u);
                     const uint32_t gf = (uint32_t)(__ballot(first) >> gb) & ((1u << kWL) - 1u);
                     if (k == 0) {
-                        if (gd && atomicOr(&fn[r[q].x], gd) == 0u) nxt[atomicAdd(&s_n1, 1u)] = r[q].x;
-                        if (gf && atomicOr(&rm[r[q].x], gf) == 0u) reached[atomicAdd(&s_nr, 1u)] = r[q].x;
+                        if (gd) (void)atomicOr(&fn[r[q].x], gd);
+                        if (gf) (void)atomicOr(&rm[r[q].x], gf);
                     }
                 }
             };
@@ -309,6 +340,8 @@ __global__ __launch_bounds__(kWBBlock) void wbatch_run(WeightedArgs a) {
                 }
                 wb_sync();
                 for (uint32_t i = tid; i < nc; i += kWBBlock) fc[cur[i]] = 0u;
+                gather(fn, nxt, &s_n1);
+                wb_sync();
                 if (tid == 0) {
                     s_n0 = s_n1;
                     s_n1 = 0;
@@ -322,7 +355,14 @@ __global__ __launch_bounds__(kWBBlock) void wbatch_run(WeightedArgs a) {
                 nxt = tq;
                 ++st_rounds;
             }
+            gather(rm, reached, &s_nr);
+            wb_sync();
             const uint32_t nr = s_nr;
+            if (tid == 0) {
+                const unsigned long long now = wall_clock64();
+                tk_a += now - tk1;
+                tk1 = now;
+            }
             // ---------------- B: DAG in-arc counts (per reached vertex and lane)
             auto count = [&](const WArc *r) {
                 unsigned long long dv[kWU], du[kWU];
@@ -562,6 +602,11 @@ __global__ __launch_bounds__(kWBBlock) void wbatch_run(WeightedArgs a) {
                 nxt = tq;
             }
             st_dag += (unsigned)nl;
+            if (tid == 0) {
+                const unsigned long long now = wall_clock64();
+                tk_b += now - tk1;
+                tk1 = now;
+            }
             const uint32_t ovf = MODE == 0 ? s_ovf : 0u;
             const uint32_t live = ~ovf;
             // ---------------- C: dependencies, rounds in reverse
@@ -696,7 +741,18 @@ __global__ __launch_bounds__(kWBBlock) void wbatch_run(WeightedArgs a) {
                 cnt[at] = 0;
             }
             for (uint32_t i = tid; i < nr; i += kWBBlock) rm[reached[i]] = 0u;
+            if (tid == 0) {
+                const unsigned long long now = wall_clock64();
+                tk_c += now - tk1;
+                tk_max = max(tk_max, now - tk0);
+            }
         }
+    }
+    if (tid == 0) {
+        if (tk_a) atomicAdd(&a.st[7], tk_a);
+        if (tk_b) atomicAdd(&a.st[8], tk_b);
+        if (tk_c) atomicAdd(&a.st[9], tk_c);
+        if (tk_max) atomicMax(&a.st[10], tk_max);
     }
     // statistics (rounds are the same in every thread, the rest per thread)
     const unsigned long long vals[7] = {st_rounds, st_arcs, st_dag, st_pairs, st_darcs, st_rl, st_dl};
