@@ -485,22 +485,56 @@ __global__ __launch_bounds__(kWBBlock) void wbatch_run(WeightedArgs a) {
                     sv[q] = (MODE == 0 && act[q]) ? s_os[wid][r[q].o][k] : 0ull;
                     dx[q] = act[q] ? wb_ld(&dist[row(r[q].x) + k]) : 0ull;
                 }
+                // the successor's lanes touched here are marked; which of them
+                // became ready is read from the counts after the round
+                unsigned long long old[kWU];
+                bool dag[kWU];
 #pragma unroll
                 for (int q = 0; q < kWU; ++q) {
-                    bool ready = false;
-                    if (act[q]) {
-                        ++st_dl;
-                        if (dv[q] + (unsigned long long)r[q].w == dx[q]) {
-                            const size_t rx = row(r[q].x) + k;
-                            if (MODE == 0) {
-                                const unsigned long long old = atomicAdd(&sig[rx], sv[q]);
-                                if (old + sv[q] < old) atomicOr(&s_ovf, kbit);
-                            }
-                            ready = atomicSub(&cnt[rx], 1) == 1;
-                        }
+                    dag[q] = act[q] && dv[q] + (unsigned long long)r[q].w == dx[q];
+                    if (act[q]) ++st_dl;
+                    old[q] = 0ull;
+                    if (dag[q]) {
+                        const size_t rx = row(r[q].x) + k;
+                        if (MODE == 0) old[q] = atomicAdd(&sig[rx], sv[q]);
+                        (void)atomicSub(&cnt[rx], 1);
                     }
-                    const uint32_t gr = (uint32_t)(__ballot(ready) >> gb) & ((1u << kWL) - 1u);
-                    if (k == 0 && gr && atomicOr(&fn[r[q].x], gr) == 0u) nxt[atomicAdd(&s_n1, 1u)] = r[q].x;
+                    const uint32_t gt = (uint32_t)(__ballot(dag[q]) >> gb) & ((1u << kWL) - 1u);
+                    if (k == 0 && gt) (void)atomicOr(&fn[r[q].x], gt);
+                }
+                if (MODE == 0) {  // exact carry test of the uint64 sums
+                    bool carry = false;
+#pragma unroll
+                    for (int q = 0; q < kWU; ++q) carry |= dag[q] && old[q] + sv[q] < old[q];
+                    if (carry) atomicOr(&s_ovf, kbit);
+                }
+            };
+            // after a round: a touched (vertex, lane) whose count reached zero is
+            // ready; the touched mask becomes the ready mask, and vertices with a
+            // ready lane form the next round's queue
+            auto gather_ready = [&](uint32_t *mask, int32_t *list, uint32_t *cntr) {
+                for (int b0 = wid * kWave; b0 < n; b0 += kWBBlock) {
+                    const int v = b0 + lane;
+                    const uint32_t m = v < n ? wb_ld32(&mask[v]) : 0u;
+                    uint32_t ready = 0u;
+                    if (m) {
+                        const unsigned long long *cr = (const unsigned long long *)&cnt[row(v)];
+                        unsigned long long c2[kWL / 2];
+#pragma unroll
+                        for (int j = 0; j < kWL / 2; ++j) c2[j] = wb_ld(&cr[j]);
+#pragma unroll
+                        for (int j = 0; j < kWL; ++j) {
+                            const uint32_t c = (uint32_t)(c2[j >> 1] >> (32 * (j & 1)));
+                            if (((m >> j) & 1u) && c == 0u) ready |= 1u << j;
+                        }
+                        __hip_atomic_store(&mask[v], ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    const unsigned long long bal = __ballot(ready != 0u);
+                    if (!bal) continue;
+                    uint32_t at = 0;
+                    if (lane == 0) at = atomicAdd(cntr, (uint32_t)__popcll(bal));
+                    at = __shfl(at, 0);
+                    if (ready) list[at + __popcll(bal & ((1ull << lane) - 1ull))] = v;
                 }
             };
             for (;;) {
@@ -586,6 +620,8 @@ __global__ __launch_bounds__(kWBBlock) void wbatch_run(WeightedArgs a) {
                 }
                 wb_sync();
                 for (uint32_t i = tid; i < nc; i += kWBBlock) fc[cur[i]] = 0u;
+                gather_ready(fn, nxt, &s_n1);
+                wb_sync();
                 if (tid == 0) {
                     lvl_off[nl + 1] = off + (int)nc;
                     s_off = off + (int)nc;
