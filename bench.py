@@ -47,6 +47,7 @@ KERNEL_FILES = {
     "batch_step": ["paper_2008_05718_amd/csrc/bc_batched.hip"] + _COMMON_SOURCES,
     "block_run": ["paper_2008_05718_amd/csrc/bc_batched.hip"] + _COMMON_SOURCES,
     "weighted_run": ["paper_2008_05718_amd/csrc/bc_weighted.hip"] + _COMMON_SOURCES,
+    "wbatch_run": ["paper_2008_05718_amd/csrc/bc_wbatch.hip"] + _COMMON_SOURCES,
 }
 KERNEL_SOURCES = sorted({f for v in KERNEL_FILES.values() for f in v})
 
@@ -81,7 +82,8 @@ def measured_traffic(kernel: str, workload: str):
     copy-kernel calibration), or None when there is none or the kernel
     sources changed since the counters were taken."""
     tag = {"batch_step<0>": "batch_step_u64", "batch_step<1>": "batch_step_f64", "block_run<0>": "block_run_u64",
-           "weighted_run<0>": "weighted_run_u64", "weighted_run<1>": "weighted_run_f64"}.get(kernel)
+           "weighted_run<0>": "weighted_run_u64", "weighted_run<1>": "weighted_run_f64",
+           "wbatch_run<0>": "wbatch_run_u64", "wbatch_run<1>": "wbatch_run_f64"}.get(kernel)
     path = os.path.join(ROOT, "profiles", f"{tag}_{workload}.md")
     if tag is None or not os.path.exists(path):
         return None
@@ -316,6 +318,8 @@ def main():
     ap.add_argument("--tune-cache", default=TUNE_CACHE, help="tune cache file to load (if it exists)")
     ap.add_argument("--tune-cache-out", help="write the process's tune cache here after tuning")
     ap.add_argument("--retune", action="store_true", help="tune even when the cache holds a result")
+    ap.add_argument("--weighted-lanes", type=int, default=0, choices=[0, 1, 16],
+                    help="graphs with arc weights: sources per workgroup (0 = library default, 16)")
     ap.add_argument("--policy-margin", type=float, default=0.0,
                     help="learned policy: log2 gain needed to override the rule (0 = library default, <0 = none)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -400,12 +404,15 @@ def main():
         gpu_ms = ev0.elapsed_time(ev1)
         return wall, gpu_ms, stats
 
-    # graphs with arc weights run on the weighted engine (one workgroup per
-    # source; no batch width, level policy or launch shape to tune, and no
-    # per-source or heuristic leg)
+    # graphs with arc weights run on the weighted engine (a persistent launch,
+    # 16 sources per workgroup; no level policy or launch shape to tune, and
+    # no per-source or heuristic leg)
     weighted = getattr(g, "weights", None) is not None
+    wextra = {}
     if weighted:
         args.no_tune, args.no_plain, args.heuristic_steps = True, True, 0
+        wextra = {"weighted_lanes": args.weighted_lanes}
+    wlanes = 1 if args.weighted_lanes == 1 else 16
 
     # ---- batched (headline); launch configuration tuned on a sample first (untimed)
     gflags = (b.BC_RUN_NO_GRAPHS if args.no_graphs else 0) | (b.BC_RUN_NO_BLOCKS if args.no_blocks else 0)
@@ -427,7 +434,7 @@ def main():
             b.bc_tune_cache_save(args.tune_cache_out)
     wall, gpu_ms, stats = timed(srcs, args.steps, args.warmup, batch=64, policy=pol, flags=gflags,
                                 grid_blocks=args.grid, lanes_per_entry=args.lanes_per_entry,
-                                policy_margin=args.policy_margin)
+                                policy_margin=args.policy_margin, **wextra)
     st = stats[-1]
     headline_bits = G.scores().copy()
     ms_step = wall * 1e3 / args.steps
@@ -452,7 +459,7 @@ def main():
     # the same bytes without the per-(vertex, source) slab term
     arcs_frac = sum(s["algo_bytes_arcs"] for s in stats) / max(sum(s["algo_bytes"] for s in stats), 1e-12)
     if weighted:
-        kernel = f"weighted_run<{k}>"
+        kernel = f"weighted_run<{k}>" if wlanes == 1 else f"wbatch_run<{k}>"
     elif k == 0 and st.get("block_workgroups", 0) > 0:
         kernel = "block_run<0>"
     else:
@@ -464,10 +471,16 @@ def main():
         f"variants={st['variant_levels']} f64={st['f64_sources']} reached pairs={st['reached_pairs']} "
         f"block engine workgroups={st['block_workgroups']} chunks={st['block_chunks']}")
     if weighted:
-        ns_run = max(st["n_sources"], 1)
-        log(f"[bench] weighted: per source {st['forward_levels'] / ns_run:.1f} relaxation rounds, "
-            f"{st['arcs_scanned'] / ns_run / max(g.nnz, 1):.2f} x nnz arcs relaxed, "
-            f"{st['steps'] / ns_run:.1f} DAG rounds, {st['lane_arcs'] / ns_run / max(g.nnz, 1):.2f} x nnz DAG-pass arcs")
+        nu = max(-(-st["n_sources"] // wlanes), 1)  # sources (one per workgroup) or lane batches
+        unit = "source" if wlanes == 1 else f"batch of {wlanes}"
+        log(f"[bench] weighted: per {unit} {st['forward_levels'] / nu:.1f} relaxation rounds, "
+            f"{st['arcs_scanned'] / nu / max(g.nnz, 1):.2f} x nnz arcs relaxed, "
+            f"{st['steps'] / nu:.1f} DAG rounds, {st['lane_arcs'] / nu / max(g.nnz, 1):.2f} x nnz DAG-pass arcs"
+            + ("" if wlanes == 1 else
+               f"; (arc, source) pairs per source: relaxation {st['phase_lane_arcs'][1] / st['n_sources'] / g.nnz:.2f}"
+               f" x nnz, DAG passes {st['phase_lane_arcs'][2] / st['n_sources'] / g.nnz:.2f} x nnz; device ms "
+               f"summed over batches (relaxation, DAG rounds, dependencies) "
+               f"{[round(x, 1) for x in st['phase_ms'][1:4]]}, longest batch {st['phase_ms'][4]:.1f} ms"))
     log("[bench] batched phase ms (fwd, sig, bwd, fin, bc):",
         [round(x, 1) for x in st["phase_ms"][1:6]], "variant ms:", [round(x, 1) for x in st["variant_ms"]])
     log("[bench] batched per phase: arcs", st["phase_arcs"][1:4], "lane arcs", st["phase_lane_arcs"][1:4],
@@ -527,7 +540,7 @@ def main():
                    "directed": bool(getattr(g, "directed", False)),
                    "arc_weights": (f"integers in [{int(g.weights.min())}, {int(g.weights.max())}]"
                                    if weighted else None),
-                   "batch": 1 if weighted else 64,
+                   "batch": wlanes if weighted else 64,
                    "policy": {1: "heuristic", 2: "mlp", 3: "tpv", 4: "wpv", 5: "pull"}.get(st["policy"]),
                    "mlp_weights_loaded": weights_loaded, "graph_chunk_steps": st["chunk_steps"],
                    "grid_blocks": st["grid_blocks"], "tuned": tuned, "tune_cache_hit": tune_cached,
