@@ -47,7 +47,8 @@ KERNEL_FILES = {
     "batch_step": ["paper_2008_05718_amd/csrc/bc_batched.hip"] + _COMMON_SOURCES,
     "block_run": ["paper_2008_05718_amd/csrc/bc_batched.hip"] + _COMMON_SOURCES,
     "weighted_run": ["paper_2008_05718_amd/csrc/bc_weighted.hip"] + _COMMON_SOURCES,
-    "wbatch_run": ["paper_2008_05718_amd/csrc/bc_wbatch.hip"] + _COMMON_SOURCES,
+    "wbatch_run": ["paper_2008_05718_amd/csrc/bc_wbatch.hip", "paper_2008_05718_amd/csrc/bc_wbatch.h"]
+    + _COMMON_SOURCES,
 }
 KERNEL_SOURCES = sorted({f for v in KERNEL_FILES.values() for f in v})
 

@@ -15,6 +15,7 @@
 
 #include "../../include/bc.h"
 #include "bc_common.h"
+#include "bc_wbatch.h"
 
 namespace bcx {
 template <int MODE> __global__ void plain_step(PlainArgs a);

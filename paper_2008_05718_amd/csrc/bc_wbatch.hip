@@ -27,6 +27,7 @@
 // order, so every result is fixed by the graph and the batch: runs are
 // bitwise reproducible.
 #include "bc_common.h"
+#include "bc_wbatch.h"
 
 namespace bcx {
 
