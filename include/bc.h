@@ -90,8 +90,10 @@ const char *bc_last_error(void);
  * library builds the in-arcs itself; the forward phase pushes over out-arcs
  * and pulls (discovery, path counts) over in-arcs, the backward phase pulls
  * dependencies from successors over out-arcs.  Such a handle keeps the
- * caller's numbering and source order (BC_KEEP_ORDER is implied) and always
- * runs the batched engine (batch = 1 means one source per traversal there).
+ * caller's numbering; unless BC_KEEP_ORDER is given it ranks the sources
+ * like an undirected handle (hop distance along out-arcs from the vertex of
+ * largest out-degree, ...).  It always runs the batched engine (batch = 1
+ * means one source per traversal there).
  * Scores are raw sums over ordered pairs, as for undirected graphs.
  * Errors: BC_ERR_INVALID_ARG (NULL pointers, negative sizes),
  * BC_ERR_INVALID_GRAPH (validation failure; bc_last_error names the rule),

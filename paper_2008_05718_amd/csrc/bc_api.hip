@@ -440,10 +440,10 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
     const bool directed = flags & BC_DIRECTED;
     if (directed && n_graphs > 1)
         return fail(BC_ERR_NOT_SUPPORTED, "directed graphs are supported one per handle (bc_graph_create)");
+    const bool keep_sources = flags & BC_KEEP_ORDER;  // the caller's own request
     if (directed) flags |= BC_SKIP_SYMMETRY_CHECK | BC_KEEP_ORDER;
     if (weights && n_graphs > 1)
         return fail(BC_ERR_NOT_SUPPORTED, "weighted graphs are supported one per handle (bc_graph_create_weighted)");
-    const bool keep_sources = flags & BC_KEEP_ORDER;  // the caller's own request
     if (weights) flags |= BC_KEEP_ORDER;  // weights stay aligned with the caller's arcs
     bc_graph *g = new bc_graph();
     g->directed = directed;
@@ -619,9 +619,10 @@ static bc_status create_impl(int32_t n_graphs, const int32_t *voff_in, int32_t n
                 source_ranks(n_graphs, voff, rp, col, &g->srank);
             }
         }
-        if (weights && !keep_sources && n > 0 && nnz > 0) {
-            // the vertex numbering stays, the sources are still ranked: a lane
-            // batch of the weighted engine then holds sources near each other
+        if ((weights || directed) && !keep_sources && n > 0 && nnz > 0) {
+            // the vertex numbering stays, the sources are still ranked (hop
+            // distance along out-arcs from the vertex of largest out-degree):
+            // a batch then holds sources near each other
             std::vector<int32_t> col((size_t)nnz);
             CR_TRY(hipMemcpy(col.data(), g->col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToHost));
             source_ranks(n_graphs, voff, rp, col, &g->srank);

@@ -94,7 +94,7 @@ def test_directed_heavy_vertices_split_by_larger_degree():
 def test_both_arcs_equal_the_undirected_engine():
     # a digraph holding both arcs of every edge is the undirected graph: same
     # adjacency, same order of every sum, so the same bits as an undirected
-    # handle that keeps the caller's numbering
+    # handle, both keeping the caller's numbering and source order
     und = W.rmat(11, 8, seed=31)
     rr = np.repeat(np.arange(und.n), np.diff(und.row_ptr.astype(np.int64)))
     dg = W.digraph_from_arcs(und.n, rr, und.col_idx.astype(np.int64))
@@ -102,10 +102,15 @@ def test_both_arcs_equal_the_undirected_engine():
     with b.Graph(und, flags=b.BC_KEEP_ORDER) as U:
         U.run(srcs, batch=64, flags=b.BC_RUN_ONE_QUEUE)
         u_bits = U.scores().copy()
-    with b.Graph(dg) as D:
+    with b.Graph(dg, flags=b.BC_KEEP_ORDER) as D:
         D.run(srcs, batch=64, flags=b.BC_RUN_ONE_QUEUE)
         d_bits = D.scores().copy()
     assert np.array_equal(u_bits.view(np.uint64), d_bits.view(np.uint64))
+    # without BC_KEEP_ORDER the digraph's sources are ranked: same scores to
+    # rounding
+    with b.Graph(dg) as D:
+        D.run(srcs, batch=64, flags=b.BC_RUN_ONE_QUEUE)
+        assert_bc_close(D.scores(), u_bits)
 
 
 def test_directed_grid_overflows_to_fp64():
