@@ -225,7 +225,8 @@ typedef struct bc_run_options {
                              this says). */
     int32_t weighted_lanes;/* graphs with arc weights: sources one workgroup runs
                              together (0 = default 16; 1 = one source per
-                             workgroup; 16).  Scores agree to rounding across
+                             workgroup; 16; graphs above 2^27 vertices always
+                             run one).  Scores agree to rounding across
                              values; a given value repeats bit for bit.     */
     int32_t reserved[4];
 } bc_run_options;

@@ -1763,8 +1763,12 @@ __global__ void sum_partials(double *dst, const double *partials, int64_t n, int
 }
 
 // Sources one workgroup runs together on a weighted graph: the run option,
-// else kWL.
-static int weighted_lanes(const bc_run_options &o) { return o.weighted_lanes == 1 ? 1 : kWL; }
+// else kWL; one when the lane batches' round records (n * kWL entries,
+// 32-bit offsets) would not fit.
+static int weighted_lanes(const bc_graph *g, const bc_run_options &o) {
+    if (o.weighted_lanes == 1 || (int64_t)g->n * kWL > (int64_t)INT32_MAX) return 1;
+    return kWL;
+}
 
 static bc_status ensure_weighted(bc_graph *g, int lanes) {
     if (g->w_wg > 0 && g->w_lanes == lanes) return BC_OK;
@@ -1807,7 +1811,7 @@ static bc_status weighted_pass(bc_graph *g, int mode, const bc_run_options &o, c
                                std::vector<int64_t> *ovf, bool *dumped) {
     ovf->clear();
     if (pos.empty()) return BC_OK;
-    const int lanes = weighted_lanes(o);
+    const int lanes = weighted_lanes(g, o);
     bc_status s = ensure_weighted(g, lanes);
     if (s != BC_OK) return s;
     const int64_t ns = (int64_t)pos.size(), n = std::max<int32_t>(g->n, 1);
