@@ -722,7 +722,6 @@ __device__ __forceinline__ void batch_begin(const BatchArgs &a, Ctl *c, int64_t 
 #ifndef BC_WAVES
 #define BC_WAVES 6
 #endif
-constexpr int kBcBatch = 8;  // dependencies loaded together by the BC accumulation
 // Register budget of the step kernel: at least BC_WAVES wavefronts per SIMD
 // (memory latency is hidden by resident wavefronts).
 // One step of the level state machine for workgroup bid of a launch of
@@ -748,6 +747,7 @@ __device__ __forceinline__ void batch_step_body(const BatchArgs &a, const unsign
     __shared__ float s_il;  // sources-per-entry threshold of this path-count / backward step
     __shared__ int s_usig;  // an undo step restores a path-count step (timing collection)
     __shared__ int s_emax[kLanes], s_emin[kLanes];
+    __shared__ double s_bct[kWavesPerBlock][kWave * 8];  // score accumulation: 64 rows x 8 lanes per wavefront
     Ctl *c = a.ctl;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     if (tid == 0) {
@@ -1146,34 +1146,46 @@ __device__ __forceinline__ void batch_step_body(const BatchArgs &a, const unsign
         }
     } else if (phase == PH_BC) {
         // dependencies -> BC in lane order (the run's source order), then
-        // clear the visited words
+        // clear the visited words.  A wavefront takes 64 consecutive
+        // vertices; their delta rows are read 8 lanes (64 bytes) at a time,
+        // 8 rows per load (coalesced), staged through LDS, and each vertex's
+        // own thread adds its lanes in ascending order (a source's own lane
+        // and lanes not reached are skipped: they would add +0.0, which
+        // leaves the non-negative sum's bits unchanged)
         const int lo = s_lo, span = s_hi - s_lo;
         const unsigned long long keep = s_lmask & ~s_dead;
-        for (int i = (int)bid * kBlock + tid; i < span; i += (int)nblk * kBlock) {
+        const int lane = lane_id(), wv = tid / kWave;
+        double *tile = s_bct[wv];
+        for (int base = ((int)bid * kWavesPerBlock + wv) * kWave; base < span; base += (int)nblk * kBlock) {
+            const int i = base + lane;
             const int w = lo + i;
-            const VisNext x = a.vn[w];
-            unsigned long long vis = x.vis & keep;
-            if (vis) {
-                double b = a.bc[w];
-                const double *dw = a.delta + (size_t)w * kLanes;
-                // the lanes' dependencies in lane order, loaded kBcBatch at a
-                // time before they are added (a source's own lane adds +0.0,
-                // which leaves the non-negative sum's bits unchanged)
-                while (vis) {
-                    double d[kBcBatch];
+            VisNext x;
+            x.vis = 0ull;
+            x.nxt = 0ull;
+            if (i < span) x = a.vn[w];
+            const unsigned long long vis = x.vis & keep;
+            if (__ballot(vis != 0ull)) {
+                double b = vis ? a.bc[w] : 0.0;
+                for (int c = 0; c < kLanes / 8; ++c) {
+                    const unsigned m8 = (unsigned)(vis >> (8 * c)) & 0xFFu;
+                    if (!__ballot(m8 != 0u)) continue;
 #pragma unroll
-                    for (int j = 0; j < kBcBatch; ++j) {
-                        d[j] = 0.0;
-                        if (vis) {
-                            const int k = __ffsll(vis) - 1;
-                            vis &= vis - 1;
-                            if (s_lsrc[k] != w) d[j] = dw[k];
-                        }
+                    for (int r = 0; r < 8; ++r) {
+                        const int vi = 8 * r + (lane >> 3);  // vertex of the 64 whose row this lane reads
+                        const int kk = lane & 7;
+                        const unsigned mv = (unsigned)__shfl((int)m8, vi);
+                        double d = 0.0;
+                        if ((mv >> kk) & 1u) d = a.delta[(size_t)(lo + base + vi) * kLanes + 8 * c + kk];
+                        tile[vi * 8 + (kk ^ (vi & 7))] = d;
                     }
+                    __builtin_amdgcn_wave_barrier();
 #pragma unroll
-                    for (int j = 0; j < kBcBatch; ++j) b += d[j];
+                    for (int j = 0; j < 8; ++j) {
+                        if (((m8 >> j) & 1u) && s_lsrc[8 * c + j] != w) b += tile[lane * 8 + (j ^ (lane & 7))];
+                    }
+                    __builtin_amdgcn_wave_barrier();
                 }
-                a.bc[w] = b;
+                if (vis) a.bc[w] = b;
             }
             if (x.vis | x.nxt) {
                 VisNext z;
