@@ -191,3 +191,35 @@ def test_weighted_degenerate_inputs_accumulate_and_duplicates():
         with pytest.raises(b.BCError) as e:
             G.run(s1, weighted_lanes=8)
         assert e.value.status == 1
+
+
+@pytest.mark.parametrize("lanes", LANES)
+def test_weighted_few_workgroups_many_batches(lanes):
+    # a device-memory cap just above the graph leaves room for the state of
+    # one or two workgroups, so each works through several chunks of several
+    # batches: the reset between batches and chunks is exercised
+    base = W.rmat(11, 8, seed=65)
+    g = W.with_weights(base, 1, 50, seed=9)
+    srcs = W.choose_sources(base, 300, seed=10)  # 19 lane batches, the last partial
+    ref, _ = oracle.bc(g, srcs)
+    with b.Graph(g) as G:
+        floor = G.info()["device_bytes"]
+        ran = False
+        for extra_mib in range(1, 41):
+            G.set_device_limit(floor + (extra_mib << 20))
+            try:
+                G.run(srcs, weighted_lanes=lanes)
+            except b.BCError as e:
+                assert e.status == 3, e  # refused before allocating
+                assert G.info()["device_bytes"] <= floor + (extra_mib << 20)
+                continue
+            ran = True
+            break
+        assert ran
+        say(f"[weighted few workgroups] lanes={lanes}: cap {extra_mib} MiB above the graph")
+        got = G.scores().copy()
+        assert_bc_close(got, ref)
+        det = G.detail(srcs, dump_index=290, weighted_lanes=lanes)
+        check_detail(g, det, int(srcs[290]))
+        G.run(srcs, weighted_lanes=lanes)
+        assert np.array_equal(G.scores().view(np.uint64), got.view(np.uint64))
