@@ -542,10 +542,13 @@ def main():
                    "arc_weights": (f"integers in [{int(g.weights.min())}, {int(g.weights.max())}]"
                                    if weighted else None),
                    "batch": wlanes if weighted else 64,
-                   "policy": {1: "heuristic", 2: "mlp", 3: "tpv", 4: "wpv", 5: "pull"}.get(st["policy"]),
-                   "mlp_weights_loaded": weights_loaded, "graph_chunk_steps": st["chunk_steps"],
-                   "grid_blocks": st["grid_blocks"], "tuned": tuned, "tune_cache_hit": tune_cached,
-                   "policy_margin": args.policy_margin},
+                   # the weighted engine has no level policy, captured chunks or launch shape
+                   "policy": None if weighted else
+                   {1: "heuristic", 2: "mlp", 3: "tpv", 4: "wpv", 5: "pull"}.get(st["policy"]),
+                   "mlp_weights_loaded": None if weighted else weights_loaded,
+                   "graph_chunk_steps": None if weighted else st["chunk_steps"],
+                   "grid_blocks": None if weighted else st["grid_blocks"], "tuned": tuned,
+                   "tune_cache_hit": tune_cached, "policy_margin": None if weighted else args.policy_margin},
         "create_s": round(create_s, 3),
         "heuristic": heur,
         "plain": plain,
