@@ -56,6 +56,8 @@ constexpr int kWBWaves = kWBBlock / kWave;
 #endif
 constexpr int kWBLight = BC_WB_LIGHT;  // entries with more arcs are walked by a whole wavefront
 constexpr int kWU = BC_WB_UNROLL;      // arcs whose loads a group issues together (divides kWL)
+static_assert(kWL <= 32 && kWave % kWL == 0, "lane masks are 32-bit words; groups tile a wavefront");
+static_assert(kWL % kWU == 0, "a load round must not reach into the next group's lanes");
 
 // Values that other threads of the workgroup change (by atomics, or by stores
 // from other wavefronts) are read and written at device scope, in the L2,
