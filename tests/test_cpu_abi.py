@@ -65,6 +65,24 @@ def test_struct_layouts_match_header(cname, pyt):
     assert _c_sizeof("", cname) == ctypes.sizeof(pyt)
 
 
+@pytest.mark.parametrize("cname,pyt", [("bc_run_options", b.RunOptions), ("bc_detail", b.Detail),
+                                       ("bc_stats", b.Stats), ("bc_level_stats", b.LevelStats)])
+def test_struct_field_offsets_match_header(cname, pyt):
+    # every field of the binding sits where the C compiler puts the field of
+    # the same name (sizes alone would not catch two fields swapped)
+    import tempfile
+    names = [f[0] for f in pyt._fields_]
+    body = "".join(f'printf("%zu\\n", offsetof({cname}, {n}));' for n in names)
+    prog = f'#include "{HEADER}"\n#include <stddef.h>\n#include <stdio.h>\nint main(void){{{body}return 0;}}\n'
+    with tempfile.TemporaryDirectory() as td:
+        c = os.path.join(td, "o.c")
+        exe = os.path.join(td, "o")
+        open(c, "w").write(prog)
+        subprocess.check_call(["gcc", c, "-o", exe])
+        got = [int(x) for x in subprocess.check_output([exe]).decode().split()]
+    assert got == [getattr(pyt, n).offset for n in names]
+
+
 def test_mlp_param_count_matches_header():
     txt = open(HEADER).read()
     m = re.search(r"#define BC_MLP_PARAMS \((.*?)\)\n", txt)
